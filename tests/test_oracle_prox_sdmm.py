@@ -1,0 +1,165 @@
+"""Pins for the oracle's proximity operators (eq. 7) and SDMM (Algorithm 1).
+
+* soft threshold vs brute-force 2D minimisation of eq. (7) on random complex scalars;
+* projections: feasibility, idempotence, variational inequality;
+* CG vs numpy.linalg.solve on a dense tiny (Phi^dagger Phi + 2I);
+* operator norm by power iteration vs the dense spectral norm;
+* special case eps >= ||y||: x_hat -> 0;
+* constraint satisfaction at convergence;
+* brute force: SLSQP on a tiny real problem reaches the same objective as SDMM;
+* the chi-square noise bound covers ~97.7% of noise draws (Monte Carlo).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import optimize
+
+from oracle.nufft import Nufft
+from oracle.prox import project_l2_ball, project_positive, soft_threshold
+from oracle.sara import Sara
+from oracle.sdmm import conjugate_gradient, operator_norm, sdmm
+from paper_1406_0359_amd import synth
+
+
+def test_soft_threshold_brute_force():
+    rng = np.random.default_rng(0)
+    for _ in range(40):
+        u = complex(*rng.normal(0, 2, 2))
+        lam = float(rng.uniform(0.05, 2.5))
+        f = lambda z: lam * math.hypot(z[0], z[1]) + 0.5 * ((z[0] - u.real) ** 2 + (z[1] - u.imag) ** 2)
+        best = min((optimize.minimize(f, x0, method="Nelder-Mead",
+                                      options=dict(xatol=1e-11, fatol=1e-14, maxiter=4000))
+                    for x0 in ([0.0, 0.0], [u.real, u.imag])), key=lambda r: r.fun)
+        got = soft_threshold(np.array([u]), lam)[0]
+        assert f([got.real, got.imag]) <= best.fun + 1e-10
+        assert abs(got - complex(*best.x)) < 1e-5
+    assert soft_threshold(np.array([0j]), 1.0)[0] == 0
+    assert soft_threshold(np.array([3 + 4j]), 5.0)[0] == 0
+    assert soft_threshold(np.array([3 + 4j]), 1.0)[0] == pytest.approx((3 + 4j) * 0.8)
+
+
+def test_positivity_projection():
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal(100) + 1j * rng.standard_normal(100)
+    p = project_positive(u)
+    assert np.all(p.real >= 0) and np.all(p.imag == 0)
+    assert np.array_equal(project_positive(p), p)
+    for _ in range(20):
+        v = np.abs(rng.standard_normal(100)) + 0j
+        assert np.vdot(u - p, v - p).real <= 1e-12
+
+
+def test_l2_ball_projection():
+    rng = np.random.default_rng(2)
+    y = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+    for eps in [0.1, 1.0, 100.0]:
+        u = y + rng.standard_normal(50) * 3
+        p = project_l2_ball(u, y, eps)
+        assert np.linalg.norm(p - y) <= eps * (1 + 1e-14)
+        assert np.allclose(project_l2_ball(p, y, eps), p)
+        for _ in range(20):
+            d = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+            v = y + d / np.linalg.norm(d) * eps * rng.uniform(0, 1)
+            assert np.vdot(u - p, v - p).real <= 1e-10
+    assert np.array_equal(project_l2_ball(y, y, 1.0), y)
+
+
+def _tiny_dense(n=8, M=40, J=6, seed=5):
+    rng = np.random.default_rng(seed)
+    uv = rng.uniform(-np.pi, np.pi, (M, 2))
+    op = Nufft(n, uv, J)
+    N = n * n
+    Phi = np.stack([op.phi(np.eye(N)[k].reshape(n, n)) for k in range(N)], axis=1)
+    return op, Phi
+
+
+def test_cg_matches_dense_solve():
+    op, Phi = _tiny_dense()
+    n = op.n
+    nu = np.linalg.norm(Phi, 2)
+    A = Phi.conj().T @ Phi / nu ** 2 + 2 * np.eye(n * n)
+    rng = np.random.default_rng(9)
+    b = rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)
+    ref = np.linalg.solve(A, b)
+    apply = lambda v: (op.phi_adj(op.phi(v.reshape(n, n))) / nu ** 2 + 2 * v.reshape(n, n)).ravel()
+    x10 = conjugate_gradient(apply, b, np.zeros_like(b), 10)
+    assert np.linalg.norm(x10 - ref) / np.linalg.norm(ref) < 2 * 0.101 ** 10 * math.sqrt(1.5) * 10
+    x40 = conjugate_gradient(apply, b, np.zeros_like(b), 40)
+    assert np.linalg.norm(x40 - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_operator_norm_power_iteration():
+    op, Phi = _tiny_dense(seed=6)
+    sv = np.linalg.svd(Phi, compute_uv=False)
+    ratio = (sv[1] / sv[0]) ** 2                  # eigenvalue ratio of Phi^dagger Phi
+    iters = int(math.ceil(math.log(1e-13) / math.log(ratio) / 2)) + 10
+    nu, lam = operator_norm(op.normal, (op.n, op.n), iters)
+    assert nu == pytest.approx(sv[0], rel=1e-11)
+    assert lam == pytest.approx(sv[0] ** 2, rel=1e-11)
+
+
+def _tiny_problem(n=8, M=48, mask=0x3, L=2, seed=21, isnr=30.0):
+    rng = np.random.default_rng(seed)
+    uv = synth.uv_coverage(M, 2 * n, rng)
+    op = Nufft(n, uv, 6)
+    x = synth.blob_image(n, 3, rng)
+    y0 = op.phi(x)
+    sigma = np.linalg.norm(y0) / math.sqrt(M) * 10 ** (-isnr / 20)
+    y = y0 + sigma * synth.unit_complex_noise(M, rng)
+    return op, Sara(n, mask, L), x, y, synth.chi2_epsilon(sigma, M)
+
+
+def test_sdmm_zero_when_ball_contains_origin():
+    op, sa, x, y, eps = _tiny_problem()
+    r = sdmm(op.phi, op.phi_adj, sa.psi, sa.psi_adj, y, 1.05 * np.linalg.norm(y), (op.n, op.n),
+             iters=400)
+    assert np.linalg.norm(r.x) < 1e-3 * np.linalg.norm(x)
+    assert r.objective[-1] < 1e-3 * np.sum(np.abs(sa.psi_adj(x)))
+
+
+def test_sdmm_constraints_at_convergence():
+    op, sa, x, y, eps = _tiny_problem(n=16, M=160, mask=0x1FF, L=2, seed=4)
+    r = sdmm(op.phi, op.phi_adj, sa.psi, sa.psi_adj, y, eps, (op.n, op.n), iters=3000)
+    xr = np.real(r.x)
+    assert np.linalg.norm(y - op.phi(xr)) <= eps * (1 + 1e-3)
+    assert xr.min() >= -1e-6 * xr.max()
+    assert np.max(np.abs(np.imag(r.x))) <= 1e-6 * xr.max()
+
+
+@pytest.mark.slow
+def test_sdmm_matches_slsqp_brute_force():
+    n = 4
+    op, sa, x, y, eps = _tiny_problem(n=n, M=10, mask=0x3, L=1, seed=8)
+    N = n * n
+    Phi = np.stack([op.phi(np.eye(N)[k].reshape(n, n)) for k in range(N)], axis=1)
+    Psit = np.stack([sa.psi_adj(np.eye(N)[k].reshape(n, n)).ravel() for k in range(N)], axis=1).real
+    D = Psit.shape[0]
+    # gamma fixed explicitly: the default (1e-3 max|Psi^dag Phi^dag y|) converges too slowly
+    # on this 4x4 case for a tight comparison.
+    r = sdmm(op.phi, op.phi_adj, sa.psi, sa.psi_adj, y, eps, (n, n), iters=5000, gamma=0.1)
+    f_sdmm = np.sum(np.abs(Psit @ np.real(r.x).ravel()))
+
+    def obj(z):
+        return z[N:].sum()
+    cons = [dict(type="ineq", fun=lambda z: z[N:] - Psit @ z[:N]),
+            dict(type="ineq", fun=lambda z: z[N:] + Psit @ z[:N]),
+            dict(type="ineq", fun=lambda z: eps ** 2 - np.sum(np.abs(y - Phi @ z[:N]) ** 2))]
+    z0 = np.concatenate([np.real(r.x).ravel(), np.abs(Psit @ np.real(r.x).ravel()) + 1e-3])
+    bounds = [(0, None)] * N + [(None, None)] * D
+    sol = optimize.minimize(obj, z0, method="SLSQP", constraints=cons, bounds=bounds,
+                            options=dict(maxiter=2000, ftol=1e-14))
+    f_ref = sol.fun
+    assert np.linalg.norm(y - Phi @ np.real(r.x).ravel()) <= eps * (1 + 1e-3)
+    assert abs(f_sdmm - f_ref) <= 1e-8 * f_ref
+
+
+def test_chi2_epsilon_coverage():
+    rng = np.random.default_rng(77)
+    M, sigma, trials = 400, 1.7, 4000
+    eps = synth.chi2_epsilon(sigma, M)
+    hits = 0
+    for _ in range(trials):
+        n = sigma * synth.unit_complex_noise(M, rng)
+        hits += np.linalg.norm(n) <= eps
+    assert abs(hits / trials - 0.977) < 0.012
