@@ -1,0 +1,217 @@
+"""Benchmark of the SDMM imaging hot path on one MI355X.
+
+A step is one complete imaging solve of the 256 x 256 SARA workload in FP64 (the plain
+method on the GPU): plan creation (uv binning, tables, upload), the operator norm by 100
+power iterations, the default gamma, and 300 SDMM iterations with 10 CG steps each, halting
+off.  ``value`` is SDMM iterations per second over the timed steps (inputs resident in HBM).
+
+Also reported:
+* ``roofline``: the dominant kernel's algorithmic bytes per launch divided by its average
+  launch time (HIP events on the stream it runs on), against 8 TB/s HBM;
+* ``cpu_baseline``: the FP64 NumPy/SciPy oracle on the same workload, timed on a bounded
+  sample (setup + a few SDMM iterations, extrapolated to the 300-iteration solve);
+* ``also``: per-stage timings and the 1024 x 1024 FP32 precision-form workload (M = 2N):
+  Phi / Phi^dagger Gvis/s, Psi / Psi^dagger GB/s and SDMM iterations per second.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(plan, stage: str) -> float:
+    """Algorithmic HBM bytes of one launch of a stage (each operand read or written once)."""
+    n, M, q = plan.n, plan.M, plan.q
+    N = n * n
+    c = 16 if plan.precision == 0 else 8          # complex element
+    coord = 4 + 2 * (c // 2)                       # packed first tap + two fractions
+    tbl = {
+        "fft_rows": N * c + 2 * N * c,             # read x, write K x n
+        "fft_cols": 2 * N * c + 4 * N * c,         # read K x n, write K x K
+        "degrid": 4 * N * c + M * (coord + c),     # read grid, coords; write y
+        "grid": M * (coord + c) + 4 * N * c,       # read y, coords; write grid
+        "ifft_cols": 4 * N * c + 2 * N * c,
+        "ifft_rows": 2 * N * c + N * c,
+        "psi_adj": N * c + q * N * c,
+        "psi": q * N * c + N * c,
+    }
+    tbl["phi"] = tbl["fft_rows"] + tbl["fft_cols"] + tbl["degrid"]
+    tbl["phi_adj"] = tbl["grid"] + tbl["ifft_cols"] + tbl["ifft_rows"]
+    return float(tbl[stage])
+
+
+# launches of each kernel stage per SDMM iteration with cg CG steps
+def launches_per_iter(cg: int) -> dict:
+    a = cg + 1            # A-applications in CG (warm-start residual + cg steps)
+    return {"fft_rows": a + 1, "fft_cols": a + 1, "degrid": a + 1, "grid": a + 1,
+            "ifft_cols": a + 1, "ifft_rows": a + 1, "psi_adj": 1, "psi": 1}
+
+
+KERNEL_NAME = {
+    "fft_rows": "k_fft_rows_fwd", "fft_cols": "k_fft_cols_fwd", "degrid": "k_degrid",
+    "grid": "k_grid", "ifft_cols": "k_fft_cols_adj", "ifft_rows": "k_fft_rows_adj",
+}
+
+
+def stage_table(plan, reps: int = 50) -> dict:
+    out = {}
+    for st in ["fft_rows", "fft_cols", "degrid", "grid", "ifft_cols", "ifft_rows", "phi",
+               "phi_adj", "psi_adj", "psi"]:
+        plan.time_stage(st, 3)
+        ms = plan.time_stage(st, reps)
+        b = stage_bytes(plan, st)
+        out[st] = {"ms": ms, "bytes": b, "GBs": b / (ms * 1e-3) / 1e9,
+                   "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
+def make_gpu_problem(w, torch, purify, synth, precision: str):
+    """Synthetic problem whose noiseless visibilities come from the GPU operator itself."""
+    p = synth.make_inputs(w)
+    plan = purify.Plan(w.n, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels,
+                       precision=precision, device="cuda:0")
+    x = plan.as_vec(p.x_true)
+    y0 = plan.phi(x)
+    torch.cuda.synchronize()
+    synth.add_noise(p, y0.cpu().numpy().astype(np.complex128))
+    return p, plan
+
+
+def cpu_baseline(w, p, sample_iters: int) -> dict:
+    """Oracle timed on this host: NUFFT set-up, 100 power iterations, gamma, and
+    ``sample_iters`` SDMM iterations; extrapolated to the full solve."""
+    from oracle.nufft import Nufft
+    from oracle.sara import Sara
+    from oracle import sdmm as osd
+
+    t0 = time.perf_counter()
+    op = Nufft(w.n, p.uv, w.J)
+    sa = Sara(w.n, w.dict_mask, w.levels)
+    nu, _ = osd.operator_norm(op.normal, (w.n, w.n), 100)
+    t1 = time.perf_counter()
+    osd.sdmm(op.phi, op.phi_adj, sa.psi, sa.psi_adj, p.y, p.epsilon, (w.n, w.n),
+             iters=sample_iters, cg_iters=w.cg_iters, nu=nu)
+    t2 = time.perf_counter()
+    setup = t1 - t0
+    per_iter = (t2 - t1) / sample_iters
+    solve_s = setup + w.iters * per_iter
+    return {"value": w.iters / solve_s, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{w.name}: set-up + 100 power iterations ({setup:.1f} s) and "
+                      f"{sample_iters} SDMM iterations ({per_iter:.2f} s each), "
+                      f"extrapolated to the {w.iters}-iteration solve; "
+                      f"single-threaded NumPy/SciPy FP64 on {platform.processor() or platform.machine()}, "
+                      f"{os.cpu_count()} host cores visible",
+            "seconds": t2 - t0}
+
+
+def precision_form(torch, purify, synth, solve_iters: int) -> dict:
+    w = synth.WORKLOADS["sara1024"]
+    p, plan = make_gpu_problem(w, torch, purify, synth, "fp32")
+    st = stage_table(plan, reps=20)
+    y = plan.as_vec(p.y)
+    plan.sdmm(y, p.epsilon, max_iter=2, nu_iter=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = plan.sdmm(y, p.epsilon, max_iter=solve_iters, nu_iter=100)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {
+        "workload": "sara1024 FP32 (n=1024, M=2097152, SARA 9 bases, L=4, J=6)",
+        "phi_gvis_s": w.M / (st["phi"]["ms"] * 1e-3) / 1e9,
+        "phi_adj_gvis_s": w.M / (st["phi_adj"]["ms"] * 1e-3) / 1e9,
+        "psi_adj_GBs": st["psi_adj"]["GBs"], "psi_GBs": st["psi"]["GBs"],
+        "sdmm_iters_s_incl_setup": solve_iters / dt,
+        "solve_iters": solve_iters, "stages": st,
+        "residual_over_eps": res.residual / p.epsilon,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-extra", action="store_true", help="skip the 1024^2 FP32 workload")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--extra-iters", type=int, default=30)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs every solve on a single "
+              "MI355X (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1406_0359_amd import purify, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = synth.WORKLOADS["sara256"]
+    p, plan0 = make_gpu_problem(w, torch, purify, synth, "fp64")
+    y = plan0.as_vec(p.y)
+
+    def step():
+        plan = purify.Plan(w.n, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels,
+                           precision="fp64", device="cuda:0")
+        return plan, plan.sdmm(y, p.epsilon, max_iter=w.iters, cg_iter=w.cg_iters, nu_iter=100)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan, res = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = args.steps * w.iters / dt
+    snr = synth.snr_db(p.x_true, res.x.cpu().numpy())
+
+    # per-stage timing (HIP events on the plan's stream) and the dominant kernel
+    st = stage_table(plan)
+    per_iter = launches_per_iter(w.cg_iters)
+    share = {k: st[k]["ms"] * per_iter[k] for k in per_iter}
+    dom = max((k for k in share if k in KERNEL_NAME), key=lambda k: share[k])
+    d = st[dom]
+    roofline = {"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["frac"], "traffic": None, "kernel": KERNEL_NAME[dom],
+                "bytes_per_launch": d["bytes"], "ms_per_launch": d["ms"]}
+
+    line = {
+        "metric": "SDMM iters/s", "value": value, "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (40 Gaussian blobs, variable-density Gaussian uv, 30 dB ISNR)",
+        "config": {"workload": "sara256: n=256, M=19661, SARA 9 bases, L=4, J=6, KB beta=2.34J, "
+                               "300 SDMM iters, CG 10, FP64; step = plan + nu + gamma + solve",
+                   "global_batch": 1, "parallelism": "single GPU"},
+        "snr_db": snr, "residual_over_eps": res.residual / p.epsilon,
+        "roofline": roofline,
+    }
+    also = {"sara256_stages": st}
+    if not args.no_extra:
+        try:
+            also["sara1024_fp32"] = precision_form(torch, purify, synth, args.extra_iters)
+        except Exception as e:  # report, do not hide the main line
+            also["sara1024_fp32_error"] = repr(e)
+    line["also"] = also
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, p, args.cpu_iters)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * purify.h -- C ABI of libpurify.so, the MI355X (gfx950) SDMM radio-interferometric imaging
+ * hot path of PURIFY (Carrillo, McEwen & Wiaux, "PURIFY: a new algorithmic framework for
+ * next-generation radio-interferometric imaging").
+ *
+ * Problem (Section 2, eqs. (2)-(3)): recover an n x n image x >= 0 from M visibilities
+ * y = Phi x + noise by   minimise ||W Psi^dagger x||_1  subject to  ||y - Phi x||_2 <= eps,
+ * solved with SDMM (Section 3, eq. (6), Algorithm 1).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Complex vectors are interleaved (re, im) pairs of the plan's precision: double for
+ *   PURIFY_FP64, float for PURIFY_FP32 (layout of std::complex / torch.complex128 /
+ *   torch.complex64).  Images are n x n row-major; axis 0 (rows, index j1) pairs with
+ *   omega_1, axis 1 with omega_2; pixel coordinate p = j - n/2.
+ * - Vectors passed to compute calls are DEVICE pointers owned by the caller.  The library
+ *   never allocates device memory: every plan-owned buffer is carved out of the caller's
+ *   workspace.  Host pointers are marked "host".
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Compute calls
+ *   enqueue on it and return without synchronising, except purify_plan_create and
+ *   purify_sdmm_solve, which return once their work is complete.
+ * - Calls return a purify_status and never throw.  On error, purify_last_error() returns a
+ *   thread-local message.  Calls on one plan must not overlap (they share the plan's
+ *   scratch buffers); different plans are independent.
+ */
+#ifndef PURIFY_H
+#define PURIFY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PURIFY_OK = 0,
+    PURIFY_E_INVALID = 1,    /* bad argument (sizes, null pointers, non-finite uv, ...) */
+    PURIFY_E_WORKSPACE = 2,  /* workspace missing or smaller than purify_plan_workspace_bytes */
+    PURIFY_E_DEVICE = 3,     /* a HIP runtime error; see purify_last_error() */
+    PURIFY_E_NONFINITE = 4   /* SDMM produced a NaN/Inf objective or residual */
+} purify_status;
+
+typedef enum {
+    PURIFY_FP64 = 0,  /* all arithmetic in double */
+    PURIFY_FP32 = 1   /* operators and prox in float; reductions, norms, CG scalars and the
+                         stopping tests in double */
+} purify_precision;
+
+/* Dictionary bits: bit 0 = Dirac basis, bit b (1..8) = Daubechies Db-b wavelet basis
+ * (Section 2.2: SARA = Dirac + Db1..Db8 = 0x1FF; BPDb8 = 1u << 8; BP = 1u). */
+#define PURIFY_DICT_SARA 0x1FFu
+
+typedef struct {
+    int32_t n;           /* image side; power of two, 16 <= n <= 4096, divisible by 2^levels */
+    int32_t oversample;  /* grid oversampling factor; must be 2 (K = 2n) */
+    int32_t J;           /* Kaiser-Bessel taps per axis, 2..16 */
+    double beta;         /* Kaiser-Bessel shape; <= 0 selects 2.34 * J */
+    int64_t M;           /* number of visibilities, 1 <= M < 2^31 */
+    const double* uv;    /* host, M x 2 row-major: (omega_1, omega_2) in radians per pixel.
+                            Any finite value; wrapped into [-pi, pi) (exact: the model is
+                            2 pi periodic in omega).  Read only during plan creation. */
+    uint32_t dict_mask;  /* bases of Psi, see PURIFY_DICT_SARA; nonzero */
+    int32_t levels;      /* wavelet levels, 1..8 */
+    int32_t precision;   /* purify_precision */
+} purify_plan_desc;
+
+typedef struct purify_plan purify_plan;
+
+/* Device workspace a plan needs (bytes), or 0 if the descriptor is invalid.  Host only. */
+size_t purify_plan_workspace_bytes(const purify_plan_desc* desc);
+
+/* Dictionary size D = q * n * n for the descriptor (q = number of bases), or 0 if invalid. */
+int64_t purify_plan_dict_size(const purify_plan_desc* desc);
+
+/* Build a plan (Section 4 measurement operator, continuous visibilities): wraps and bins
+ * the uv points on the host (grid coordinates kappa = omega K / 2 pi in double, split into
+ * an integer first tap and a fractional offset), sorts them by grid tile, computes the
+ * deapodisation, FFT twiddles, Kaiser-Bessel series and Daubechies filters, and uploads
+ * them into `workspace` (device, >= purify_plan_workspace_bytes(desc) bytes, 256-byte
+ * aligned, owned by the caller and kept alive until purify_plan_destroy).  Synchronous on
+ * `stream`.  *out receives a host handle. */
+purify_status purify_plan_create(const purify_plan_desc* desc, void* workspace, size_t bytes,
+                                 void* stream, purify_plan** out);
+
+/* Release the host handle.  The workspace stays owned by the caller. */
+void purify_plan_destroy(purify_plan* plan);
+
+/* y = Phi x = G F Z S x (Section 4; Phi of eq. (2)).  x: device, N = n*n complex.
+ * y: device, M complex in the caller's uv order. */
+purify_status purify_phi(const purify_plan* plan, const void* x, void* y, void* stream);
+
+/* x = Phi^dagger y = S Z^T F^dagger G^T y (the exact adjoint of purify_phi). */
+purify_status purify_phi_adj(const purify_plan* plan, const void* y, void* x, void* stream);
+
+/* x = Psi alpha = (1/sqrt q) sum_b W_b^T alpha_b (Section 2.2).  alpha: device, D complex
+ * laid out as q blocks of n x n in dictionary order [Dirac, Db1, ..., Db8] restricted to
+ * dict_mask, each wavelet block in Mallat layout. */
+purify_status purify_psi(const purify_plan* plan, const void* alpha, void* x, void* stream);
+
+/* alpha = Psi^dagger x = (1/sqrt q) [x; W_1 x; ...] (Section 2.2), layout as purify_psi. */
+purify_status purify_psi_adj(const purify_plan* plan, const void* x, void* alpha, void* stream);
+
+typedef struct {
+    double epsilon;       /* l2 bound of eq. (2) on ||y - Phi x||, unnormalised units */
+    double gamma;         /* SDMM step gamma (Algorithm 1); <= 0: 1e-3 max|Psi^dag Phi~^dag y~| */
+    double nu;            /* ||Phi||_2 used to normalise Phi; <= 0: power iteration */
+    double xi;            /* halting: relative objective variation bound (Section 3) */
+    double slack;         /* halting: accept ||y~ - Phi~ x|| <= eps~ (1 + slack) */
+    int32_t max_iter;     /* T_max (Algorithm 1), >= 1 */
+    int32_t cg_iter;      /* conjugate-gradient steps per global update, >= 1 */
+    int32_t check_every;  /* halting test period in iterations (>= 1) when halting != 0 */
+    int32_t halting;      /* 0: run exactly max_iter iterations; 1: Section 3 stopping rule */
+    int32_t nu_iter;      /* power-iteration count when nu <= 0 (e.g. 100) */
+    int32_t reserved;
+    const double* weights; /* device, D doubles (diagonal W of eq. (3)), or NULL for W = I */
+    double* history;      /* host, 2 * max_iter doubles or NULL: per iteration the objective
+                             ||W Psi^dag x_hat||_1 and the residual ||y~ - Phi~ x_hat|| */
+} purify_sdmm_params;
+
+typedef struct {
+    int32_t iterations;   /* iterations run */
+    int32_t converged;    /* 1 if the stopping rule fired */
+    double objective;     /* last ||W Psi^dagger x_hat||_1 */
+    double residual;      /* last ||y - Phi x_hat||_2 in unnormalised units */
+    double nu;            /* operator norm used */
+    double gamma;         /* gamma used */
+} purify_sdmm_info;
+
+/* SDMM (Algorithm 1) for eq. (3) with R = 1: f1 = ||W .||_1 on Psi^dagger x, f2 = positive
+ * orthant, f3 = l2 ball of radius epsilon about y on Phi x.  The global update solves
+ * (Phi~^dagger Phi~ + 2 I) x = sum_i x_i by cg_iter warm-started conjugate-gradient steps
+ * (Section 3), with Phi~ = Phi / nu.  y: device, M complex in uv order.  x_out: device, N
+ * complex; receives x_hat (the image is its real part).  Uses the plan's solver state, so
+ * one solve per plan at a time.  Returns after the last iteration (synchronous). */
+purify_status purify_sdmm_solve(purify_plan* plan, const void* y, const purify_sdmm_params* params,
+                                void* x_out, purify_sdmm_info* info, void* stream);
+
+/* Kernel stages that purify_time_stage can time (one launch = one application). */
+typedef enum {
+    PURIFY_STAGE_FFT_ROWS = 0,     /* S Z + row transforms of Phi            (n x n -> K x n) */
+    PURIFY_STAGE_FFT_COLS = 1,     /* column transforms of Phi               (K x n -> K x K) */
+    PURIFY_STAGE_DEGRID = 2,       /* G: Kaiser-Bessel interpolation          (K x K -> M)     */
+    PURIFY_STAGE_GRID = 3,         /* G^T: tiled gridding                     (M -> K x K)     */
+    PURIFY_STAGE_IFFT_COLS = 4,    /* column transforms of Phi^dagger         (K x K -> K x n) */
+    PURIFY_STAGE_IFFT_ROWS = 5,    /* row transforms + Z^T S of Phi^dagger    (K x n -> n x n) */
+    PURIFY_STAGE_PHI = 6,          /* whole Phi                                                */
+    PURIFY_STAGE_PHI_ADJ = 7,      /* whole Phi^dagger                                         */
+    PURIFY_STAGE_PSI_ADJ = 8,      /* whole Psi^dagger                                         */
+    PURIFY_STAGE_PSI = 9           /* whole Psi                                                */
+} purify_stage;
+
+/* Time `reps` back-to-back launches of one stage on the plan's internal buffers (their
+ * contents are whatever the last call left; inputs are not validated) with HIP events
+ * recorded on `stream`; *ms_per_launch receives the average.  Synchronous. */
+purify_status purify_time_stage(purify_plan* plan, int32_t stage, int32_t reps, void* stream,
+                                double* ms_per_launch);
+
+/* Host-side introspection (no GPU needed). */
+/* Daubechies Db-b lowpass filter the library uses (extremal phase, sum h = sqrt 2), computed
+ * by its own spectral factorisation.  Writes min(2b, cap) doubles to h (host); returns 2b,
+ * or -1 if b is not in 1..8. */
+int32_t purify_daubechies_filter(int32_t b, double* h, int32_t cap);
+/* Kaiser-Bessel kernel psi(t) (I0(beta sqrt(1-(2t/J)^2)) / I0(beta), 0 outside |t| <= J/2)
+ * as evaluated by the kernels' series, in double, for `count` host values t -> out. */
+int32_t purify_kb_kernel(int32_t J, double beta, int32_t count, const double* t, double* out);
+/* Deapodisation factors s_j = 1 / psi_hat((j - n/2)/K), j < n (host, n doubles). */
+int32_t purify_deapodisation(int32_t n, int32_t K, int32_t J, double beta, double* out);
+
+const char* purify_status_string(purify_status status);
+const char* purify_last_error(void);
+/* Library version string. */
+const char* purify_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PURIFY_H */

@@ -1,0 +1,454 @@
+// C ABI of libpurify (declared in include/purify.h) and the SDMM driver (Algorithm 1).
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace purify {
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename T>
+struct Ops {
+    const Plan& P;
+    hipStream_t s;
+    using C = cpx<T>;
+
+    // y = scale * G F Z S x ; y in user order when perm is given, else in sorted order
+    void phi(const C* x, C* y, double scale, const int32_t* perm) const {
+        launch_fft_rows_fwd<T>(P, x, (C*)P.tmp, s);
+        launch_fft_cols_fwd<T>(P, (const C*)P.tmp, (C*)P.grid, s);
+        launch_degrid<T>(P, (const C*)P.grid, y, perm, scale, s);
+    }
+    // x = c1 * S Z^T F^dag G^T y + c2 * v  (partial Re<v, x> into dot when given)
+    void phi_adj(const C* y, const int32_t* perm, C* x, double c1, const C* v, double c2,
+                 double* dot) const {
+        launch_grid<T>(P, y, perm, (C*)P.grid, s);
+        launch_fft_cols_adj<T>(P, (const C*)P.grid, (C*)P.tmp, s);
+        launch_fft_rows_adj<T>(P, (const C*)P.tmp, x, c1, v, c2, dot, s);
+    }
+    // q = (Phi~^dag Phi~ + 2 I) v, Phi~ = Phi / nu
+    void apply_A(const C* v, C* q, double inv_nu2, double* dot) const {
+        phi(v, (C*)P.vis, 1.0, nullptr);
+        phi_adj((const C*)P.vis, nullptr, q, inv_nu2, v, 2.0, dot);
+    }
+};
+
+double* part_buf(const Plan& P, int k) { return P.part + (size_t)k * MAX_PARTIALS; }
+
+template <typename T>
+purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* prm, void* x_out,
+                        purify_sdmm_info* info, hipStream_t s) {
+    using C = cpx<T>;
+    const Ops<T> op{P, s};
+    const int64_t N = P.N, M = P.M, D = P.D;
+    const C zero = mk<T>(0, 0);
+    double* sc = P.sc;
+    double* part0 = part_buf(P, 0);
+    double* part1 = part_buf(P, 1);
+    const int rows_blocks = fft_rows_adj_blocks<T>(P);
+
+    PURIFY_HIP(hipMemsetAsync(sc, 0, SL_COUNT * sizeof(double), s));
+
+    // Operator norm nu = ||Phi||_2 by power iteration on Phi^dag Phi from the all-ones image.
+    double nu = prm->nu;
+    if (!(nu > 0)) {
+        C* v = (C*)P.p;
+        C* w = (C*)P.qv;
+        launch_fill<T>(v, mk<T>((T)(1.0 / std::sqrt((double)N)), 0), N, s);
+        for (int it = 0; it < prm->nu_iter; ++it) {
+            op.phi(v, (C*)P.vis, 1.0, nullptr);
+            op.phi_adj((const C*)P.vis, nullptr, w, 1.0, nullptr, 0.0, nullptr);
+            const int nb = launch_norm2_part<T>(w, N, part0, s);
+            launch_finalize(part0, nb, sc, SL_LAMBDA, FIN_LAMBDA, 0, nullptr, 0, s);
+            launch_scale_by_slot<T>(v, w, sc, SL_INVLAMBDA, N, s);
+        }
+        double lam = 0;
+        PURIFY_HIP(hipMemcpyAsync(&lam, sc + SL_LAMBDA, sizeof(double), hipMemcpyDeviceToHost, s));
+        PURIFY_HIP(hipStreamSynchronize(s));
+        nu = std::sqrt(lam);
+        if (!(nu > 0) || !std::isfinite(nu)) {
+            set_error("operator norm is zero or not finite");
+            return PURIFY_E_NONFINITE;
+        }
+    }
+    const double inv_nu = 1.0 / nu, inv_nu2 = inv_nu * inv_nu;
+    const double eps_t = prm->epsilon * inv_nu;
+
+    // y~ = y / nu in solver (tile-sorted) order
+    C* yt = (C*)P.ytil;
+    launch_permute_scale<T>((const C*)y_user, P.perm, inv_nu, yt, M, s);
+
+    // gamma = 1e-3 max |Psi^dag Phi~^dag y~| unless given
+    double gamma = prm->gamma;
+    if (!(gamma > 0)) {
+        op.phi_adj(yt, nullptr, (C*)P.p, inv_nu, nullptr, 0.0, nullptr);
+        launch_psi_adj<T>(P, (const C*)P.p, (C*)P.v1, s);
+        const int nb = launch_maxabs_part<T>((const C*)P.v1, D, part0, s);
+        launch_finalize(part0, nb, sc, SL_MAXABS, FIN_MAX, 0, nullptr, 0, s);
+        double mx = 0;
+        PURIFY_HIP(hipMemcpyAsync(&mx, sc + SL_MAXABS, sizeof(double), hipMemcpyDeviceToHost, s));
+        PURIFY_HIP(hipStreamSynchronize(s));
+        gamma = 1e-3 * mx;
+        if (!(gamma > 0)) gamma = 1e-12;
+    }
+
+    // Algorithm 1 initialisation: x_hat = 0, z_i = 0, and x_i = L_i^dag L_i x_hat = 0.
+    C* xh = (C*)P.xh;
+    C *x1 = (C*)P.x1, *x2 = (C*)P.x2, *x3 = (C*)P.x3;
+    C *r = (C*)P.r, *p = (C*)P.p, *q = (C*)P.qv;
+    C *z1 = (C*)P.z1, *v1 = (C*)P.v1, *z2 = (C*)P.z2, *z3 = (C*)P.z3, *v3 = (C*)P.v3;
+    launch_fill<T>(xh, zero, N, s);
+    launch_fill<T>(x1, zero, N, s);
+    launch_fill<T>(x2, zero, N, s);
+    launch_fill<T>(x3, zero, N, s);
+    launch_fill<T>(z1, zero, D, s);
+    launch_fill<T>(z2, zero, N, s);
+    launch_fill<T>(z3, zero, M, s);
+
+    const int T_max = prm->max_iter;
+    const int check = prm->check_every > 0 ? prm->check_every : 1;
+    int it_done = 0;
+    bool converged = false;
+    for (int t = 0; t < T_max; ++t) {
+        const int hi = t % P.hist_cap;
+        // Global update (step 5): CG on (Phi~^dag Phi~ + 2I) x = x1 + x2 + x3, warm start.
+        op.apply_A(xh, q, inv_nu2, nullptr);
+        int nb = launch_cg_init<T>(x1, x2, x3, q, r, p, N, part0, s);
+        launch_finalize(part0, nb, sc, SL_RHO, FIN_STORE, 0, nullptr, 0, s);
+        for (int c = 0; c < prm->cg_iter; ++c) {
+            op.apply_A(p, q, inv_nu2, part1);
+            launch_finalize(part1, rows_blocks, sc, 0, FIN_CG_ALPHA, 0, nullptr, 0, s);
+            nb = launch_cg_xr<T>(xh, r, p, q, sc, N, part0, s);
+            launch_finalize(part0, nb, sc, 0, FIN_CG_BETA, 0, nullptr, 0, s);
+            launch_cg_p<T>(p, r, sc, N, s);
+        }
+        // i = 1: l1 prior on Psi^dag x_hat
+        launch_psi_adj<T>(P, xh, v1, s);
+        nb = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part0, s);
+        launch_finalize(part0, nb, sc, SL_OBJ, FIN_HIST_OBJ, 0, P.hist, hi, s);
+        launch_psi<T>(P, v1, x1, s);
+        // i = 2: positivity
+        launch_prox_pos<T>(xh, z2, x2, N, s);
+        // i = 3: l2 ball about y~ on Phi~ x_hat
+        op.phi(xh, v3, inv_nu, nullptr);
+        nb = launch_ball_part<T>(v3, z3, yt, M, part0, part1, s);
+        launch_finalize(part0, nb, sc, SL_D2, FIN_BALL, eps_t, nullptr, 0, s);
+        launch_finalize(part1, nb, sc, SL_RES2, FIN_HIST_RES, 0, P.hist, hi, s);
+        launch_prox_ball<T>(v3, z3, yt, sc, M, s);
+        op.phi_adj(v3, nullptr, x3, inv_nu, nullptr, 0.0, nullptr);
+        it_done = t + 1;
+
+        if (prm->halting && t >= 1 && ((t + 1) % check == 0 || t + 1 == T_max)) {
+            double h[4];
+            const int hp = (t - 1) % P.hist_cap;
+            PURIFY_HIP(hipMemcpyAsync(h, P.hist + 2 * hp, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            PURIFY_HIP(hipMemcpyAsync(h + 2, P.hist + 2 * hi, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            PURIFY_HIP(hipStreamSynchronize(s));
+            const double f = h[2], fp = h[0], res = h[3];
+            if (!std::isfinite(f) || !std::isfinite(res)) break;
+            if (f > 0 && std::fabs(f - fp) / f < prm->xi && res <= eps_t * (1.0 + prm->slack)) {
+                converged = true;
+                break;
+            }
+        }
+    }
+    PURIFY_HIP(hipMemcpyAsync(x_out, xh, (size_t)N * sizeof(C), hipMemcpyDeviceToDevice, s));
+    double scal[SL_COUNT];
+    PURIFY_HIP(hipMemcpyAsync(scal, sc, sizeof(scal), hipMemcpyDeviceToHost, s));
+    if (prm->history) {
+        const int cnt = it_done < P.hist_cap ? it_done : P.hist_cap;
+        PURIFY_HIP(hipMemcpyAsync(prm->history, P.hist, (size_t)2 * cnt * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+    }
+    PURIFY_HIP(hipStreamSynchronize(s));
+    if (info) {
+        info->iterations = it_done;
+        info->converged = converged ? 1 : 0;
+        info->objective = scal[SL_OBJ];
+        info->residual = std::sqrt(scal[SL_RES2]) * nu;
+        info->nu = nu;
+        info->gamma = gamma;
+    }
+    if (scal[SL_NONFINITE] != 0.0 || !std::isfinite(scal[SL_OBJ]) || !std::isfinite(scal[SL_RES2])) {
+        set_error("non-finite objective or residual in SDMM");
+        return PURIFY_E_NONFINITE;
+    }
+    return PURIFY_OK;
+}
+
+template <typename T>
+void run_stage(const Plan& P, int stage, hipStream_t s) {
+    using C = cpx<T>;
+    const Ops<T> op{P, s};
+    switch (stage) {
+        case PURIFY_STAGE_FFT_ROWS: launch_fft_rows_fwd<T>(P, (const C*)P.xh, (C*)P.tmp, s); break;
+        case PURIFY_STAGE_FFT_COLS: launch_fft_cols_fwd<T>(P, (const C*)P.tmp, (C*)P.grid, s); break;
+        case PURIFY_STAGE_DEGRID: launch_degrid<T>(P, (const C*)P.grid, (C*)P.vis, nullptr, 1.0, s); break;
+        case PURIFY_STAGE_GRID: launch_grid<T>(P, (const C*)P.vis, nullptr, (C*)P.grid, s); break;
+        case PURIFY_STAGE_IFFT_COLS: launch_fft_cols_adj<T>(P, (const C*)P.grid, (C*)P.tmp, s); break;
+        case PURIFY_STAGE_IFFT_ROWS:
+            launch_fft_rows_adj<T>(P, (const C*)P.tmp, (C*)P.qv, 1.0, nullptr, 0.0, nullptr, s);
+            break;
+        case PURIFY_STAGE_PHI: op.phi((const C*)P.xh, (C*)P.vis, 1.0, nullptr); break;
+        case PURIFY_STAGE_PHI_ADJ: op.phi_adj((const C*)P.vis, nullptr, (C*)P.qv, 1.0, nullptr, 0.0, nullptr); break;
+        case PURIFY_STAGE_PSI_ADJ: launch_psi_adj<T>(P, (const C*)P.xh, (C*)P.v1, s); break;
+        case PURIFY_STAGE_PSI: launch_psi<T>(P, (const C*)P.v1, (C*)P.qv, s); break;
+        default: break;
+    }
+}
+
+bool f64(const Plan& P) { return P.precision == PURIFY_FP64; }
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace purify
+
+using namespace purify;
+
+#define CHECK_PLAN(pl)                                   \
+    do {                                                 \
+        if (!(pl)) {                                     \
+            set_error("null plan");                      \
+            return PURIFY_E_INVALID;                     \
+        }                                                \
+    } while (0)
+
+#define CHECK_LAUNCH()                                                           \
+    do {                                                                         \
+        hipError_t _e = hipGetLastError();                                       \
+        if (_e != hipSuccess) {                                                  \
+            set_error(std::string("kernel launch: ") + hipGetErrorString(_e));   \
+            return PURIFY_E_DEVICE;                                              \
+        }                                                                        \
+    } while (0)
+
+extern "C" {
+
+size_t purify_plan_workspace_bytes(const purify_plan_desc* desc) {
+    const DescCheck c = check_desc(desc);
+    if (!c.ok) {
+        set_error(c.why);
+        return 0;
+    }
+    Plan P;
+    return layout(P, desc, nullptr);
+}
+
+int64_t purify_plan_dict_size(const purify_plan_desc* desc) {
+    const DescCheck c = check_desc(desc);
+    if (!c.ok) {
+        set_error(c.why);
+        return 0;
+    }
+    Plan P;
+    layout(P, desc, nullptr);
+    return P.D;
+}
+
+purify_status purify_plan_create(const purify_plan_desc* desc, void* workspace, size_t bytes,
+                                 void* stream, purify_plan** out) {
+    if (!out) {
+        set_error("null output pointer");
+        return PURIFY_E_INVALID;
+    }
+    *out = nullptr;
+    const DescCheck c = check_desc(desc);
+    if (!c.ok) {
+        set_error(c.why);
+        return PURIFY_E_INVALID;
+    }
+    if (!desc->uv) {
+        set_error("null uv");
+        return PURIFY_E_INVALID;
+    }
+    purify_plan* h = new (std::nothrow) purify_plan();
+    if (!h) {
+        set_error("host allocation failed");
+        return PURIFY_E_INVALID;
+    }
+    Plan& P = h->P;
+    const size_t need = layout(P, desc, nullptr);
+    if (!workspace || bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255u)) {
+        set_error("workspace missing, unaligned or smaller than " + std::to_string(need) + " bytes");
+        delete h;
+        return PURIFY_E_WORKSPACE;
+    }
+    layout(P, desc, (char*)workspace);
+    P.ws = (char*)workspace;
+    P.ws_bytes = bytes;
+    const purify_status st = build_plan(P, desc, (hipStream_t)stream);
+    if (st != PURIFY_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return PURIFY_OK;
+}
+
+void purify_plan_destroy(purify_plan* plan) { delete plan; }
+
+purify_status purify_phi(const purify_plan* plan, const void* x, void* y, void* stream) {
+    CHECK_PLAN(plan);
+    if (!x || !y) {
+        set_error("null vector");
+        return PURIFY_E_INVALID;
+    }
+    const Plan& P = plan->P;
+    hipStream_t s = (hipStream_t)stream;
+    if (f64(P)) Ops<double>{P, s}.phi((const cpx<double>*)x, (cpx<double>*)y, 1.0, P.perm);
+    else Ops<float>{P, s}.phi((const cpx<float>*)x, (cpx<float>*)y, 1.0, P.perm);
+    CHECK_LAUNCH();
+    return PURIFY_OK;
+}
+
+purify_status purify_phi_adj(const purify_plan* plan, const void* y, void* x, void* stream) {
+    CHECK_PLAN(plan);
+    if (!x || !y) {
+        set_error("null vector");
+        return PURIFY_E_INVALID;
+    }
+    const Plan& P = plan->P;
+    hipStream_t s = (hipStream_t)stream;
+    if (f64(P)) Ops<double>{P, s}.phi_adj((const cpx<double>*)y, P.perm, (cpx<double>*)x, 1.0, nullptr, 0.0, nullptr);
+    else Ops<float>{P, s}.phi_adj((const cpx<float>*)y, P.perm, (cpx<float>*)x, 1.0, nullptr, 0.0, nullptr);
+    CHECK_LAUNCH();
+    return PURIFY_OK;
+}
+
+purify_status purify_psi(const purify_plan* plan, const void* alpha, void* x, void* stream) {
+    CHECK_PLAN(plan);
+    if (!x || !alpha) {
+        set_error("null vector");
+        return PURIFY_E_INVALID;
+    }
+    const Plan& P = plan->P;
+    hipStream_t s = (hipStream_t)stream;
+    if (f64(P)) launch_psi<double>(P, (const cpx<double>*)alpha, (cpx<double>*)x, s);
+    else launch_psi<float>(P, (const cpx<float>*)alpha, (cpx<float>*)x, s);
+    CHECK_LAUNCH();
+    return PURIFY_OK;
+}
+
+purify_status purify_psi_adj(const purify_plan* plan, const void* x, void* alpha, void* stream) {
+    CHECK_PLAN(plan);
+    if (!x || !alpha) {
+        set_error("null vector");
+        return PURIFY_E_INVALID;
+    }
+    const Plan& P = plan->P;
+    hipStream_t s = (hipStream_t)stream;
+    if (f64(P)) launch_psi_adj<double>(P, (const cpx<double>*)x, (cpx<double>*)alpha, s);
+    else launch_psi_adj<float>(P, (const cpx<float>*)x, (cpx<float>*)alpha, s);
+    CHECK_LAUNCH();
+    return PURIFY_OK;
+}
+
+purify_status purify_sdmm_solve(purify_plan* plan, const void* y, const purify_sdmm_params* params,
+                                void* x_out, purify_sdmm_info* info, void* stream) {
+    CHECK_PLAN(plan);
+    if (!y || !params || !x_out) {
+        set_error("null argument");
+        return PURIFY_E_INVALID;
+    }
+    if (params->max_iter < 1 || params->cg_iter < 1 || !(params->epsilon >= 0) ||
+        (params->nu <= 0 && params->nu_iter < 1)) {
+        set_error("invalid SDMM parameters (max_iter, cg_iter >= 1; epsilon >= 0; nu_iter >= 1 when nu <= 0)");
+        return PURIFY_E_INVALID;
+    }
+    Plan& P = plan->P;
+    hipStream_t s = (hipStream_t)stream;
+    purify_status st = f64(P) ? sdmm_impl<double>(P, y, params, x_out, info, s)
+                              : sdmm_impl<float>(P, y, params, x_out, info, s);
+    if (st == PURIFY_OK) CHECK_LAUNCH();
+    return st;
+}
+
+purify_status purify_time_stage(purify_plan* plan, int32_t stage, int32_t reps, void* stream,
+                                double* ms_per_launch) {
+    CHECK_PLAN(plan);
+    if (stage < 0 || stage > PURIFY_STAGE_PSI || reps < 1 || !ms_per_launch) {
+        set_error("invalid stage or reps");
+        return PURIFY_E_INVALID;
+    }
+    const Plan& P = plan->P;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    PURIFY_HIP(hipEventCreate(&e0));
+    PURIFY_HIP(hipEventCreate(&e1));
+    PURIFY_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) {
+        if (f64(P)) run_stage<double>(P, stage, s);
+        else run_stage<float>(P, stage, s);
+    }
+    PURIFY_HIP(hipEventRecord(e1, s));
+    PURIFY_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    PURIFY_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_launch = (double)ms / reps;
+    CHECK_LAUNCH();
+    return PURIFY_OK;
+}
+
+int32_t purify_daubechies_filter(int32_t b, double* h, int32_t cap) {
+    double tmp[2 * 8];
+    const int F = daubechies(b, tmp);
+    if (F < 0) return -1;
+    for (int i = 0; i < F && i < cap; ++i) h[i] = tmp[i];
+    return F;
+}
+
+int32_t purify_kb_kernel(int32_t J, double beta, int32_t count, const double* t, double* out) {
+    if (J < 2 || J > 16 || count < 0 || (count > 0 && (!t || !out))) return -1;
+    if (!(beta > 0)) beta = 2.34 * J;
+    double c[KB_MAX_TERMS];
+    const int nt = kb_series(beta, 1e-18, c, nullptr);
+    const double a1 = beta * beta / ((double)J * J), hJ = 0.5 * J;
+    for (int i = 0; i < count; ++i) {
+        const double tv = t[i];
+        if (!(std::fabs(tv) <= hJ)) {
+            out[i] = 0.0;
+            continue;
+        }
+        const double w = a1 * ((hJ - tv) * (hJ + tv));
+        double acc = c[nt - 1];
+        for (int k = nt - 2; k >= 0; --k) acc = acc * w + c[k];
+        out[i] = acc;
+    }
+    return count;
+}
+
+int32_t purify_deapodisation(int32_t n, int32_t K, int32_t J, double beta, double* out) {
+    if (n < 1 || K < 1 || J < 2 || J > 16 || !out) return -1;
+    if (!(beta > 0)) beta = 2.34 * J;
+    double c[KB_MAX_TERMS];
+    long double i0b = 0;
+    kb_series(beta, 1e-18, c, &i0b);
+    for (int j = 0; j < n; ++j) out[j] = 1.0 / kb_hat((double)(j - n / 2) / K, J, beta, i0b);
+    return n;
+}
+
+const char* purify_status_string(purify_status status) {
+    switch (status) {
+        case PURIFY_OK: return "ok";
+        case PURIFY_E_INVALID: return "invalid argument";
+        case PURIFY_E_WORKSPACE: return "workspace too small or missing";
+        case PURIFY_E_DEVICE: return "HIP device error";
+        case PURIFY_E_NONFINITE: return "non-finite value in the solver";
+        default: return "unknown status";
+    }
+}
+
+const char* purify_last_error(void) { return g_last_error.c_str(); }
+
+const char* purify_version(void) { return "purify-mi355x 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+// Internal declarations shared by the host runtime and the HIP kernels of libpurify.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/purify.h"
+
+namespace purify {
+
+// ---------------------------------------------------------------------------------------
+// Complex numbers: interleaved (re, im), 8- or 16-byte aligned so loads are single vector
+// instructions.
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T x, y;
+};
+
+template <typename T> __host__ __device__ __forceinline__ cpx<T> mk(T a, T b) { return {a, b}; }
+template <typename T> __host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __host__ __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __host__ __device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __host__ __device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) { return {s * a.x, s * a.y}; }
+template <typename T> __host__ __device__ __forceinline__ cpx<T> conjg(cpx<T> a) { return {a.x, -a.y}; }
+// a * conj(b)
+template <typename T> __host__ __device__ __forceinline__ cpx<T> mulc(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+// multiply by i and by -i
+template <typename T> __host__ __device__ __forceinline__ cpx<T> mul_i(cpx<T> a) { return {-a.y, a.x}; }
+template <typename T> __host__ __device__ __forceinline__ cpx<T> mul_mi(cpx<T> a) { return {a.y, -a.x}; }
+
+// ---------------------------------------------------------------------------------------
+// Kaiser-Bessel kernel as a power series in w = (beta/2)^2 (1 - (2t/J)^2):
+//   psi(t) = I0(2 sqrt w) / I0(beta) = sum_k w^k / (k!)^2 / I0(beta)
+// All terms are positive, so Horner evaluation has no cancellation.  Passed by value in
+// kernel arguments (uniform, scalar registers).
+constexpr int KB_MAX_TERMS = 64;
+template <typename T>
+struct KBSeries {
+    T c[KB_MAX_TERMS];   // c_k = 1 / ((k!)^2 I0(beta))
+    T a1;                // beta^2 / J^2 :  w = a1 (J/2 - t)(J/2 + t)
+    T halfJ;             // J / 2
+    T tap0;              // J/2 - 1: offset of tap 0 is t_0 = f + tap0
+    int nterms;
+};
+
+template <typename T>
+__device__ __forceinline__ T kb_eval(const KBSeries<T>& kb, T t) {
+    T w = kb.a1 * ((kb.halfJ - t) * (kb.halfJ + t));
+    T acc = kb.c[kb.nterms - 1];
+    for (int k = kb.nterms - 2; k >= 0; --k) acc = acc * w + kb.c[k];
+    return acc;
+}
+
+// Daubechies filter bank for the wavelet passes: up to 8 bases, 16 taps each.
+constexpr int MAX_WAV = 8;
+constexpr int MAX_TAPS = 16;
+
+// ---------------------------------------------------------------------------------------
+// Scalar slots (doubles) of the solver, in device memory.
+enum Slot : int {
+    SL_RHO = 0, SL_PQ, SL_ALPHA, SL_BETA, SL_RHONEW,
+    SL_OBJ, SL_RES2, SL_D2, SL_BALL, SL_LAMBDA, SL_INVLAMBDA, SL_MAXABS, SL_NONFINITE,
+    SL_COUNT = 32
+};
+
+constexpr int MAX_PARTIALS = 8192;   // per partial-sum buffer
+constexpr int NUM_PARTIAL_BUFS = 4;
+
+// ---------------------------------------------------------------------------------------
+// Plan: host handle with device pointers into the caller's workspace.
+struct Plan {
+    // descriptor
+    int n = 0, K = 0, J = 0, levels = 0, precision = 0;
+    int64_t M = 0;
+    double beta = 0;
+    uint32_t dict_mask = 0;
+    int q = 0;                 // number of bases
+    bool has_dirac = false;
+    int nwav = 0;              // wavelet bases
+    int wav_N[MAX_WAV] = {};   // Daubechies order of each wavelet basis (dictionary order)
+    int wav_block[MAX_WAV] = {};  // alpha block index of each wavelet basis
+    int TT = 32, nT = 0;       // gridding tile side and tiles per axis
+    int64_t D = 0, N = 0;
+    size_t elem = 0;           // bytes per complex element
+    double kb_i0beta = 0;      // I0(beta)
+    int kb_terms = 0;
+    double kb_c[KB_MAX_TERMS] = {};
+    double filt[MAX_WAV][MAX_TAPS] = {};
+
+    // device buffers (carved from the workspace)
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    int32_t* base = nullptr;     // M: packed first taps (k0_1 | k0_2 << 16), sorted order
+    void* frac = nullptr;        // 2M reals: fractional offsets, sorted order
+    int32_t* perm = nullptr;     // M: sorted position -> caller index
+    int32_t* tileoff = nullptr;  // 4 nT^2 + 1 class offsets
+    void* deap = nullptr;        // n reals
+    void* tw = nullptr;          // n complex: exp(-2 pi i t / n)
+    void* tw2 = nullptr;         // n complex: exp(-pi i t / n)
+    void* filters = nullptr;     // MAX_WAV * 2 * MAX_TAPS reals (h then g)
+    void* grid = nullptr;        // K x K complex, layout [k2][k1]
+    void* tmp = nullptr;         // K x n complex, layout [k2][j1]
+    double* part = nullptr;      // NUM_PARTIAL_BUFS * MAX_PARTIALS
+    double* sc = nullptr;        // SL_COUNT scalars
+    double* hist = nullptr;      // 2 * hist_cap doubles
+    int hist_cap = 0;
+    // solver state
+    void *xh = nullptr, *x1 = nullptr, *x2 = nullptr, *x3 = nullptr;
+    void *r = nullptr, *p = nullptr, *qv = nullptr;
+    void *z2 = nullptr, *ytil = nullptr, *z3 = nullptr, *v3 = nullptr;
+    void *z1 = nullptr, *v1 = nullptr;
+    void *wt = nullptr;          // wavelet temp: nwav * N complex
+    void *ws2 = nullptr;         // wavelet LL temp: nwav * N/4 complex (x2 ping-pong)
+    void *vis = nullptr;         // M complex scratch (visibility-space temp)
+
+    KBSeries<double> kb64{};
+    KBSeries<float> kb32{};
+};
+
+// ---------------------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files, instantiated for float and double).
+template <typename T> void launch_fft_rows_fwd(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s);
+template <typename T> void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s);
+template <typename T> void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s);
+// x = c1 * (S Z^T F^dag rows)(tmp) + c2 * v   (v may be null); optional partial Re<v, x>
+template <typename T> void launch_fft_rows_adj(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1,
+                                               const cpx<T>* v, double c2, double* dot_part,
+                                               hipStream_t s);
+template <typename T> int fft_rows_adj_blocks(const Plan& P);
+
+// G: y[perm ? perm[m] : m] = scale * sum psi psi grid
+template <typename T> void launch_degrid(const Plan& P, const cpx<T>* grid, cpx<T>* y, const int32_t* perm,
+                                         double scale, hipStream_t s);
+// G^T: grid = sum psi psi y[perm ? perm[m] : m]
+template <typename T> void launch_grid(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* grid,
+                                       hipStream_t s);
+
+template <typename T> void launch_psi_adj(const Plan& P, const cpx<T>* x, cpx<T>* alpha, hipStream_t s);
+template <typename T> void launch_psi(const Plan& P, const cpx<T>* alpha, cpx<T>* x, hipStream_t s);
+
+// Vector kernels (vector.hip)
+template <typename T> void launch_fill(cpx<T>* v, cpx<T> val, int64_t n, hipStream_t s);
+// partial sums of |v|^2 (into part), grid-stride; returns number of partials
+template <typename T> int launch_norm2_part(const cpx<T>* v, int64_t n, double* part, hipStream_t s);
+template <typename T> int launch_maxabs_part(const cpx<T>* v, int64_t n, double* part, hipStream_t s);
+// finalize: sum (or max) partials into slot, then apply op
+enum FinalOp : int {
+    FIN_STORE = 0,        // sc[slot] = sum
+    FIN_CG_ALPHA = 1,     // sc[PQ] = sum; sc[ALPHA] = rho == 0 ? 0 : rho / pq
+    FIN_CG_BETA = 2,      // rn = sum; sc[BETA] = rho == 0 ? 0 : rn / rho; sc[RHO] = rn
+    FIN_LAMBDA = 3,       // sc[LAMBDA] = sqrt(sum); sc[INVLAMBDA] = 1/that (0 if 0)
+    FIN_MAX = 4,          // sc[slot] = max
+    FIN_BALL = 5,         // sc[D2] = sum; sc[BALL] = min(1, eps / sqrt(sum)) (1 if 0)
+    FIN_HIST_OBJ = 6,     // sc[OBJ] = sum; hist[2*it] = sum
+    FIN_HIST_RES = 7      // sc[RES2] = sum; hist[2*it+1] = sqrt(sum)
+};
+void launch_finalize(const double* part, int count, double* sc, int slot, int op, double arg,
+                     double* hist, int hist_index, hipStream_t s);
+
+template <typename T> int launch_cg_init(const cpx<T>* x1, const cpx<T>* x2, const cpx<T>* x3,
+                                         const cpx<T>* q, cpx<T>* r, cpx<T>* p, int64_t n,
+                                         double* part, hipStream_t s);
+template <typename T> int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q,
+                                       const double* sc, int64_t n, double* part, hipStream_t s);
+template <typename T> void launch_cg_p(cpx<T>* p, const cpx<T>* r, const double* sc, int64_t n,
+                                       hipStream_t s);
+template <typename T> int launch_prox_l1(cpx<T>* v1, cpx<T>* z1, const double* w, double gamma,
+                                         int64_t n, double* part, hipStream_t s);
+template <typename T> void launch_prox_pos(const cpx<T>* xh, cpx<T>* z2, cpx<T>* x2, int64_t n,
+                                           hipStream_t s);
+template <typename T> int launch_ball_part(const cpx<T>* v3, const cpx<T>* z3, const cpx<T>* yt,
+                                           int64_t n, double* part_d, double* part_res,
+                                           hipStream_t s);
+template <typename T> void launch_prox_ball(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const double* sc,
+                                            int64_t n, hipStream_t s);
+template <typename T> void launch_permute_scale(const cpx<T>* y_user, const int32_t* perm, double scale,
+                                                cpx<T>* y_sorted, int64_t n, hipStream_t s);
+template <typename T> void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc,
+                                                int slot, int64_t n, hipStream_t s);
+
+// error helper
+void set_error(const std::string& msg);
+
+// Host-side plan construction (plan.cpp)
+struct DescCheck {
+    bool ok = false;
+    std::string why;
+};
+DescCheck check_desc(const purify_plan_desc* d);
+size_t layout(Plan& P, const purify_plan_desc* d, char* ws);
+purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s);
+int kb_series(double beta, double tol, double* c, long double* i0b_out);
+double kb_hat(double nu, int J, double beta, long double i0b);
+int daubechies(int N, double* h_out);
+
+}  // namespace purify
+
+#define PURIFY_HIP(expr)                                                                   \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess) {                                                            \
+            ::purify::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));        \
+            return PURIFY_E_DEVICE;                                                        \
+        }                                                                                  \
+    } while (0)
+
+// The plan struct handle type of the C ABI
+struct purify_plan {
+    purify::Plan P;
+};

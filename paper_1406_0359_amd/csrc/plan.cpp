@@ -1,0 +1,367 @@
+// Plan construction for libpurify: host-side set-up of the measurement operator and the
+// dictionary (Section 4 NUFFT; Section 2.2 SARA), and the layout of the caller's workspace.
+//
+// Everything here runs once per plan on the host in long double / double:
+//  * Kaiser-Bessel series coefficients and I0(beta);
+//  * deapodisation s_j = 1 / psi_hat((j - n/2) / K);
+//  * FFT twiddle tables exp(-2 pi i t / n) and exp(-pi i t / n);
+//  * Daubechies Db1..Db8 extremal-phase filters by spectral factorisation (own root finder);
+//  * uv wrapping, grid coordinates kappa = omega K / (2 pi), first taps and fractions, and a
+//    stable counting sort of the visibilities by (grid tile, spill class).
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace purify {
+
+namespace {
+
+constexpr long double PI_L = 3.141592653589793238462643383279502884L;
+constexpr int HIST_CAP = 65536;
+
+long double i0_series(long double x) {
+    // I0(x) = sum_k (x^2/4)^k / (k!)^2, all terms positive
+    const long double w = x * x / 4.0L;
+    long double term = 1.0L, sum = 1.0L;
+    for (int k = 1; k < 400; ++k) {
+        term *= w / ((long double)k * k);
+        sum += term;
+        if (term < sum * 1e-22L) break;
+    }
+    return sum;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// Kaiser-Bessel series: psi(t) = sum_k c_k w^k, w = (beta/2)^2 (1 - (2t/J)^2),
+// c_k = 1 / ((k!)^2 I0(beta)).  The number of terms is chosen so that the first omitted
+// term, at the largest w (t = 0), is below `tol` relative to psi(0) = 1.
+int kb_series(double beta, double tol, double* c, long double* i0b_out) {
+    const long double i0b = i0_series((long double)beta);
+    const long double wmax = (long double)beta * beta / 4.0L;
+    long double fk = 1.0L;   // 1/(k!)^2
+    int k = 0;
+    for (; k < KB_MAX_TERMS; ++k) {
+        if (k > 0) fk /= (long double)k * k;
+        c[k] = (double)(fk / i0b);
+        // bound on the tail at wmax relative to psi(0) = 1
+        long double next = fk / ((long double)(k + 1) * (k + 1)) * powl(wmax, k + 1) / i0b;
+        if (k >= 1 && next < tol) {
+            ++k;
+            break;
+        }
+    }
+    if (i0b_out) *i0b_out = i0b;
+    return k;
+}
+
+double kb_hat(double nu, int J, double beta, long double i0b) {
+    const long double z2 = (long double)beta * beta - powl(PI_L * J * nu, 2);
+    long double v;
+    if (z2 > 0) {
+        const long double z = sqrtl(z2);
+        v = J * sinhl(z) / z;
+    } else if (z2 < 0) {
+        const long double z = sqrtl(-z2);
+        v = J * sinl(z) / z;
+    } else {
+        v = J;
+    }
+    return (double)(v / i0b);
+}
+
+// ---------------------------------------------------------------------------------------
+// Daubechies filters.  |H(w)|^2 = 2 cos^{2N}(w/2) P(sin^2(w/2)) with
+// P(y) = sum_{k<N} C(N-1+k, k) y^k.  Roots of P by the Weierstrass (Durand-Kerner)
+// iteration in long double, polished by Newton; each root y gives the pair z, 1/z of
+// z^2 - (2 - 4y) z + 1 = 0 and the one inside the unit circle is kept (extremal phase).
+// h = coefficients of (z + 1)^N prod (z - z_r), highest power first, scaled to sum sqrt 2.
+int daubechies(int N, double* h_out) {
+    typedef std::complex<long double> C;
+    if (N < 1 || N > 8) return -1;
+    std::vector<long double> pc(N);
+    for (int k = 0; k < N; ++k) {
+        long double b = 1.0L;   // C(N-1+k, k)
+        for (int j = 1; j <= k; ++j) b = b * (N - 1 + j) / j;
+        pc[k] = b;
+    }
+    const int deg = N - 1;
+    std::vector<C> roots;
+    if (deg > 0) {
+        auto peval = [&](C y) {
+            C acc = pc[deg];
+            for (int k = deg - 1; k >= 0; --k) acc = acc * y + pc[k];
+            return acc;
+        };
+        auto dpeval = [&](C y) {
+            C acc = (long double)deg * pc[deg];
+            for (int k = deg - 1; k >= 1; --k) acc = acc * y + (long double)k * pc[k];
+            return acc;
+        };
+        roots.resize(deg);
+        C seed(0.4L, 0.9L), cur(1.0L, 0.0L);
+        for (int i = 0; i < deg; ++i) {
+            cur *= seed;
+            roots[i] = cur;
+        }
+        for (int it = 0; it < 2000; ++it) {
+            long double change = 0;
+            for (int i = 0; i < deg; ++i) {
+                C den = pc[deg];
+                for (int j = 0; j < deg; ++j)
+                    if (j != i) den *= (roots[i] - roots[j]);
+                const C d = peval(roots[i]) / den;
+                roots[i] -= d;
+                change = std::max(change, std::abs(d));
+            }
+            if (change < 1e-30L) break;
+        }
+        for (int i = 0; i < deg; ++i)
+            for (int it = 0; it < 4; ++it) roots[i] -= peval(roots[i]) / dpeval(roots[i]);
+    }
+    std::vector<C> poly(1, C(1.0L, 0.0L));
+    auto mul_lin = [&](C a) {   // poly *= (z - a), highest power first
+        std::vector<C> out(poly.size() + 1, C(0, 0));
+        for (size_t i = 0; i < poly.size(); ++i) {
+            out[i] += poly[i];
+            out[i + 1] -= a * poly[i];
+        }
+        poly.swap(out);
+    };
+    for (int i = 0; i < N; ++i) mul_lin(C(-1.0L, 0.0L));
+    for (const C& y : roots) {
+        const C b = 2.0L - 4.0L * y;
+        const C disc = std::sqrt(b * b - 4.0L);
+        const C z1 = (b + disc) / 2.0L, z2 = (b - disc) / 2.0L;
+        mul_lin(std::abs(z1) < 1.0L ? z1 : z2);
+    }
+    long double sum = 0;
+    for (const C& c : poly) sum += c.real();
+    const long double scale = sqrtl(2.0L) / sum;
+    for (int i = 0; i < 2 * N; ++i) h_out[i] = (double)(poly[i].real() * scale);
+    return 2 * N;
+}
+
+// ---------------------------------------------------------------------------------------
+DescCheck check_desc(const purify_plan_desc* d) {
+    DescCheck c;
+    if (!d) { c.why = "null descriptor"; return c; }
+    if (!is_pow2(d->n) || d->n < 16 || d->n > 4096) { c.why = "n must be a power of two in [16, 4096]"; return c; }
+    if (d->oversample != 2) { c.why = "oversample must be 2"; return c; }
+    if (d->J < 2 || d->J > 16) { c.why = "J must be in [2, 16]"; return c; }
+    if (d->M < 1 || d->M >= (int64_t)1 << 31) { c.why = "M must be in [1, 2^31)"; return c; }
+    if ((d->dict_mask & 0x1FFu) == 0 || (d->dict_mask & ~0x1FFu)) { c.why = "dict_mask must be a nonzero subset of 0x1FF"; return c; }
+    if (d->levels < 1 || d->levels > 8) { c.why = "levels must be in [1, 8]"; return c; }
+    if (d->n % (1 << d->levels) != 0 || (d->n >> d->levels) < 1) { c.why = "n must be divisible by 2^levels"; return c; }
+    if (d->precision != PURIFY_FP64 && d->precision != PURIFY_FP32) { c.why = "unknown precision"; return c; }
+    c.ok = true;
+    return c;
+}
+
+// Fill the descriptor-derived fields and carve the workspace (ws may be null: sizing only).
+size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
+    P.n = d->n;
+    P.K = 2 * d->n;
+    P.J = d->J;
+    P.M = d->M;
+    P.levels = d->levels;
+    P.precision = d->precision;
+    P.beta = d->beta > 0 ? d->beta : 2.34 * d->J;
+    P.dict_mask = d->dict_mask & 0x1FFu;
+    P.has_dirac = (P.dict_mask & 1u) != 0;
+    P.q = 0;
+    P.nwav = 0;
+    for (int b = 0; b < 9; ++b)
+        if (P.dict_mask >> b & 1u) {
+            if (b > 0) {
+                P.wav_N[P.nwav] = b;
+                P.wav_block[P.nwav] = P.q;
+                ++P.nwav;
+            }
+            ++P.q;
+        }
+    P.N = (int64_t)P.n * P.n;
+    P.D = (int64_t)P.q * P.N;
+    P.TT = P.K >= 64 ? 32 : 16;
+    P.nT = P.K / P.TT;
+    const size_t es = P.precision == PURIFY_FP64 ? sizeof(double) : sizeof(float);
+    const size_t ce = 2 * es;
+    P.elem = ce;
+    const size_t M = (size_t)P.M, N = (size_t)P.N, D = (size_t)P.D, K = (size_t)P.K;
+
+    size_t off = 0;
+    auto carve = [&](size_t bytes) -> void* {
+        off = align256(off);
+        void* p = ws ? (void*)(ws + off) : nullptr;
+        off += bytes;
+        return p;
+    };
+    P.base = (int32_t*)carve(M * 4);
+    P.frac = carve(2 * M * es);
+    P.perm = (int32_t*)carve(M * 4);
+    P.tileoff = (int32_t*)carve(((size_t)4 * P.nT * P.nT + 1) * 4);
+    P.deap = carve(P.n * es);
+    P.tw = carve(P.n * ce);
+    P.tw2 = carve(P.n * ce);
+    P.filters = carve((size_t)MAX_WAV * 2 * MAX_TAPS * es);
+    P.grid = carve(K * K * ce);
+    P.tmp = carve(K * P.n * ce);
+    P.part = (double*)carve((size_t)NUM_PARTIAL_BUFS * MAX_PARTIALS * sizeof(double));
+    P.sc = (double*)carve(SL_COUNT * sizeof(double));
+    P.hist_cap = HIST_CAP;
+    P.hist = (double*)carve((size_t)2 * HIST_CAP * sizeof(double));
+    P.xh = carve(N * ce);
+    P.x1 = carve(N * ce);
+    P.x2 = carve(N * ce);
+    P.x3 = carve(N * ce);
+    P.r = carve(N * ce);
+    P.p = carve(N * ce);
+    P.qv = carve(N * ce);
+    P.z2 = carve(N * ce);
+    P.ytil = carve(M * ce);
+    P.z3 = carve(M * ce);
+    P.v3 = carve(M * ce);
+    P.vis = carve(M * ce);
+    P.z1 = carve(D * ce);
+    P.v1 = carve(D * ce);
+    const size_t nw = P.nwav > 0 ? (size_t)P.nwav : 1;
+    P.wt = carve(nw * N * ce);
+    P.ws2 = carve(nw * N * ce);
+    return align256(off);
+}
+
+// ---------------------------------------------------------------------------------------
+// Host-side plan tables and visibility binning; uploads into the workspace.
+purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
+    const int n = P.n, K = P.K, J = P.J, TT = P.TT, nT = P.nT;
+    const int64_t M = P.M;
+    const bool f64 = P.precision == PURIFY_FP64;
+
+    // Kaiser-Bessel series (FP64 tolerance for the FP64 path, ~1e-9 for FP32).
+    long double i0b = 0;
+    P.kb_terms = kb_series(P.beta, f64 ? 1e-18 : 1e-10, P.kb_c, &i0b);
+    P.kb_i0beta = (double)i0b;
+    const double a1 = P.beta * P.beta / ((double)J * J);
+    P.kb64 = KBSeries<double>{};
+    P.kb32 = KBSeries<float>{};
+    for (int k = 0; k < P.kb_terms; ++k) {
+        P.kb64.c[k] = P.kb_c[k];
+        P.kb32.c[k] = (float)P.kb_c[k];
+    }
+    P.kb64.nterms = P.kb32.nterms = P.kb_terms;
+    P.kb64.a1 = a1;
+    P.kb32.a1 = (float)a1;
+    P.kb64.halfJ = 0.5 * J;
+    P.kb32.halfJ = 0.5f * J;
+    P.kb64.tap0 = 0.5 * J - 1.0;
+    P.kb32.tap0 = 0.5f * J - 1.0f;
+
+    // Deapodisation and twiddles.
+    std::vector<double> deap(n);
+    for (int j = 0; j < n; ++j) deap[j] = 1.0 / kb_hat((double)(j - n / 2) / K, J, P.beta, i0b);
+    std::vector<double> tw(2 * n), tw2(2 * n);
+    for (int t = 0; t < n; ++t) {
+        const long double a = 2.0L * PI_L * t / n;
+        tw[2 * t] = (double)cosl(a);
+        tw[2 * t + 1] = (double)-sinl(a);
+        const long double b = PI_L * t / n;
+        tw2[2 * t] = (double)cosl(b);
+        tw2[2 * t + 1] = (double)-sinl(b);
+    }
+    // Filters: [basis][h(16) | g(16)], g[k] = (-1)^k h[F-1-k].
+    std::vector<double> filt((size_t)MAX_WAV * 2 * MAX_TAPS, 0.0);
+    for (int i = 0; i < P.nwav; ++i) {
+        double h[MAX_TAPS] = {};
+        const int F = daubechies(P.wav_N[i], h);
+        for (int k = 0; k < F; ++k) {
+            P.filt[i][k] = h[k];
+            filt[(size_t)i * 2 * MAX_TAPS + k] = h[k];
+            filt[(size_t)i * 2 * MAX_TAPS + MAX_TAPS + k] = ((k & 1) ? -1.0 : 1.0) * h[F - 1 - k];
+        }
+    }
+
+    // Visibility binning.
+    std::vector<int32_t> base(M), key(M);
+    std::vector<double> fr(2 * M);
+    const double twopi = 2.0 * M_PI;
+    const int nkeys = 4 * nT * nT;
+    std::vector<int64_t> cnt(nkeys + 1, 0);
+    static const int rank_of_class[4] = {0, 1, 3, 2};
+    for (int64_t m = 0; m < M; ++m) {
+        int k0m[2];
+        for (int ax = 0; ax < 2; ++ax) {
+            double w = d->uv[2 * m + ax];
+            if (!std::isfinite(w)) {
+                set_error("non-finite uv coordinate");
+                return PURIFY_E_INVALID;
+            }
+            if (w < -M_PI || w >= M_PI) {
+                w = std::fmod(w + M_PI, twopi);
+                if (w < 0) w += twopi;
+                w -= M_PI;
+                if (w >= M_PI) w -= twopi;
+            }
+            const double kap = (w * K) / (2.0 * M_PI);
+            const double k0 = std::floor(kap - 0.5 * J) + 1.0;
+            fr[2 * m + ax] = kap - k0 - (0.5 * J - 1.0);
+            int km = (int)((int64_t)k0 % K);
+            if (km < 0) km += K;
+            k0m[ax] = km;
+        }
+        base[m] = k0m[0] | (k0m[1] << 16);
+        const int t1 = k0m[0] / TT, t2 = k0m[1] / TT;
+        const int s1 = (k0m[0] % TT) + J - 1 >= TT, s2 = (k0m[1] % TT) + J - 1 >= TT;
+        key[m] = (t2 * nT + t1) * 4 + rank_of_class[s1 + 2 * s2];
+        ++cnt[key[m] + 1];
+    }
+    for (int k = 0; k < nkeys; ++k) cnt[k + 1] += cnt[k];
+    std::vector<int32_t> off(nkeys + 1);
+    for (int k = 0; k <= nkeys; ++k) off[k] = (int32_t)cnt[k];
+    std::vector<int32_t> perm(M), sbase(M);
+    std::vector<double> sfr(2 * M);
+    {
+        std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+        for (int64_t m = 0; m < M; ++m) {
+            const int64_t p = pos[key[m]]++;
+            perm[p] = (int32_t)m;
+            sbase[p] = base[m];
+            sfr[2 * p] = fr[2 * m];
+            sfr[2 * p + 1] = fr[2 * m + 1];
+        }
+    }
+
+    // Upload (pageable host memory; synchronous at the end).
+    auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    std::vector<float> f32buf;
+    auto up_real = [&](void* dst, const std::vector<double>& v) -> hipError_t {
+        if (f64) return up(dst, v.data(), v.size() * sizeof(double));
+        f32buf.assign(v.begin(), v.end());
+        hipError_t e = up(dst, f32buf.data(), f32buf.size() * sizeof(float));
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);   // f32buf is reused
+    };
+    PURIFY_HIP(up(P.base, sbase.data(), M * 4));
+    PURIFY_HIP(up(P.perm, perm.data(), M * 4));
+    PURIFY_HIP(up(P.tileoff, off.data(), off.size() * 4));
+    PURIFY_HIP(up_real(P.frac, sfr));
+    PURIFY_HIP(up_real(P.deap, deap));
+    PURIFY_HIP(up_real(P.tw, tw));
+    PURIFY_HIP(up_real(P.tw2, tw2));
+    PURIFY_HIP(up_real(P.filters, filt));
+    PURIFY_HIP(hipMemsetAsync(P.sc, 0, SL_COUNT * sizeof(double), s));
+    PURIFY_HIP(hipStreamSynchronize(s));
+    return PURIFY_OK;
+}
+
+}  // namespace purify

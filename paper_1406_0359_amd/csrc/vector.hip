@@ -1,0 +1,362 @@
+// Vector kernels of SDMM (Algorithm 1): the three proximity steps with their dual updates
+// (eq. (7) applied to the functions of eq. (6)), the conjugate-gradient updates of the
+// global step, and deterministic FP64 reductions.
+//
+// Reductions are two-stage and fixed-order: each workgroup of a grid-stride kernel writes
+// one FP64 partial (wavefront shuffle tree, then waves in order), and a single-workgroup
+// finalize kernel sums the partials in a fixed pattern and derives the solver scalars
+// (CG alpha / beta, the l2-ball scale, ...) on the device.  No float atomics, so the FP64
+// path is bitwise reproducible.
+#include "common.h"
+
+namespace purify {
+
+namespace {
+
+constexpr int RED_BLOCKS = 1024;   // grid size of every reducing vector kernel
+constexpr int VT = 256;
+
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[VT / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < VT / 64; ++i) t += red[i];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ double block_max(double v) {
+    __shared__ double red[VT / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < VT / 64; ++i) t = fmax(t, red[i]);
+    __syncthreads();
+    return t;
+}
+
+int red_blocks(int64_t n) {
+    int64_t b = (n + VT - 1) / VT;
+    return (int)(b < RED_BLOCKS ? (b < 1 ? 1 : b) : RED_BLOCKS);
+}
+unsigned ew_blocks(int64_t n) { return (unsigned)((n + VT - 1) / VT); }
+
+#define GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x; i < (n); i += (int64_t)gridDim.x * VT)
+
+template <typename T>
+__global__ void __launch_bounds__(VT) k_fill(cpx<T>* v, cpx<T> val, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) v[i] = val;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VT) k_norm2(const cpx<T>* __restrict__ v, int64_t n, double* part) {
+    double acc = 0;
+    GRID_STRIDE(i, n) {
+        const cpx<T> a = v[i];
+        acc += (double)a.x * a.x + (double)a.y * a.y;
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VT) k_maxabs(const cpx<T>* __restrict__ v, int64_t n, double* part) {
+    double acc = 0;
+    GRID_STRIDE(i, n) {
+        const cpx<T> a = v[i];
+        acc = fmax(acc, sqrt((double)a.x * a.x + (double)a.y * a.y));
+    }
+    const double t = block_max(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(VT)
+k_finalize(const double* __restrict__ part, int count, double* sc, int slot, int op, double arg,
+           double* hist, int hist_index) {
+    double acc = 0;
+    if (op == FIN_MAX) {
+        for (int i = threadIdx.x; i < count; i += VT) acc = fmax(acc, part[i]);
+        acc = block_max(acc);
+    } else {
+        for (int i = threadIdx.x; i < count; i += VT) acc += part[i];
+        acc = block_sum(acc);
+    }
+    if (threadIdx.x != 0) return;
+    const bool bad = !(acc == acc) || acc == INFINITY;
+    if (bad) sc[SL_NONFINITE] = 1.0;
+    switch (op) {
+        case FIN_STORE:
+        case FIN_MAX: sc[slot] = acc; break;
+        case FIN_CG_ALPHA: {
+            sc[SL_PQ] = acc;
+            const double rho = sc[SL_RHO];
+            sc[SL_ALPHA] = rho == 0.0 ? 0.0 : rho / acc;
+        } break;
+        case FIN_CG_BETA: {
+            const double rho = sc[SL_RHO];
+            sc[SL_BETA] = rho == 0.0 ? 0.0 : acc / rho;
+            sc[SL_RHO] = acc;
+        } break;
+        case FIN_LAMBDA: {
+            const double l = sqrt(acc);
+            sc[SL_LAMBDA] = l;
+            sc[SL_INVLAMBDA] = l > 0.0 ? 1.0 / l : 0.0;
+        } break;
+        case FIN_BALL: {
+            sc[SL_D2] = acc;
+            const double nd = sqrt(acc);
+            sc[SL_BALL] = (nd == 0.0 || arg >= nd) ? 1.0 : arg / nd;
+        } break;
+        case FIN_HIST_OBJ:
+            sc[SL_OBJ] = acc;
+            if (hist) hist[2 * hist_index] = acc;
+            break;
+        case FIN_HIST_RES:
+            sc[SL_RES2] = acc;
+            if (hist) hist[2 * hist_index + 1] = sqrt(acc);
+            break;
+        default: break;
+    }
+}
+
+// r = x1 + x2 + x3 - q ; p = r ; partial <r, r>
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_cg_init(const cpx<T>* __restrict__ x1, const cpx<T>* __restrict__ x2, const cpx<T>* __restrict__ x3,
+          const cpx<T>* __restrict__ q, cpx<T>* __restrict__ r, cpx<T>* __restrict__ p, int64_t n,
+          double* part) {
+    double acc = 0;
+    GRID_STRIDE(i, n) {
+        const cpx<T> v = x1[i] + x2[i] + x3[i] - q[i];
+        r[i] = v;
+        p[i] = v;
+        acc += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// x += alpha p ; r -= alpha q ; partial <r, r>
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_cg_xr(cpx<T>* __restrict__ x, cpx<T>* __restrict__ r, const cpx<T>* __restrict__ p,
+        const cpx<T>* __restrict__ q, const double* __restrict__ sc, int64_t n, double* part) {
+    const T alpha = (T)sc[SL_ALPHA];
+    double acc = 0;
+    GRID_STRIDE(i, n) {
+        x[i] = x[i] + alpha * p[i];
+        const cpx<T> v = r[i] - alpha * q[i];
+        r[i] = v;
+        acc += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// p = r + beta p
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_cg_p(cpx<T>* __restrict__ p, const cpx<T>* __restrict__ r, const double* __restrict__ sc, int64_t n) {
+    const T beta = (T)sc[SL_BETA];
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) p[i] = r[i] + beta * p[i];
+}
+
+// i = 1 of Algorithm 1: u = v1 + z1 ; r1 = soft(u, gamma w) ; z1 = u - r1 ; v1 <- r1 - z1 ;
+// partial sum_j w_j |v1_j| (objective ||W Psi^dag x_hat||_1, before the update).
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_prox_l1(cpx<T>* __restrict__ v1, cpx<T>* __restrict__ z1, const double* __restrict__ w, double gamma,
+          int64_t n, double* part) {
+    double acc = 0;
+    GRID_STRIDE(i, n) {
+        const cpx<T> v = v1[i];
+        const double wi = w ? w[i] : 1.0;
+        acc += wi * sqrt((double)v.x * v.x + (double)v.y * v.y);
+        const cpx<T> u = v + z1[i];
+        const T mag = sqrt(u.x * u.x + u.y * u.y);
+        const T thr = (T)(gamma * wi);
+        const T s = mag > thr ? (T)1 - thr / mag : (T)0;
+        const cpx<T> r1 = s * u;
+        const cpx<T> z = u - r1;
+        z1[i] = z;
+        v1[i] = r1 - z;
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// i = 2: u = x_hat + z2 ; r2 = max(Re u, 0) ; z2 = u - r2 ; x2 = r2 - z2
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_prox_pos(const cpx<T>* __restrict__ xh, cpx<T>* __restrict__ z2, cpx<T>* __restrict__ x2, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i >= n) return;
+    const cpx<T> u = xh[i] + z2[i];
+    const cpx<T> r2 = mk<T>(u.x > 0 ? u.x : (T)0, (T)0);
+    const cpx<T> z = u - r2;
+    z2[i] = z;
+    x2[i] = r2 - z;
+}
+
+// i = 3, pass 1: partial ||v3 + z3 - y~||^2 and ||y~ - v3||^2
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_ball_part(const cpx<T>* __restrict__ v3, const cpx<T>* __restrict__ z3, const cpx<T>* __restrict__ yt,
+            int64_t n, double* part_d, double* part_res) {
+    double ad = 0, ar = 0;
+    GRID_STRIDE(i, n) {
+        const cpx<T> v = v3[i], y = yt[i];
+        const cpx<T> d = v + z3[i] - y;
+        ad += (double)d.x * d.x + (double)d.y * d.y;
+        const double rx = (double)y.x - v.x, ry = (double)y.y - v.y;
+        ar += rx * rx + ry * ry;
+    }
+    const double td = block_sum(ad);
+    const double tr = block_sum(ar);
+    if (threadIdx.x == 0) {
+        part_d[blockIdx.x] = td;
+        part_res[blockIdx.x] = tr;
+    }
+}
+
+// i = 3, pass 2: u = v3 + z3 ; r3 = y~ + (u - y~) s ; z3 = u - r3 ; v3 <- r3 - z3
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_prox_ball(cpx<T>* __restrict__ v3, cpx<T>* __restrict__ z3, const cpx<T>* __restrict__ yt,
+            const double* __restrict__ sc, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i >= n) return;
+    const T s = (T)sc[SL_BALL];
+    const cpx<T> y = yt[i];
+    const cpx<T> u = v3[i] + z3[i];
+    const cpx<T> r3 = y + s * (u - y);
+    const cpx<T> z = u - r3;
+    z3[i] = z;
+    v3[i] = r3 - z;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_permute_scale(const cpx<T>* __restrict__ yu, const int32_t* __restrict__ perm, T scale,
+                cpx<T>* __restrict__ ys, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) ys[i] = scale * yu[perm[i]];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_scale_by_slot(cpx<T>* __restrict__ dst, const cpx<T>* __restrict__ src, const double* __restrict__ sc,
+                int slot, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) dst[i] = (T)sc[slot] * src[i];
+}
+
+}  // namespace
+
+template <typename T>
+void launch_fill(cpx<T>* v, cpx<T> val, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, v, val, n);
+}
+template <typename T>
+int launch_norm2_part(const cpx<T>* v, int64_t n, double* part, hipStream_t s) {
+    const int b = red_blocks(n);
+    hipLaunchKernelGGL(k_norm2<T>, dim3(b), dim3(VT), 0, s, v, n, part);
+    return b;
+}
+template <typename T>
+int launch_maxabs_part(const cpx<T>* v, int64_t n, double* part, hipStream_t s) {
+    const int b = red_blocks(n);
+    hipLaunchKernelGGL(k_maxabs<T>, dim3(b), dim3(VT), 0, s, v, n, part);
+    return b;
+}
+void launch_finalize(const double* part, int count, double* sc, int slot, int op, double arg,
+                     double* hist, int hist_index, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VT), 0, s, part, count, sc, slot, op, arg, hist,
+                       hist_index);
+}
+template <typename T>
+int launch_cg_init(const cpx<T>* x1, const cpx<T>* x2, const cpx<T>* x3, const cpx<T>* q, cpx<T>* r,
+                   cpx<T>* p, int64_t n, double* part, hipStream_t s) {
+    const int b = red_blocks(n);
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(b), dim3(VT), 0, s, x1, x2, x3, q, r, p, n, part);
+    return b;
+}
+template <typename T>
+int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q, const double* sc, int64_t n,
+                 double* part, hipStream_t s) {
+    const int b = red_blocks(n);
+    hipLaunchKernelGGL(k_cg_xr<T>, dim3(b), dim3(VT), 0, s, x, r, p, q, sc, n, part);
+    return b;
+}
+template <typename T>
+void launch_cg_p(cpx<T>* p, const cpx<T>* r, const double* sc, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_p<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, p, r, sc, n);
+}
+template <typename T>
+int launch_prox_l1(cpx<T>* v1, cpx<T>* z1, const double* w, double gamma, int64_t n, double* part,
+                   hipStream_t s) {
+    const int b = red_blocks(n);
+    hipLaunchKernelGGL(k_prox_l1<T>, dim3(b), dim3(VT), 0, s, v1, z1, w, gamma, n, part);
+    return b;
+}
+template <typename T>
+void launch_prox_pos(const cpx<T>* xh, cpx<T>* z2, cpx<T>* x2, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_prox_pos<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, xh, z2, x2, n);
+}
+template <typename T>
+int launch_ball_part(const cpx<T>* v3, const cpx<T>* z3, const cpx<T>* yt, int64_t n, double* part_d,
+                     double* part_res, hipStream_t s) {
+    const int b = red_blocks(n);
+    hipLaunchKernelGGL(k_ball_part<T>, dim3(b), dim3(VT), 0, s, v3, z3, yt, n, part_d, part_res);
+    return b;
+}
+template <typename T>
+void launch_prox_ball(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const double* sc, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_prox_ball<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, v3, z3, yt, sc, n);
+}
+template <typename T>
+void launch_permute_scale(const cpx<T>* y_user, const int32_t* perm, double scale, cpx<T>* y_sorted,
+                          int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_permute_scale<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, y_user, perm, (T)scale,
+                       y_sorted, n);
+}
+template <typename T>
+void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc, int slot, int64_t n,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_by_slot<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, dst, src, sc, slot, n);
+}
+
+#define PURIFY_INST_VEC(T)                                                                              \
+    template void launch_fill<T>(cpx<T>*, cpx<T>, int64_t, hipStream_t);                                \
+    template int launch_norm2_part<T>(const cpx<T>*, int64_t, double*, hipStream_t);                     \
+    template int launch_maxabs_part<T>(const cpx<T>*, int64_t, double*, hipStream_t);                    \
+    template int launch_cg_init<T>(const cpx<T>*, const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*,  \
+                                   cpx<T>*, int64_t, double*, hipStream_t);                              \
+    template int launch_cg_xr<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const cpx<T>*, const double*, int64_t, \
+                                 double*, hipStream_t);                                                  \
+    template void launch_cg_p<T>(cpx<T>*, const cpx<T>*, const double*, int64_t, hipStream_t);          \
+    template int launch_prox_l1<T>(cpx<T>*, cpx<T>*, const double*, double, int64_t, double*, hipStream_t); \
+    template void launch_prox_pos<T>(const cpx<T>*, cpx<T>*, cpx<T>*, int64_t, hipStream_t);            \
+    template int launch_ball_part<T>(const cpx<T>*, const cpx<T>*, const cpx<T>*, int64_t, double*,      \
+                                     double*, hipStream_t);                                              \
+    template void launch_prox_ball<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const double*, int64_t, hipStream_t); \
+    template void launch_permute_scale<T>(const cpx<T>*, const int32_t*, double, cpx<T>*, int64_t,       \
+                                          hipStream_t);                                                  \
+    template void launch_scale_by_slot<T>(cpx<T>*, const cpx<T>*, const double*, int, int64_t, hipStream_t);
+
+PURIFY_INST_VEC(float)
+PURIFY_INST_VEC(double)
+
+}  // namespace purify

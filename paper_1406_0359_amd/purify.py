@@ -1,0 +1,293 @@
+"""ctypes binding over libpurify.so (the C ABI declared in include/purify.h).
+
+This module only marshals arguments: every step of Phi, Phi^dagger, Psi, Psi^dagger and
+SDMM runs in the library's HIP kernels.  PyTorch supplies device memory (the plan workspace
+and the vectors) and the current HIP stream.  If the library is missing the first call
+raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libpurify.so")
+
+FP64, FP32 = 0, 1
+DICT_SARA = 0x1FF
+
+STAGES = {
+    "fft_rows": 0, "fft_cols": 1, "degrid": 2, "grid": 3, "ifft_cols": 4, "ifft_rows": 5,
+    "phi": 6, "phi_adj": 7, "psi_adj": 8, "psi": 9,
+}
+
+_STATUS = {0: "ok", 1: "invalid argument", 2: "workspace", 3: "device error", 4: "non-finite"}
+
+
+class PurifyError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_STATUS.get(status, status)} ({last_error()})")
+        self.status = status
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("oversample", ctypes.c_int32), ("J", ctypes.c_int32),
+        ("beta", ctypes.c_double), ("M", ctypes.c_int64), ("uv", ctypes.POINTER(ctypes.c_double)),
+        ("dict_mask", ctypes.c_uint32), ("levels", ctypes.c_int32), ("precision", ctypes.c_int32),
+    ]
+
+
+class SdmmParams(ctypes.Structure):
+    _fields_ = [
+        ("epsilon", ctypes.c_double), ("gamma", ctypes.c_double), ("nu", ctypes.c_double),
+        ("xi", ctypes.c_double), ("slack", ctypes.c_double),
+        ("max_iter", ctypes.c_int32), ("cg_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
+        ("halting", ctypes.c_int32), ("nu_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("weights", ctypes.c_void_p), ("history", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class SdmmInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+        ("objective", ctypes.c_double), ("residual", ctypes.c_double),
+        ("nu", ctypes.c_double), ("gamma", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libpurify.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"libpurify.so not found at {path}; run paper_1406_0359_amd.build")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pdesc = ctypes.POINTER(PlanDesc)
+    sig = {
+        "purify_plan_workspace_bytes": (ctypes.c_size_t, [pdesc]),
+        "purify_plan_dict_size": (i64, [pdesc]),
+        "purify_plan_create": (i32, [pdesc, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+        "purify_plan_destroy": (None, [vp]),
+        "purify_phi": (i32, [vp, vp, vp, vp]),
+        "purify_phi_adj": (i32, [vp, vp, vp, vp]),
+        "purify_psi": (i32, [vp, vp, vp, vp]),
+        "purify_psi_adj": (i32, [vp, vp, vp, vp]),
+        "purify_sdmm_solve": (i32, [vp, vp, ctypes.POINTER(SdmmParams), vp,
+                                    ctypes.POINTER(SdmmInfo), vp]),
+        "purify_time_stage": (i32, [vp, i32, i32, vp, ctypes.POINTER(dbl)]),
+        "purify_daubechies_filter": (i32, [i32, ctypes.POINTER(dbl), i32]),
+        "purify_kb_kernel": (i32, [i32, dbl, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
+        "purify_deapodisation": (i32, [i32, i32, i32, dbl, ctypes.POINTER(dbl)]),
+        "purify_status_string": (ctypes.c_char_p, [i32]),
+        "purify_last_error": (ctypes.c_char_p, []),
+        "purify_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    if _lib is None:
+        return ""
+    return _lib.purify_last_error().decode()
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise PurifyError(status, what)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# --- host-only queries -------------------------------------------------------------------
+def daubechies_filter(b: int) -> np.ndarray:
+    lib = load_library()
+    h = np.zeros(16)
+    F = lib.purify_daubechies_filter(b, _dptr(h), 16)
+    if F < 0:
+        raise ValueError("b must be in 1..8")
+    return h[:F].copy()
+
+
+def kb_kernel(J: int, t, beta: float = 0.0) -> np.ndarray:
+    lib = load_library()
+    t = np.ascontiguousarray(t, dtype=np.float64).ravel()
+    out = np.zeros_like(t)
+    if lib.purify_kb_kernel(J, beta, t.size, _dptr(t), _dptr(out)) < 0:
+        raise ValueError("bad kb arguments")
+    return out
+
+
+def deapodisation(n: int, K: int, J: int, beta: float = 0.0) -> np.ndarray:
+    lib = load_library()
+    out = np.zeros(n)
+    if lib.purify_deapodisation(n, K, J, beta, _dptr(out)) < 0:
+        raise ValueError("bad deapodisation arguments")
+    return out
+
+
+def _desc(n, uv, J, beta, dict_mask, levels, precision):
+    d = PlanDesc()
+    d.n, d.oversample, d.J, d.beta = n, 2, J, beta
+    d.M = uv.shape[0]
+    d.uv = _dptr(uv)
+    d.dict_mask, d.levels, d.precision = dict_mask, levels, precision
+    return d
+
+
+def workspace_bytes(n: int, M: int, J: int = 6, dict_mask: int = DICT_SARA, levels: int = 4,
+                    precision: int = FP64) -> int:
+    lib = load_library()
+    uv = np.zeros((1, 2))
+    d = _desc(n, uv, J, 0.0, dict_mask, levels, precision)
+    d.M = M
+    return int(lib.purify_plan_workspace_bytes(ctypes.byref(d)))
+
+
+@dataclass
+class SolveResult:
+    x: "object"                  # torch complex tensor (n, n); the image is x.real
+    iterations: int
+    converged: bool
+    objective: float
+    residual: float
+    nu: float
+    gamma: float
+    history: Optional[np.ndarray]
+
+
+class Plan:
+    """A measurement operator / dictionary / solver plan on one GPU.
+
+    ``uv`` is an (M, 2) float64 host array of frequencies in radians per pixel.  The plan's
+    workspace is a torch uint8 tensor on ``device``; vectors are torch complex tensors of
+    the plan's precision (complex128 for fp64, complex64 for fp32) on the same device.
+    """
+
+    def __init__(self, n: int, uv, J: int = 6, beta: float = 0.0, dict_mask: int = DICT_SARA,
+                 levels: int = 4, precision: str = "fp64", device="cuda:0"):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.n, self.J, self.levels, self.dict_mask = n, J, levels, dict_mask
+        self.precision = FP64 if precision in ("fp64", FP64) else FP32
+        self.cdtype = torch.complex128 if self.precision == FP64 else torch.complex64
+        self.uv = np.ascontiguousarray(uv, dtype=np.float64).reshape(-1, 2)
+        self.M = self.uv.shape[0]
+        d = _desc(n, self.uv, J, beta, dict_mask, levels, self.precision)
+        self.ws_bytes = int(self.lib.purify_plan_workspace_bytes(ctypes.byref(d)))
+        if self.ws_bytes == 0:
+            raise PurifyError(1, "purify_plan_workspace_bytes")
+        self.D = int(self.lib.purify_plan_dict_size(ctypes.byref(d)))
+        self.q = self.D // (n * n)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.purify_plan_create(ctypes.byref(d), self.workspace.data_ptr(),
+                                               self.ws_bytes, self._stream(), ctypes.byref(h)),
+                   "purify_plan_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.purify_plan_destroy(h)
+            self.handle = None
+
+    # --- helpers ------------------------------------------------------------------------
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def _vec(self, t, count: int, name: str):
+        if not isinstance(t, self.torch.Tensor) or t.device != self.device:
+            raise ValueError(f"{name} must be a torch tensor on {self.device}")
+        if t.dtype != self.cdtype or not t.is_contiguous() or t.numel() != count:
+            raise ValueError(f"{name} must be contiguous {self.cdtype} with {count} elements")
+        return t.data_ptr()
+
+    def empty(self, *shape):
+        return self.torch.empty(*shape, dtype=self.cdtype, device=self.device)
+
+    def as_vec(self, a):
+        """Copy host data (numpy / torch) to a contiguous device vector of the plan's type."""
+        t = self.torch.as_tensor(np.asarray(a)) if not isinstance(a, self.torch.Tensor) else a
+        return t.to(device=self.device, dtype=self.cdtype).contiguous()
+
+    # --- operators ----------------------------------------------------------------------
+    def phi(self, x, out=None):
+        """y = Phi x (x: n x n, y: M in uv order)."""
+        y = self.empty(self.M) if out is None else out
+        _check(self.lib.purify_phi(self.handle, self._vec(x, self.n * self.n, "x"),
+                                   self._vec(y, self.M, "y"), self._stream()), "purify_phi")
+        return y
+
+    def phi_adj(self, y, out=None):
+        x = self.empty(self.n, self.n) if out is None else out
+        _check(self.lib.purify_phi_adj(self.handle, self._vec(y, self.M, "y"),
+                                       self._vec(x, self.n * self.n, "x"), self._stream()),
+               "purify_phi_adj")
+        return x
+
+    def psi(self, alpha, out=None):
+        x = self.empty(self.n, self.n) if out is None else out
+        _check(self.lib.purify_psi(self.handle, self._vec(alpha, self.D, "alpha"),
+                                   self._vec(x, self.n * self.n, "x"), self._stream()),
+               "purify_psi")
+        return x
+
+    def psi_adj(self, x, out=None):
+        a = self.empty(self.q, self.n, self.n) if out is None else out
+        _check(self.lib.purify_psi_adj(self.handle, self._vec(x, self.n * self.n, "x"),
+                                       self._vec(a, self.D, "alpha"), self._stream()),
+               "purify_psi_adj")
+        return a
+
+    def sdmm(self, y, epsilon: float, max_iter: int = 300, cg_iter: int = 10,
+             gamma: float = 0.0, nu: float = 0.0, nu_iter: int = 100, halting: bool = False,
+             xi: float = 1e-4, slack: float = 1e-3, check_every: int = 10, weights=None,
+             record_history: bool = False, out=None) -> SolveResult:
+        """SDMM (Algorithm 1) for eq. (3) with R = 1; returns x_hat and solver info."""
+        x = self.empty(self.n, self.n) if out is None else out
+        p = SdmmParams()
+        p.epsilon, p.gamma, p.nu, p.xi, p.slack = epsilon, gamma, nu, xi, slack
+        p.max_iter, p.cg_iter, p.check_every = max_iter, cg_iter, check_every
+        p.halting, p.nu_iter, p.reserved = int(bool(halting)), nu_iter, 0
+        if weights is not None:
+            if (weights.dtype != self.torch.float64 or weights.numel() != self.D
+                    or weights.device != self.device or not weights.is_contiguous()):
+                raise ValueError("weights must be a contiguous float64 device tensor of size D")
+            p.weights = weights.data_ptr()
+        hist = np.zeros(2 * max_iter) if record_history else None
+        p.history = _dptr(hist) if hist is not None else None
+        info = SdmmInfo()
+        _check(self.lib.purify_sdmm_solve(self.handle, self._vec(y, self.M, "y"), ctypes.byref(p),
+                                          self._vec(x, self.n * self.n, "x"), ctypes.byref(info),
+                                          self._stream()), "purify_sdmm_solve")
+        if hist is not None:
+            hist = hist[: 2 * info.iterations].reshape(-1, 2)
+        return SolveResult(x, info.iterations, bool(info.converged), info.objective,
+                           info.residual, info.nu, info.gamma, hist)
+
+    def time_stage(self, stage: str, reps: int = 20) -> float:
+        """Average milliseconds per launch of one stage (HIP events on the current stream)."""
+        ms = ctypes.c_double()
+        _check(self.lib.purify_time_stage(self.handle, STAGES[stage], reps, self._stream(),
+                                          ctypes.byref(ms)), "purify_time_stage")
+        return ms.value

@@ -1,0 +1,118 @@
+"""GPU parity of Phi, Phi^dagger, Psi, Psi^dagger against the FP64 oracle, through the C ABI.
+
+Tolerances: FP64 path, relative l2 <= 1e-12 and element-wise max error <= 1e-11 of the
+largest reference value (operators are sums of at most ~K^2 well-conditioned terms);
+FP32 path, relative l2 <= 1e-5 per operator (the precision-form target).  Sizes span several
+grid tiles and FFT sizes with ragged visibility counts (not multiples of 256 or of a tile's
+load), several kernel widths (J = 4, 5, 6, 8; 5 takes the generic-J kernels) and dictionaries.
+"""
+import numpy as np
+import pytest
+
+from gpu_cases import DEV, max_rel, rand_complex, rel_l2, to_np, uv_case
+from oracle.nufft import Nufft
+from oracle.sara import Sara
+
+torch = pytest.importorskip("torch")
+from paper_1406_0359_amd import purify  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+PHI_CASES = [  # n, M, J, uniform_frac
+    (16, 1, 6, 0.0),
+    (16, 333, 6, 0.0),
+    (32, 1000, 4, 0.5),
+    (64, 2048, 6, 0.0),
+    (64, 2049, 8, 0.2),
+    (64, 777, 5, 1.0),
+    (128, 5001, 6, 0.1),
+    (256, 19661, 6, 0.0),
+    (512, 40000, 8, 0.1),
+]
+
+
+@pytest.mark.parametrize("n,M,J,uf", PHI_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_phi_and_adjoint_match_oracle(n, M, J, uf, prec):
+    uv = uv_case(M, n, 1000 + n + M, uf)
+    op = Nufft(n, uv, J)
+    plan = purify.Plan(n, uv, J=J, dict_mask=1, levels=1, precision=prec, device=DEV)
+    x = rand_complex((n, n), 1)
+    y = rand_complex(M, 2)
+    ref_y = op.phi(x)
+    ref_x = op.phi_adj(y)
+    got_y = to_np(plan.phi(plan.as_vec(x)))
+    got_x = to_np(plan.phi_adj(plan.as_vec(y)))
+    if prec == "fp64":
+        assert rel_l2(got_y, ref_y) < 1e-12 and max_rel(got_y, ref_y) < 1e-11
+        assert rel_l2(got_x, ref_x) < 1e-12 and max_rel(got_x, ref_x) < 1e-11
+    else:
+        assert rel_l2(got_y, ref_y) < 1e-5
+        assert rel_l2(got_x, ref_x) < 1e-5
+
+
+def test_phi_rejects_wrong_dtype_and_size():
+    uv = uv_case(100, 32, 5)
+    plan = purify.Plan(32, uv, dict_mask=1, levels=1, device=DEV)
+    with pytest.raises(ValueError):
+        plan.phi(torch.zeros(32, 32, dtype=torch.complex64, device=DEV))
+    with pytest.raises(ValueError):
+        plan.phi(torch.zeros(31, 32, dtype=torch.complex128, device=DEV))
+
+
+def test_gpu_adjoint_identity_fp64():
+    n, M = 128, 3000
+    uv = uv_case(M, n, 9)
+    plan = purify.Plan(n, uv, dict_mask=1, levels=1, device=DEV)
+    x = plan.as_vec(rand_complex((n, n), 3))
+    y = plan.as_vec(rand_complex(M, 4))
+    lhs = torch.vdot(plan.phi(x), y).item()
+    rhs = torch.vdot(x.reshape(-1), plan.phi_adj(y).reshape(-1)).item()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_uv_outside_principal_range_is_wrapped():
+    n, M = 32, 200
+    uv = uv_case(M, n, 11)
+    shifted = uv + 2 * np.pi * np.random.default_rng(0).integers(-3, 4, size=uv.shape)
+    a = purify.Plan(n, uv, dict_mask=1, levels=1, device=DEV)
+    b = purify.Plan(n, shifted, dict_mask=1, levels=1, device=DEV)
+    x = a.as_vec(rand_complex((n, n), 5))
+    assert rel_l2(to_np(b.phi(x)), to_np(a.phi(x))) < 1e-12
+
+
+PSI_CASES = [  # n, mask, levels
+    (16, 0x1FF, 2),
+    (16, 1 << 8, 3),     # Db8 (16 taps) wrapping a length-2 coarse axis
+    (64, 1 << 8, 4),
+    (64, 0x1FF, 4),
+    (64, 0x006, 1),
+    (128, 0x101, 5),
+    (256, 0x1FF, 4),
+]
+
+
+@pytest.mark.parametrize("n,mask,L", PSI_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_psi_and_adjoint_match_oracle(n, mask, L, prec):
+    uv = uv_case(10, n, 3)
+    sa = Sara(n, mask, L)
+    plan = purify.Plan(n, uv, dict_mask=mask, levels=L, precision=prec, device=DEV)
+    x = rand_complex((n, n), 7)
+    a = rand_complex((sa.q, n, n), 8)
+    ref_a = sa.psi_adj(x)
+    ref_x = sa.psi(a)
+    got_a = to_np(plan.psi_adj(plan.as_vec(x)))
+    got_x = to_np(plan.psi(plan.as_vec(a)))
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert rel_l2(got_a, ref_a) < tol
+    assert rel_l2(got_x, ref_x) < tol
+    if prec == "fp64":
+        assert max_rel(got_a, ref_a) < 1e-11 and max_rel(got_x, ref_x) < 1e-11
+
+
+def test_gpu_tight_frame():
+    n = 256
+    plan = purify.Plan(n, uv_case(10, n, 1), dict_mask=0x1FF, levels=4, device=DEV)
+    x = plan.as_vec(rand_complex((n, n), 12))
+    assert rel_l2(to_np(plan.psi(plan.psi_adj(x))), to_np(x)) < 1e-13
