@@ -76,7 +76,7 @@ int64_t purify_plan_dict_size(const purify_plan_desc* desc);
 /* Build a plan (Section 4 measurement operator, continuous visibilities): wraps and bins
  * the uv points on the host (grid coordinates kappa = omega K / 2 pi in double, split into
  * an integer first tap and a fractional offset), sorts them by grid tile, computes the
- * deapodisation, FFT twiddles, Kaiser-Bessel series and Daubechies filters, and uploads
+ * deapodisation, FFT twiddles, Kaiser-Bessel per-tap polynomials and Daubechies filters, and uploads
  * them into `workspace` (device, >= purify_plan_workspace_bytes(desc) bytes, 256-byte
  * aligned, owned by the caller and kept alive until purify_plan_destroy).  Synchronous on
  * `stream`.  *out receives a host handle. */
@@ -101,6 +101,10 @@ purify_status purify_psi(const purify_plan* plan, const void* alpha, void* x, vo
 /* alpha = Psi^dagger x = (1/sqrt q) [x; W_1 x; ...] (Section 2.2), layout as purify_psi. */
 purify_status purify_psi_adj(const purify_plan* plan, const void* x, void* alpha, void* stream);
 
+/* purify_sdmm_params.flags: enqueue every kernel eagerly instead of replaying one captured
+ * HIP graph per SDMM iteration (same kernels, same results; for debugging and tests). */
+#define PURIFY_SDMM_NO_GRAPH 1
+
 typedef struct {
     double epsilon;       /* l2 bound of eq. (2) on ||y - Phi x||, unnormalised units */
     double gamma;         /* SDMM step gamma (Algorithm 1); <= 0: 1e-3 max|Psi^dag Phi~^dag y~| */
@@ -112,7 +116,7 @@ typedef struct {
     int32_t check_every;  /* halting test period in iterations (>= 1) when halting != 0 */
     int32_t halting;      /* 0: run exactly max_iter iterations; 1: Section 3 stopping rule */
     int32_t nu_iter;      /* power-iteration count when nu <= 0 (e.g. 100) */
-    int32_t reserved;
+    int32_t flags;        /* PURIFY_SDMM_* bits; 0 = defaults */
     const double* weights; /* device, D doubles (diagonal W of eq. (3)), or NULL for W = I */
     double* history;      /* host, 2 * max_iter doubles or NULL: per iteration the objective
                              ||W Psi^dag x_hat||_1 and the residual ||y~ - Phi~ x_hat|| */
@@ -132,7 +136,10 @@ typedef struct {
  * (Phi~^dagger Phi~ + 2 I) x = sum_i x_i by cg_iter warm-started conjugate-gradient steps
  * (Section 3), with Phi~ = Phi / nu.  y: device, M complex in uv order.  x_out: device, N
  * complex; receives x_hat (the image is its real part).  Uses the plan's solver state, so
- * one solve per plan at a time.  Returns after the last iteration (synchronous). */
+ * one solve per plan at a time.  Internally the solve runs on two library-created streams
+ * ordered after `stream`'s prior work (branch i = 1 of Algorithm 1 overlaps branches 2-3),
+ * replaying one captured HIP graph per iteration.  Returns after the last iteration
+ * (synchronous). */
 purify_status purify_sdmm_solve(purify_plan* plan, const void* y, const purify_sdmm_params* params,
                                 void* x_out, purify_sdmm_info* info, void* stream);
 

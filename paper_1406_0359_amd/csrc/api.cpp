@@ -40,132 +40,209 @@ struct Ops {
 
 double* part_buf(const Plan& P, int k) { return P.part + (size_t)k * MAX_PARTIALS; }
 
+// RAII holder for the solver's internal streams, events and graphs.
+struct SolveResources {
+    hipStream_t cs = nullptr, cs2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, done = nullptr;
+    hipGraph_t g_iter = nullptr, g_pow = nullptr;
+    hipGraphExec_t x_iter = nullptr, x_pow = nullptr;
+    ~SolveResources() {
+        if (x_iter) (void)hipGraphExecDestroy(x_iter);
+        if (x_pow) (void)hipGraphExecDestroy(x_pow);
+        if (g_iter) (void)hipGraphDestroy(g_iter);
+        if (g_pow) (void)hipGraphDestroy(g_pow);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (done) (void)hipEventDestroy(done);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (cs2) (void)hipStreamDestroy(cs2);
+    }
+};
+
+template <typename T>
+struct Sdmm {
+    using C = cpx<T>;
+    Plan& P;
+    const purify_sdmm_params* prm;
+    double inv_nu = 1, inv_nu2 = 1, eps_t = 0, gamma = 0;
+
+    double* part(int k) const { return part_buf(P, k); }
+
+    // One power-iteration step: v <- Phi^dag Phi v / ||Phi^dag Phi v||, lambda in sc.
+    void enqueue_power_step(hipStream_t s) const {
+        const Ops<T> op{P, s};
+        C* v = (C*)P.p;
+        C* w = (C*)P.qv;
+        op.phi(v, (C*)P.vis, 1.0, nullptr);
+        op.phi_adj((const C*)P.vis, nullptr, w, 1.0, nullptr, 0.0, nullptr);
+        const int nb = launch_norm2_part<T>(w, P.N, part(0), s);
+        launch_finalize(part(0), nb, P.sc, SL_LAMBDA, FIN_LAMBDA, 0, nullptr, 0, s);
+        launch_scale_by_slot<T>(v, w, P.sc, SL_INVLAMBDA, P.N, s);
+    }
+
+    // One SDMM iteration (Algorithm 1, steps 5-9).  Branch i = 1 runs on s2 between the
+    // fork and join events; CG and branches i = 2, 3 run on s.
+    void enqueue_iteration(hipStream_t s, hipStream_t s2, hipEvent_t fork, hipEvent_t join) const {
+        const Ops<T> op{P, s};
+        const int64_t N = P.N, M = P.M, D = P.D;
+        double* sc = P.sc;
+        C* xh = (C*)P.xh;
+        C *x1 = (C*)P.x1, *x2 = (C*)P.x2, *x3 = (C*)P.x3;
+        C *r = (C*)P.r, *p = (C*)P.p, *q = (C*)P.qv;
+        C *z1 = (C*)P.z1, *v1 = (C*)P.v1, *z2 = (C*)P.z2, *z3 = (C*)P.z3, *v3 = (C*)P.v3;
+        const C* yt = (const C*)P.ytil;
+        const int rows_blocks = fft_rows_adj_blocks<T>(P);
+        // Global update (step 5): CG on (Phi~^dag Phi~ + 2I) x = x1 + x2 + x3, warm start.
+        op.apply_A(xh, q, inv_nu2, nullptr);
+        int nb = launch_cg_init<T>(x1, x2, x3, q, r, p, N, part(0), s);
+        launch_finalize(part(0), nb, sc, SL_RHO, FIN_STORE, 0, nullptr, 0, s);
+        for (int c = 0; c < prm->cg_iter; ++c) {
+            op.apply_A(p, q, inv_nu2, part(1));
+            launch_finalize(part(1), rows_blocks, sc, 0, FIN_CG_ALPHA, 0, nullptr, 0, s);
+            nb = launch_cg_xr<T>(xh, r, p, q, sc, N, part(0), s);
+            launch_finalize(part(0), nb, sc, 0, FIN_CG_BETA, 0, nullptr, 0, s);
+            launch_cg_p<T>(p, r, sc, N, s);
+        }
+        // i = 1 (on s2): l1 prior on Psi^dag x_hat
+        (void)hipEventRecord(fork, s);
+        (void)hipStreamWaitEvent(s2, fork, 0);
+        launch_psi_adj<T>(P, xh, v1, s2);
+        nb = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part(2), s2);
+        launch_finalize(part(2), nb, sc, SL_OBJ, FIN_HIST_OBJ, 0, P.hist, P.hist_cap, s2);
+        launch_psi<T>(P, v1, x1, s2);
+        (void)hipEventRecord(join, s2);
+        // i = 2: positivity
+        launch_prox_pos<T>(xh, z2, x2, N, s);
+        // i = 3: l2 ball about y~ on Phi~ x_hat
+        op.phi(xh, v3, inv_nu, nullptr);
+        nb = launch_ball_part<T>(v3, z3, yt, M, part(0), part(1), s);
+        launch_finalize(part(0), nb, sc, SL_D2, FIN_BALL, eps_t, nullptr, 0, s);
+        launch_finalize(part(1), nb, sc, SL_RES2, FIN_HIST_RES, 0, P.hist, P.hist_cap, s);
+        launch_prox_ball<T>(v3, z3, yt, sc, M, s);
+        op.phi_adj(v3, nullptr, x3, inv_nu, nullptr, 0.0, nullptr);
+        (void)hipStreamWaitEvent(s, join, 0);
+        launch_iter_advance(sc, s);
+    }
+};
+
+purify_status capture(hipStream_t cs, hipGraph_t* g, hipGraphExec_t* x) {
+    PURIFY_HIP(hipStreamEndCapture(cs, g));
+    PURIFY_HIP(hipGraphInstantiate(x, *g, nullptr, nullptr, 0));
+    return PURIFY_OK;
+}
+
 template <typename T>
 purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* prm, void* x_out,
                         purify_sdmm_info* info, hipStream_t s) {
     using C = cpx<T>;
-    const Ops<T> op{P, s};
     const int64_t N = P.N, M = P.M, D = P.D;
     const C zero = mk<T>(0, 0);
     double* sc = P.sc;
-    double* part0 = part_buf(P, 0);
-    double* part1 = part_buf(P, 1);
-    const int rows_blocks = fft_rows_adj_blocks<T>(P);
+    const bool use_graph = (prm->flags & PURIFY_SDMM_NO_GRAPH) == 0;
+    Sdmm<T> S{P, prm};
+    SolveResources R;
+    PURIFY_HIP(hipStreamCreateWithFlags(&R.cs, hipStreamNonBlocking));
+    PURIFY_HIP(hipStreamCreateWithFlags(&R.cs2, hipStreamNonBlocking));
+    PURIFY_HIP(hipEventCreateWithFlags(&R.fork, hipEventDisableTiming));
+    PURIFY_HIP(hipEventCreateWithFlags(&R.join, hipEventDisableTiming));
+    PURIFY_HIP(hipEventCreateWithFlags(&R.done, hipEventDisableTiming));
+    hipStream_t cs = R.cs;
 
-    PURIFY_HIP(hipMemsetAsync(sc, 0, SL_COUNT * sizeof(double), s));
+    // the solver's streams start after the caller's prior work on s
+    PURIFY_HIP(hipEventRecord(R.done, s));
+    PURIFY_HIP(hipStreamWaitEvent(cs, R.done, 0));
+    const Ops<T> opc{P, cs};
+    PURIFY_HIP(hipMemsetAsync(sc, 0, SL_COUNT * sizeof(double), cs));
 
     // Operator norm nu = ||Phi||_2 by power iteration on Phi^dag Phi from the all-ones image.
     double nu = prm->nu;
     if (!(nu > 0)) {
-        C* v = (C*)P.p;
-        C* w = (C*)P.qv;
-        launch_fill<T>(v, mk<T>((T)(1.0 / std::sqrt((double)N)), 0), N, s);
-        for (int it = 0; it < prm->nu_iter; ++it) {
-            op.phi(v, (C*)P.vis, 1.0, nullptr);
-            op.phi_adj((const C*)P.vis, nullptr, w, 1.0, nullptr, 0.0, nullptr);
-            const int nb = launch_norm2_part<T>(w, N, part0, s);
-            launch_finalize(part0, nb, sc, SL_LAMBDA, FIN_LAMBDA, 0, nullptr, 0, s);
-            launch_scale_by_slot<T>(v, w, sc, SL_INVLAMBDA, N, s);
+        launch_fill<T>((C*)P.p, mk<T>((T)(1.0 / std::sqrt((double)N)), 0), N, cs);
+        if (use_graph && prm->nu_iter > 1) {
+            PURIFY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+            S.enqueue_power_step(cs);
+            purify_status st = capture(cs, &R.g_pow, &R.x_pow);
+            if (st != PURIFY_OK) return st;
+            for (int it = 0; it < prm->nu_iter; ++it) PURIFY_HIP(hipGraphLaunch(R.x_pow, cs));
+        } else {
+            for (int it = 0; it < prm->nu_iter; ++it) S.enqueue_power_step(cs);
         }
         double lam = 0;
-        PURIFY_HIP(hipMemcpyAsync(&lam, sc + SL_LAMBDA, sizeof(double), hipMemcpyDeviceToHost, s));
-        PURIFY_HIP(hipStreamSynchronize(s));
+        PURIFY_HIP(hipMemcpyAsync(&lam, sc + SL_LAMBDA, sizeof(double), hipMemcpyDeviceToHost, cs));
+        PURIFY_HIP(hipStreamSynchronize(cs));
         nu = std::sqrt(lam);
         if (!(nu > 0) || !std::isfinite(nu)) {
             set_error("operator norm is zero or not finite");
             return PURIFY_E_NONFINITE;
         }
     }
-    const double inv_nu = 1.0 / nu, inv_nu2 = inv_nu * inv_nu;
-    const double eps_t = prm->epsilon * inv_nu;
+    S.inv_nu = 1.0 / nu;
+    S.inv_nu2 = S.inv_nu * S.inv_nu;
+    S.eps_t = prm->epsilon * S.inv_nu;
 
     // y~ = y / nu in solver (tile-sorted) order
-    C* yt = (C*)P.ytil;
-    launch_permute_scale<T>((const C*)y_user, P.perm, inv_nu, yt, M, s);
+    launch_permute_scale<T>((const C*)y_user, P.perm, S.inv_nu, (C*)P.ytil, M, cs);
 
     // gamma = 1e-3 max |Psi^dag Phi~^dag y~| unless given
     double gamma = prm->gamma;
     if (!(gamma > 0)) {
-        op.phi_adj(yt, nullptr, (C*)P.p, inv_nu, nullptr, 0.0, nullptr);
-        launch_psi_adj<T>(P, (const C*)P.p, (C*)P.v1, s);
-        const int nb = launch_maxabs_part<T>((const C*)P.v1, D, part0, s);
-        launch_finalize(part0, nb, sc, SL_MAXABS, FIN_MAX, 0, nullptr, 0, s);
+        opc.phi_adj((const C*)P.ytil, nullptr, (C*)P.p, S.inv_nu, nullptr, 0.0, nullptr);
+        launch_psi_adj<T>(P, (const C*)P.p, (C*)P.v1, cs);
+        const int nb = launch_maxabs_part<T>((const C*)P.v1, D, part_buf(P, 0), cs);
+        launch_finalize(part_buf(P, 0), nb, sc, SL_MAXABS, FIN_MAX, 0, nullptr, 0, cs);
         double mx = 0;
-        PURIFY_HIP(hipMemcpyAsync(&mx, sc + SL_MAXABS, sizeof(double), hipMemcpyDeviceToHost, s));
-        PURIFY_HIP(hipStreamSynchronize(s));
+        PURIFY_HIP(hipMemcpyAsync(&mx, sc + SL_MAXABS, sizeof(double), hipMemcpyDeviceToHost, cs));
+        PURIFY_HIP(hipStreamSynchronize(cs));
         gamma = 1e-3 * mx;
         if (!(gamma > 0)) gamma = 1e-12;
     }
+    S.gamma = gamma;
 
     // Algorithm 1 initialisation: x_hat = 0, z_i = 0, and x_i = L_i^dag L_i x_hat = 0.
-    C* xh = (C*)P.xh;
-    C *x1 = (C*)P.x1, *x2 = (C*)P.x2, *x3 = (C*)P.x3;
-    C *r = (C*)P.r, *p = (C*)P.p, *q = (C*)P.qv;
-    C *z1 = (C*)P.z1, *v1 = (C*)P.v1, *z2 = (C*)P.z2, *z3 = (C*)P.z3, *v3 = (C*)P.v3;
-    launch_fill<T>(xh, zero, N, s);
-    launch_fill<T>(x1, zero, N, s);
-    launch_fill<T>(x2, zero, N, s);
-    launch_fill<T>(x3, zero, N, s);
-    launch_fill<T>(z1, zero, D, s);
-    launch_fill<T>(z2, zero, N, s);
-    launch_fill<T>(z3, zero, M, s);
+    for (void* v : {P.xh, P.x1, P.x2, P.x3, P.z2}) launch_fill<T>((C*)v, zero, N, cs);
+    launch_fill<T>((C*)P.z1, zero, D, cs);
+    launch_fill<T>((C*)P.z3, zero, M, cs);
+    PURIFY_HIP(hipMemsetAsync(sc, 0, SL_COUNT * sizeof(double), cs));
 
+    if (use_graph) {
+        PURIFY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        S.enqueue_iteration(cs, R.cs2, R.fork, R.join);
+        purify_status st = capture(cs, &R.g_iter, &R.x_iter);
+        if (st != PURIFY_OK) return st;
+    }
     const int T_max = prm->max_iter;
     const int check = prm->check_every > 0 ? prm->check_every : 1;
     int it_done = 0;
     bool converged = false;
     for (int t = 0; t < T_max; ++t) {
-        const int hi = t % P.hist_cap;
-        // Global update (step 5): CG on (Phi~^dag Phi~ + 2I) x = x1 + x2 + x3, warm start.
-        op.apply_A(xh, q, inv_nu2, nullptr);
-        int nb = launch_cg_init<T>(x1, x2, x3, q, r, p, N, part0, s);
-        launch_finalize(part0, nb, sc, SL_RHO, FIN_STORE, 0, nullptr, 0, s);
-        for (int c = 0; c < prm->cg_iter; ++c) {
-            op.apply_A(p, q, inv_nu2, part1);
-            launch_finalize(part1, rows_blocks, sc, 0, FIN_CG_ALPHA, 0, nullptr, 0, s);
-            nb = launch_cg_xr<T>(xh, r, p, q, sc, N, part0, s);
-            launch_finalize(part0, nb, sc, 0, FIN_CG_BETA, 0, nullptr, 0, s);
-            launch_cg_p<T>(p, r, sc, N, s);
-        }
-        // i = 1: l1 prior on Psi^dag x_hat
-        launch_psi_adj<T>(P, xh, v1, s);
-        nb = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part0, s);
-        launch_finalize(part0, nb, sc, SL_OBJ, FIN_HIST_OBJ, 0, P.hist, hi, s);
-        launch_psi<T>(P, v1, x1, s);
-        // i = 2: positivity
-        launch_prox_pos<T>(xh, z2, x2, N, s);
-        // i = 3: l2 ball about y~ on Phi~ x_hat
-        op.phi(xh, v3, inv_nu, nullptr);
-        nb = launch_ball_part<T>(v3, z3, yt, M, part0, part1, s);
-        launch_finalize(part0, nb, sc, SL_D2, FIN_BALL, eps_t, nullptr, 0, s);
-        launch_finalize(part1, nb, sc, SL_RES2, FIN_HIST_RES, 0, P.hist, hi, s);
-        launch_prox_ball<T>(v3, z3, yt, sc, M, s);
-        op.phi_adj(v3, nullptr, x3, inv_nu, nullptr, 0.0, nullptr);
+        if (use_graph) PURIFY_HIP(hipGraphLaunch(R.x_iter, cs));
+        else S.enqueue_iteration(cs, R.cs2, R.fork, R.join);
         it_done = t + 1;
-
         if (prm->halting && t >= 1 && ((t + 1) % check == 0 || t + 1 == T_max)) {
             double h[4];
-            const int hp = (t - 1) % P.hist_cap;
-            PURIFY_HIP(hipMemcpyAsync(h, P.hist + 2 * hp, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-            PURIFY_HIP(hipMemcpyAsync(h + 2, P.hist + 2 * hi, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-            PURIFY_HIP(hipStreamSynchronize(s));
+            const int hi = t % P.hist_cap, hp = (t - 1) % P.hist_cap;
+            PURIFY_HIP(hipMemcpyAsync(h, P.hist + 2 * hp, 2 * sizeof(double), hipMemcpyDeviceToHost, cs));
+            PURIFY_HIP(hipMemcpyAsync(h + 2, P.hist + 2 * hi, 2 * sizeof(double), hipMemcpyDeviceToHost, cs));
+            PURIFY_HIP(hipStreamSynchronize(cs));
             const double f = h[2], fp = h[0], res = h[3];
             if (!std::isfinite(f) || !std::isfinite(res)) break;
-            if (f > 0 && std::fabs(f - fp) / f < prm->xi && res <= eps_t * (1.0 + prm->slack)) {
+            if (f > 0 && std::fabs(f - fp) / f < prm->xi && res <= S.eps_t * (1.0 + prm->slack)) {
                 converged = true;
                 break;
             }
         }
     }
-    PURIFY_HIP(hipMemcpyAsync(x_out, xh, (size_t)N * sizeof(C), hipMemcpyDeviceToDevice, s));
+    PURIFY_HIP(hipMemcpyAsync(x_out, P.xh, (size_t)N * sizeof(C), hipMemcpyDeviceToDevice, cs));
     double scal[SL_COUNT];
-    PURIFY_HIP(hipMemcpyAsync(scal, sc, sizeof(scal), hipMemcpyDeviceToHost, s));
+    PURIFY_HIP(hipMemcpyAsync(scal, sc, sizeof(scal), hipMemcpyDeviceToHost, cs));
     if (prm->history) {
         const int cnt = it_done < P.hist_cap ? it_done : P.hist_cap;
         PURIFY_HIP(hipMemcpyAsync(prm->history, P.hist, (size_t)2 * cnt * sizeof(double),
-                                  hipMemcpyDeviceToHost, s));
+                                  hipMemcpyDeviceToHost, cs));
     }
-    PURIFY_HIP(hipStreamSynchronize(s));
+    PURIFY_HIP(hipStreamSynchronize(cs));
+    PURIFY_HIP(hipEventRecord(R.done, cs));
+    PURIFY_HIP(hipStreamWaitEvent(s, R.done, 0));
     if (info) {
         info->iterations = it_done;
         info->converged = converged ? 1 : 0;
@@ -409,29 +486,17 @@ int32_t purify_daubechies_filter(int32_t b, double* h, int32_t cap) {
 int32_t purify_kb_kernel(int32_t J, double beta, int32_t count, const double* t, double* out) {
     if (J < 2 || J > 16 || count < 0 || (count > 0 && (!t || !out))) return -1;
     if (!(beta > 0)) beta = 2.34 * J;
-    double c[KB_MAX_TERMS];
-    const int nt = kb_series(beta, 1e-18, c, nullptr);
-    const double a1 = beta * beta / ((double)J * J), hJ = 0.5 * J;
-    for (int i = 0; i < count; ++i) {
-        const double tv = t[i];
-        if (!(std::fabs(tv) <= hJ)) {
-            out[i] = 0.0;
-            continue;
-        }
-        const double w = a1 * ((hJ - tv) * (hJ + tv));
-        double acc = c[nt - 1];
-        for (int k = nt - 2; k >= 0; --k) acc = acc * w + c[k];
-        out[i] = acc;
-    }
+    const int deg = KBDeg<double>::value;
+    std::vector<long double> c((size_t)J * (deg + 1));
+    kb_fit(J, beta, deg, c.data());
+    for (int i = 0; i < count; ++i) out[i] = kb_eval_fit(c.data(), J, deg, t[i]);
     return count;
 }
 
 int32_t purify_deapodisation(int32_t n, int32_t K, int32_t J, double beta, double* out) {
     if (n < 1 || K < 1 || J < 2 || J > 16 || !out) return -1;
     if (!(beta > 0)) beta = 2.34 * J;
-    double c[KB_MAX_TERMS];
-    long double i0b = 0;
-    kb_series(beta, 1e-18, c, &i0b);
+    const long double i0b = kb_i0((long double)beta);
     for (int j = 0; j < n; ++j) out[j] = 1.0 / kb_hat((double)(j - n / 2) / K, J, beta, i0b);
     return n;
 }

@@ -36,26 +36,30 @@ template <typename T> __host__ __device__ __forceinline__ cpx<T> mul_i(cpx<T> a)
 template <typename T> __host__ __device__ __forceinline__ cpx<T> mul_mi(cpx<T> a) { return {a.y, -a.x}; }
 
 // ---------------------------------------------------------------------------------------
-// Kaiser-Bessel kernel as a power series in w = (beta/2)^2 (1 - (2t/J)^2):
-//   psi(t) = I0(2 sqrt w) / I0(beta) = sum_k w^k / (k!)^2 / I0(beta)
-// All terms are positive, so Horner evaluation has no cancellation.  Passed by value in
-// kernel arguments (uniform, scalar registers).
-constexpr int KB_MAX_TERMS = 64;
-template <typename T>
-struct KBSeries {
-    T c[KB_MAX_TERMS];   // c_k = 1 / ((k!)^2 I0(beta))
-    T a1;                // beta^2 / J^2 :  w = a1 (J/2 - t)(J/2 + t)
-    T halfJ;             // J / 2
-    T tap0;              // J/2 - 1: offset of tap 0 is t_0 = f + tap0
-    int nterms;
-};
+// Kaiser-Bessel kernel psi(t) = I0(beta sqrt(1 - (2t/J)^2)) / I0(beta), |t| <= J/2.
+// A visibility's J taps per axis sit at t_a = f + (J/2 - 1) - a with f in [0, 1), so tap a
+// only ever evaluates psi on one unit interval.  The plan fits, per tap, a polynomial of
+// fixed degree in x = f - 1/2 (Chebyshev interpolation in long double, converted to
+// monomials), checked against the Bessel series to 1e-14 (FP64) / 1e-8 (FP32) absolute.
+// Evaluating all J taps together is J independent Horner chains with uniform coefficients.
+template <typename T> struct KBDeg;
+template <> struct KBDeg<double> { static constexpr int value = 17; };
+template <> struct KBDeg<float> { static constexpr int value = 9; };
+constexpr int KB_MAX_J = 16;
+constexpr int KB_MAX_COEF = KB_MAX_J * 18;
 
-template <typename T>
-__device__ __forceinline__ T kb_eval(const KBSeries<T>& kb, T t) {
-    T w = kb.a1 * ((kb.halfJ - t) * (kb.halfJ + t));
-    T acc = kb.c[kb.nterms - 1];
-    for (int k = kb.nterms - 2; k >= 0; --k) acc = acc * w + kb.c[k];
-    return acc;
+// w[a] = psi(f + J/2 - 1 - a), a < J;  c: [a][k] coefficients, k = 0..DEG (device memory)
+template <typename T, int J>
+__device__ __forceinline__ void kb_weights(const T* __restrict__ c, T f, T* w) {
+    constexpr int NC = KBDeg<T>::value + 1;
+    const T x = f - (T)0.5;
+#pragma unroll
+    for (int a = 0; a < J; ++a) w[a] = c[a * NC + NC - 1];
+#pragma unroll
+    for (int k = NC - 2; k >= 0; --k) {
+#pragma unroll
+        for (int a = 0; a < J; ++a) w[a] = w[a] * x + c[a * NC + k];
+    }
 }
 
 // Daubechies filter bank for the wavelet passes: up to 8 bases, 16 taps each.
@@ -66,7 +70,7 @@ constexpr int MAX_TAPS = 16;
 // Scalar slots (doubles) of the solver, in device memory.
 enum Slot : int {
     SL_RHO = 0, SL_PQ, SL_ALPHA, SL_BETA, SL_RHONEW,
-    SL_OBJ, SL_RES2, SL_D2, SL_BALL, SL_LAMBDA, SL_INVLAMBDA, SL_MAXABS, SL_NONFINITE,
+    SL_OBJ, SL_RES2, SL_D2, SL_BALL, SL_LAMBDA, SL_INVLAMBDA, SL_MAXABS, SL_NONFINITE, SL_ITER,
     SL_COUNT = 32
 };
 
@@ -90,8 +94,7 @@ struct Plan {
     int64_t D = 0, N = 0;
     size_t elem = 0;           // bytes per complex element
     double kb_i0beta = 0;      // I0(beta)
-    int kb_terms = 0;
-    double kb_c[KB_MAX_TERMS] = {};
+    double kb_fit_err = 0;     // max |polynomial - psi| found when the plan was built
     double filt[MAX_WAV][MAX_TAPS] = {};
 
     // device buffers (carved from the workspace)
@@ -101,10 +104,12 @@ struct Plan {
     void* frac = nullptr;        // 2M reals: fractional offsets, sorted order
     int32_t* perm = nullptr;     // M: sorted position -> caller index
     int32_t* tileoff = nullptr;  // 4 nT^2 + 1 class offsets
+    int32_t* tilecover = nullptr;  // nT^2: max number of visibilities covering one cell of the tile
     void* deap = nullptr;        // n reals
     void* tw = nullptr;          // n complex: exp(-2 pi i t / n)
     void* tw2 = nullptr;         // n complex: exp(-pi i t / n)
     void* filters = nullptr;     // MAX_WAV * 2 * MAX_TAPS reals (h then g)
+    void* kbpoly = nullptr;      // J * (KBDeg + 1) reals: per-tap polynomial coefficients
     void* grid = nullptr;        // K x K complex, layout [k2][k1]
     void* tmp = nullptr;         // K x n complex, layout [k2][j1]
     double* part = nullptr;      // NUM_PARTIAL_BUFS * MAX_PARTIALS
@@ -119,9 +124,6 @@ struct Plan {
     void *wt = nullptr;          // wavelet temp: nwav * N complex
     void *ws2 = nullptr;         // wavelet LL temp: nwav * N/4 complex (x2 ping-pong)
     void *vis = nullptr;         // M complex scratch (visibility-space temp)
-
-    KBSeries<double> kb64{};
-    KBSeries<float> kb32{};
 };
 
 // ---------------------------------------------------------------------------------------
@@ -158,9 +160,12 @@ enum FinalOp : int {
     FIN_LAMBDA = 3,       // sc[LAMBDA] = sqrt(sum); sc[INVLAMBDA] = 1/that (0 if 0)
     FIN_MAX = 4,          // sc[slot] = max
     FIN_BALL = 5,         // sc[D2] = sum; sc[BALL] = min(1, eps / sqrt(sum)) (1 if 0)
-    FIN_HIST_OBJ = 6,     // sc[OBJ] = sum; hist[2*it] = sum
+    FIN_HIST_OBJ = 6,     // sc[OBJ] = sum; hist[2*it] = sum, it = sc[ITER] mod hist_index
     FIN_HIST_RES = 7      // sc[RES2] = sum; hist[2*it+1] = sqrt(sum)
 };
+// sc[ITER] += 1 (end of an SDMM iteration)
+void launch_iter_advance(double* sc, hipStream_t s);
+// For FIN_HIST_*, hist_index is the history capacity and the row is sc[SL_ITER] mod it.
 void launch_finalize(const double* part, int count, double* sc, int slot, int op, double arg,
                      double* hist, int hist_index, hipStream_t s);
 
@@ -196,7 +201,10 @@ struct DescCheck {
 DescCheck check_desc(const purify_plan_desc* d);
 size_t layout(Plan& P, const purify_plan_desc* d, char* ws);
 purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s);
-int kb_series(double beta, double tol, double* c, long double* i0b_out);
+long double kb_i0(long double x);
+// per-tap polynomial coefficients (J x (deg+1), row a = tap), returns max abs fit error
+double kb_fit(int J, double beta, int deg, long double* coef);
+double kb_eval_fit(const long double* coef, int J, int deg, double t);
 double kb_hat(double nu, int J, double beta, long double i0b);
 int daubechies(int N, double* h_out);
 

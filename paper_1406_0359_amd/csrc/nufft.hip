@@ -19,30 +19,56 @@ namespace purify {
 
 namespace {
 
+constexpr int GRID_THREADS = 256;
+
+// Runtime-J variant of kb_weights (J <= 16), for the less common kernel widths.
+template <typename T>
+__device__ __forceinline__ void kb_weights_any(const T* __restrict__ c, T f, T* w, int J) {
+    constexpr int NC = KBDeg<T>::value + 1;
+    const T x = f - (T)0.5;
+#pragma unroll
+    for (int a = 0; a < KB_MAX_J; ++a)
+        if (a < J) w[a] = c[a * NC + NC - 1];
+#pragma unroll
+    for (int k = NC - 2; k >= 0; --k) {
+#pragma unroll
+        for (int a = 0; a < KB_MAX_J; ++a)
+            if (a < J) w[a] = w[a] * x + c[a * NC + k];
+    }
+}
+
+template <typename T, int J>
+__device__ __forceinline__ void tap_weights(const T* __restrict__ c, T f, T* w, int Jr) {
+    if constexpr (J > 0) kb_weights<T, J>(c, f, w);
+    else kb_weights_any<T>(c, f, w, Jr);
+}
+
+// G: one thread per visibility (tile-sorted order), J x J gather.  J = 0: runtime Jr.
 template <typename T, int J>
 __global__ void __launch_bounds__(256)
 k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
-         const int32_t* __restrict__ base, const T* __restrict__ frac, int M, int K, T scale,
-         KBSeries<T> kb) {
+         const int32_t* __restrict__ base, const T* __restrict__ frac, const T* __restrict__ kbc,
+         int M, int K, T scale, int Jr) {
+    constexpr int JJ = J > 0 ? J : KB_MAX_J;
+    const int Jn = J > 0 ? J : Jr;
     const int m = blockIdx.x * 256 + threadIdx.x;
     if (m >= M) return;
     const int b = base[m];
     const int k1 = b & 0xFFFF, k2 = (b >> 16) & 0xFFFF;
-    const T f1 = frac[2 * m], f2 = frac[2 * m + 1];
-    T wa[J], wb[J];
-#pragma unroll
-    for (int a = 0; a < J; ++a) {
-        wa[a] = kb_eval(kb, f1 + (kb.tap0 - (T)a));
-        wb[a] = kb_eval(kb, f2 + (kb.tap0 - (T)a));
-    }
+    const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[m];
+    T wa[JJ], wb[JJ];
+    tap_weights<T, J>(kbc, f.x, wa, Jr);
+    tap_weights<T, J>(kbc, f.y, wb, Jr);
     const int mask = K - 1;
     T ax = 0, ay = 0;
 #pragma unroll
-    for (int bb = 0; bb < J; ++bb) {
+    for (int bb = 0; bb < JJ; ++bb) {
+        if (bb >= Jn) break;
         const cpx<T>* row = grid + (size_t)((k2 + bb) & mask) * K;
         T rx = 0, ry = 0;
 #pragma unroll
-        for (int a = 0; a < J; ++a) {
+        for (int a = 0; a < JJ; ++a) {
+            if (a >= Jn) break;
             const cpx<T> g = row[(k1 + a) & mask];
             rx += wa[a] * g.x;
             ry += wa[a] * g.y;
@@ -53,121 +79,172 @@ k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t*
     y[perm ? perm[m] : m] = mk<T>(scale * ax, scale * ay);
 }
 
-// Generic-J variant (J <= 16) for the less common kernel widths.
+// Gridding accumulates in LDS with integer atomics on a fixed-point representation:
+// contributions are scaled by an exact power of two per tile and rounded to int32 (FP32
+// path) or int64 (FP64 path).  Integer addition is associative, so the result does not
+// depend on the order in which lanes and waves add (bit-reproducible gridding), and LDS
+// integer atomics run at full rate.  The scale is chosen from the tile's largest |y| and
+// the plan's bound on how many visibilities cover one cell of the tile, so no sum can
+// overflow:  |cell| <= cover * max|y| * max psi^2 <= 2^(bits-2) quanta.
+template <typename T> struct FixedAcc;
+template <> struct FixedAcc<float> {
+    using I = int;
+    static constexpr int BITS = 30;
+    static __device__ __forceinline__ I conv(float v) { return __float2int_rn(v); }
+};
+template <> struct FixedAcc<double> {
+    using I = long long;
+    static constexpr int BITS = 61;
+    static __device__ __forceinline__ I conv(double v) { return __double2ll_rn(v); }
+};
+
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_degrid_any(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
-             const int32_t* __restrict__ base, const T* __restrict__ frac, int M, int K, T scale,
-             KBSeries<T> kb, int J) {
-    const int m = blockIdx.x * 256 + threadIdx.x;
-    if (m >= M) return;
-    const int b = base[m];
-    const int k1 = b & 0xFFFF, k2 = (b >> 16) & 0xFFFF;
-    const T f1 = frac[2 * m], f2 = frac[2 * m + 1];
-    T wa[16], wb[16];
-    for (int a = 0; a < J; ++a) {
-        wa[a] = kb_eval(kb, f1 + (kb.tap0 - (T)a));
-        wb[a] = kb_eval(kb, f2 + (kb.tap0 - (T)a));
-    }
-    const int mask = K - 1;
-    T ax = 0, ay = 0;
-    for (int bb = 0; bb < J; ++bb) {
-        const cpx<T>* row = grid + (size_t)((k2 + bb) & mask) * K;
-        T rx = 0, ry = 0;
-        for (int a = 0; a < J; ++a) {
-            const cpx<T> g = row[(k1 + a) & mask];
-            rx += wa[a] * g.x;
-            ry += wa[a] * g.y;
-        }
-        ax += wb[bb] * rx;
-        ay += wb[bb] * ry;
-    }
-    y[perm ? perm[m] : m] = mk<T>(scale * ax, scale * ay);
+__device__ __forceinline__ void lds_add(typename FixedAcc<T>::I* p, typename FixedAcc<T>::I v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Contributions of visibilities [start, end) that land in this tile's body (bounds-checked).
 template <typename T, int J, int TT>
 __device__ __forceinline__ void grid_range(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
                                            const int32_t* __restrict__ base, const T* __restrict__ frac,
-                                           int start, int end, int K, int t1o, int t2o,
-                                           const KBSeries<T>& kb, int Jr, T* acc_re, T* acc_im) {
-    constexpr int JJ = J > 0 ? J : 16;
+                                           const T* __restrict__ kbc, int start, int end, int K,
+                                           int t1o, int t2o, int Jr, T inv_q,
+                                           typename FixedAcc<T>::I* acc) {
+    using Acc = FixedAcc<T>;
+    constexpr int JJ = J > 0 ? J : KB_MAX_J;
     const int mask = K - 1;
     const int Jn = J > 0 ? J : Jr;
-    for (int idx = start + (int)threadIdx.x; idx < end; idx += (int)blockDim.x) {
+    for (int idx = start + (int)threadIdx.x; idx < end; idx += GRID_THREADS) {
         const int b = base[idx];
         const int k1 = b & 0xFFFF, k2 = (b >> 16) & 0xFFFF;
-        const T f1 = frac[2 * idx], f2 = frac[2 * idx + 1];
+        const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[idx];
         const cpx<T> v = y[perm ? perm[idx] : idx];
-        T wa[JJ];
-#pragma unroll
-        for (int a = 0; a < JJ; ++a)
-            if (a < Jn) wa[a] = kb_eval(kb, f1 + (kb.tap0 - (T)a));
+        T wa[JJ], wb[JJ];
+        tap_weights<T, J>(kbc, f.x, wa, Jr);
+        tap_weights<T, J>(kbc, f.y, wb, Jr);
 #pragma unroll
         for (int bb = 0; bb < JJ; ++bb) {
             if (bb >= Jn) break;
             const int c2 = ((k2 + bb) & mask) - t2o;
             if ((unsigned)c2 >= (unsigned)TT) continue;
-            const T wbv = kb_eval(kb, f2 + (kb.tap0 - (T)bb));
-            const T vx = wbv * v.x, vy = wbv * v.y;
+            const T s = wb[bb] * inv_q;
+            const T vx = s * v.x, vy = s * v.y;
 #pragma unroll
             for (int a = 0; a < JJ; ++a) {
                 if (a >= Jn) break;
                 const int c1 = ((k1 + a) & mask) - t1o;
                 if ((unsigned)c1 < (unsigned)TT) {
-                    atomicAdd(&acc_re[c2 * TT + c1], wa[a] * vx);
-                    atomicAdd(&acc_im[c2 * TT + c1], wa[a] * vy);
+                    lds_add<T>(&acc[2 * (c2 * TT + c1)], Acc::conv(wa[a] * vx));
+                    lds_add<T>(&acc[2 * (c2 * TT + c1) + 1], Acc::conv(wa[a] * vy));
                 }
             }
         }
     }
 }
 
+// Own visibilities whose footprint lies inside the tile (spill class 0): no bounds checks;
+// tap (a, bb) is at a fixed offset from the first tap's cell.
 template <typename T, int J, int TT>
-__global__ void __launch_bounds__(256)
-k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int32_t* __restrict__ base,
-       const T* __restrict__ frac, const int32_t* __restrict__ off, cpx<T>* __restrict__ grid, int K,
-       int nT, KBSeries<T> kb, int Jr) {
-    __shared__ T acc_re[TT * TT];
-    __shared__ T acc_im[TT * TT];
-    const int tile = blockIdx.x;
-    const int t1 = tile % nT, t2 = tile / nT;
-    for (int i = threadIdx.x; i < TT * TT; i += blockDim.x) {
-        acc_re[i] = 0;
-        acc_im[i] = 0;
-    }
-    __syncthreads();
-    const int t1m = (t1 + nT - 1) % nT, t2m = (t2 + nT - 1) % nT;
-    const int L = t2 * nT + t1m, U = t2m * nT + t1, Dg = t2m * nT + t1m;
-    const int t1o = t1 * TT, t2o = t2 * TT;
-    // own visibilities (every spill class), then the three neighbours' spill sets
-    grid_range<T, J, TT>(y, perm, base, frac, off[4 * tile], off[4 * tile + 4], K, t1o, t2o, kb, Jr, acc_re, acc_im);
-    grid_range<T, J, TT>(y, perm, base, frac, off[4 * L + 1], off[4 * L + 3], K, t1o, t2o, kb, Jr, acc_re, acc_im);
-    grid_range<T, J, TT>(y, perm, base, frac, off[4 * U + 2], off[4 * U + 4], K, t1o, t2o, kb, Jr, acc_re, acc_im);
-    grid_range<T, J, TT>(y, perm, base, frac, off[4 * Dg + 2], off[4 * Dg + 3], K, t1o, t2o, kb, Jr, acc_re, acc_im);
-    __syncthreads();
-    for (int i = threadIdx.x; i < TT * TT; i += blockDim.x) {
-        const int r = i / TT, c = i % TT;
-        grid[(size_t)(t2o + r) * K + t1o + c] = mk<T>(acc_re[i], acc_im[i]);
+__device__ __forceinline__ void grid_interior(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
+                                              const int32_t* __restrict__ base, const T* __restrict__ frac,
+                                              const T* __restrict__ kbc, int start, int end, int t1o,
+                                              int t2o, T inv_q, typename FixedAcc<T>::I* acc) {
+    using Acc = FixedAcc<T>;
+    for (int idx = start + (int)threadIdx.x; idx < end; idx += GRID_THREADS) {
+        const int b = base[idx];
+        const int c1 = (b & 0xFFFF) - t1o, c2 = ((b >> 16) & 0xFFFF) - t2o;
+        const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[idx];
+        const cpx<T> v = y[perm ? perm[idx] : idx];
+        T wa[J], wb[J];
+        kb_weights<T, J>(kbc, f.x, wa);
+        kb_weights<T, J>(kbc, f.y, wb);
+        typename Acc::I* p = acc + 2 * (c2 * TT + c1);
+#pragma unroll
+        for (int bb = 0; bb < J; ++bb) {
+            const T s = wb[bb] * inv_q;
+            const T vx = s * v.x, vy = s * v.y;
+#pragma unroll
+            for (int a = 0; a < J; ++a) {
+                lds_add<T>(p + 2 * (bb * TT + a), Acc::conv(wa[a] * vx));
+                lds_add<T>(p + 2 * (bb * TT + a) + 1, Acc::conv(wa[a] * vy));
+            }
+        }
     }
 }
 
-template <typename T>
-const KBSeries<T>& kb_of(const Plan& P);
-template <>
-const KBSeries<float>& kb_of<float>(const Plan& P) { return P.kb32; }
-template <>
-const KBSeries<double>& kb_of<double>(const Plan& P) { return P.kb64; }
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// G^T: one workgroup per TT x TT tile; own visibilities plus the three neighbours' spill
+// ranges; fixed-point LDS accumulation; one write of the tile.
+template <typename T, int J, int TT>
+__global__ void __launch_bounds__(GRID_THREADS)
+k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int32_t* __restrict__ base,
+       const T* __restrict__ frac, const T* __restrict__ kbc, const int32_t* __restrict__ off,
+       const int32_t* __restrict__ cover, cpx<T>* __restrict__ grid, int K, int nT, int Jr) {
+    using Acc = FixedAcc<T>;
+    __shared__ typename Acc::I acc[2 * TT * TT];
+    __shared__ double red[GRID_THREADS / 64];
+    const int tile = blockIdx.x;
+    const int t1 = tile % nT, t2 = tile / nT;
+    const int t1m = (t1 + nT - 1) % nT, t2m = (t2 + nT - 1) % nT;
+    const int L = t2 * nT + t1m, U = t2m * nT + t1, Dg = t2m * nT + t1m;
+    const int t1o = t1 * TT, t2o = t2 * TT;
+    const int s0 = off[4 * tile], s1 = off[4 * tile + 1], s4 = off[4 * tile + 4];
+    const int ls = off[4 * L + 1], le = off[4 * L + 3];
+    const int us = off[4 * U + 2], ue = off[4 * U + 4];
+    const int ds = off[4 * Dg + 2], de = off[4 * Dg + 3];
+    for (int i = threadIdx.x; i < 2 * TT * TT; i += GRID_THREADS) acc[i] = 0;
+    // pass 1: largest component magnitude of y over every visibility touching the tile
+    double ym = 0.0;
+    for (int r = 0; r < 4; ++r) {
+        const int st = r == 0 ? s0 : (r == 1 ? ls : (r == 2 ? us : ds));
+        const int en = r == 0 ? s4 : (r == 1 ? le : (r == 2 ? ue : de));
+        for (int idx = st + (int)threadIdx.x; idx < en; idx += GRID_THREADS) {
+            const cpx<T> v = y[perm ? perm[idx] : idx];
+            ym = fmax(ym, fmax(fabs((double)v.x), fabs((double)v.y)));
+        }
+    }
+    ym = wave_max(ym);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ym;
+    __syncthreads();
+    ym = 0.0;
+#pragma unroll
+    for (int w = 0; w < GRID_THREADS / 64; ++w) ym = fmax(ym, red[w]);
+    // quantum q = 2^e with 2 * cover * max|y| <= 2^BITS q: at most `cover` visibilities add
+    // to one cell, each by at most max|y| (psi <= 1; the factor 2 is margin)
+    const double bound = 2.0 * (double)cover[tile] * ym;
+    const int e = bound > 0.0 ? ilogb(bound) + 1 - Acc::BITS : 0;
+    const T inv_q = (T)ldexp(1.0, -e);
+    const T q = (T)ldexp(1.0, e);
+    if (bound > 0.0) {
+        if constexpr (J > 0) grid_interior<T, J, TT>(y, perm, base, frac, kbc, s0, s1, t1o, t2o, inv_q, acc);
+        else grid_range<T, J, TT>(y, perm, base, frac, kbc, s0, s1, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT>(y, perm, base, frac, kbc, s1, s4, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT>(y, perm, base, frac, kbc, ls, le, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT>(y, perm, base, frac, kbc, us, ue, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT>(y, perm, base, frac, kbc, ds, de, K, t1o, t2o, Jr, inv_q, acc);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < TT * TT; i += GRID_THREADS) {
+        const int r = i / TT, c = i % TT;
+        grid[(size_t)(t2o + r) * K + t1o + c] = mk<T>(q * (T)acc[2 * i], q * (T)acc[2 * i + 1]);
+    }
+}
 
 template <typename T, int TT>
 void grid_tt(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* grid, hipStream_t s) {
-    const dim3 g(P.nT * P.nT), b(256);
+    const dim3 g(P.nT * P.nT), b(GRID_THREADS);
     const T* fr = (const T*)P.frac;
-    const KBSeries<T>& kb = kb_of<T>(P);
+    const T* kbc = (const T*)P.kbpoly;
     switch (P.J) {
-        case 4: hipLaunchKernelGGL((k_grid<T, 4, TT>), g, b, 0, s, y, perm, P.base, fr, P.tileoff, grid, P.K, P.nT, kb, 4); break;
-        case 6: hipLaunchKernelGGL((k_grid<T, 6, TT>), g, b, 0, s, y, perm, P.base, fr, P.tileoff, grid, P.K, P.nT, kb, 6); break;
-        case 8: hipLaunchKernelGGL((k_grid<T, 8, TT>), g, b, 0, s, y, perm, P.base, fr, P.tileoff, grid, P.K, P.nT, kb, 8); break;
-        default: hipLaunchKernelGGL((k_grid<T, 0, TT>), g, b, 0, s, y, perm, P.base, fr, P.tileoff, grid, P.K, P.nT, kb, P.J); break;
+        case 4: hipLaunchKernelGGL((k_grid<T, 4, TT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 4); break;
+        case 6: hipLaunchKernelGGL((k_grid<T, 6, TT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 6); break;
+        case 8: hipLaunchKernelGGL((k_grid<T, 8, TT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 8); break;
+        default: hipLaunchKernelGGL((k_grid<T, 0, TT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, P.J); break;
     }
 }
 
@@ -179,12 +256,12 @@ void launch_degrid(const Plan& P, const cpx<T>* grid, cpx<T>* y, const int32_t* 
     const int M = (int)P.M;
     const dim3 g((M + 255) / 256), b(256);
     const T* fr = (const T*)P.frac;
-    const KBSeries<T>& kb = kb_of<T>(P);
+    const T* kbc = (const T*)P.kbpoly;
     switch (P.J) {
-        case 4: hipLaunchKernelGGL((k_degrid<T, 4>), g, b, 0, s, grid, y, perm, P.base, fr, M, P.K, (T)scale, kb); break;
-        case 6: hipLaunchKernelGGL((k_degrid<T, 6>), g, b, 0, s, grid, y, perm, P.base, fr, M, P.K, (T)scale, kb); break;
-        case 8: hipLaunchKernelGGL((k_degrid<T, 8>), g, b, 0, s, grid, y, perm, P.base, fr, M, P.K, (T)scale, kb); break;
-        default: hipLaunchKernelGGL((k_degrid_any<T>), g, b, 0, s, grid, y, perm, P.base, fr, M, P.K, (T)scale, kb, P.J); break;
+        case 4: hipLaunchKernelGGL((k_degrid<T, 4>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, M, P.K, (T)scale, 4); break;
+        case 6: hipLaunchKernelGGL((k_degrid<T, 6>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, M, P.K, (T)scale, 6); break;
+        case 8: hipLaunchKernelGGL((k_degrid<T, 8>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, M, P.K, (T)scale, 8); break;
+        default: hipLaunchKernelGGL((k_degrid<T, 0>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, M, P.K, (T)scale, P.J); break;
     }
 }
 

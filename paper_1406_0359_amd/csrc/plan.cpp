@@ -42,26 +42,81 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
-// Kaiser-Bessel series: psi(t) = sum_k c_k w^k, w = (beta/2)^2 (1 - (2t/J)^2),
-// c_k = 1 / ((k!)^2 I0(beta)).  The number of terms is chosen so that the first omitted
-// term, at the largest w (t = 0), is below `tol` relative to psi(0) = 1.
-int kb_series(double beta, double tol, double* c, long double* i0b_out) {
+long double kb_i0(long double x) { return i0_series(x); }
+
+namespace {
+long double psi_ld(long double t, int J, long double beta, long double i0b) {
+    const long double u = 1.0L - (2.0L * t / J) * (2.0L * t / J);
+    if (u < 0) return 0.0L;
+    return i0_series(beta * sqrtl(u)) / i0b;
+}
+}  // namespace
+
+// Per-tap polynomial fit of psi on each tap's unit interval: tap a covers
+// t = x + 1/2 + (J/2 - 1) - a, x in [-1/2, 1/2].  Chebyshev interpolation at deg+1 nodes
+// (long double), converted to monomials in x.  Returns the max abs error of the double
+// Horner evaluation against the Bessel series over a fine grid.
+double kb_fit(int J, double beta, int deg, long double* coef) {
     const long double i0b = i0_series((long double)beta);
-    const long double wmax = (long double)beta * beta / 4.0L;
-    long double fk = 1.0L;   // 1/(k!)^2
-    int k = 0;
-    for (; k < KB_MAX_TERMS; ++k) {
-        if (k > 0) fk /= (long double)k * k;
-        c[k] = (double)(fk / i0b);
-        // bound on the tail at wmax relative to psi(0) = 1
-        long double next = fk / ((long double)(k + 1) * (k + 1)) * powl(wmax, k + 1) / i0b;
-        if (k >= 1 && next < tol) {
-            ++k;
-            break;
+    const long double h = 0.5L * J - 1.0L;
+    const int nc = deg + 1;
+    std::vector<long double> vals(nc), b(nc), tj(nc), tjm(nc), tjp(nc), mono(nc);
+    for (int a = 0; a < J; ++a) {
+        for (int i = 0; i < nc; ++i) {
+            const long double y = cosl(PI_L * (i + 0.5L) / nc);     // node in [-1, 1]
+            vals[i] = psi_ld(0.5L * y + 0.5L + h - a, J, beta, i0b);
+        }
+        for (int j = 0; j < nc; ++j) {
+            long double acc = 0;
+            for (int i = 0; i < nc; ++i) acc += vals[i] * cosl(PI_L * j * (i + 0.5L) / nc);
+            b[j] = acc * 2.0L / nc;
+        }
+        b[0] *= 0.5L;
+        // sum_j b_j T_j(y), y = 2x, as monomials in y
+        std::fill(mono.begin(), mono.end(), 0.0L);
+        std::fill(tjm.begin(), tjm.end(), 0.0L);
+        std::fill(tj.begin(), tj.end(), 0.0L);
+        tjm[0] = 1.0L;            // T_0
+        if (nc > 1) tj[1] = 1.0L; // T_1
+        for (int k = 0; k < nc; ++k) mono[k] += b[0] * tjm[k];
+        for (int j = 1; j < nc; ++j) {
+            for (int k = 0; k < nc; ++k) mono[k] += b[j] * tj[k];
+            // T_{j+1} = 2 y T_j - T_{j-1}
+            std::fill(tjp.begin(), tjp.end(), 0.0L);
+            for (int k = 0; k + 1 < nc; ++k) tjp[k + 1] = 2.0L * tj[k];
+            for (int k = 0; k < nc; ++k) tjp[k] -= tjm[k];
+            tjm.swap(tj);
+            tj.swap(tjp);
+        }
+        long double p2 = 1.0L;
+        for (int k = 0; k < nc; ++k) {
+            coef[a * nc + k] = mono[k] * p2;   // y^k = 2^k x^k
+            p2 *= 2.0L;
         }
     }
-    if (i0b_out) *i0b_out = i0b;
-    return k;
+    double err = 0;
+    const int S = 2001;
+    for (int a = 0; a < J; ++a)
+        for (int i = 0; i < S; ++i) {
+            const double x = -0.5 + (double)i / (S - 1);
+            double acc = (double)coef[a * nc + nc - 1];
+            for (int k = nc - 2; k >= 0; --k) acc = acc * x + (double)coef[a * nc + k];
+            const double ref = (double)psi_ld((long double)x + 0.5L + h - a, J, beta, i0b);
+            err = std::max(err, std::fabs(acc - ref));
+        }
+    return err;
+}
+
+// Evaluate the fitted psi at any t in [-J/2, J/2) (0 outside), as the kernels do in FP64.
+double kb_eval_fit(const long double* coef, int J, int deg, double t) {
+    const double h = 0.5 * J - 1.0;
+    const int a = (int)std::ceil(h - t);
+    if (a < 0 || a >= J) return 0.0;
+    const double x = t - h + a - 0.5;
+    const int nc = deg + 1;
+    double acc = (double)coef[a * nc + nc - 1];
+    for (int k = nc - 2; k >= 0; --k) acc = acc * x + (double)coef[a * nc + k];
+    return acc;
 }
 
 double kb_hat(double nu, int J, double beta, long double i0b) {
@@ -209,10 +264,12 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
     P.frac = carve(2 * M * es);
     P.perm = (int32_t*)carve(M * 4);
     P.tileoff = (int32_t*)carve(((size_t)4 * P.nT * P.nT + 1) * 4);
+    P.tilecover = (int32_t*)carve((size_t)P.nT * P.nT * 4);
     P.deap = carve(P.n * es);
     P.tw = carve(P.n * ce);
     P.tw2 = carve(P.n * ce);
     P.filters = carve((size_t)MAX_WAV * 2 * MAX_TAPS * es);
+    P.kbpoly = carve((size_t)KB_MAX_COEF * es);
     P.grid = carve(K * K * ce);
     P.tmp = carve(K * P.n * ce);
     P.part = (double*)carve((size_t)NUM_PARTIAL_BUFS * MAX_PARTIALS * sizeof(double));
@@ -246,24 +303,19 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     const int64_t M = P.M;
     const bool f64 = P.precision == PURIFY_FP64;
 
-    // Kaiser-Bessel series (FP64 tolerance for the FP64 path, ~1e-9 for FP32).
-    long double i0b = 0;
-    P.kb_terms = kb_series(P.beta, f64 ? 1e-18 : 1e-10, P.kb_c, &i0b);
+    // Kaiser-Bessel per-tap polynomials.
+    const long double i0b = i0_series((long double)P.beta);
     P.kb_i0beta = (double)i0b;
-    const double a1 = P.beta * P.beta / ((double)J * J);
-    P.kb64 = KBSeries<double>{};
-    P.kb32 = KBSeries<float>{};
-    for (int k = 0; k < P.kb_terms; ++k) {
-        P.kb64.c[k] = P.kb_c[k];
-        P.kb32.c[k] = (float)P.kb_c[k];
+    const int deg = f64 ? KBDeg<double>::value : KBDeg<float>::value;
+    std::vector<long double> kbc((size_t)J * (deg + 1));
+    P.kb_fit_err = kb_fit(J, P.beta, deg, kbc.data());
+    const double fit_tol = f64 ? 1e-13 : 1e-7;
+    if (!(P.kb_fit_err <= fit_tol)) {
+        set_error("Kaiser-Bessel polynomial fit error " + std::to_string(P.kb_fit_err) +
+                  " exceeds tolerance for this J/beta");
+        return PURIFY_E_INVALID;
     }
-    P.kb64.nterms = P.kb32.nterms = P.kb_terms;
-    P.kb64.a1 = a1;
-    P.kb32.a1 = (float)a1;
-    P.kb64.halfJ = 0.5 * J;
-    P.kb32.halfJ = 0.5f * J;
-    P.kb64.tap0 = 0.5 * J - 1.0;
-    P.kb32.tap0 = 0.5f * J - 1.0f;
+    std::vector<double> kbd(kbc.begin(), kbc.end());
 
     // Deapodisation and twiddles.
     std::vector<double> deap(n);
@@ -339,6 +391,36 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
         }
     }
 
+    // Per-tile bound on the number of visibilities that add to one cell (gridding scale):
+    // count first taps per cell, sum over the J x J window of first taps that reach each
+    // cell (cyclic), and take the maximum over each tile.
+    std::vector<int32_t> cover((size_t)nT * nT, 0);
+    {
+        std::vector<int32_t> cnt((size_t)K * K, 0), row((size_t)K * K, 0);
+        for (int64_t m = 0; m < M; ++m) {
+            const int k1 = base[m] & 0xFFFF, k2 = (base[m] >> 16) & 0xFFFF;
+            ++cnt[(size_t)k2 * K + k1];
+        }
+        for (int k2 = 0; k2 < K; ++k2) {
+            const int32_t* c = &cnt[(size_t)k2 * K];
+            int32_t* r = &row[(size_t)k2 * K];
+            for (int k1 = 0; k1 < K; ++k1) {
+                int32_t acc = 0;
+                for (int a = 0; a < J; ++a) acc += c[(k1 - a + K) & (K - 1)];
+                r[k1] = acc;
+            }
+        }
+        for (int k2 = 0; k2 < K; ++k2) {
+            const int t2 = k2 / TT;
+            for (int k1 = 0; k1 < K; ++k1) {
+                int32_t acc = 0;
+                for (int b = 0; b < J; ++b) acc += row[(size_t)((k2 - b + K) & (K - 1)) * K + k1];
+                int32_t& cv = cover[(size_t)t2 * nT + k1 / TT];
+                if (acc > cv) cv = acc;
+            }
+        }
+    }
+
     // Upload (pageable host memory; synchronous at the end).
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
@@ -354,11 +436,13 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     PURIFY_HIP(up(P.base, sbase.data(), M * 4));
     PURIFY_HIP(up(P.perm, perm.data(), M * 4));
     PURIFY_HIP(up(P.tileoff, off.data(), off.size() * 4));
+    PURIFY_HIP(up(P.tilecover, cover.data(), cover.size() * 4));
     PURIFY_HIP(up_real(P.frac, sfr));
     PURIFY_HIP(up_real(P.deap, deap));
     PURIFY_HIP(up_real(P.tw, tw));
     PURIFY_HIP(up_real(P.tw2, tw2));
     PURIFY_HIP(up_real(P.filters, filt));
+    PURIFY_HIP(up_real(P.kbpoly, kbd));
     PURIFY_HIP(hipMemsetAsync(P.sc, 0, SL_COUNT * sizeof(double), s));
     PURIFY_HIP(hipStreamSynchronize(s));
     return PURIFY_OK;

@@ -118,14 +118,16 @@ k_finalize(const double* __restrict__ part, int count, double* sc, int slot, int
             const double nd = sqrt(acc);
             sc[SL_BALL] = (nd == 0.0 || arg >= nd) ? 1.0 : arg / nd;
         } break;
-        case FIN_HIST_OBJ:
+        case FIN_HIST_OBJ: {
             sc[SL_OBJ] = acc;
-            if (hist) hist[2 * hist_index] = acc;
-            break;
-        case FIN_HIST_RES:
+            const int row = (int)sc[SL_ITER] % hist_index;
+            if (hist) hist[2 * row] = acc;
+        } break;
+        case FIN_HIST_RES: {
             sc[SL_RES2] = acc;
-            if (hist) hist[2 * hist_index + 1] = sqrt(acc);
-            break;
+            const int row = (int)sc[SL_ITER] % hist_index;
+            if (hist) hist[2 * row + 1] = sqrt(acc);
+        } break;
         default: break;
     }
 }
@@ -247,6 +249,10 @@ k_prox_ball(cpx<T>* __restrict__ v3, cpx<T>* __restrict__ z3, const cpx<T>* __re
     v3[i] = r3 - z;
 }
 
+__global__ void k_iter_advance(double* sc) {
+    if (threadIdx.x == 0) sc[SL_ITER] += 1.0;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(VT)
 k_permute_scale(const cpx<T>* __restrict__ yu, const int32_t* __restrict__ perm, T scale,
@@ -285,6 +291,9 @@ void launch_finalize(const double* part, int count, double* sc, int slot, int op
                      double* hist, int hist_index, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VT), 0, s, part, count, sc, slot, op, arg, hist,
                        hist_index);
+}
+void launch_iter_advance(double* sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_iter_advance, dim3(1), dim3(64), 0, s, sc);
 }
 template <typename T>
 int launch_cg_init(const cpx<T>* x1, const cpx<T>* x2, const cpx<T>* x3, const cpx<T>* q, cpx<T>* r,

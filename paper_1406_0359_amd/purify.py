@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libpurify.so")
 
 FP64, FP32 = 0, 1
 DICT_SARA = 0x1FF
+SDMM_NO_GRAPH = 1
 
 STAGES = {
     "fft_rows": 0, "fft_cols": 1, "degrid": 2, "grid": 3, "ifft_cols": 4, "ifft_rows": 5,
@@ -47,7 +48,7 @@ class SdmmParams(ctypes.Structure):
         ("epsilon", ctypes.c_double), ("gamma", ctypes.c_double), ("nu", ctypes.c_double),
         ("xi", ctypes.c_double), ("slack", ctypes.c_double),
         ("max_iter", ctypes.c_int32), ("cg_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
-        ("halting", ctypes.c_int32), ("nu_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("halting", ctypes.c_int32), ("nu_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("weights", ctypes.c_void_p), ("history", ctypes.POINTER(ctypes.c_double)),
     ]
 
@@ -262,13 +263,14 @@ class Plan:
     def sdmm(self, y, epsilon: float, max_iter: int = 300, cg_iter: int = 10,
              gamma: float = 0.0, nu: float = 0.0, nu_iter: int = 100, halting: bool = False,
              xi: float = 1e-4, slack: float = 1e-3, check_every: int = 10, weights=None,
-             record_history: bool = False, out=None) -> SolveResult:
+             record_history: bool = False, graph: bool = True, out=None) -> SolveResult:
         """SDMM (Algorithm 1) for eq. (3) with R = 1; returns x_hat and solver info."""
         x = self.empty(self.n, self.n) if out is None else out
         p = SdmmParams()
         p.epsilon, p.gamma, p.nu, p.xi, p.slack = epsilon, gamma, nu, xi, slack
         p.max_iter, p.cg_iter, p.check_every = max_iter, cg_iter, check_every
-        p.halting, p.nu_iter, p.reserved = int(bool(halting)), nu_iter, 0
+        p.halting, p.nu_iter = int(bool(halting)), nu_iter
+        p.flags = 0 if graph else SDMM_NO_GRAPH
         if weights is not None:
             if (weights.dtype != self.torch.float64 or weights.numel() != self.D
                     or weights.device != self.device or not weights.is_contiguous()):

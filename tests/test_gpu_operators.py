@@ -60,6 +60,18 @@ def test_phi_rejects_wrong_dtype_and_size():
         plan.phi(torch.zeros(31, 32, dtype=torch.complex128, device=DEV))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gridding_is_order_independent(prec):
+    # integer LDS accumulation: the adjoint is bitwise reproducible
+    n, M = 256, 60000
+    uv = uv_case(M, n, 21)
+    plan = purify.Plan(n, uv, dict_mask=1, levels=1, precision=prec, device=DEV)
+    y = plan.as_vec(rand_complex(M, 22))
+    a = to_np(plan.phi_adj(y))
+    b = to_np(plan.phi_adj(y))
+    assert np.array_equal(a, b)
+
+
 def test_gpu_adjoint_identity_fp64():
     n, M = 128, 3000
     uv = uv_case(M, n, 9)
