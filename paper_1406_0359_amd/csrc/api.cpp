@@ -75,13 +75,14 @@ struct Sdmm {
         C* w = (C*)P.qv;
         op.phi(v, (C*)P.vis, 1.0, nullptr);
         op.phi_adj((const C*)P.vis, nullptr, w, 1.0, nullptr, 0.0, nullptr);
-        const int nb = launch_norm2_part<T>(w, P.N, part(0), s);
-        launch_finalize(part(0), nb, P.sc, SL_LAMBDA, FIN_LAMBDA, 0, nullptr, 0, s);
-        launch_scale_by_slot<T>(v, w, P.sc, SL_INVLAMBDA, P.N, s);
+        const int nb = launch_norm2_part<T>(w, P.N, part(6), s);
+        launch_power_normalise<T>(v, w, part(6), nb, P.sc, P.N, s);
     }
 
     // One SDMM iteration (Algorithm 1, steps 5-9).  Branch i = 1 runs on s2 between the
-    // fork and join events; CG and branches i = 2, 3 run on s.
+    // fork and join events; CG and branches i = 2, 3 run on s.  Scalars (CG alpha and beta,
+    // the l2-ball scale) are summed from partial-sum buffers inside the kernels that use
+    // them; rho alternates between buffers 0 and 1, <p, Ap> uses buffer 2.
     void enqueue_iteration(hipStream_t s, hipStream_t s2, hipEvent_t fork, hipEvent_t join) const {
         const Ops<T> op{P, s};
         const int64_t N = P.N, M = P.M, D = P.D;
@@ -94,31 +95,28 @@ struct Sdmm {
         const int rows_blocks = fft_rows_adj_blocks<T>(P);
         // Global update (step 5): CG on (Phi~^dag Phi~ + 2I) x = x1 + x2 + x3, warm start.
         op.apply_A(xh, q, inv_nu2, nullptr);
-        int nb = launch_cg_init<T>(x1, x2, x3, q, r, p, N, part(0), s);
-        launch_finalize(part(0), nb, sc, SL_RHO, FIN_STORE, 0, nullptr, 0, s);
+        const int nb = launch_cg_init<T>(x1, x2, x3, q, r, p, N, part(0), s);
         for (int c = 0; c < prm->cg_iter; ++c) {
-            op.apply_A(p, q, inv_nu2, part(1));
-            launch_finalize(part(1), rows_blocks, sc, 0, FIN_CG_ALPHA, 0, nullptr, 0, s);
-            nb = launch_cg_xr<T>(xh, r, p, q, sc, N, part(0), s);
-            launch_finalize(part(0), nb, sc, 0, FIN_CG_BETA, 0, nullptr, 0, s);
-            launch_cg_p<T>(p, r, sc, N, s);
+            double* rho = part(c & 1);
+            double* rho_next = part((c + 1) & 1);
+            op.apply_A(p, q, inv_nu2, part(2));
+            launch_cg_xr<T>(xh, r, p, q, rho, nb, part(2), rows_blocks, N, rho_next, s);
+            launch_cg_p<T>(p, r, rho, rho_next, nb, N, s);
         }
         // i = 1 (on s2): l1 prior on Psi^dag x_hat
         (void)hipEventRecord(fork, s);
         (void)hipStreamWaitEvent(s2, fork, 0);
         launch_psi_adj<T>(P, xh, v1, s2);
-        nb = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part(2), s2);
-        launch_finalize(part(2), nb, sc, SL_OBJ, FIN_HIST_OBJ, 0, P.hist, P.hist_cap, s2);
+        const int nb1 = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part(3), s2);
+        launch_finalize(part(3), nb1, sc, SL_OBJ, FIN_HIST_OBJ, 0, P.hist, P.hist_cap, s2);
         launch_psi<T>(P, v1, x1, s2);
         (void)hipEventRecord(join, s2);
         // i = 2: positivity
         launch_prox_pos<T>(xh, z2, x2, N, s);
         // i = 3: l2 ball about y~ on Phi~ x_hat
         op.phi(xh, v3, inv_nu, nullptr);
-        nb = launch_ball_part<T>(v3, z3, yt, M, part(0), part(1), s);
-        launch_finalize(part(0), nb, sc, SL_D2, FIN_BALL, eps_t, nullptr, 0, s);
-        launch_finalize(part(1), nb, sc, SL_RES2, FIN_HIST_RES, 0, P.hist, P.hist_cap, s);
-        launch_prox_ball<T>(v3, z3, yt, sc, M, s);
+        const int nb3 = launch_ball_part<T>(v3, z3, yt, M, part(4), part(5), s);
+        launch_prox_ball<T>(v3, z3, yt, part(4), part(5), nb3, eps_t, sc, P.hist, P.hist_cap, M, s);
         op.phi_adj(v3, nullptr, x3, inv_nu, nullptr, 0.0, nullptr);
         (void)hipStreamWaitEvent(s, join, 0);
         launch_iter_advance(sc, s);
@@ -188,8 +186,8 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     if (!(gamma > 0)) {
         opc.phi_adj((const C*)P.ytil, nullptr, (C*)P.p, S.inv_nu, nullptr, 0.0, nullptr);
         launch_psi_adj<T>(P, (const C*)P.p, (C*)P.v1, cs);
-        const int nb = launch_maxabs_part<T>((const C*)P.v1, D, part_buf(P, 0), cs);
-        launch_finalize(part_buf(P, 0), nb, sc, SL_MAXABS, FIN_MAX, 0, nullptr, 0, cs);
+        const int nb = launch_maxabs_part<T>((const C*)P.v1, D, part_buf(P, 7), cs);
+        launch_finalize(part_buf(P, 7), nb, sc, SL_MAXABS, FIN_MAX, 0, nullptr, 0, cs);
         double mx = 0;
         PURIFY_HIP(hipMemcpyAsync(&mx, sc + SL_MAXABS, sizeof(double), hipMemcpyDeviceToHost, cs));
         PURIFY_HIP(hipStreamSynchronize(cs));

@@ -75,7 +75,7 @@ enum Slot : int {
 };
 
 constexpr int MAX_PARTIALS = 8192;   // per partial-sum buffer
-constexpr int NUM_PARTIAL_BUFS = 4;
+constexpr int NUM_PARTIAL_BUFS = 8;
 
 // ---------------------------------------------------------------------------------------
 // Plan: host handle with device pointers into the caller's workspace.
@@ -91,6 +91,8 @@ struct Plan {
     int wav_N[MAX_WAV] = {};   // Daubechies order of each wavelet basis (dictionary order)
     int wav_block[MAX_WAV] = {};  // alpha block index of each wavelet basis
     int TT = 32, nT = 0;       // gridding tile side and tiles per axis
+    int grid_threads = 256;    // gridding workgroup size (256 or 1024)
+    int max_tile_load = 0;     // most visibilities one gridding workgroup handles
     int64_t D = 0, N = 0;
     size_t elem = 0;           // bytes per complex element
     double kb_i0beta = 0;      // I0(beta)
@@ -172,10 +174,16 @@ void launch_finalize(const double* part, int count, double* sc, int slot, int op
 template <typename T> int launch_cg_init(const cpx<T>* x1, const cpx<T>* x2, const cpx<T>* x3,
                                          const cpx<T>* q, cpx<T>* r, cpx<T>* p, int64_t n,
                                          double* part, hipStream_t s);
+// CG step with alpha = rho / <p, q> summed from partials inside the kernel
 template <typename T> int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q,
-                                       const double* sc, int64_t n, double* part, hipStream_t s);
-template <typename T> void launch_cg_p(cpx<T>* p, const cpx<T>* r, const double* sc, int64_t n,
-                                       hipStream_t s);
+                                       const double* rho_part, int rho_count, const double* pq_part,
+                                       int pq_count, int64_t n, double* part, hipStream_t s);
+// p = r + (rho_new / rho) p, both from partials
+template <typename T> void launch_cg_p(cpx<T>* p, const cpx<T>* r, const double* rho_part,
+                                       const double* rhonew_part, int count, int64_t n, hipStream_t s);
+// power-iteration normalisation v = w / ||w|| (||w||^2 from partials), sc[LAMBDA] = ||w||
+template <typename T> void launch_power_normalise(cpx<T>* v, const cpx<T>* w, const double* part,
+                                                  int count, double* sc, int64_t n, hipStream_t s);
 template <typename T> int launch_prox_l1(cpx<T>* v1, cpx<T>* z1, const double* w, double gamma,
                                          int64_t n, double* part, hipStream_t s);
 template <typename T> void launch_prox_pos(const cpx<T>* xh, cpx<T>* z2, cpx<T>* x2, int64_t n,
@@ -183,8 +191,9 @@ template <typename T> void launch_prox_pos(const cpx<T>* xh, cpx<T>* z2, cpx<T>*
 template <typename T> int launch_ball_part(const cpx<T>* v3, const cpx<T>* z3, const cpx<T>* yt,
                                            int64_t n, double* part_d, double* part_res,
                                            hipStream_t s);
-template <typename T> void launch_prox_ball(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const double* sc,
-                                            int64_t n, hipStream_t s);
+template <typename T> void launch_prox_ball(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const double* part_d,
+                                            const double* part_res, int count, double eps, double* sc,
+                                            double* hist, int hist_cap, int64_t n, hipStream_t s);
 template <typename T> void launch_permute_scale(const cpx<T>* y_user, const int32_t* perm, double scale,
                                                 cpx<T>* y_sorted, int64_t n, hipStream_t s);
 template <typename T> void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc,

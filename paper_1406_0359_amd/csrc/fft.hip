@@ -1,236 +1,376 @@
 // F and F^dagger of the measurement operator Phi = G F Z S (NUFFT, Section 4), fused with
 // S (deapodisation) and Z (zero padding / cropping).
 //
-// One axis of F Z acting on n pixels p = j - n/2 and producing K = 2n frequencies is
+// One axis of F Z maps n pixels p = j - n/2 to K = 2n frequencies:
 //     (D v)[k] = sum_j v_j exp(-2 pi i k (j - n/2) / K).
 // Splitting the output by parity, k = 2k' + r (r = 0, 1):
 //     (D v)[2k' + r] = (-1)^k' i^r FFT_n( v_j exp(-pi i r j / n) )[k'],
-// so each line costs two n-point FFTs and the n zero rows of the padded grid are never
-// read.  The adjoint (K -> n) splits the input by parity instead:
+// so each line costs two n-point FFTs and the zero half of the padded line is never
+// touched.  The adjoint (K -> n) splits the input by parity instead:
 //     (D^dag u)[j] = IFFT_n((-1)^k' u_2k')[j] + (-i) exp(pi i j / n) IFFT_n((-1)^k' u_2k'+1)[j].
 //
-// Passes (image x is n x n row-major, the grid is K x K stored [k2][k1]):
-//   rows_fwd : x rows  --(S, D along axis 1)-->  tmp[k2][j1]    (K x n)
-//   cols_fwd : tmp rows --(D along axis 0)-->    grid[k2][k1]   (K x K)
-//   cols_adj : grid rows --(D^dag along k1)-->   tmp[k2][j1]
-//   rows_adj : tmp columns --(D^dag along k2, S)--> x rows (+ fused CG epilogue)
-// Every transform is a self-sorting Stockham FFT (radix 4, one radix-2 pass when log2 n is
-// odd) on lines held in LDS; twiddles come from an FP64-accurate table.
+// Layouts (row-major): image x[j1][j2] (n x n), intermediate tmp[j1][k2] (n x K), grid
+// G[k1][k2] (K x K).  Passes:
+//   rows_fwd : each image row j1      -> tmp row j1     (S, D along axis 1)
+//   cols_fwd : each tmp column k2     -> G column k2    (D along axis 0)
+//   cols_adj : each G column k2       -> tmp column k2  (D^dag along axis 0)
+//   rows_adj : each tmp row j1        -> image row j1   (D^dag along axis 1, S, epilogue)
+// Row passes read and write whole rows; column passes handle C adjacent columns per
+// workgroup so every global access is a contiguous run of C elements.
+//
+// Each n-point transform is a self-sorting (Stockham) FFT with large radices (8..32) held in
+// registers: one thread owns n/RMAX butterflies of each pass, runs the radix-R DFT in
+// registers (unrolled, compile-time roots of unity), and passes exchange data through one
+// LDS line buffer.  n = 1024 is two radix-32 passes: a single LDS round trip.  Inter-pass
+// twiddles come from an FP64-accurate table staged in LDS.
 #include "common.h"
 
 namespace purify {
 
 namespace {
 
-constexpr int LDS_PAD = 1;   // one complex of padding per LDS line (transposed accesses)
+// ---------------------------------------------------------------------------------------
+// Compile-time roots of unity: cos and sin of 2 pi k / L, by octant reduction and Taylor
+// series of the reduced angle (|phi| < pi/4).
+struct CS {
+    double c, s;
+};
+constexpr double taylor_sin(double x) {
+    double term = x, sum = x;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double taylor_cos(double x) {
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        sum += term;
+    }
+    return sum;
+}
+constexpr CS root(int k, int L) {
+    // angle = 2 pi k / L = (pi / 4) * (8k / L); split 8k = q L + r
+    const long long num = 8LL * (k % L);
+    const int q = (int)(num / L);
+    const double frac = (double)(num % L) / (double)L;   // in [0, 1)
+    const double pi4 = 0.78539816339744830961566084581987572;
+    // angle = q pi/4 + phi, phi = frac pi/4; use the nearest octant boundary
+    double phi = frac * pi4;
+    int oct = q;
+    if (frac > 0.5) {
+        phi = (frac - 1.0) * pi4;
+        oct = q + 1;
+    }
+    const double c0 = taylor_cos(phi), s0 = taylor_sin(phi);
+    const double h = 0.70710678118654752440084436210484904;
+    double c = 0, s = 0;
+    switch (oct & 7) {
+        case 0: c = c0; s = s0; break;
+        case 1: c = h * (c0 - s0); s = h * (c0 + s0); break;
+        case 2: c = -s0; s = c0; break;
+        case 3: c = -h * (c0 + s0); s = h * (c0 - s0); break;
+        case 4: c = -c0; s = -s0; break;
+        case 5: c = h * (s0 - c0); s = -h * (c0 + s0); break;
+        case 6: c = s0; s = -c0; break;
+        default: c = h * (c0 + s0); s = h * (s0 - c0); break;
+    }
+    return CS{c, s};
+}
+template <int L>
+struct Roots {
+    CS w[L > 0 ? L : 1];
+    constexpr Roots() : w() {
+        for (int k = 0; k < L; ++k) w[k] = root(k, L);
+    }
+};
 
-template <typename T, bool INV>
-__device__ __forceinline__ cpx<T> twid(const cpx<T>* __restrict__ tw, int idx) {
-    cpx<T> w = tw[idx];
-    if (INV) w.y = -w.y;
-    return w;
+constexpr int bitrev(int i, int R) {
+    int r = 0;
+    for (int b = 1; b < R; b <<= 1) {
+        r = (r << 1) | (i & 1);
+        i >>= 1;
+    }
+    return r;
 }
 
-// In-LDS Stockham FFT of NLINES lines of N = 2^LOGN points (line stride ls), NT threads.
-// Data in natural order on entry and on exit; forward sign exp(-2 pi i), INV = conjugate.
-template <typename T, int LOGN, int NLINES, int NT, bool INV>
-__device__ __forceinline__ void lds_fft(cpx<T>* buf, int ls, const cpx<T>* __restrict__ tw, int tid) {
-    constexpr int N = 1 << LOGN;
-    constexpr int NR4 = LOGN / 2;
-    constexpr bool HAS_R2 = (LOGN & 1) != 0;
-    constexpr int Q = N / 4;
-    constexpr int BF = NLINES * Q;
-    constexpr int E = (BF + NT - 1) / NT;
+// v[st+k] <- a+b ; v[st+k+H] <- (a-b) w^k  for every radix-2 DIF stage of an R-point DFT.
+template <typename T, int R, int LEN, bool INV>
+__device__ __forceinline__ void dif_stages(cpx<T>* v) {
+    if constexpr (LEN >= 2) {
+        constexpr int H = LEN / 2;
+        constexpr Roots<LEN> tab{};
 #pragma unroll
-    for (int s = 0; s < NR4; ++s) {
-        const int Ns = 1 << (2 * s);
-        const int tws = N >> (2 * s + 2);
-        cpx<T> v[E][4];
-        int gb[E];
+        for (int st = 0; st < R; st += LEN) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int g = tid + e * NT;
-            gb[e] = g;
-            if (g < BF) {
-                const int line = g / Q, j = g % Q;
-                const cpx<T>* src = buf + line * ls + j;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[e][r] = src[r * Q];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int g = gb[e];
-            if (g < BF) {
-                const int line = g / Q, j = g % Q;
-                const int k = j & (Ns - 1);
-                if (s > 0) {
-                    v[e][1] = v[e][1] * twid<T, INV>(tw, k * tws);
-                    v[e][2] = v[e][2] * twid<T, INV>(tw, 2 * k * tws);
-                    v[e][3] = v[e][3] * twid<T, INV>(tw, 3 * k * tws);
-                }
-                const cpx<T> s02 = v[e][0] + v[e][2], d02 = v[e][0] - v[e][2];
-                const cpx<T> s13 = v[e][1] + v[e][3], d13 = v[e][1] - v[e][3];
-                cpx<T>* dst = buf + line * ls + ((j - k) << 2) + k;
-                dst[0] = s02 + s13;
-                dst[2 * Ns] = s02 - s13;
-                if (INV) {
-                    dst[Ns] = d02 + mul_i(d13);
-                    dst[3 * Ns] = d02 + mul_mi(d13);
+            for (int k = 0; k < H; ++k) {
+                const cpx<T> a = v[st + k], b = v[st + k + H];
+                v[st + k] = a + b;
+                const cpx<T> d = a - b;
+                if (k == 0) {
+                    v[st + k + H] = d;
+                } else if (4 * k == LEN) {
+                    v[st + k + H] = INV ? mul_i(d) : mul_mi(d);
                 } else {
-                    dst[Ns] = d02 + mul_mi(d13);
-                    dst[3 * Ns] = d02 + mul_i(d13);
+                    const T c = (T)tab.w[k].c;
+                    const T s = INV ? (T)tab.w[k].s : -(T)tab.w[k].s;
+                    v[st + k + H] = mk<T>(d.x * c - d.y * s, d.x * s + d.y * c);
                 }
             }
         }
-        __syncthreads();
+        dif_stages<T, R, LEN / 2, INV>(v);
     }
-    if (HAS_R2) {
-        constexpr int H = N / 2;
-        constexpr int BF2 = NLINES * H;
-        constexpr int E2 = (BF2 + NT - 1) / NT;
-        cpx<T> a[E2], b[E2];
+}
+
+// In-register R-point DFT: natural order in, natural order out (forward exp(-2 pi i),
+// INV = conjugate).
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void reg_dft(cpx<T>* v) {
+    dif_stages<T, R, R, INV>(v);
+    cpx<T> t[R];
 #pragma unroll
-        for (int e = 0; e < E2; ++e) {
-            const int g = tid + e * NT;
-            if (g < BF2) {
-                const int line = g / H, j = g % H;
-                a[e] = buf[line * ls + j];
-                b[e] = buf[line * ls + j + H];
-            }
+    for (int i = 0; i < R; ++i) t[i] = v[i];
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = t[bitrev(i, R)];
+}
+
+// ---------------------------------------------------------------------------------------
+// Radix plans: product of the radices is n; RMAX elements live in registers per thread.
+template <typename T, int LOGN>
+struct Radices;
+#define PURIFY_RADICES(TY, LG, NP_, R0, R1, R2)              \
+    template <>                                               \
+    struct Radices<TY, LG> {                                  \
+        static constexpr int NP = NP_;                        \
+        static constexpr int r[3] = {R0, R1, R2};             \
+    };
+PURIFY_RADICES(float, 4, 1, 16, 1, 1)
+PURIFY_RADICES(float, 5, 1, 32, 1, 1)
+PURIFY_RADICES(float, 6, 2, 8, 8, 1)
+PURIFY_RADICES(float, 7, 2, 16, 8, 1)
+PURIFY_RADICES(float, 8, 2, 16, 16, 1)
+PURIFY_RADICES(float, 9, 2, 32, 16, 1)
+PURIFY_RADICES(float, 10, 2, 32, 32, 1)
+PURIFY_RADICES(float, 11, 3, 32, 16, 4)
+PURIFY_RADICES(float, 12, 3, 16, 16, 16)
+PURIFY_RADICES(double, 4, 1, 16, 1, 1)
+PURIFY_RADICES(double, 5, 2, 16, 2, 1)
+PURIFY_RADICES(double, 6, 2, 8, 8, 1)
+PURIFY_RADICES(double, 7, 2, 16, 8, 1)
+PURIFY_RADICES(double, 8, 2, 16, 16, 1)
+PURIFY_RADICES(double, 9, 3, 16, 16, 2)
+PURIFY_RADICES(double, 10, 3, 16, 16, 4)
+PURIFY_RADICES(double, 11, 3, 16, 16, 8)
+PURIFY_RADICES(double, 12, 3, 16, 16, 16)
+
+template <typename T, int LOGN>
+struct Plan1D {
+    using Rd = Radices<T, LOGN>;
+    static constexpr int N = 1 << LOGN;
+    static constexpr int NP = Rd::NP;
+    static constexpr int R0 = Rd::r[0];
+    static constexpr int RL = Rd::r[NP - 1];
+    static constexpr int RMAX = (Rd::r[0] > Rd::r[1] ? (Rd::r[0] > Rd::r[2] ? Rd::r[0] : Rd::r[2])
+                                                      : (Rd::r[1] > Rd::r[2] ? Rd::r[1] : Rd::r[2]));
+    static constexpr int TL = N / RMAX;          // threads per line
+    static constexpr int LS = N + 1;             // LDS line stride (padding)
+    // register slot i on entry holds position in_pos(tl, i); on exit out_pos(tl, i)
+    __device__ static __forceinline__ int in_pos(int tl, int i) {
+        return tl + (i / R0) * TL + (i % R0) * (N / R0);
+    }
+    __device__ static __forceinline__ int out_pos(int tl, int i) {
+        return tl + (i / RL) * TL + (i % RL) * (N / RL);
+    }
+};
+
+template <typename T, int LOGN, int P, bool INV>
+__device__ __forceinline__ void fft_pass(cpx<T>* v, cpx<T>* line, int tl, const cpx<T>* W) {
+    using PL = Plan1D<T, LOGN>;
+    using Rd = Radices<T, LOGN>;
+    constexpr int N = PL::N;
+    constexpr int R = Rd::r[P];
+    constexpr int NB = PL::RMAX / R;   // butterflies per thread in this pass
+    constexpr int NS = P == 0 ? 1 : (P == 1 ? Rd::r[0] : Rd::r[0] * Rd::r[1]);
+    if constexpr (P > 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = tl + b * PL::TL;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b * R + r] = line[j + r * (N / R)];
         }
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < E2; ++e) {
-            const int g = tid + e * NT;
-            if (g < BF2) {
-                const int line = g / H, j = g % H;
-                const cpx<T> bt = b[e] * twid<T, INV>(tw, j);
-                buf[line * ls + j] = a[e] + bt;
-                buf[line * ls + j + H] = a[e] - bt;
+        for (int b = 0; b < NB; ++b) {
+            const int j = tl + b * PL::TL;
+            const int k = j % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cpx<T> w = W[r * k * (N / (NS * R))];
+                if (INV) w.y = -w.y;
+                v[b * R + r] = v[b * R + r] * w;
             }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) reg_dft<T, R, INV>(v + b * R);
+    if constexpr (P < Rd::NP - 1) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = tl + b * PL::TL;
+            const int k = j % NS;
+            const int o = (j - k) * R + k;
+#pragma unroll
+            for (int t = 0; t < R; ++t) line[o + t * NS] = v[b * R + t];
         }
         __syncthreads();
     }
 }
 
-// Rows (image lines) per workgroup for the row passes, and columns per workgroup for the
-// column passes.  Two LDS lines (parities) per image line.
+// Run every pass on this thread's registers; `line` is this line's LDS buffer.
+template <typename T, int LOGN, bool INV>
+__device__ __forceinline__ void line_fft(cpx<T>* v, cpx<T>* line, int tl, const cpx<T>* W) {
+    using Rd = Radices<T, LOGN>;
+    fft_pass<T, LOGN, 0, INV>(v, line, tl, W);
+    if constexpr (Rd::NP > 1) fft_pass<T, LOGN, 1, INV>(v, line, tl, W);
+    if constexpr (Rd::NP > 2) fft_pass<T, LOGN, 2, INV>(v, line, tl, W);
+}
+
 template <typename T>
-constexpr int rows_per_wg(int logn) {
-    const int N = 1 << logn;
-    const int es = 2 * sizeof(T);
-    int b_lds = 65536 / (2 * N * es);
-    int b_occ = N / 256;
-    int b = b_lds < b_occ ? b_lds : b_occ;
-    if (b < 1) b = 1;
-    int b_min = 128 / N;       // keep at least one wavefront of butterflies
-    if (b < b_min) b = b_min;
-    return b;
+__device__ __forceinline__ cpx<T> neg(cpx<T> a) { return mk<T>(-a.x, -a.y); }
+
+// Row passes: 64-thread workgroups (more rows per workgroup only when a row has fewer
+// threads).  Column passes: C adjacent columns (64-byte runs) as long as the LDS lines and
+// the twiddle table fit in 160 KB.
+template <typename T, int LOGN>
+constexpr int rows_per_wg() {
+    constexpr int tl = Plan1D<T, LOGN>::TL;
+    return tl >= 64 ? 1 : 64 / tl;
 }
-constexpr int cols_per_wg(int logn) {
-    const int N = 1 << logn;
-    int c = 128 / N;
-    return c < 1 ? 1 : c;
-}
-constexpr int threads_for(int lines, int logn) {
-    int bf = lines * (1 << logn) / 4;
-    return bf < 64 ? 64 : (bf > 256 ? 256 : bf);
+template <typename T, int LOGN>
+constexpr int cols_per_wg() {
+    constexpr int want = sizeof(T) == 4 ? 8 : 4;
+    constexpr int N = 1 << LOGN;
+    constexpr int budget = 160 * 1024 / (int)(2 * sizeof(T));
+    int c = want;
+    while (c > 1 && N + c * (N + 1) > budget) c >>= 1;
+    return c;
 }
 
+template <typename T, int LOGN>
+__device__ __forceinline__ void stage_twiddles(cpx<T>* Wl, const cpx<T>* __restrict__ tw, int nthreads) {
+    for (int i = threadIdx.x; i < (1 << LOGN); i += nthreads) Wl[i] = tw[i];
+}
+
+// ---------------------------------------------------------------------------------------
 template <typename T, int LOGN, int B>
-__global__ void __launch_bounds__(threads_for(2 * B, LOGN))
+__global__ void __launch_bounds__((B * Plan1D<T, LOGN>::TL))
 k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __restrict__ deap,
                const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2) {
-    constexpr int N = 1 << LOGN;
-    constexpr int NT = threads_for(2 * B, LOGN);
-    constexpr int LS = N + LDS_PAD;
+    using PL = Plan1D<T, LOGN>;
+    constexpr int N = PL::N, K = 2 * N, NT = B * PL::TL;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-    const int tid = threadIdx.x;
-    const int row0 = blockIdx.x * B;
-    for (int idx = tid; idx < B * N; idx += NT) {
-        const int b = idx / N, j = idx % N;
-        const T s = deap[row0 + b] * deap[j];
-        const cpx<T> v = s * x[(size_t)(row0 + b) * N + j];
-        buf[(2 * b) * LS + j] = v;
-        buf[(2 * b + 1) * LS + j] = v * tw2[j];
-    }
+    cpx<T>* Wl = reinterpret_cast<cpx<T>*>(smem_raw);
+    stage_twiddles<T, LOGN>(Wl, tw, NT);
+    const int lr = threadIdx.x / PL::TL, tl = threadIdx.x % PL::TL;
+    cpx<T>* line = Wl + N + lr * PL::LS;
+    const int row = blockIdx.x * B + lr;
+    const T srow = deap[row];
+    const cpx<T>* xr = x + (size_t)row * N;
+    cpx<T>* outr = tmp + (size_t)row * K;
     __syncthreads();
-    lds_fft<T, LOGN, 2 * B, NT, false>(buf, LS, tw, tid);
-    for (int idx = tid; idx < 2 * N * B; idx += NT) {
-        const int b = idx % B, k2 = idx / B;
-        const int r = k2 & 1, kp = k2 >> 1;
-        cpx<T> v = buf[(2 * b + r) * LS + kp];
-        if (kp & 1) v = mk<T>(-v.x, -v.y);
-        if (r) v = mul_i(v);
-        tmp[(size_t)k2 * N + row0 + b] = v;
+    cpx<T> v[PL::RMAX];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int p = PL::in_pos(tl, i);
+            cpx<T> a = (srow * deap[p]) * xr[p];
+            if (r) a = a * tw2[p];
+            v[i] = a;
+        }
+        line_fft<T, LOGN, false>(v, line, tl, Wl);
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int kp = PL::out_pos(tl, i);
+            cpx<T> o = (kp & 1) ? neg(v[i]) : v[i];
+            if (r) o = mul_i(o);
+            outr[2 * kp + r] = o;
+        }
     }
 }
 
 template <typename T, int LOGN, int C>
-__global__ void __launch_bounds__(threads_for(2 * C, LOGN))
-k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid,
-               const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2) {
-    constexpr int N = 1 << LOGN;
-    constexpr int K = 2 * N;
-    constexpr int NT = threads_for(2 * C, LOGN);
-    constexpr int LS = N + LDS_PAD;
+__global__ void __launch_bounds__((C * Plan1D<T, LOGN>::TL))
+k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const cpx<T>* __restrict__ tw,
+               const cpx<T>* __restrict__ tw2) {
+    using PL = Plan1D<T, LOGN>;
+    constexpr int N = PL::N, K = 2 * N, NT = C * PL::TL;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-    const int tid = threadIdx.x;
-    const int col0 = blockIdx.x * C;
-    for (int idx = tid; idx < C * N; idx += NT) {
-        const int c = idx / N, j = idx % N;
-        const cpx<T> v = tmp[(size_t)(col0 + c) * N + j];
-        buf[(2 * c) * LS + j] = v;
-        buf[(2 * c + 1) * LS + j] = v * tw2[j];
-    }
+    cpx<T>* Wl = reinterpret_cast<cpx<T>*>(smem_raw);
+    stage_twiddles<T, LOGN>(Wl, tw, NT);
+    const int c = threadIdx.x % C, tl = threadIdx.x / C;
+    cpx<T>* line = Wl + N + c * PL::LS;
+    const int col = blockIdx.x * C + c;
     __syncthreads();
-    lds_fft<T, LOGN, 2 * C, NT, false>(buf, LS, tw, tid);
-    for (int idx = tid; idx < C * K; idx += NT) {
-        const int c = idx / K, k1 = idx % K;
-        const int r = k1 & 1, kp = k1 >> 1;
-        cpx<T> v = buf[(2 * c + r) * LS + kp];
-        if (kp & 1) v = mk<T>(-v.x, -v.y);
-        if (r) v = mul_i(v);
-        grid[(size_t)(col0 + c) * K + k1] = v;
+    cpx<T> v[PL::RMAX];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int p = PL::in_pos(tl, i);
+            cpx<T> a = tmp[(size_t)p * K + col];
+            if (r) a = a * tw2[p];
+            v[i] = a;
+        }
+        line_fft<T, LOGN, false>(v, line, tl, Wl);
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int kp = PL::out_pos(tl, i);
+            cpx<T> o = (kp & 1) ? neg(v[i]) : v[i];
+            if (r) o = mul_i(o);
+            grid[(size_t)(2 * kp + r) * K + col] = o;
+        }
     }
 }
 
 template <typename T, int LOGN, int C>
-__global__ void __launch_bounds__(threads_for(2 * C, LOGN))
-k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp,
-               const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2) {
-    constexpr int N = 1 << LOGN;
-    constexpr int K = 2 * N;
-    constexpr int NT = threads_for(2 * C, LOGN);
-    constexpr int LS = N + LDS_PAD;
+__global__ void __launch_bounds__((C * Plan1D<T, LOGN>::TL))
+k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const cpx<T>* __restrict__ tw,
+               const cpx<T>* __restrict__ tw2) {
+    using PL = Plan1D<T, LOGN>;
+    constexpr int N = PL::N, K = 2 * N, NT = C * PL::TL;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-    const int tid = threadIdx.x;
-    const int col0 = blockIdx.x * C;
-    for (int idx = tid; idx < C * K; idx += NT) {
-        const int c = idx / K, k1 = idx % K;
-        const int r = k1 & 1, kp = k1 >> 1;
-        cpx<T> v = grid[(size_t)(col0 + c) * K + k1];
-        if (kp & 1) v = mk<T>(-v.x, -v.y);
-        buf[(2 * c + r) * LS + kp] = v;
-    }
+    cpx<T>* Wl = reinterpret_cast<cpx<T>*>(smem_raw);
+    stage_twiddles<T, LOGN>(Wl, tw, NT);
+    const int c = threadIdx.x % C, tl = threadIdx.x / C;
+    cpx<T>* line = Wl + N + c * PL::LS;
+    const int col = blockIdx.x * C + c;
     __syncthreads();
-    lds_fft<T, LOGN, 2 * C, NT, true>(buf, LS, tw, tid);
-    for (int idx = tid; idx < C * N; idx += NT) {
-        const int c = idx / N, j = idx % N;
-        const cpx<T> a = buf[(2 * c) * LS + j];
-        const cpx<T> b = buf[(2 * c + 1) * LS + j];
-        // a + (-i) exp(pi i j / n) b,  exp(pi i j/n) = conj(tw2[j])
-        const cpx<T> t = mulc(b, tw2[j]);
-        tmp[(size_t)(col0 + c) * N + j] = a + mul_mi(t);
+    cpx<T> v[PL::RMAX], a0[PL::RMAX];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int kp = PL::in_pos(tl, i);
+            const cpx<T> u = grid[(size_t)(2 * kp + r) * K + col];
+            v[i] = (kp & 1) ? neg(u) : u;
+        }
+        line_fft<T, LOGN, true>(v, line, tl, Wl);
+        if (r == 0) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) a0[i] = v[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int j = PL::out_pos(tl, i);
+        tmp[(size_t)j * K + col] = a0[i] + mul_mi(mulc(v[i], tw2[j]));
     }
 }
 
-__device__ __forceinline__ double block_sum_256(double v, double* red) {
+__device__ __forceinline__ double block_sum_dyn(double v, double* red) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -245,63 +385,76 @@ __device__ __forceinline__ double block_sum_256(double v, double* red) {
 }
 
 template <typename T, int LOGN, int B>
-__global__ void __launch_bounds__(threads_for(2 * B, LOGN))
+__global__ void __launch_bounds__((B * Plan1D<T, LOGN>::TL))
 k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* __restrict__ deap,
                const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2, T c1,
-               const cpx<T>* __restrict__ v, T c2, double* __restrict__ dot_part) {
-    constexpr int N = 1 << LOGN;
-    constexpr int K = 2 * N;
-    constexpr int NT = threads_for(2 * B, LOGN);
-    constexpr int LS = N + LDS_PAD;
+               const cpx<T>* __restrict__ vin, T c2, double* __restrict__ dot_part) {
+    using PL = Plan1D<T, LOGN>;
+    constexpr int N = PL::N, K = 2 * N, NT = B * PL::TL;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[8];
-    const int tid = threadIdx.x;
-    const int row0 = blockIdx.x * B;
-    for (int idx = tid; idx < B * K; idx += NT) {
-        const int b = idx % B, k2 = idx / B;
-        const int r = k2 & 1, kp = k2 >> 1;
-        cpx<T> u = tmp[(size_t)k2 * N + row0 + b];
-        if (kp & 1) u = mk<T>(-u.x, -u.y);
-        buf[(2 * b + r) * LS + kp] = u;
-    }
+    cpx<T>* Wl = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[16];
+    stage_twiddles<T, LOGN>(Wl, tw, NT);
+    const int lr = threadIdx.x / PL::TL, tl = threadIdx.x % PL::TL;
+    cpx<T>* line = Wl + N + lr * PL::LS;
+    const int row = blockIdx.x * B + lr;
+    const cpx<T>* inr = tmp + (size_t)row * K;
     __syncthreads();
-    lds_fft<T, LOGN, 2 * B, NT, true>(buf, LS, tw, tid);
+    cpx<T> v[PL::RMAX], a0[PL::RMAX];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int kp = PL::in_pos(tl, i);
+            const cpx<T> u = inr[2 * kp + r];
+            v[i] = (kp & 1) ? neg(u) : u;
+        }
+        line_fft<T, LOGN, true>(v, line, tl, Wl);
+        if (r == 0) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) a0[i] = v[i];
+        }
+    }
+    const T srow = c1 * deap[row];
     double acc = 0.0;
-    for (int idx = tid; idx < B * N; idx += NT) {
-        const int b = idx / N, j = idx % N;
-        const cpx<T> a = buf[(2 * b) * LS + j];
-        const cpx<T> bb = buf[(2 * b + 1) * LS + j];
-        const cpx<T> t = a + mul_mi(mulc(bb, tw2[j]));
-        const T s = c1 * deap[row0 + b] * deap[j];
-        cpx<T> o = s * t;
-        const size_t off = (size_t)(row0 + b) * N + j;
-        if (v) {
-            const cpx<T> vv = v[off];
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int j = PL::out_pos(tl, i);
+        const cpx<T> t = a0[i] + mul_mi(mulc(v[i], tw2[j]));
+        cpx<T> o = (srow * deap[j]) * t;
+        const size_t off = (size_t)row * N + j;
+        if (vin) {
+            const cpx<T> vv = vin[off];
             o = o + c2 * vv;
-            if (dot_part) acc += (double)vv.x * (double)o.x + (double)vv.y * (double)o.y;
+            acc += (double)vv.x * (double)o.x + (double)vv.y * (double)o.y;
         }
         x[off] = o;
     }
     if (dot_part) {
-        const double tot = block_sum_256(acc, red);
-        if (tid == 0) dot_part[blockIdx.x] = tot;
+        const double tot = block_sum_dyn(acc, red);
+        if (threadIdx.x == 0) dot_part[blockIdx.x] = tot;
     }
 }
 
 template <typename F>
 void set_lds_limit(F* f, size_t bytes) {
-    if (bytes > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(f),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)bytes);
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(f),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T, int LOGN>
+size_t lds_bytes(int lines) {
+    using PL = Plan1D<T, LOGN>;
+    return (size_t)(PL::N + lines * PL::LS) * sizeof(cpx<T>);
 }
 
 template <typename T, int LOGN>
 void rows_fwd_impl(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s) {
-    constexpr int B = rows_per_wg<T>(LOGN);
-    constexpr int NT = threads_for(2 * B, LOGN);
+    constexpr int B = rows_per_wg<T, LOGN>();
+    constexpr int NT = B * Plan1D<T, LOGN>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = (size_t)2 * B * (N + LDS_PAD) * sizeof(cpx<T>);
+    const size_t lds = lds_bytes<T, LOGN>(B);
     auto f = k_fft_rows_fwd<T, LOGN, B>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, x, tmp, (const T*)P.deap,
@@ -309,10 +462,10 @@ void rows_fwd_impl(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s) {
 }
 template <typename T, int LOGN>
 void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
-    constexpr int C = cols_per_wg(LOGN);
-    constexpr int NT = threads_for(2 * C, LOGN);
+    constexpr int C = cols_per_wg<T, LOGN>();
+    constexpr int NT = C * Plan1D<T, LOGN>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = (size_t)2 * C * (N + LDS_PAD) * sizeof(cpx<T>);
+    const size_t lds = lds_bytes<T, LOGN>(C);
     auto f = k_fft_cols_fwd<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, tmp, grid, (const cpx<T>*)P.tw,
@@ -320,10 +473,10 @@ void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s
 }
 template <typename T, int LOGN>
 void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s) {
-    constexpr int C = cols_per_wg(LOGN);
-    constexpr int NT = threads_for(2 * C, LOGN);
+    constexpr int C = cols_per_wg<T, LOGN>();
+    constexpr int NT = C * Plan1D<T, LOGN>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = (size_t)2 * C * (N + LDS_PAD) * sizeof(cpx<T>);
+    const size_t lds = lds_bytes<T, LOGN>(C);
     auto f = k_fft_cols_adj<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, grid, tmp, (const cpx<T>*)P.tw,
@@ -332,10 +485,10 @@ void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s
 template <typename T, int LOGN>
 void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* v,
                    double c2, double* dot_part, hipStream_t s) {
-    constexpr int B = rows_per_wg<T>(LOGN);
-    constexpr int NT = threads_for(2 * B, LOGN);
+    constexpr int B = rows_per_wg<T, LOGN>();
+    constexpr int NT = B * Plan1D<T, LOGN>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = (size_t)2 * B * (N + LDS_PAD) * sizeof(cpx<T>);
+    const size_t lds = lds_bytes<T, LOGN>(B);
     auto f = k_fft_rows_adj<T, LOGN, B>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, tmp, x, (const T*)P.deap,
@@ -348,8 +501,8 @@ int ilog2(int n) {
     return l;
 }
 
-#define PURIFY_LOGN_DISPATCH(LOGN_VAR, CALL)          \
-    switch (LOGN_VAR) {                               \
+#define PURIFY_LOGN_DISPATCH(LOGN_VAR, CALL)            \
+    switch (LOGN_VAR) {                                 \
         case 4: { constexpr int L_ = 4; CALL; } break;  \
         case 5: { constexpr int L_ = 5; CALL; } break;  \
         case 6: { constexpr int L_ = 6; CALL; } break;  \
@@ -359,7 +512,7 @@ int ilog2(int n) {
         case 10: { constexpr int L_ = 10; CALL; } break; \
         case 11: { constexpr int L_ = 11; CALL; } break; \
         case 12: { constexpr int L_ = 12; CALL; } break; \
-        default: break;                               \
+        default: break;                                 \
     }
 
 }  // namespace
@@ -384,7 +537,7 @@ void launch_fft_rows_adj(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1,
 template <typename T>
 int fft_rows_adj_blocks(const Plan& P) {
     int r = 0;
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (r = (1 << L_) / rows_per_wg<T>(L_)));
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (r = (1 << L_) / rows_per_wg<T, L_>()));
     return r;
 }
 

@@ -19,21 +19,18 @@ namespace purify {
 
 namespace {
 
-constexpr int GRID_THREADS = 256;
 
 // Runtime-J variant of kb_weights (J <= 16), for the less common kernel widths.
 template <typename T>
-__device__ __forceinline__ void kb_weights_any(const T* __restrict__ c, T f, T* w, int J) {
+__device__ __noinline__ void kb_weights_any(const T* __restrict__ c, T f, T* w, int J) {
     constexpr int NC = KBDeg<T>::value + 1;
     const T x = f - (T)0.5;
+#pragma unroll 1
+    for (int a = 0; a < J; ++a) {
+        T acc = c[a * NC + NC - 1];
 #pragma unroll
-    for (int a = 0; a < KB_MAX_J; ++a)
-        if (a < J) w[a] = c[a * NC + NC - 1];
-#pragma unroll
-    for (int k = NC - 2; k >= 0; --k) {
-#pragma unroll
-        for (int a = 0; a < KB_MAX_J; ++a)
-            if (a < J) w[a] = w[a] * x + c[a * NC + k];
+        for (int k = NC - 2; k >= 0; --k) acc = acc * x + c[a * NC + k];
+        w[a] = acc;
     }
 }
 
@@ -43,13 +40,15 @@ __device__ __forceinline__ void tap_weights(const T* __restrict__ c, T f, T* w, 
     else kb_weights_any<T>(c, f, w, Jr);
 }
 
-// G: one thread per visibility (tile-sorted order), J x J gather.  J = 0: runtime Jr.
+// G: one thread per visibility (tile-sorted order), J x J gather from the row-major grid
+// G[k1][k2].  J = 0: runtime Jr.
 template <typename T, int J>
 __global__ void __launch_bounds__(256)
 k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
          const int32_t* __restrict__ base, const T* __restrict__ frac, const T* __restrict__ kbc,
          int M, int K, T scale, int Jr) {
     constexpr int JJ = J > 0 ? J : KB_MAX_J;
+    constexpr int UNR = J > 0 ? J : 1;   // generic width: plain loops
     const int Jn = J > 0 ? J : Jr;
     const int m = blockIdx.x * 256 + threadIdx.x;
     if (m >= M) return;
@@ -61,20 +60,20 @@ k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t*
     tap_weights<T, J>(kbc, f.y, wb, Jr);
     const int mask = K - 1;
     T ax = 0, ay = 0;
-#pragma unroll
-    for (int bb = 0; bb < JJ; ++bb) {
-        if (bb >= Jn) break;
-        const cpx<T>* row = grid + (size_t)((k2 + bb) & mask) * K;
+#pragma unroll UNR
+    for (int a = 0; a < JJ; ++a) {
+        if (a >= Jn) break;
+        const cpx<T>* row = grid + (size_t)((k1 + a) & mask) * K;
         T rx = 0, ry = 0;
-#pragma unroll
-        for (int a = 0; a < JJ; ++a) {
-            if (a >= Jn) break;
-            const cpx<T> g = row[(k1 + a) & mask];
-            rx += wa[a] * g.x;
-            ry += wa[a] * g.y;
+#pragma unroll UNR
+        for (int bb = 0; bb < JJ; ++bb) {
+            if (bb >= Jn) break;
+            const cpx<T> g = row[(k2 + bb) & mask];
+            rx += wb[bb] * g.x;
+            ry += wb[bb] * g.y;
         }
-        ax += wb[bb] * rx;
-        ay += wb[bb] * ry;
+        ax += wa[a] * rx;
+        ay += wa[a] * ry;
     }
     y[perm ? perm[m] : m] = mk<T>(scale * ax, scale * ay);
 }
@@ -104,7 +103,7 @@ __device__ __forceinline__ void lds_add(typename FixedAcc<T>::I* p, typename Fix
 }
 
 // Contributions of visibilities [start, end) that land in this tile's body (bounds-checked).
-template <typename T, int J, int TT>
+template <typename T, int J, int TT, int GRID_THREADS>
 __device__ __forceinline__ void grid_range(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
                                            const int32_t* __restrict__ base, const T* __restrict__ frac,
                                            const T* __restrict__ kbc, int start, int end, int K,
@@ -112,6 +111,7 @@ __device__ __forceinline__ void grid_range(const cpx<T>* __restrict__ y, const i
                                            typename FixedAcc<T>::I* acc) {
     using Acc = FixedAcc<T>;
     constexpr int JJ = J > 0 ? J : KB_MAX_J;
+    constexpr int UNR = J > 0 ? J : 1;   // generic width: plain loops
     const int mask = K - 1;
     const int Jn = J > 0 ? J : Jr;
     for (int idx = start + (int)threadIdx.x; idx < end; idx += GRID_THREADS) {
@@ -122,20 +122,20 @@ __device__ __forceinline__ void grid_range(const cpx<T>* __restrict__ y, const i
         T wa[JJ], wb[JJ];
         tap_weights<T, J>(kbc, f.x, wa, Jr);
         tap_weights<T, J>(kbc, f.y, wb, Jr);
-#pragma unroll
-        for (int bb = 0; bb < JJ; ++bb) {
-            if (bb >= Jn) break;
-            const int c2 = ((k2 + bb) & mask) - t2o;
-            if ((unsigned)c2 >= (unsigned)TT) continue;
-            const T s = wb[bb] * inv_q;
+#pragma unroll UNR
+        for (int a = 0; a < JJ; ++a) {
+            if (a >= Jn) break;
+            const int c1 = ((k1 + a) & mask) - t1o;
+            if ((unsigned)c1 >= (unsigned)TT) continue;
+            const T s = wa[a] * inv_q;
             const T vx = s * v.x, vy = s * v.y;
-#pragma unroll
-            for (int a = 0; a < JJ; ++a) {
-                if (a >= Jn) break;
-                const int c1 = ((k1 + a) & mask) - t1o;
-                if ((unsigned)c1 < (unsigned)TT) {
-                    lds_add<T>(&acc[2 * (c2 * TT + c1)], Acc::conv(wa[a] * vx));
-                    lds_add<T>(&acc[2 * (c2 * TT + c1) + 1], Acc::conv(wa[a] * vy));
+#pragma unroll UNR
+            for (int bb = 0; bb < JJ; ++bb) {
+                if (bb >= Jn) break;
+                const int c2 = ((k2 + bb) & mask) - t2o;
+                if ((unsigned)c2 < (unsigned)TT) {
+                    lds_add<T>(&acc[2 * (c1 * TT + c2)], Acc::conv(wb[bb] * vx));
+                    lds_add<T>(&acc[2 * (c1 * TT + c2) + 1], Acc::conv(wb[bb] * vy));
                 }
             }
         }
@@ -144,7 +144,7 @@ __device__ __forceinline__ void grid_range(const cpx<T>* __restrict__ y, const i
 
 // Own visibilities whose footprint lies inside the tile (spill class 0): no bounds checks;
 // tap (a, bb) is at a fixed offset from the first tap's cell.
-template <typename T, int J, int TT>
+template <typename T, int J, int TT, int GRID_THREADS>
 __device__ __forceinline__ void grid_interior(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
                                               const int32_t* __restrict__ base, const T* __restrict__ frac,
                                               const T* __restrict__ kbc, int start, int end, int t1o,
@@ -158,15 +158,15 @@ __device__ __forceinline__ void grid_interior(const cpx<T>* __restrict__ y, cons
         T wa[J], wb[J];
         kb_weights<T, J>(kbc, f.x, wa);
         kb_weights<T, J>(kbc, f.y, wb);
-        typename Acc::I* p = acc + 2 * (c2 * TT + c1);
+        typename Acc::I* p = acc + 2 * (c1 * TT + c2);
 #pragma unroll
-        for (int bb = 0; bb < J; ++bb) {
-            const T s = wb[bb] * inv_q;
+        for (int a = 0; a < J; ++a) {
+            const T s = wa[a] * inv_q;
             const T vx = s * v.x, vy = s * v.y;
 #pragma unroll
-            for (int a = 0; a < J; ++a) {
-                lds_add<T>(p + 2 * (bb * TT + a), Acc::conv(wa[a] * vx));
-                lds_add<T>(p + 2 * (bb * TT + a) + 1, Acc::conv(wa[a] * vy));
+            for (int bb = 0; bb < J; ++bb) {
+                lds_add<T>(p + 2 * (a * TT + bb), Acc::conv(wb[bb] * vx));
+                lds_add<T>(p + 2 * (a * TT + bb) + 1, Acc::conv(wb[bb] * vy));
             }
         }
     }
@@ -180,7 +180,7 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // G^T: one workgroup per TT x TT tile; own visibilities plus the three neighbours' spill
 // ranges; fixed-point LDS accumulation; one write of the tile.
-template <typename T, int J, int TT>
+template <typename T, int J, int TT, int GRID_THREADS>
 __global__ void __launch_bounds__(GRID_THREADS)
 k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int32_t* __restrict__ base,
        const T* __restrict__ frac, const T* __restrict__ kbc, const int32_t* __restrict__ off,
@@ -221,30 +221,30 @@ k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int
     const T inv_q = (T)ldexp(1.0, -e);
     const T q = (T)ldexp(1.0, e);
     if (bound > 0.0) {
-        if constexpr (J > 0) grid_interior<T, J, TT>(y, perm, base, frac, kbc, s0, s1, t1o, t2o, inv_q, acc);
-        else grid_range<T, J, TT>(y, perm, base, frac, kbc, s0, s1, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT>(y, perm, base, frac, kbc, s1, s4, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT>(y, perm, base, frac, kbc, ls, le, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT>(y, perm, base, frac, kbc, us, ue, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT>(y, perm, base, frac, kbc, ds, de, K, t1o, t2o, Jr, inv_q, acc);
+        if constexpr (J > 0) grid_interior<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, s0, s1, t1o, t2o, inv_q, acc);
+        else grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, s0, s1, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, s1, s4, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, ls, le, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, us, ue, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, ds, de, K, t1o, t2o, Jr, inv_q, acc);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < TT * TT; i += GRID_THREADS) {
         const int r = i / TT, c = i % TT;
-        grid[(size_t)(t2o + r) * K + t1o + c] = mk<T>(q * (T)acc[2 * i], q * (T)acc[2 * i + 1]);
+        grid[(size_t)(t1o + r) * K + t2o + c] = mk<T>(q * (T)acc[2 * i], q * (T)acc[2 * i + 1]);
     }
 }
 
-template <typename T, int TT>
+template <typename T, int TT, int NT>
 void grid_tt(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* grid, hipStream_t s) {
-    const dim3 g(P.nT * P.nT), b(GRID_THREADS);
+    const dim3 g(P.nT * P.nT), b(NT);
     const T* fr = (const T*)P.frac;
     const T* kbc = (const T*)P.kbpoly;
     switch (P.J) {
-        case 4: hipLaunchKernelGGL((k_grid<T, 4, TT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 4); break;
-        case 6: hipLaunchKernelGGL((k_grid<T, 6, TT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 6); break;
-        case 8: hipLaunchKernelGGL((k_grid<T, 8, TT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 8); break;
-        default: hipLaunchKernelGGL((k_grid<T, 0, TT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, P.J); break;
+        case 4: hipLaunchKernelGGL((k_grid<T, 4, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 4); break;
+        case 6: hipLaunchKernelGGL((k_grid<T, 6, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 6); break;
+        case 8: hipLaunchKernelGGL((k_grid<T, 8, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 8); break;
+        default: hipLaunchKernelGGL((k_grid<T, 0, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, P.J); break;
     }
 }
 
@@ -265,10 +265,17 @@ void launch_degrid(const Plan& P, const cpx<T>* grid, cpx<T>* y, const int32_t* 
     }
 }
 
+// Tiles whose visibility lists (own plus spill-ins) exceed 256 get 1024-thread workgroups,
+// so even the heaviest tile takes only a few rounds.
 template <typename T>
 void launch_grid(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* grid, hipStream_t s) {
-    if (P.TT == 16) grid_tt<T, 16>(P, y, perm, grid, s);
-    else grid_tt<T, 32>(P, y, perm, grid, s);
+    const bool wide = P.grid_threads > 256;
+    if (P.TT == 16) {
+        grid_tt<T, 16, 256>(P, y, perm, grid, s);
+    } else {
+        if (wide) grid_tt<T, 32, 1024>(P, y, perm, grid, s);
+        else grid_tt<T, 32, 256>(P, y, perm, grid, s);
+    }
 }
 
 template void launch_degrid<float>(const Plan&, const cpx<float>*, cpx<float>*, const int32_t*, double, hipStream_t);

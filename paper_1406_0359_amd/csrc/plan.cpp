@@ -391,6 +391,19 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
         }
     }
 
+    // Heaviest gridding workgroup: own visibilities plus the spill-ins from three neighbours.
+    P.max_tile_load = 0;
+    for (int t2 = 0; t2 < nT; ++t2)
+        for (int t1 = 0; t1 < nT; ++t1) {
+            const int t = t2 * nT + t1;
+            const int L = t2 * nT + (t1 + nT - 1) % nT, U = ((t2 + nT - 1) % nT) * nT + t1;
+            const int Dg = ((t2 + nT - 1) % nT) * nT + (t1 + nT - 1) % nT;
+            const int load = (off[4 * t + 4] - off[4 * t]) + (off[4 * L + 3] - off[4 * L + 1]) +
+                             (off[4 * U + 4] - off[4 * U + 2]) + (off[4 * Dg + 3] - off[4 * Dg + 2]);
+            P.max_tile_load = std::max(P.max_tile_load, load);
+        }
+    P.grid_threads = P.max_tile_load > 256 ? 1024 : 256;
+
     // Per-tile bound on the number of visibilities that add to one cell (gridding scale):
     // count first taps per cell, sum over the J x J window of first taps that reach each
     // cell (cyclic), and take the maximum over each tile.

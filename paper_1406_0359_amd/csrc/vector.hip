@@ -44,6 +44,24 @@ __device__ __forceinline__ double block_max(double v) {
     return t;
 }
 
+// Every workgroup of a consumer kernel re-sums a partial-sum buffer in the same fixed
+// order, so all of them see the identical scalar (no finalize launch, still deterministic).
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int count) {
+    __shared__ double red2[VT / 64];
+    double acc = 0;
+    for (int i = threadIdx.x; i < count; i += VT) acc += part[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red2[w] = acc;
+    __syncthreads();
+    double t = 0;
+#pragma unroll
+    for (int i = 0; i < VT / 64; ++i) t += red2[i];
+    __syncthreads();
+    return t;
+}
+
 int red_blocks(int64_t n) {
     int64_t b = (n + VT - 1) / VT;
     return (int)(b < RED_BLOCKS ? (b < 1 ? 1 : b) : RED_BLOCKS);
@@ -149,12 +167,16 @@ k_cg_init(const cpx<T>* __restrict__ x1, const cpx<T>* __restrict__ x2, const cp
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// x += alpha p ; r -= alpha q ; partial <r, r>
+// CG step: alpha = rho / Re<p, q> from the partial sums of both (rho == 0: alpha = 0,
+// the early stop); x += alpha p ; r -= alpha q ; partial <r, r> of the new residual.
 template <typename T>
 __global__ void __launch_bounds__(VT)
 k_cg_xr(cpx<T>* __restrict__ x, cpx<T>* __restrict__ r, const cpx<T>* __restrict__ p,
-        const cpx<T>* __restrict__ q, const double* __restrict__ sc, int64_t n, double* part) {
-    const T alpha = (T)sc[SL_ALPHA];
+        const cpx<T>* __restrict__ q, const double* __restrict__ rho_part, int rho_count,
+        const double* __restrict__ pq_part, int pq_count, int64_t n, double* part) {
+    const double rho = sum_partials(rho_part, rho_count);
+    const double pq = sum_partials(pq_part, pq_count);
+    const T alpha = (T)(rho == 0.0 ? 0.0 : rho / pq);
     double acc = 0;
     GRID_STRIDE(i, n) {
         x[i] = x[i] + alpha * p[i];
@@ -166,13 +188,15 @@ k_cg_xr(cpx<T>* __restrict__ x, cpx<T>* __restrict__ r, const cpx<T>* __restrict
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// p = r + beta p
+// p = r + beta p, beta = rho_new / rho (0 when rho == 0)
 template <typename T>
 __global__ void __launch_bounds__(VT)
-k_cg_p(cpx<T>* __restrict__ p, const cpx<T>* __restrict__ r, const double* __restrict__ sc, int64_t n) {
-    const T beta = (T)sc[SL_BETA];
-    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
-    if (i < n) p[i] = r[i] + beta * p[i];
+k_cg_p(cpx<T>* __restrict__ p, const cpx<T>* __restrict__ r, const double* __restrict__ rho_part,
+       const double* __restrict__ rhonew_part, int count, int64_t n) {
+    const double rho = sum_partials(rho_part, count);
+    const double rn = sum_partials(rhonew_part, count);
+    const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
+    GRID_STRIDE(i, n) p[i] = r[i] + beta * p[i];
 }
 
 // i = 1 of Algorithm 1: u = v1 + z1 ; r1 = soft(u, gamma w) ; z1 = u - r1 ; v1 <- r1 - z1 ;
@@ -233,20 +257,49 @@ k_ball_part(const cpx<T>* __restrict__ v3, const cpx<T>* __restrict__ z3, const 
     }
 }
 
-// i = 3, pass 2: u = v3 + z3 ; r3 = y~ + (u - y~) s ; z3 = u - r3 ; v3 <- r3 - z3
+// i = 3, pass 2: s = min(1, eps~ / ||v3 + z3 - y~||) from the partial sums;
+// u = v3 + z3 ; r3 = y~ + (u - y~) s ; z3 = u - r3 ; v3 <- r3 - z3.  Workgroup 0 also
+// records ||u - y~||^2, the residual ||y~ - v3||^2 and its history row.
 template <typename T>
 __global__ void __launch_bounds__(VT)
 k_prox_ball(cpx<T>* __restrict__ v3, cpx<T>* __restrict__ z3, const cpx<T>* __restrict__ yt,
-            const double* __restrict__ sc, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
-    if (i >= n) return;
-    const T s = (T)sc[SL_BALL];
-    const cpx<T> y = yt[i];
-    const cpx<T> u = v3[i] + z3[i];
-    const cpx<T> r3 = y + s * (u - y);
-    const cpx<T> z = u - r3;
-    z3[i] = z;
-    v3[i] = r3 - z;
+            const double* __restrict__ part_d, const double* __restrict__ part_res, int count,
+            double eps, double* sc, double* hist, int hist_cap, int64_t n) {
+    const double d2 = sum_partials(part_d, count);
+    const double nd = sqrt(d2);
+    const T s = (T)((nd == 0.0 || eps >= nd) ? 1.0 : eps / nd);
+    if (blockIdx.x == 0) {
+        const double res2 = sum_partials(part_res, count);
+        if (threadIdx.x == 0) {
+            sc[SL_D2] = d2;
+            sc[SL_RES2] = res2;
+            if (!(d2 == d2) || !(res2 == res2) || d2 == INFINITY || res2 == INFINITY) sc[SL_NONFINITE] = 1.0;
+            if (hist) hist[2 * ((int)sc[SL_ITER] % hist_cap) + 1] = sqrt(res2);
+        }
+    }
+    GRID_STRIDE(i, n) {
+        const cpx<T> y = yt[i];
+        const cpx<T> u = v3[i] + z3[i];
+        const cpx<T> r3 = y + s * (u - y);
+        const cpx<T> z = u - r3;
+        z3[i] = z;
+        v3[i] = r3 - z;
+    }
+}
+
+// Power iteration: v = w / ||w|| with ||w||^2 from the partial sums; workgroup 0 records
+// lambda = ||w|| (so nu = sqrt(lambda) after the last step).
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_power_normalise(cpx<T>* __restrict__ v, const cpx<T>* __restrict__ w, const double* __restrict__ part,
+                  int count, double* sc, int64_t n) {
+    const double l = sqrt(sum_partials(part, count));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[SL_LAMBDA] = l;
+        if (!(l == l) || l == INFINITY) sc[SL_NONFINITE] = 1.0;
+    }
+    const T inv = (T)(l > 0.0 ? 1.0 / l : 0.0);
+    GRID_STRIDE(i, n) v[i] = inv * w[i];
 }
 
 __global__ void k_iter_advance(double* sc) {
@@ -303,15 +356,19 @@ int launch_cg_init(const cpx<T>* x1, const cpx<T>* x2, const cpx<T>* x3, const c
     return b;
 }
 template <typename T>
-int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q, const double* sc, int64_t n,
-                 double* part, hipStream_t s) {
+int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q, const double* rho_part,
+                 int rho_count, const double* pq_part, int pq_count, int64_t n, double* part,
+                 hipStream_t s) {
     const int b = red_blocks(n);
-    hipLaunchKernelGGL(k_cg_xr<T>, dim3(b), dim3(VT), 0, s, x, r, p, q, sc, n, part);
+    hipLaunchKernelGGL(k_cg_xr<T>, dim3(b), dim3(VT), 0, s, x, r, p, q, rho_part, rho_count, pq_part,
+                       pq_count, n, part);
     return b;
 }
 template <typename T>
-void launch_cg_p(cpx<T>* p, const cpx<T>* r, const double* sc, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_p<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, p, r, sc, n);
+void launch_cg_p(cpx<T>* p, const cpx<T>* r, const double* rho_part, const double* rhonew_part,
+                 int count, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_p<T>, dim3(red_blocks(n)), dim3(VT), 0, s, p, r, rho_part, rhonew_part,
+                       count, n);
 }
 template <typename T>
 int launch_prox_l1(cpx<T>* v1, cpx<T>* z1, const double* w, double gamma, int64_t n, double* part,
@@ -332,8 +389,16 @@ int launch_ball_part(const cpx<T>* v3, const cpx<T>* z3, const cpx<T>* yt, int64
     return b;
 }
 template <typename T>
-void launch_prox_ball(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const double* sc, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_prox_ball<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, v3, z3, yt, sc, n);
+void launch_prox_ball(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const double* part_d,
+                      const double* part_res, int count, double eps, double* sc, double* hist,
+                      int hist_cap, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_prox_ball<T>, dim3(red_blocks(n)), dim3(VT), 0, s, v3, z3, yt, part_d, part_res,
+                       count, eps, sc, hist, hist_cap, n);
+}
+template <typename T>
+void launch_power_normalise(cpx<T>* v, const cpx<T>* w, const double* part, int count, double* sc,
+                            int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_power_normalise<T>, dim3(red_blocks(n)), dim3(VT), 0, s, v, w, part, count, sc, n);
 }
 template <typename T>
 void launch_permute_scale(const cpx<T>* y_user, const int32_t* perm, double scale, cpx<T>* y_sorted,
@@ -353,14 +418,18 @@ void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc, int 
     template int launch_maxabs_part<T>(const cpx<T>*, int64_t, double*, hipStream_t);                    \
     template int launch_cg_init<T>(const cpx<T>*, const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*,  \
                                    cpx<T>*, int64_t, double*, hipStream_t);                              \
-    template int launch_cg_xr<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const cpx<T>*, const double*, int64_t, \
-                                 double*, hipStream_t);                                                  \
-    template void launch_cg_p<T>(cpx<T>*, const cpx<T>*, const double*, int64_t, hipStream_t);          \
+    template int launch_cg_xr<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const cpx<T>*, const double*, int,     \
+                                 const double*, int, int64_t, double*, hipStream_t);                     \
+    template void launch_cg_p<T>(cpx<T>*, const cpx<T>*, const double*, const double*, int, int64_t,      \
+                                 hipStream_t);                                                           \
+    template void launch_power_normalise<T>(cpx<T>*, const cpx<T>*, const double*, int, double*, int64_t, \
+                                            hipStream_t);                                                \
     template int launch_prox_l1<T>(cpx<T>*, cpx<T>*, const double*, double, int64_t, double*, hipStream_t); \
     template void launch_prox_pos<T>(const cpx<T>*, cpx<T>*, cpx<T>*, int64_t, hipStream_t);            \
     template int launch_ball_part<T>(const cpx<T>*, const cpx<T>*, const cpx<T>*, int64_t, double*,      \
                                      double*, hipStream_t);                                              \
-    template void launch_prox_ball<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const double*, int64_t, hipStream_t); \
+    template void launch_prox_ball<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const double*, const double*, int,  \
+                                      double, double*, double*, int, int64_t, hipStream_t);             \
     template void launch_permute_scale<T>(const cpx<T>*, const int32_t*, double, cpx<T>*, int64_t,       \
                                           hipStream_t);                                                  \
     template void launch_scale_by_slot<T>(cpx<T>*, const cpx<T>*, const double*, int, int64_t, hipStream_t);
