@@ -112,6 +112,7 @@ struct Plan {
     void* tw2 = nullptr;         // n complex: exp(-pi i t / n)
     void* filters = nullptr;     // MAX_WAV * 2 * MAX_TAPS reals (h then g)
     void* kbpoly = nullptr;      // J * (KBDeg + 1) reals: per-tap polynomial coefficients
+    void* wtab = nullptr;        // FP64 plans: M x 2J tap weights (sorted order), else null
     void* grid = nullptr;        // K x K complex, layout [k2][k1]
     void* tmp = nullptr;         // K x n complex, layout [k2][j1]
     double* part = nullptr;      // NUM_PARTIAL_BUFS * MAX_PARTIALS

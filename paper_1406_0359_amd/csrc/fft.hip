@@ -16,7 +16,8 @@
 //   cols_adj : each G column k2       -> tmp column k2  (D^dag along axis 0)
 //   rows_adj : each tmp row j1        -> image row j1   (D^dag along axis 1, S, epilogue)
 // Row passes read and write whole rows; column passes handle C adjacent columns per
-// workgroup so every global access is a contiguous run of C elements.
+// workgroup so every global access is a contiguous run of C elements.  The two parities of
+// a line run on separate thread groups; the adjoint combines them through LDS.
 //
 // Each n-point transform is a self-sorting (Stockham) FFT with large radices (8..32) held in
 // registers: one thread owns n/RMAX butterflies of each pass, runs the radix-R DFT in
@@ -240,41 +241,70 @@ __device__ __forceinline__ void line_fft(cpx<T>* v, cpx<T>* line, int tl, const 
 template <typename T>
 __device__ __forceinline__ cpx<T> neg(cpx<T> a) { return mk<T>(-a.x, -a.y); }
 
-// Row passes: 64-thread workgroups (more rows per workgroup only when a row has fewer
-// threads).  Column passes: C adjacent columns (64-byte runs) as long as the LDS lines and
-// the twiddle table fit in 160 KB.
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).  Column
+// passes read and write runs of C columns, so neighbouring column groups share cache
+// lines: give each XCD a contiguous range of column groups.
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    if (nb % 8 != 0) return b;
+    return (b % 8) * (nb / 8) + b / 8;
+}
+
+// Workgroup shapes.  Each n-point line transform uses TL threads; the two output parities of
+// a line are separate thread groups.  Row passes: B rows per workgroup (64-128 threads).
+// Column passes: C adjacent columns (contiguous runs of C elements), at most 256 threads,
+// at least ~256 workgroups, and LDS (2C lines + twiddle table) within 160 KB.
 template <typename T, int LOGN>
 constexpr int rows_per_wg() {
     constexpr int tl = Plan1D<T, LOGN>::TL;
-    return tl >= 64 ? 1 : 64 / tl;
+    int b = 64 / (2 * tl);
+    if (b < 1) b = 1;
+    if (b > (1 << LOGN)) b = 1 << LOGN;
+    return b;
+}
+template <typename T, int LOGN>
+constexpr bool twiddles_in_lds() {
+    constexpr int N = 1 << LOGN;
+    return (size_t)(N + 2 * (N + 1)) * 2 * sizeof(T) <= 160 * 1024;
 }
 template <typename T, int LOGN>
 constexpr int cols_per_wg() {
-    constexpr int want = sizeof(T) == 4 ? 8 : 4;
     constexpr int N = 1 << LOGN;
-    constexpr int budget = 160 * 1024 / (int)(2 * sizeof(T));
-    int c = want;
-    while (c > 1 && N + c * (N + 1) > budget) c >>= 1;
+    constexpr int tl = Plan1D<T, LOGN>::TL;
+    int c = 128 / tl;
+    if (c > (2 * N) / 256) c = (2 * N) / 256;
+    if (c > 8) c = 8;
+    if (c < 1) c = 1;
+    const int tab = twiddles_in_lds<T, LOGN>() ? N : 0;
+    while (c > 1 && (size_t)(tab + 2 * c * (N + 1)) * 2 * sizeof(T) > 160 * 1024) c >>= 1;
     return c;
 }
 
 template <typename T, int LOGN>
-__device__ __forceinline__ void stage_twiddles(cpx<T>* Wl, const cpx<T>* __restrict__ tw, int nthreads) {
-    for (int i = threadIdx.x; i < (1 << LOGN); i += nthreads) Wl[i] = tw[i];
+__device__ __forceinline__ const cpx<T>* stage_twiddles(cpx<T>* Wl, const cpx<T>* __restrict__ tw) {
+    if constexpr (twiddles_in_lds<T, LOGN>()) {
+        for (int i = threadIdx.x; i < (1 << LOGN); i += blockDim.x) Wl[i] = tw[i];
+        return Wl;
+    } else {
+        return tw;
+    }
 }
+template <typename T, int LOGN>
+constexpr int table_elems() { return twiddles_in_lds<T, LOGN>() ? (1 << LOGN) : 0; }
 
 // ---------------------------------------------------------------------------------------
+// rows_fwd: thread (b, r, tl), line 2b + r; tmp[row][2k' + r] = (-1)^k' i^r FFT(s x tw2^r)[k']
 template <typename T, int LOGN, int B>
-__global__ void __launch_bounds__((B * Plan1D<T, LOGN>::TL))
+__global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN>::TL))
 k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __restrict__ deap,
                const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2) {
     using PL = Plan1D<T, LOGN>;
-    constexpr int N = PL::N, K = 2 * N, NT = B * PL::TL;
+    constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* Wl = reinterpret_cast<cpx<T>*>(smem_raw);
-    stage_twiddles<T, LOGN>(Wl, tw, NT);
-    const int lr = threadIdx.x / PL::TL, tl = threadIdx.x % PL::TL;
-    cpx<T>* line = Wl + N + lr * PL::LS;
+    cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
+    const int tl = threadIdx.x % PL::TL, r = (threadIdx.x / PL::TL) & 1, lr = threadIdx.x / (2 * PL::TL);
+    cpx<T>* line = base + table_elems<T, LOGN>() + (2 * lr + r) * PL::LS;
     const int row = blockIdx.x * B + lr;
     const T srow = deap[row];
     const cpx<T>* xr = x + (size_t)row * N;
@@ -282,91 +312,88 @@ k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* 
     __syncthreads();
     cpx<T> v[PL::RMAX];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int p = PL::in_pos(tl, i);
+        cpx<T> a = (srow * deap[p]) * xr[p];
+        if (r) a = a * tw2[p];
+        v[i] = a;
+    }
+    line_fft<T, LOGN, false>(v, line, tl, W);
 #pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) {
-            const int p = PL::in_pos(tl, i);
-            cpx<T> a = (srow * deap[p]) * xr[p];
-            if (r) a = a * tw2[p];
-            v[i] = a;
-        }
-        line_fft<T, LOGN, false>(v, line, tl, Wl);
-#pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) {
-            const int kp = PL::out_pos(tl, i);
-            cpx<T> o = (kp & 1) ? neg(v[i]) : v[i];
-            if (r) o = mul_i(o);
-            outr[2 * kp + r] = o;
-        }
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int kp = PL::out_pos(tl, i);
+        cpx<T> o = (kp & 1) ? neg(v[i]) : v[i];
+        if (r) o = mul_i(o);
+        outr[2 * kp + r] = o;
     }
 }
 
+// cols_fwd: thread (c, r, tl) with c fastest (coalesced runs of C columns)
 template <typename T, int LOGN, int C>
-__global__ void __launch_bounds__((C * Plan1D<T, LOGN>::TL))
+__global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN>::TL))
 k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const cpx<T>* __restrict__ tw,
                const cpx<T>* __restrict__ tw2) {
     using PL = Plan1D<T, LOGN>;
-    constexpr int N = PL::N, K = 2 * N, NT = C * PL::TL;
+    constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* Wl = reinterpret_cast<cpx<T>*>(smem_raw);
-    stage_twiddles<T, LOGN>(Wl, tw, NT);
-    const int c = threadIdx.x % C, tl = threadIdx.x / C;
-    cpx<T>* line = Wl + N + c * PL::LS;
-    const int col = blockIdx.x * C + c;
+    cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
+    const int c = threadIdx.x % C, r = (threadIdx.x / C) & 1, tl = threadIdx.x / (2 * C);
+    cpx<T>* line = base + table_elems<T, LOGN>() + (2 * c + r) * PL::LS;
+    const int col = xcd_block() * C + c;
     __syncthreads();
     cpx<T> v[PL::RMAX];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int p = PL::in_pos(tl, i);
+        cpx<T> a = tmp[(size_t)p * K + col];
+        if (r) a = a * tw2[p];
+        v[i] = a;
+    }
+    line_fft<T, LOGN, false>(v, line, tl, W);
 #pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) {
-            const int p = PL::in_pos(tl, i);
-            cpx<T> a = tmp[(size_t)p * K + col];
-            if (r) a = a * tw2[p];
-            v[i] = a;
-        }
-        line_fft<T, LOGN, false>(v, line, tl, Wl);
-#pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) {
-            const int kp = PL::out_pos(tl, i);
-            cpx<T> o = (kp & 1) ? neg(v[i]) : v[i];
-            if (r) o = mul_i(o);
-            grid[(size_t)(2 * kp + r) * K + col] = o;
-        }
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int kp = PL::out_pos(tl, i);
+        cpx<T> o = (kp & 1) ? neg(v[i]) : v[i];
+        if (r) o = mul_i(o);
+        grid[(size_t)(2 * kp + r) * K + col] = o;
     }
 }
 
+// cols_adj: parity lines transformed in parallel, results meet in LDS, then
+// tmp[j][col] = A[j] + (-i) exp(pi i j / n) B[j]
 template <typename T, int LOGN, int C>
-__global__ void __launch_bounds__((C * Plan1D<T, LOGN>::TL))
+__global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN>::TL))
 k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const cpx<T>* __restrict__ tw,
                const cpx<T>* __restrict__ tw2) {
     using PL = Plan1D<T, LOGN>;
-    constexpr int N = PL::N, K = 2 * N, NT = C * PL::TL;
+    constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* Wl = reinterpret_cast<cpx<T>*>(smem_raw);
-    stage_twiddles<T, LOGN>(Wl, tw, NT);
-    const int c = threadIdx.x % C, tl = threadIdx.x / C;
-    cpx<T>* line = Wl + N + c * PL::LS;
-    const int col = blockIdx.x * C + c;
+    cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
+    const int c = threadIdx.x % C, r = (threadIdx.x / C) & 1, tl = threadIdx.x / (2 * C);
+    cpx<T>* lines = base + table_elems<T, LOGN>();
+    cpx<T>* line = lines + (2 * c + r) * PL::LS;
+    const int col = xcd_block() * C + c;
     __syncthreads();
-    cpx<T> v[PL::RMAX], a0[PL::RMAX];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-#pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) {
-            const int kp = PL::in_pos(tl, i);
-            const cpx<T> u = grid[(size_t)(2 * kp + r) * K + col];
-            v[i] = (kp & 1) ? neg(u) : u;
-        }
-        line_fft<T, LOGN, true>(v, line, tl, Wl);
-        if (r == 0) {
-#pragma unroll
-            for (int i = 0; i < PL::RMAX; ++i) a0[i] = v[i];
-        }
-    }
+    cpx<T> v[PL::RMAX];
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
-        const int j = PL::out_pos(tl, i);
-        tmp[(size_t)j * K + col] = a0[i] + mul_mi(mulc(v[i], tw2[j]));
+        const int kp = PL::in_pos(tl, i);
+        const cpx<T> u = grid[(size_t)(2 * kp + r) * K + col];
+        v[i] = (kp & 1) ? neg(u) : u;
+    }
+    line_fft<T, LOGN, true>(v, line, tl, W);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
+    __syncthreads();
+    const cpx<T>* la = lines + (2 * c) * PL::LS;
+    const cpx<T>* lb = la + PL::LS;
+#pragma unroll
+    for (int q = 0; q < PL::RMAX / 2; ++q) {
+        const int j = r + 2 * tl + q * 2 * PL::TL;
+        tmp[(size_t)j * K + col] = la[j] + mul_mi(mulc(lb[j], tw2[j]));
     }
 }
 
@@ -384,43 +411,43 @@ __device__ __forceinline__ double block_sum_dyn(double v, double* red) {
     return t;
 }
 
+// rows_adj: thread (b, tl, r) with r fastest; parity lines in parallel, combined in LDS;
+// x[row][j] = c1 s_row s_j (A[j] + (-i) exp(pi i j/n) B[j]) + c2 v, partial Re<v, x>
 template <typename T, int LOGN, int B>
-__global__ void __launch_bounds__((B * Plan1D<T, LOGN>::TL))
+__global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN>::TL))
 k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* __restrict__ deap,
                const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2, T c1,
                const cpx<T>* __restrict__ vin, T c2, double* __restrict__ dot_part) {
     using PL = Plan1D<T, LOGN>;
-    constexpr int N = PL::N, K = 2 * N, NT = B * PL::TL;
+    constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
-    cpx<T>* Wl = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
     __shared__ double red[16];
-    stage_twiddles<T, LOGN>(Wl, tw, NT);
-    const int lr = threadIdx.x / PL::TL, tl = threadIdx.x % PL::TL;
-    cpx<T>* line = Wl + N + lr * PL::LS;
+    const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
+    const int r = threadIdx.x & 1, tl = (threadIdx.x >> 1) % PL::TL, lr = threadIdx.x / (2 * PL::TL);
+    cpx<T>* lines = base + table_elems<T, LOGN>() + (2 * lr) * PL::LS;
+    cpx<T>* line = lines + r * PL::LS;
     const int row = blockIdx.x * B + lr;
     const cpx<T>* inr = tmp + (size_t)row * K;
     __syncthreads();
-    cpx<T> v[PL::RMAX], a0[PL::RMAX];
+    cpx<T> v[PL::RMAX];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-#pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) {
-            const int kp = PL::in_pos(tl, i);
-            const cpx<T> u = inr[2 * kp + r];
-            v[i] = (kp & 1) ? neg(u) : u;
-        }
-        line_fft<T, LOGN, true>(v, line, tl, Wl);
-        if (r == 0) {
-#pragma unroll
-            for (int i = 0; i < PL::RMAX; ++i) a0[i] = v[i];
-        }
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int kp = PL::in_pos(tl, i);
+        const cpx<T> u = inr[2 * kp + r];
+        v[i] = (kp & 1) ? neg(u) : u;
     }
+    line_fft<T, LOGN, true>(v, line, tl, W);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
+    __syncthreads();
     const T srow = c1 * deap[row];
     double acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        const int j = PL::out_pos(tl, i);
-        const cpx<T> t = a0[i] + mul_mi(mulc(v[i], tw2[j]));
+    for (int q = 0; q < PL::RMAX / 2; ++q) {
+        const int j = r + 2 * tl + q * 2 * PL::TL;
+        const cpx<T> t = lines[j] + mul_mi(mulc(lines[PL::LS + j], tw2[j]));
         cpx<T> o = (srow * deap[j]) * t;
         const size_t off = (size_t)row * N + j;
         if (vin) {
@@ -446,15 +473,15 @@ void set_lds_limit(F* f, size_t bytes) {
 template <typename T, int LOGN>
 size_t lds_bytes(int lines) {
     using PL = Plan1D<T, LOGN>;
-    return (size_t)(PL::N + lines * PL::LS) * sizeof(cpx<T>);
+    return (size_t)(table_elems<T, LOGN>() + lines * PL::LS) * sizeof(cpx<T>);
 }
 
 template <typename T, int LOGN>
 void rows_fwd_impl(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s) {
     constexpr int B = rows_per_wg<T, LOGN>();
-    constexpr int NT = B * Plan1D<T, LOGN>::TL;
+    constexpr int NT = 2 * B * Plan1D<T, LOGN>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = lds_bytes<T, LOGN>(B);
+    const size_t lds = lds_bytes<T, LOGN>(2 * B);
     auto f = k_fft_rows_fwd<T, LOGN, B>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, x, tmp, (const T*)P.deap,
@@ -463,9 +490,9 @@ void rows_fwd_impl(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s) {
 template <typename T, int LOGN>
 void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
     constexpr int C = cols_per_wg<T, LOGN>();
-    constexpr int NT = C * Plan1D<T, LOGN>::TL;
+    constexpr int NT = 2 * C * Plan1D<T, LOGN>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = lds_bytes<T, LOGN>(C);
+    const size_t lds = lds_bytes<T, LOGN>(2 * C);
     auto f = k_fft_cols_fwd<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, tmp, grid, (const cpx<T>*)P.tw,
@@ -474,9 +501,9 @@ void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s
 template <typename T, int LOGN>
 void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s) {
     constexpr int C = cols_per_wg<T, LOGN>();
-    constexpr int NT = C * Plan1D<T, LOGN>::TL;
+    constexpr int NT = 2 * C * Plan1D<T, LOGN>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = lds_bytes<T, LOGN>(C);
+    const size_t lds = lds_bytes<T, LOGN>(2 * C);
     auto f = k_fft_cols_adj<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, grid, tmp, (const cpx<T>*)P.tw,
@@ -486,9 +513,9 @@ template <typename T, int LOGN>
 void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* v,
                    double c2, double* dot_part, hipStream_t s) {
     constexpr int B = rows_per_wg<T, LOGN>();
-    constexpr int NT = B * Plan1D<T, LOGN>::TL;
+    constexpr int NT = 2 * B * Plan1D<T, LOGN>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = lds_bytes<T, LOGN>(B);
+    const size_t lds = lds_bytes<T, LOGN>(2 * B);
     auto f = k_fft_rows_adj<T, LOGN, B>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, tmp, x, (const T*)P.deap,

@@ -34,10 +34,42 @@ __device__ __noinline__ void kb_weights_any(const T* __restrict__ c, T f, T* w, 
     }
 }
 
+// FP64 plans store every visibility's 2J tap weights (computed once at plan time) and the
+// kernels read them; FP32 plans evaluate the per-tap polynomials on the fly (an FP64 table
+// of 18 coefficients per tap does not fit in registers, and reading 16 B per tap weight
+// from a cache-resident table is cheaper than re-evaluating it).
+template <typename T, int J>
+__device__ __forceinline__ void visibility_weights(const T* __restrict__ wtab, const T* __restrict__ kbc,
+                                                   int idx, cpx<T> f, T* wa, T* wb, int Jr);
+
 template <typename T, int J>
 __device__ __forceinline__ void tap_weights(const T* __restrict__ c, T f, T* w, int Jr) {
     if constexpr (J > 0) kb_weights<T, J>(c, f, w);
     else kb_weights_any<T>(c, f, w, Jr);
+}
+
+template <typename T, int J>
+__device__ __forceinline__ void visibility_weights(const T* __restrict__ wtab, const T* __restrict__ kbc,
+                                                   int idx, cpx<T> f, T* wa, T* wb, int Jr) {
+    if constexpr (sizeof(T) == 8) {
+        const int Jn = J > 0 ? J : Jr;
+        const T* w = wtab + (size_t)idx * 2 * Jn;
+        if constexpr (J > 0) {
+#pragma unroll
+            for (int a = 0; a < J; ++a) {
+                wa[a] = w[a];
+                wb[a] = w[J + a];
+            }
+        } else {
+            for (int a = 0; a < Jn; ++a) {
+                wa[a] = w[a];
+                wb[a] = w[Jn + a];
+            }
+        }
+    } else {
+        tap_weights<T, J>(kbc, f.x, wa, Jr);
+        tap_weights<T, J>(kbc, f.y, wb, Jr);
+    }
 }
 
 // G: one thread per visibility (tile-sorted order), J x J gather from the row-major grid
@@ -46,7 +78,7 @@ template <typename T, int J>
 __global__ void __launch_bounds__(256)
 k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
          const int32_t* __restrict__ base, const T* __restrict__ frac, const T* __restrict__ kbc,
-         int M, int K, T scale, int Jr) {
+         const T* __restrict__ wtab, int M, int K, T scale, int Jr) {
     constexpr int JJ = J > 0 ? J : KB_MAX_J;
     constexpr int UNR = J > 0 ? J : 1;   // generic width: plain loops
     const int Jn = J > 0 ? J : Jr;
@@ -56,8 +88,7 @@ k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t*
     const int k1 = b & 0xFFFF, k2 = (b >> 16) & 0xFFFF;
     const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[m];
     T wa[JJ], wb[JJ];
-    tap_weights<T, J>(kbc, f.x, wa, Jr);
-    tap_weights<T, J>(kbc, f.y, wb, Jr);
+    visibility_weights<T, J>(wtab, kbc, m, f, wa, wb, Jr);
     const int mask = K - 1;
     T ax = 0, ay = 0;
 #pragma unroll UNR
@@ -88,13 +119,20 @@ k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t*
 template <typename T> struct FixedAcc;
 template <> struct FixedAcc<float> {
     using I = int;
-    static constexpr int BITS = 30;
+    static constexpr int BITS = 30;   // bound on a cell sum, in quanta
+    static constexpr int CBITS = 30;  // bound on one contribution, in quanta
     static __device__ __forceinline__ I conv(float v) { return __float2int_rn(v); }
 };
 template <> struct FixedAcc<double> {
     using I = long long;
-    static constexpr int BITS = 61;
-    static __device__ __forceinline__ I conv(double v) { return __double2ll_rn(v); }
+    static constexpr int BITS = 62;
+    static constexpr int CBITS = 51;
+    // exact round-to-nearest for |v| < 2^51: adding 1.5 * 2^52 leaves round(v) in the low
+    // mantissa bits
+    static __device__ __forceinline__ I conv(double v) {
+        const double t = v + 6755399441055744.0;
+        return __double_as_longlong(t) - 0x4338000000000000LL;
+    }
 };
 
 template <typename T>
@@ -106,22 +144,26 @@ __device__ __forceinline__ void lds_add(typename FixedAcc<T>::I* p, typename Fix
 template <typename T, int J, int TT, int GRID_THREADS>
 __device__ __forceinline__ void grid_range(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
                                            const int32_t* __restrict__ base, const T* __restrict__ frac,
-                                           const T* __restrict__ kbc, int start, int end, int K,
-                                           int t1o, int t2o, int Jr, T inv_q,
+                                           const T* __restrict__ kbc, const T* __restrict__ wtab,
+                                           int start, int end, int K, int t1o, int t2o, int Jr, T inv_q,
                                            typename FixedAcc<T>::I* acc) {
     using Acc = FixedAcc<T>;
     constexpr int JJ = J > 0 ? J : KB_MAX_J;
     constexpr int UNR = J > 0 ? J : 1;   // generic width: plain loops
     const int mask = K - 1;
     const int Jn = J > 0 ? J : Jr;
-    for (int idx = start + (int)threadIdx.x; idx < end; idx += GRID_THREADS) {
+    // visibilities are sorted by cell inside each spill class; each thread takes a contiguous
+    // chunk so the lanes of a wave add to different cells
+    const int chunk = (end - start + GRID_THREADS - 1) / GRID_THREADS;
+    const int c0 = start + (int)threadIdx.x * chunk;
+    const int c1e = min(end, c0 + chunk);
+    for (int idx = c0; idx < c1e; ++idx) {
         const int b = base[idx];
         const int k1 = b & 0xFFFF, k2 = (b >> 16) & 0xFFFF;
         const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[idx];
         const cpx<T> v = y[perm ? perm[idx] : idx];
         T wa[JJ], wb[JJ];
-        tap_weights<T, J>(kbc, f.x, wa, Jr);
-        tap_weights<T, J>(kbc, f.y, wb, Jr);
+        visibility_weights<T, J>(wtab, kbc, idx, f, wa, wb, Jr);
 #pragma unroll UNR
         for (int a = 0; a < JJ; ++a) {
             if (a >= Jn) break;
@@ -147,17 +189,20 @@ __device__ __forceinline__ void grid_range(const cpx<T>* __restrict__ y, const i
 template <typename T, int J, int TT, int GRID_THREADS>
 __device__ __forceinline__ void grid_interior(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
                                               const int32_t* __restrict__ base, const T* __restrict__ frac,
-                                              const T* __restrict__ kbc, int start, int end, int t1o,
-                                              int t2o, T inv_q, typename FixedAcc<T>::I* acc) {
+                                              const T* __restrict__ kbc, const T* __restrict__ wtab,
+                                              int start, int end, int t1o, int t2o, T inv_q,
+                                              typename FixedAcc<T>::I* acc) {
     using Acc = FixedAcc<T>;
-    for (int idx = start + (int)threadIdx.x; idx < end; idx += GRID_THREADS) {
+    const int chunk = (end - start + GRID_THREADS - 1) / GRID_THREADS;
+    const int i0 = start + (int)threadIdx.x * chunk;
+    const int i1 = min(end, i0 + chunk);
+    for (int idx = i0; idx < i1; ++idx) {
         const int b = base[idx];
         const int c1 = (b & 0xFFFF) - t1o, c2 = ((b >> 16) & 0xFFFF) - t2o;
         const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[idx];
         const cpx<T> v = y[perm ? perm[idx] : idx];
         T wa[J], wb[J];
-        kb_weights<T, J>(kbc, f.x, wa);
-        kb_weights<T, J>(kbc, f.y, wb);
+        visibility_weights<T, J>(wtab, kbc, idx, f, wa, wb, J);
         typename Acc::I* p = acc + 2 * (c1 * TT + c2);
 #pragma unroll
         for (int a = 0; a < J; ++a) {
@@ -183,8 +228,9 @@ __device__ __forceinline__ double wave_max(double v) {
 template <typename T, int J, int TT, int GRID_THREADS>
 __global__ void __launch_bounds__(GRID_THREADS)
 k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int32_t* __restrict__ base,
-       const T* __restrict__ frac, const T* __restrict__ kbc, const int32_t* __restrict__ off,
-       const int32_t* __restrict__ cover, cpx<T>* __restrict__ grid, int K, int nT, int Jr) {
+       const T* __restrict__ frac, const T* __restrict__ kbc, const T* __restrict__ wtab,
+       const int32_t* __restrict__ off, const int32_t* __restrict__ cover, cpx<T>* __restrict__ grid,
+       int K, int nT, int Jr) {
     using Acc = FixedAcc<T>;
     __shared__ typename Acc::I acc[2 * TT * TT];
     __shared__ double red[GRID_THREADS / 64];
@@ -214,19 +260,20 @@ k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int
     ym = 0.0;
 #pragma unroll
     for (int w = 0; w < GRID_THREADS / 64; ++w) ym = fmax(ym, red[w]);
-    // quantum q = 2^e with 2 * cover * max|y| <= 2^BITS q: at most `cover` visibilities add
-    // to one cell, each by at most max|y| (psi <= 1; the factor 2 is margin)
+    // quantum q = 2^e with 2 * cover * max|y| <= 2^BITS q (at most `cover` visibilities add
+    // to one cell, each by at most max|y|, psi <= 1, factor 2 margin) and
+    // 2 * max|y| <= 2^CBITS q (one contribution)
     const double bound = 2.0 * (double)cover[tile] * ym;
-    const int e = bound > 0.0 ? ilogb(bound) + 1 - Acc::BITS : 0;
+    const int e = bound > 0.0 ? max(ilogb(bound) + 1 - Acc::BITS, ilogb(2.0 * ym) + 1 - Acc::CBITS) : 0;
     const T inv_q = (T)ldexp(1.0, -e);
     const T q = (T)ldexp(1.0, e);
     if (bound > 0.0) {
-        if constexpr (J > 0) grid_interior<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, s0, s1, t1o, t2o, inv_q, acc);
-        else grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, s0, s1, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, s1, s4, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, ls, le, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, us, ue, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, ds, de, K, t1o, t2o, Jr, inv_q, acc);
+        if constexpr (J > 0) grid_interior<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, s0, s1, t1o, t2o, inv_q, acc);
+        else grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, s0, s1, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, s1, s4, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, ls, le, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, us, ue, K, t1o, t2o, Jr, inv_q, acc);
+        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, ds, de, K, t1o, t2o, Jr, inv_q, acc);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < TT * TT; i += GRID_THREADS) {
@@ -241,10 +288,10 @@ void grid_tt(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* grid, 
     const T* fr = (const T*)P.frac;
     const T* kbc = (const T*)P.kbpoly;
     switch (P.J) {
-        case 4: hipLaunchKernelGGL((k_grid<T, 4, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 4); break;
-        case 6: hipLaunchKernelGGL((k_grid<T, 6, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 6); break;
-        case 8: hipLaunchKernelGGL((k_grid<T, 8, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, 8); break;
-        default: hipLaunchKernelGGL((k_grid<T, 0, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, P.tileoff, P.tilecover, grid, P.K, P.nT, P.J); break;
+        case 4: hipLaunchKernelGGL((k_grid<T, 4, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, (const T*)P.wtab, P.tileoff, P.tilecover, grid, P.K, P.nT, 4); break;
+        case 6: hipLaunchKernelGGL((k_grid<T, 6, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, (const T*)P.wtab, P.tileoff, P.tilecover, grid, P.K, P.nT, 6); break;
+        case 8: hipLaunchKernelGGL((k_grid<T, 8, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, (const T*)P.wtab, P.tileoff, P.tilecover, grid, P.K, P.nT, 8); break;
+        default: hipLaunchKernelGGL((k_grid<T, 0, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, (const T*)P.wtab, P.tileoff, P.tilecover, grid, P.K, P.nT, P.J); break;
     }
 }
 
@@ -258,24 +305,17 @@ void launch_degrid(const Plan& P, const cpx<T>* grid, cpx<T>* y, const int32_t* 
     const T* fr = (const T*)P.frac;
     const T* kbc = (const T*)P.kbpoly;
     switch (P.J) {
-        case 4: hipLaunchKernelGGL((k_degrid<T, 4>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, M, P.K, (T)scale, 4); break;
-        case 6: hipLaunchKernelGGL((k_degrid<T, 6>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, M, P.K, (T)scale, 6); break;
-        case 8: hipLaunchKernelGGL((k_degrid<T, 8>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, M, P.K, (T)scale, 8); break;
-        default: hipLaunchKernelGGL((k_degrid<T, 0>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, M, P.K, (T)scale, P.J); break;
+        case 4: hipLaunchKernelGGL((k_degrid<T, 4>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, 4); break;
+        case 6: hipLaunchKernelGGL((k_degrid<T, 6>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, 6); break;
+        case 8: hipLaunchKernelGGL((k_degrid<T, 8>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, 8); break;
+        default: hipLaunchKernelGGL((k_degrid<T, 0>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, P.J); break;
     }
 }
 
-// Tiles whose visibility lists (own plus spill-ins) exceed 256 get 1024-thread workgroups,
-// so even the heaviest tile takes only a few rounds.
 template <typename T>
 void launch_grid(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* grid, hipStream_t s) {
-    const bool wide = P.grid_threads > 256;
-    if (P.TT == 16) {
-        grid_tt<T, 16, 256>(P, y, perm, grid, s);
-    } else {
-        if (wide) grid_tt<T, 32, 1024>(P, y, perm, grid, s);
-        else grid_tt<T, 32, 256>(P, y, perm, grid, s);
-    }
+    if (P.TT == 16) grid_tt<T, 16, 256>(P, y, perm, grid, s);
+    else grid_tt<T, 32, 256>(P, y, perm, grid, s);
 }
 
 template void launch_degrid<float>(const Plan&, const cpx<float>*, cpx<float>*, const int32_t*, double, hipStream_t);

@@ -246,7 +246,8 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
         }
     P.N = (int64_t)P.n * P.n;
     P.D = (int64_t)P.q * P.N;
-    P.TT = P.K >= 64 ? 32 : 16;
+    // 16 x 16 tiles up to K = 1024 (more, lighter workgroups for small grids), else 32 x 32
+    P.TT = P.K > 1024 ? 32 : 16;
     P.nT = P.K / P.TT;
     const size_t es = P.precision == PURIFY_FP64 ? sizeof(double) : sizeof(float);
     const size_t ce = 2 * es;
@@ -290,6 +291,9 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
     P.vis = carve(M * ce);
     P.z1 = carve(D * ce);
     P.v1 = carve(D * ce);
+    // FP64: every visibility's 2J tap weights, computed once (degridding and gridding read
+    // them instead of evaluating the polynomials).
+    P.wtab = P.precision == PURIFY_FP64 ? carve(M * 2 * (size_t)P.J * sizeof(double)) : nullptr;
     const size_t nw = P.nwav > 0 ? (size_t)P.nwav : 1;
     P.wt = carve(nw * N * ce);
     P.ws2 = carve(nw * N * ce);
@@ -378,17 +382,30 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     for (int k = 0; k < nkeys; ++k) cnt[k + 1] += cnt[k];
     std::vector<int32_t> off(nkeys + 1);
     for (int k = 0; k <= nkeys; ++k) off[k] = (int32_t)cnt[k];
-    std::vector<int32_t> perm(M), sbase(M);
-    std::vector<double> sfr(2 * M);
+    // Order: by (tile, spill class), then by first-tap cell inside each bucket (row-major),
+    // ties in caller order.  Neighbouring visibilities then share grid cache lines.
+    std::vector<int32_t> order(M);
     {
         std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
-        for (int64_t m = 0; m < M; ++m) {
-            const int64_t p = pos[key[m]]++;
-            perm[p] = (int32_t)m;
-            sbase[p] = base[m];
-            sfr[2 * p] = fr[2 * m];
-            sfr[2 * p + 1] = fr[2 * m + 1];
+        for (int64_t m = 0; m < M; ++m) order[pos[key[m]]++] = (int32_t)m;
+        for (int k = 0; k < nkeys; ++k) {
+            auto b0 = order.begin() + off[k], b1 = order.begin() + off[k + 1];
+            if (b1 - b0 > 1)
+                std::stable_sort(b0, b1, [&](int32_t a, int32_t b) {
+                    const int ca = ((base[a] & 0xFFFF) << 16) | ((base[a] >> 16) & 0xFFFF);
+                    const int cb = ((base[b] & 0xFFFF) << 16) | ((base[b] >> 16) & 0xFFFF);
+                    return ca < cb;
+                });
         }
+    }
+    std::vector<int32_t> perm(M), sbase(M);
+    std::vector<double> sfr(2 * M);
+    for (int64_t p = 0; p < M; ++p) {
+        const int32_t m = order[p];
+        perm[p] = m;
+        sbase[p] = base[m];
+        sfr[2 * p] = fr[2 * m];
+        sfr[2 * p + 1] = fr[2 * m + 1];
     }
 
     // Heaviest gridding workgroup: own visibilities plus the spill-ins from three neighbours.
@@ -402,7 +419,7 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
                              (off[4 * U + 4] - off[4 * U + 2]) + (off[4 * Dg + 3] - off[4 * Dg + 2]);
             P.max_tile_load = std::max(P.max_tile_load, load);
         }
-    P.grid_threads = P.max_tile_load > 256 ? 1024 : 256;
+    P.grid_threads = 256;
 
     // Per-tile bound on the number of visibilities that add to one cell (gridding scale):
     // count first taps per cell, sum over the J x J window of first taps that reach each
@@ -434,6 +451,23 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
         }
     }
 
+    // FP64 tap weights in sorted order: w[p][a] = psi(f1 + J/2 - 1 - a), w[p][J + a] likewise
+    // for axis 2, from the same per-tap polynomials the FP32 kernels evaluate.
+    std::vector<double> wt;
+    if (f64) {
+        wt.resize((size_t)M * 2 * J);
+        const int nc = deg + 1;
+        for (int64_t q = 0; q < M; ++q)
+            for (int ax = 0; ax < 2; ++ax) {
+                const double x = sfr[2 * q + ax] - 0.5;
+                for (int a = 0; a < J; ++a) {
+                    double acc = kbd[(size_t)a * nc + nc - 1];
+                    for (int k = nc - 2; k >= 0; --k) acc = acc * x + kbd[(size_t)a * nc + k];
+                    wt[(size_t)q * 2 * J + (size_t)ax * J + a] = acc;
+                }
+            }
+    }
+
     // Upload (pageable host memory; synchronous at the end).
     auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
         return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
@@ -456,6 +490,7 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     PURIFY_HIP(up_real(P.tw2, tw2));
     PURIFY_HIP(up_real(P.filters, filt));
     PURIFY_HIP(up_real(P.kbpoly, kbd));
+    if (f64) PURIFY_HIP(up(P.wtab, wt.data(), wt.size() * sizeof(double)));
     PURIFY_HIP(hipMemsetAsync(P.sc, 0, SL_COUNT * sizeof(double), s));
     PURIFY_HIP(hipStreamSynchronize(s));
     return PURIFY_OK;
