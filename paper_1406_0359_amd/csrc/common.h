@@ -75,6 +75,8 @@ enum Slot : int {
 };
 
 constexpr int MAX_PARTIALS = 8192;   // per partial-sum buffer
+constexpr int GRID_UNIT = 1024;      // smallest gridding work unit (visibility passes)
+constexpr int GRID_REC = 16;         // ints per gridding work-unit record
 constexpr int NUM_PARTIAL_BUFS = 8;
 
 // ---------------------------------------------------------------------------------------
@@ -107,6 +109,14 @@ struct Plan {
     int32_t* perm = nullptr;     // M: sorted position -> caller index
     int32_t* tileoff = nullptr;  // 4 nT^2 + 1 class offsets
     int32_t* tilecover = nullptr;  // nT^2: max number of visibilities covering one cell of the tile
+    int32_t* gwork = nullptr;    // gridding work-unit records, GRID_REC ints each
+    int nwork = 0;
+    int grid_unit = 0;           // visibility passes per gridding work unit before a split
+    int32_t* gmerge = nullptr;   // split tiles {tile, parts, first partial slot}
+    int nmerge = 0, gmerge_cap = 0;
+    void* gscratch = nullptr;    // split tiles: one integer partial tile per part
+    int32_t* gexp = nullptr;     // split tiles: scale exponent of each partial tile
+    int gslots = 0;
     void* deap = nullptr;        // n reals
     void* tw = nullptr;          // n complex: exp(-2 pi i t / n)
     void* tw2 = nullptr;         // n complex: exp(-pi i t / n)

@@ -140,159 +140,180 @@ __device__ __forceinline__ void lds_add(typename FixedAcc<T>::I* p, typename Fix
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Contributions of visibilities [start, end) that land in this tile's body (bounds-checked).
-template <typename T, int J, int TT, int GRID_THREADS>
-__device__ __forceinline__ void grid_range(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
-                                           const int32_t* __restrict__ base, const T* __restrict__ frac,
-                                           const T* __restrict__ kbc, const T* __restrict__ wtab,
-                                           int start, int end, int K, int t1o, int t2o, int Jr, T inv_q,
-                                           typename FixedAcc<T>::I* acc) {
-    using Acc = FixedAcc<T>;
-    constexpr int JJ = J > 0 ? J : KB_MAX_J;
-    constexpr int UNR = J > 0 ? J : 1;   // generic width: plain loops
-    const int mask = K - 1;
-    const int Jn = J > 0 ? J : Jr;
-    // visibilities are sorted by cell inside each spill class; each thread takes a contiguous
-    // chunk so the lanes of a wave add to different cells
-    const int chunk = (end - start + GRID_THREADS - 1) / GRID_THREADS;
-    const int c0 = start + (int)threadIdx.x * chunk;
-    const int c1e = min(end, c0 + chunk);
-    for (int idx = c0; idx < c1e; ++idx) {
-        const int b = base[idx];
-        const int k1 = b & 0xFFFF, k2 = (b >> 16) & 0xFFFF;
-        const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[idx];
-        const cpx<T> v = y[perm ? perm[idx] : idx];
-        T wa[JJ], wb[JJ];
-        visibility_weights<T, J>(wtab, kbc, idx, f, wa, wb, Jr);
-#pragma unroll UNR
-        for (int a = 0; a < JJ; ++a) {
-            if (a >= Jn) break;
-            const int c1 = ((k1 + a) & mask) - t1o;
-            if ((unsigned)c1 >= (unsigned)TT) continue;
-            const T s = wa[a] * inv_q;
-            const T vx = s * v.x, vy = s * v.y;
-#pragma unroll UNR
-            for (int bb = 0; bb < JJ; ++bb) {
-                if (bb >= Jn) break;
-                const int c2 = ((k2 + bb) & mask) - t2o;
-                if ((unsigned)c2 < (unsigned)TT) {
-                    lds_add<T>(&acc[2 * (c1 * TT + c2)], Acc::conv(wb[bb] * vx));
-                    lds_add<T>(&acc[2 * (c1 * TT + c2) + 1], Acc::conv(wb[bb] * vy));
-                }
-            }
-        }
-    }
-}
-
-// Own visibilities whose footprint lies inside the tile (spill class 0): no bounds checks;
-// tap (a, bb) is at a fixed offset from the first tap's cell.
-template <typename T, int J, int TT, int GRID_THREADS>
-__device__ __forceinline__ void grid_interior(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
-                                              const int32_t* __restrict__ base, const T* __restrict__ frac,
-                                              const T* __restrict__ kbc, const T* __restrict__ wtab,
-                                              int start, int end, int t1o, int t2o, T inv_q,
-                                              typename FixedAcc<T>::I* acc) {
-    using Acc = FixedAcc<T>;
-    const int chunk = (end - start + GRID_THREADS - 1) / GRID_THREADS;
-    const int i0 = start + (int)threadIdx.x * chunk;
-    const int i1 = min(end, i0 + chunk);
-    for (int idx = i0; idx < i1; ++idx) {
-        const int b = base[idx];
-        const int c1 = (b & 0xFFFF) - t1o, c2 = ((b >> 16) & 0xFFFF) - t2o;
-        const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[idx];
-        const cpx<T> v = y[perm ? perm[idx] : idx];
-        T wa[J], wb[J];
-        visibility_weights<T, J>(wtab, kbc, idx, f, wa, wb, J);
-        typename Acc::I* p = acc + 2 * (c1 * TT + c2);
-#pragma unroll
-        for (int a = 0; a < J; ++a) {
-            const T s = wa[a] * inv_q;
-            const T vx = s * v.x, vy = s * v.y;
-#pragma unroll
-            for (int bb = 0; bb < J; ++bb) {
-                lds_add<T>(p + 2 * (a * TT + bb), Acc::conv(wb[bb] * vx));
-                lds_add<T>(p + 2 * (a * TT + bb) + 1, Acc::conv(wb[bb] * vy));
-            }
-        }
-    }
-}
-
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
 }
 
-// G^T: one workgroup per TT x TT tile; own visibilities plus the three neighbours' spill
-// ranges; fixed-point LDS accumulation; one write of the tile.
-template <typename T, int J, int TT, int GRID_THREADS>
-__global__ void __launch_bounds__(GRID_THREADS)
+// G^T: one work unit per workgroup.  A unit is a TT x TT tile, or one part of a heavy tile
+// whose visibility list was split over several workgroups.  Its visibility passes (its share
+// of the tile's own visibilities and of the three neighbours' spill-ins) form one item list;
+// each thread takes a contiguous chunk (so the lanes of a wave add to different cells) and
+// loads CHR items at a time -- coordinates, weights and values -- before adding any, so the
+// loads of a chunk overlap.  Contributions accumulate in LDS in fixed point (integer
+// atomics: the sum does not depend on the order of the adds).  A whole tile is written to
+// the grid; a part stores its integer partial tile and scale exponent in its own slot, and
+// k_grid_merge sums the parts of each split tile in part order.
+template <typename T, int J, int TT, int NT, int CHR>
+__global__ void __launch_bounds__(NT)
 k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int32_t* __restrict__ base,
        const T* __restrict__ frac, const T* __restrict__ kbc, const T* __restrict__ wtab,
-       const int32_t* __restrict__ off, const int32_t* __restrict__ cover, cpx<T>* __restrict__ grid,
-       int K, int nT, int Jr) {
+       const int32_t* __restrict__ work, typename FixedAcc<T>::I* __restrict__ partial,
+       int32_t* __restrict__ pexp, cpx<T>* __restrict__ grid, int K, int nT, int Jr) {
     using Acc = FixedAcc<T>;
+    constexpr int JJ = J > 0 ? J : KB_MAX_J;
+    constexpr int UNR = J > 0 ? J : 1;
     __shared__ typename Acc::I acc[2 * TT * TT];
-    __shared__ double red[GRID_THREADS / 64];
-    const int tile = blockIdx.x;
-    const int t1 = tile % nT, t2 = tile / nT;
-    const int t1m = (t1 + nT - 1) % nT, t2m = (t2 + nT - 1) % nT;
-    const int L = t2 * nT + t1m, U = t2m * nT + t1, Dg = t2m * nT + t1m;
-    const int t1o = t1 * TT, t2o = t2 * TT;
-    const int s0 = off[4 * tile], s1 = off[4 * tile + 1], s4 = off[4 * tile + 4];
-    const int ls = off[4 * L + 1], le = off[4 * L + 3];
-    const int us = off[4 * U + 2], ue = off[4 * U + 4];
-    const int ds = off[4 * Dg + 2], de = off[4 * Dg + 3];
-    for (int i = threadIdx.x; i < 2 * TT * TT; i += GRID_THREADS) acc[i] = 0;
-    // pass 1: largest component magnitude of y over every visibility touching the tile
+    __shared__ double red[NT / 64];
+    const int32_t* w = work + GRID_REC * blockIdx.x;
+    const int tile = w[0], slot = w[1], cover = w[2], total = w[3];
+    int rs[5], cum[6];
+    cum[0] = 0;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        rs[r] = w[4 + 2 * r];
+        cum[r + 1] = cum[r] + w[5 + 2 * r] - rs[r];
+    }
+    const int t1o = (tile % nT) * TT, t2o = (tile / nT) * TT;
+    const int mask = K - 1;
+    const int Jn = J > 0 ? J : Jr;
+    for (int i = threadIdx.x; i < 2 * TT * TT; i += NT) acc[i] = 0;
+    const int ch = (total + NT - 1) / NT;
+    const int j0 = (int)threadIdx.x * ch;
+    auto item = [&](int j) {
+        int idx = rs[0] + j;
+#pragma unroll
+        for (int r = 1; r < 5; ++r)
+            if (j >= cum[r]) idx = rs[r] + (j - cum[r]);
+        return idx;
+    };
+    // largest component magnitude of y over the unit's items (a separate pass only when a
+    // thread's chunk does not fit in one batch)
     double ym = 0.0;
-    for (int r = 0; r < 4; ++r) {
-        const int st = r == 0 ? s0 : (r == 1 ? ls : (r == 2 ? us : ds));
-        const int en = r == 0 ? s4 : (r == 1 ? le : (r == 2 ? ue : de));
-        for (int idx = st + (int)threadIdx.x; idx < en; idx += GRID_THREADS) {
-            const cpx<T> v = y[perm ? perm[idx] : idx];
-            ym = fmax(ym, fmax(fabs((double)v.x), fabs((double)v.y)));
+    if (ch > CHR) {
+        for (int s = 0; s < ch; ++s) {
+            const int j = j0 + s;
+            if (j < total) {
+                const int idx = item(j);
+                const cpx<T> v = y[perm ? perm[idx] : idx];
+                ym = fmax(ym, fmax(fabs((double)v.x), fabs((double)v.y)));
+            }
         }
     }
-    ym = wave_max(ym);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ym;
-    __syncthreads();
-    ym = 0.0;
+    T inv_q = 0;
+    int e = 0;
+    bool any = false;
+    for (int s0 = 0; s0 < ch; s0 += CHR) {
+        int bk[CHR];
+        cpx<T> vv[CHR];
+        T wa[CHR][JJ], wb[CHR][JJ];
+        bool ok[CHR];
 #pragma unroll
-    for (int w = 0; w < GRID_THREADS / 64; ++w) ym = fmax(ym, red[w]);
-    // quantum q = 2^e with 2 * cover * max|y| <= 2^BITS q (at most `cover` visibilities add
-    // to one cell, each by at most max|y|, psi <= 1, factor 2 margin) and
-    // 2 * max|y| <= 2^CBITS q (one contribution)
-    const double bound = 2.0 * (double)cover[tile] * ym;
-    const int e = bound > 0.0 ? max(ilogb(bound) + 1 - Acc::BITS, ilogb(2.0 * ym) + 1 - Acc::CBITS) : 0;
-    const T inv_q = (T)ldexp(1.0, -e);
-    const T q = (T)ldexp(1.0, e);
-    if (bound > 0.0) {
-        if constexpr (J > 0) grid_interior<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, s0, s1, t1o, t2o, inv_q, acc);
-        else grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, s0, s1, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, s1, s4, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, ls, le, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, us, ue, K, t1o, t2o, Jr, inv_q, acc);
-        grid_range<T, J, TT, GRID_THREADS>(y, perm, base, frac, kbc, wtab, ds, de, K, t1o, t2o, Jr, inv_q, acc);
+        for (int c = 0; c < CHR; ++c) {
+            const int j = j0 + s0 + c;
+            ok[c] = s0 + c < ch && j < total;
+            if (ok[c]) {
+                const int idx = item(j);
+                bk[c] = base[idx];
+                const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[idx];
+                vv[c] = y[perm ? perm[idx] : idx];
+                visibility_weights<T, J>(wtab, kbc, idx, f, wa[c], wb[c], Jr);
+                if (ch <= CHR) ym = fmax(ym, fmax(fabs((double)vv[c].x), fabs((double)vv[c].y)));
+            }
+        }
+        if (s0 == 0) {
+            ym = wave_max(ym);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ym;
+            __syncthreads();
+            ym = 0.0;
+#pragma unroll
+            for (int wv = 0; wv < NT / 64; ++wv) ym = fmax(ym, red[wv]);
+            // quantum q = 2^e with 2 * cover * max|y| <= 2^BITS q (at most `cover`
+            // visibilities add to one cell, each by at most max|y|, psi <= 1, factor 2
+            // margin) and 2 * max|y| <= 2^CBITS q (one contribution)
+            const double bound = 2.0 * (double)cover * ym;
+            any = bound > 0.0;
+            e = any ? max(ilogb(bound) + 1 - Acc::BITS, ilogb(2.0 * ym) + 1 - Acc::CBITS) : 0;
+            inv_q = (T)ldexp(1.0, -e);
+        }
+        if (!any) break;
+#pragma unroll
+        for (int c = 0; c < CHR; ++c) {
+            if (!ok[c]) continue;
+            const int k1 = bk[c] & 0xFFFF, k2 = (bk[c] >> 16) & 0xFFFF;
+#pragma unroll UNR
+            for (int a = 0; a < JJ; ++a) {
+                if (a >= Jn) break;
+                const int c1 = ((k1 + a) & mask) - t1o;
+                if ((unsigned)c1 >= (unsigned)TT) continue;
+                const T sc = wa[c][a] * inv_q;
+                const T vx = sc * vv[c].x, vy = sc * vv[c].y;
+#pragma unroll UNR
+                for (int bb = 0; bb < JJ; ++bb) {
+                    if (bb >= Jn) break;
+                    const int c2 = ((k2 + bb) & mask) - t2o;
+                    if ((unsigned)c2 < (unsigned)TT) {
+                        lds_add<T>(&acc[2 * (c1 * TT + c2)], Acc::conv(wb[c][bb] * vx));
+                        lds_add<T>(&acc[2 * (c1 * TT + c2) + 1], Acc::conv(wb[c][bb] * vy));
+                    }
+                }
+            }
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < TT * TT; i += GRID_THREADS) {
+    if (slot < 0) {
+        const T q = (T)ldexp(1.0, e);
+        for (int i = threadIdx.x; i < TT * TT; i += NT) {
+            const int r = i / TT, c = i % TT;
+            grid[(size_t)(t1o + r) * K + t2o + c] = mk<T>(q * (T)acc[2 * i], q * (T)acc[2 * i + 1]);
+        }
+        return;
+    }
+    typename Acc::I* pt = partial + (size_t)slot * 2 * TT * TT;
+    for (int i = threadIdx.x; i < 2 * TT * TT; i += NT) pt[i] = acc[i];
+    if (threadIdx.x == 0) pexp[slot] = e;
+}
+
+// Sum of the partial tiles of each split tile (one workgroup per split tile), in part order
+// and in double, then written to the grid.
+template <typename T, int TT>
+__global__ void __launch_bounds__(256)
+k_grid_merge(const int32_t* __restrict__ merge, const typename FixedAcc<T>::I* __restrict__ partial,
+             const int32_t* __restrict__ pexp, cpx<T>* __restrict__ grid, int K, int nT) {
+    const int tile = merge[3 * blockIdx.x], parts = merge[3 * blockIdx.x + 1];
+    const int slot0 = merge[3 * blockIdx.x + 2];
+    const int t1o = (tile % nT) * TT, t2o = (tile / nT) * TT;
+    for (int i = threadIdx.x; i < TT * TT; i += 256) {
+        double sr = 0.0, si = 0.0;
+        for (int p = 0; p < parts; ++p) {
+            const typename FixedAcc<T>::I* pt = partial + (size_t)(slot0 + p) * 2 * TT * TT;
+            const int e = pexp[slot0 + p];
+            sr += ldexp((double)pt[2 * i], e);
+            si += ldexp((double)pt[2 * i + 1], e);
+        }
         const int r = i / TT, c = i % TT;
-        grid[(size_t)(t1o + r) * K + t2o + c] = mk<T>(q * (T)acc[2 * i], q * (T)acc[2 * i + 1]);
+        grid[(size_t)(t1o + r) * K + t2o + c] = mk<T>((T)sr, (T)si);
     }
 }
 
 template <typename T, int TT, int NT>
 void grid_tt(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* grid, hipStream_t s) {
-    const dim3 g(P.nT * P.nT), b(NT);
+    const dim3 g(P.nwork), b(NT);
+    using I = typename FixedAcc<T>::I;
+    constexpr int C = sizeof(T) == 8 ? 2 : 4;   // items per batch (register budget)
+    I* scr = (I*)P.gscratch;
     const T* fr = (const T*)P.frac;
     const T* kbc = (const T*)P.kbpoly;
+    const T* wt = (const T*)P.wtab;
     switch (P.J) {
-        case 4: hipLaunchKernelGGL((k_grid<T, 4, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, (const T*)P.wtab, P.tileoff, P.tilecover, grid, P.K, P.nT, 4); break;
-        case 6: hipLaunchKernelGGL((k_grid<T, 6, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, (const T*)P.wtab, P.tileoff, P.tilecover, grid, P.K, P.nT, 6); break;
-        case 8: hipLaunchKernelGGL((k_grid<T, 8, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, (const T*)P.wtab, P.tileoff, P.tilecover, grid, P.K, P.nT, 8); break;
-        default: hipLaunchKernelGGL((k_grid<T, 0, TT, NT>), g, b, 0, s, y, perm, P.base, fr, kbc, (const T*)P.wtab, P.tileoff, P.tilecover, grid, P.K, P.nT, P.J); break;
+        case 4: hipLaunchKernelGGL((k_grid<T, 4, TT, NT, C>), g, b, 0, s, y, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, 4); break;
+        case 6: hipLaunchKernelGGL((k_grid<T, 6, TT, NT, C>), g, b, 0, s, y, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, 6); break;
+        case 8: hipLaunchKernelGGL((k_grid<T, 8, TT, NT, C>), g, b, 0, s, y, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, 8); break;
+        default: hipLaunchKernelGGL((k_grid<T, 0, TT, NT, 1>), g, b, 0, s, y, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, P.J); break;
     }
+    if (P.nmerge > 0)
+        hipLaunchKernelGGL((k_grid_merge<T, TT>), dim3(P.nmerge), dim3(256), 0, s, P.gmerge, scr, P.gexp, grid, P.K, P.nT);
 }
 
 }  // namespace

@@ -266,6 +266,25 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
     P.perm = (int32_t*)carve(M * 4);
     P.tileoff = (int32_t*)carve(((size_t)4 * P.nT * P.nT + 1) * 4);
     P.tilecover = (int32_t*)carve((size_t)P.nT * P.nT * 4);
+    // Gridding work units: a tile whose visibility list (own + spill-ins) exceeds
+    // the unit U is split over several workgroups, each writing a private partial tile that a
+    // second kernel sums.  A visibility is in at most four tiles' lists, so a split tile
+    // (load > U) has parts = ceil(load / U) < 2 load / U, the parts of all split tiles number
+    // below 8M / U and split tiles below 4M / U.
+    // The unit grows with M / tiles so that the partial tiles never exceed four grids.
+    {
+        const size_t tiles = (size_t)P.nT * P.nT;
+        P.grid_unit = (int)std::max<int64_t>(GRID_UNIT, (2 * (int64_t)M + (int64_t)tiles - 1) / (int64_t)tiles);
+        const size_t parts_max = (size_t)(8 * M / P.grid_unit) + 1;
+        const size_t split_max = std::min(tiles, (size_t)(4 * M / P.grid_unit) + 1);
+        P.gslots = (int)parts_max;
+        P.gmerge_cap = (int)split_max;
+        P.gwork = (int32_t*)carve((tiles + parts_max) * GRID_REC * sizeof(int32_t));
+        P.gmerge = (int32_t*)carve(split_max * 3 * sizeof(int32_t));
+        const size_t ib = P.precision == PURIFY_FP64 ? 8 : 4;
+        P.gscratch = carve(parts_max * 2 * (size_t)P.TT * P.TT * ib);
+        P.gexp = (int32_t*)carve(parts_max * sizeof(int32_t));
+    }
     P.deap = carve(P.n * es);
     P.tw = carve(P.n * ce);
     P.tw2 = carve(P.n * ce);
@@ -420,7 +439,6 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
             P.max_tile_load = std::max(P.max_tile_load, load);
         }
     P.grid_threads = 256;
-
     // Per-tile bound on the number of visibilities that add to one cell (gridding scale):
     // count first taps per cell, sum over the J x J window of first taps that reach each
     // cell (cyclic), and take the maximum over each tile.
@@ -449,6 +467,70 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
                 if (acc > cv) cv = acc;
             }
         }
+    }
+
+    // Work list: heavy tiles first (their parts start earliest), then the rest.  One record
+    // of GRID_REC ints per work unit: {tile, partial slot or -1, cover, visibility passes,
+    // then [start, end) of its share of the tile's five visibility ranges: own interior, own
+    // spilling, and the left, upper and diagonal neighbours' spill-ins}.  Merge list: one
+    // entry {tile, parts, first partial slot} per split tile.
+    std::vector<int32_t> work, merge;
+    {
+        std::vector<std::pair<int, int>> load_tile;   // (load, tile)
+        auto ranges = [&](int t, int* s, int* e) {
+            const int t1 = t % nT, t2 = t / nT;
+            const int L = t2 * nT + (t1 + nT - 1) % nT, U = ((t2 + nT - 1) % nT) * nT + t1;
+            const int Dg = ((t2 + nT - 1) % nT) * nT + (t1 + nT - 1) % nT;
+            s[0] = off[4 * t];      e[0] = off[4 * t + 1];
+            s[1] = off[4 * t + 1];  e[1] = off[4 * t + 4];
+            s[2] = off[4 * L + 1];  e[2] = off[4 * L + 3];
+            s[3] = off[4 * U + 2];  e[3] = off[4 * U + 4];
+            s[4] = off[4 * Dg + 2]; e[4] = off[4 * Dg + 3];
+        };
+        for (int t = 0; t < nT * nT; ++t) {
+            int s[5], e[5], load = 0;
+            ranges(t, s, e);
+            for (int r = 0; r < 5; ++r) load += e[r] - s[r];
+            load_tile.push_back({load, t});
+        }
+        std::stable_sort(load_tile.begin(), load_tile.end(),
+                         [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first > b.first; });
+        int slot = 0;
+        for (const auto& lt : load_tile) {
+            const int t = lt.second;
+            const int parts = std::max(1, (lt.first + P.grid_unit - 1) / P.grid_unit);
+            int s[5], e[5];
+            ranges(t, s, e);
+            for (int q = 0; q < parts; ++q) {
+                int32_t rec[GRID_REC] = {};
+                rec[0] = t;
+                rec[1] = parts > 1 ? slot + q : -1;
+                rec[2] = cover[t];
+                int total = 0;
+                for (int r = 0; r < 5; ++r) {
+                    // part q of parts takes [s + len q / parts, s + len (q + 1) / parts)
+                    const int64_t len = e[r] - s[r];
+                    rec[4 + 2 * r] = s[r] + (int)(len * q / parts);
+                    rec[5 + 2 * r] = s[r] + (int)(len * (q + 1) / parts);
+                    total += rec[5 + 2 * r] - rec[4 + 2 * r];
+                }
+                rec[3] = total;
+                work.insert(work.end(), rec, rec + GRID_REC);
+            }
+            if (parts > 1) {
+                merge.push_back(t);
+                merge.push_back(parts);
+                merge.push_back(slot);
+                slot += parts;
+            }
+        }
+        const size_t work_cap = (size_t)nT * nT + (size_t)P.gslots;
+        if (slot > P.gslots || (int)(merge.size() / 3) > P.gmerge_cap || work.size() / GRID_REC > work_cap) {
+            set_error("internal: gridding work list exceeds its bound");
+            return PURIFY_E_INVALID;
+        }
+        P.nwork = (int)(work.size() / GRID_REC);
+        P.nmerge = (int)(merge.size() / 3);
     }
 
     // FP64 tap weights in sorted order: w[p][a] = psi(f1 + J/2 - 1 - a), w[p][J + a] likewise
@@ -484,6 +566,8 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     PURIFY_HIP(up(P.perm, perm.data(), M * 4));
     PURIFY_HIP(up(P.tileoff, off.data(), off.size() * 4));
     PURIFY_HIP(up(P.tilecover, cover.data(), cover.size() * 4));
+    PURIFY_HIP(up(P.gwork, work.data(), work.size() * sizeof(int32_t)));
+    if (!merge.empty()) PURIFY_HIP(up(P.gmerge, merge.data(), merge.size() * sizeof(int32_t)));
     PURIFY_HIP(up_real(P.frac, sfr));
     PURIFY_HIP(up_real(P.deap, deap));
     PURIFY_HIP(up_real(P.tw, tw));

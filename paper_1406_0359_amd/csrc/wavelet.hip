@@ -7,9 +7,9 @@
 // with g[k] = (-1)^k h[2N-1-k]; a level filters axis 1 then axis 0 of the top-left Ls x Ls
 // block and the next level recurses on its LL quarter.  Synthesis is the exact transpose.
 //
-// All wavelet bases run in the same launch (blockIdx.z = basis); a level is two separable
-// passes through a per-basis temporary so no launch reads what it writes.  The finest
-// synthesis pass sums every basis (and the Dirac block) and writes the image once.
+// All wavelet bases run in the same launch; a level is one launch of 2D tiles (both axes
+// through LDS).  The finest synthesis level sums every basis (and the Dirac block) per
+// output tile and writes the image once.
 #include "common.h"
 
 namespace purify {
@@ -23,153 +23,268 @@ struct WavArgs {
     int dirac_block;      // -1 if no Dirac basis
 };
 
-// filters layout: [basis][0..15] = h, [basis][16..31] = g
+// filters layout: [basis][0..15] = h, [basis][16..31] = g.  Kernels stage a basis' taps in
+// LDS (lanes index them by output parity, which a register array cannot serve).
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_dwt_rows_fwd(const cpx<T>* __restrict__ src, int src_stride_basis, cpx<T>* __restrict__ wt,
-               const T* __restrict__ filt, WavArgs A, int Ls, T scale) {
-    const int i = blockIdx.z;
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= Ls * Ls) return;
-    const int n = A.n;
-    const int r = idx / Ls, o = idx % Ls;
-    const int half = Ls >> 1;
-    const bool hi = o >= half;
-    const int oi = hi ? o - half : o;
-    const T* f = filt + i * 2 * MAX_TAPS + (hi ? MAX_TAPS : 0);
-    const cpx<T>* s = src + (size_t)A.block[i] * src_stride_basis + (size_t)r * n;
-    if (src_stride_basis == 0) s = src + (size_t)r * n;
-    const int F = A.flen[i];
-    T ax = 0, ay = 0;
-    int pos = (2 * oi) % Ls;
-    for (int k = 0; k < F; ++k) {
-        const cpx<T> v = s[pos];
-        ax += f[k] * v.x;
-        ay += f[k] * v.y;
-        if (++pos == Ls) pos = 0;
-    }
-    wt[(size_t)i * n * n + (size_t)r * n + o] = mk<T>(scale * ax, scale * ay);
+__device__ __forceinline__ void load_taps(T* sh, const T* __restrict__ filt, int basis) {
+    if (threadIdx.x < 2 * MAX_TAPS) sh[threadIdx.x] = filt[basis * 2 * MAX_TAPS + threadIdx.x];
 }
 
+// Every level is one launch of 2D tiles over all bases, both axes through LDS.  Each thread
+// computes output pairs that read the same inputs: the lowpass and highpass coefficient at
+// one position (analysis), or the even and odd sample from one window of coefficients
+// (synthesis), so every LDS read feeds two outputs.
+constexpr int AP = 16;                      // analysis tile: outputs per axis per subband (max)
+constexpr int AR = 2 * AP + MAX_TAPS - 2;   // analysis tile: input rows/cols needed (max, even)
+constexpr int SP = 32;                      // synthesis tile: outputs per axis (max)
+constexpr int SC = SP / 2 + MAX_TAPS / 2 - 1;   // synthesis window per axis per subband (max)
+
+// One analysis level on a tile: coefficients at positions [ap ti1, ap ti1 + ap) x
+// [ap ti2, ...) of all four subbands of the Ls x Ls block (ap = min(AP, Ls/2)), from the
+// (2 ap + F - 2)^2 input window starting at (2 ap ti1, 2 ap ti2) (periodic).  Axis 1 is
+// filtered first, then axis 0.  Window rows are stored even samples first, then odd, so
+// lanes with consecutive outputs read consecutive LDS words.  src: the image (level 0,
+// shared by all bases, times `scale`; src_bstride = 0) or the previous level's LL blocks
+// (compact slots).  Detail subbands go to the alpha block; the LL subband goes to `llout`
+// (compact slots of (n/2)^2 per basis, row stride Ls/2), or into the alpha block at the
+// coarsest level (llout == null), so no launch reads what it writes.  blockIdx.z == nwav
+// copies the image into the Dirac block instead.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_dwt_cols_fwd(const cpx<T>* __restrict__ wt, cpx<T>* __restrict__ alpha, const T* __restrict__ filt,
-               WavArgs A, int Ls) {
-    const int i = blockIdx.z;
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= Ls * Ls) return;
-    const int n = A.n;
-    const int o = idx / Ls, c = idx % Ls;
-    const int half = Ls >> 1;
-    const bool hi = o >= half;
-    const int oi = hi ? o - half : o;
-    const T* f = filt + i * 2 * MAX_TAPS + (hi ? MAX_TAPS : 0);
-    const cpx<T>* s = wt + (size_t)i * n * n + c;
-    const int F = A.flen[i];
-    T ax = 0, ay = 0;
-    int pos = (2 * oi) % Ls;
-    for (int k = 0; k < F; ++k) {
-        const cpx<T> v = s[(size_t)pos * n];
-        ax += f[k] * v.x;
-        ay += f[k] * v.y;
-        if (++pos == Ls) pos = 0;
-    }
-    alpha[(size_t)A.block[i] * n * n + (size_t)o * n + c] = mk<T>(ax, ay);
-}
-
-__device__ __forceinline__ int pmod(int a, int m) {
-    int r = a % m;
-    return r < 0 ? r + m : r;
-}
-
-// Transpose of the axis-0 analysis of one level: rows [0, half) of the block are the
-// lowpass (LL from `ll` when given, the rest from alpha), rows [half, Ls) the highpass.
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_dwt_cols_inv(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ ll, cpx<T>* __restrict__ wt,
-               const T* __restrict__ filt, WavArgs A, int Ls) {
-    const int i = blockIdx.z;
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= Ls * Ls) return;
+k_wav_fwd_level(const cpx<T>* __restrict__ src, size_t src_bstride, int src_ld, cpx<T>* __restrict__ alpha,
+                cpx<T>* __restrict__ llout, const T* __restrict__ filt, WavArgs A, int Ls, T scale) {
+    constexpr int IS = AR + 1, MS = 2 * AP + 1;
+    __shared__ cpx<T> in[AR * IS];
+    __shared__ cpx<T> mid[AR * MS];
+    __shared__ T tp[2 * MAX_TAPS];
     const int n = A.n;
     const size_t N = (size_t)n * n;
-    const int m = idx / Ls, c = idx % Ls;
     const int half = Ls >> 1;
-    const T* h = filt + i * 2 * MAX_TAPS;
-    const T* g = h + MAX_TAPS;
-    const cpx<T>* al = alpha + (size_t)A.block[i] * N;
-    const cpx<T>* lo = (ll && c < half) ? ll + (size_t)i * N : al;
-    const int F = A.flen[i];
-    T ax = 0, ay = 0;
-    for (int k = m & 1; k < F; k += 2) {
-        const int ii = pmod((m - k) / 2, half);
-        const cpx<T> a = lo[(size_t)ii * n + c];
-        const cpx<T> d = al[(size_t)(half + ii) * n + c];
-        ax += h[k] * a.x + g[k] * d.x;
-        ay += h[k] * a.y + g[k] * d.y;
-    }
-    wt[(size_t)i * N + (size_t)m * n + c] = mk<T>(ax, ay);
-}
-
-// Transpose of the axis-1 analysis; writes the basis' LL for the next finer level.
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_dwt_rows_inv(const cpx<T>* __restrict__ wt, cpx<T>* __restrict__ out, const T* __restrict__ filt,
-               WavArgs A, int Ls) {
-    const int i = blockIdx.z;
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= Ls * Ls) return;
-    const int n = A.n;
-    const size_t N = (size_t)n * n;
-    const int r = idx / Ls, m = idx % Ls;
-    const int half = Ls >> 1;
-    const T* h = filt + i * 2 * MAX_TAPS;
-    const T* g = h + MAX_TAPS;
-    const cpx<T>* s = wt + (size_t)i * N + (size_t)r * n;
-    const int F = A.flen[i];
-    T ax = 0, ay = 0;
-    for (int k = m & 1; k < F; k += 2) {
-        const int ii = pmod((m - k) / 2, half);
-        const cpx<T> a = s[ii];
-        const cpx<T> d = s[half + ii];
-        ax += h[k] * a.x + g[k] * d.x;
-        ay += h[k] * a.y + g[k] * d.y;
-    }
-    out[(size_t)i * N + (size_t)r * n + m] = mk<T>(ax, ay);
-}
-
-// Finest synthesis level: axis-1 transpose for every basis, summed with the Dirac block,
-// scaled by 1/sqrt(q), written to the image.
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_dwt_rows_inv_sum(const cpx<T>* __restrict__ wt, const cpx<T>* __restrict__ alpha, cpx<T>* __restrict__ x,
-                   const T* __restrict__ filt, WavArgs A, T scale) {
-    const int n = A.n;
-    const size_t N = (size_t)n * n;
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (int)N) return;
-    const int r = idx / n, m = idx % n;
-    const int half = n >> 1;
-    T ax = 0, ay = 0;
-    if (A.dirac_block >= 0) {
-        const cpx<T> v = alpha[(size_t)A.dirac_block * N + idx];
-        ax = v.x;
-        ay = v.y;
-    }
-    for (int i = 0; i < A.nwav; ++i) {
-        const T* h = filt + i * 2 * MAX_TAPS;
-        const T* g = h + MAX_TAPS;
-        const cpx<T>* s = wt + (size_t)i * N + (size_t)r * n;
-        const int F = A.flen[i];
-        for (int k = m & 1; k < F; k += 2) {
-            const int ii = pmod((m - k) / 2, half);
-            const cpx<T> a = s[ii];
-            const cpx<T> d = s[half + ii];
-            ax += h[k] * a.x + g[k] * d.x;
-            ay += h[k] * a.y + g[k] * d.y;
+    const int ap = half < AP ? half : AP;
+    const int tiles = half / ap;
+    const int ti1 = blockIdx.x / tiles, ti2 = blockIdx.x % tiles;
+    const int r0 = 2 * ap * ti1, c0 = 2 * ap * ti2;
+    const int z = blockIdx.z;
+    if (z == A.nwav) {
+        cpx<T>* d = alpha + (size_t)A.dirac_block * N;
+        for (int i = threadIdx.x; i < 4 * ap * ap; i += 256) {
+            const size_t o = (size_t)(r0 + i / (2 * ap)) * n + c0 + i % (2 * ap);
+            d[o] = scale * src[o];
         }
+        return;
     }
-    x[idx] = mk<T>(scale * ax, scale * ay);
+    const size_t blk = (size_t)A.block[z] * N;
+    const cpx<T>* s = src + (size_t)z * src_bstride;
+    const int F = A.flen[z];
+    const int R = 2 * ap + F - 2, RH = R >> 1;
+    load_taps(tp, filt, z);
+    for (int i = threadIdx.x; i < R * R; i += 256) {
+        const int a = i / R, b = i - a * R;
+        in[a * IS + (b & 1) * RH + (b >> 1)] =
+            s[(size_t)((r0 + a) & (Ls - 1)) * src_ld + ((c0 + b) & (Ls - 1))];
+    }
+    __syncthreads();
+    // axis 1: window row a, position oi -> mid[a][oi] (low), mid[a][ap + oi] (high)
+    for (int i = threadIdx.x; i < R * ap; i += 256) {
+        const int a = i / ap, oi = i - a * ap;
+        const cpx<T>* row = in + a * IS + oi;
+        T lx = 0, ly = 0, hx = 0, hy = 0;
+#pragma unroll
+        for (int k = 0; k < MAX_TAPS; ++k) {
+            if (k >= F) break;
+            const cpx<T> v = row[(k & 1) * RH + (k >> 1)];
+            const T h = tp[k], g = tp[MAX_TAPS + k];
+            lx += h * v.x;
+            ly += h * v.y;
+            hx += g * v.x;
+            hy += g * v.y;
+        }
+        mid[a * MS + oi] = mk<T>(lx, ly);
+        mid[a * MS + ap + oi] = mk<T>(hx, hy);
+    }
+    __syncthreads();
+    // axis 0: position oi, column o1 (low | high along axis 1) -> both axis-0 subbands
+    for (int i = threadIdx.x; i < 2 * ap * ap; i += 256) {
+        const int oi = i / (2 * ap), o1 = i - oi * (2 * ap);
+        const cpx<T>* col = mid + 2 * oi * MS + o1;
+        T lx = 0, ly = 0, hx = 0, hy = 0;
+#pragma unroll
+        for (int k = 0; k < MAX_TAPS; ++k) {
+            if (k >= F) break;
+            const cpx<T> v = col[k * MS];
+            const T h = tp[k], g = tp[MAX_TAPS + k];
+            lx += h * v.x;
+            ly += h * v.y;
+            hx += g * v.x;
+            hy += g * v.y;
+        }
+        const int row = ap * ti1 + oi;
+        const int cl = (o1 >= ap ? half + o1 - ap : o1) + ap * ti2;
+        if (o1 < ap && llout) llout[(size_t)z * (N / 4) + (size_t)row * half + cl] = mk<T>(scale * lx, scale * ly);
+        else alpha[blk + (size_t)row * n + cl] = mk<T>(scale * lx, scale * ly);
+        alpha[blk + (size_t)(half + row) * n + cl] = mk<T>(scale * hx, scale * hy);
+    }
+}
+
+// Synthesis of one level on a po x po output tile (po = min(SP, Ls)) of one basis: loads
+// the window of the four subbands the tile reaches (po/2 + F/2 - 1 positions per axis per
+// subband, periodic) into `in`, undoes axis 0 into `mid`, then axis 1; returns the thread's
+// outputs (pairs of adjacent samples along axis 1) through `emit`.
+// Window layout: rows [0, C) lowpass and [C, 2C) highpass along axis 0, columns likewise.
+template <typename T, int NTH, int CMAX, typename Emit>
+__device__ __forceinline__ void synth_tile(const cpx<T>* __restrict__ alpha, size_t blk, const cpx<T>* __restrict__ lls,
+                                          int lld, int n, int half, int po, int m0, int m1, int F,
+                                          const T* tp, cpx<T>* in, cpx<T>* mid, int tid, Emit emit) {
+    constexpr int WS = 2 * CMAX + 1;   // LDS row stride of `in` and `mid`
+    const int C = po / 2 + F / 2 - 1;
+    const int s0 = m0 / 2 - F / 2 + 1, s1 = m1 / 2 - F / 2 + 1;   // first window index
+    for (int i = tid; i < 4 * C * C; i += NTH) {
+        const int u = i / (2 * C), v = i - u * (2 * C);
+        const bool h0 = u >= C, h1 = v >= C;
+        const int i0 = (s0 + (h0 ? u - C : u)) & (half - 1), i1 = (s1 + (h1 ? v - C : v)) & (half - 1);
+        cpx<T> val;
+        if (!h0 && !h1) val = lls[(size_t)i0 * lld + i1];
+        else val = alpha[blk + (size_t)(i0 + (h0 ? half : 0)) * n + i1 + (h1 ? half : 0)];
+        in[u * WS + v] = val;
+    }
+    __syncthreads();
+    // undo axis 0: output rows 2j, 2j+1 (j = m0/2 + jr) for every window column v
+    const int hp = po / 2;
+    for (int i = tid; i < hp * 2 * C; i += NTH) {
+        const int jr = i / (2 * C), v = i - jr * (2 * C);
+        T ex = 0, ey = 0, ox = 0, oy = 0;
+#pragma unroll
+        for (int t = 0; t < MAX_TAPS / 2; ++t) {
+            if (2 * t >= F) break;
+            const int u = jr + F / 2 - 1 - t;   // window row of index j - t
+            const cpx<T> lo = in[u * WS + v], hv = in[(C + u) * WS + v];
+            const T he = tp[2 * t], ge = tp[MAX_TAPS + 2 * t];
+            const T ho = tp[2 * t + 1], go = tp[MAX_TAPS + 2 * t + 1];
+            ex += he * lo.x + ge * hv.x;
+            ey += he * lo.y + ge * hv.y;
+            ox += ho * lo.x + go * hv.x;
+            oy += ho * lo.y + go * hv.y;
+        }
+        mid[(2 * jr) * WS + v] = mk<T>(ex, ey);
+        mid[(2 * jr + 1) * WS + v] = mk<T>(ox, oy);
+    }
+    __syncthreads();
+    // undo axis 1: row r, output columns 2j, 2j+1
+    for (int i = tid; i < po * hp; i += NTH) {
+        const int r = i / hp, jc = i - r * hp;
+        T ex = 0, ey = 0, ox = 0, oy = 0;
+#pragma unroll
+        for (int t = 0; t < MAX_TAPS / 2; ++t) {
+            if (2 * t >= F) break;
+            const int v = jc + F / 2 - 1 - t;
+            const cpx<T> lo = mid[r * WS + v], hv = mid[r * WS + C + v];
+            const T he = tp[2 * t], ge = tp[MAX_TAPS + 2 * t];
+            const T ho = tp[2 * t + 1], go = tp[MAX_TAPS + 2 * t + 1];
+            ex += he * lo.x + ge * hv.x;
+            ey += he * lo.y + ge * hv.y;
+            ox += ho * lo.x + go * hv.x;
+            oy += ho * lo.y + go * hv.y;
+        }
+        emit(i, r, 2 * jc, mk<T>(ex, ey), mk<T>(ox, oy));
+    }
+}
+
+// One synthesis level (output side Ls, level >= 1) for every basis (blockIdx.z): the
+// coarser LL comes from `llin` (compact slots of (n/2)^2 per basis) or, at the coarsest
+// level, from the alpha block; the result goes to `out` (compact slots, row stride Ls).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_wav_inv_level(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ llin, int ll_from_alpha,
+                cpx<T>* __restrict__ out, const T* __restrict__ filt, WavArgs A, int Ls) {
+    constexpr int WS = 2 * SC + 1;
+    __shared__ cpx<T> in[2 * SC * WS];
+    __shared__ cpx<T> mid[SP * WS];
+    __shared__ T tp[2 * MAX_TAPS];
+    const int n = A.n;
+    const size_t N = (size_t)n * n;
+    const int half = Ls >> 1;
+    const int po = Ls < SP ? Ls : SP;
+    const int tiles = Ls / po;
+    const int m0 = po * (blockIdx.x / tiles), m1 = po * (blockIdx.x % tiles);
+    const int z = blockIdx.z;
+    const size_t blk = (size_t)A.block[z] * N;
+    const cpx<T>* lls = ll_from_alpha ? alpha + blk : llin + (size_t)z * (N / 4);
+    const int lld = ll_from_alpha ? n : half;
+    load_taps(tp, filt, z);
+    cpx<T>* o = out + (size_t)z * (N / 4);
+    synth_tile<T, 256, SC>(alpha, blk, lls, lld, n, half, po, m0, m1, A.flen[z], tp, in, mid, (int)threadIdx.x,
+                       [&](int, int r, int c, cpx<T> e, cpx<T> od) {
+                           o[(size_t)(m0 + r) * Ls + m1 + c] = e;
+                           o[(size_t)(m0 + r) * Ls + m1 + c + 1] = od;
+                       });
+}
+
+// Finest synthesis level: the image tile (16 x 16) sums every basis plus the Dirac block,
+// times `scale`.  NSLOT groups of 256 threads synthesise different bases concurrently and
+// their partial sums are added in slot order (a fixed order: deterministic).
+constexpr int FP = 16;
+constexpr int NSLOT = 4;
+template <typename T>
+__global__ void __launch_bounds__(256 * NSLOT)
+k_wav_inv_final(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ llin, int ll_from_alpha,
+                cpx<T>* __restrict__ x, const T* __restrict__ filt, WavArgs A, T scale) {
+    constexpr int CF = FP / 2 + MAX_TAPS / 2 - 1;
+    constexpr int WS = 2 * CF + 1;
+    __shared__ cpx<T> in[NSLOT][2 * CF * WS];
+    __shared__ cpx<T> mid[NSLOT][FP * WS];
+    __shared__ T tp[NSLOT][2 * MAX_TAPS];
+    __shared__ cpx<T> part[NSLOT][FP * FP];
+    const int n = A.n;
+    const size_t N = (size_t)n * n;
+    const int half = n >> 1;
+    const int tiles = n / FP;
+    const int m0 = FP * (blockIdx.x / tiles), m1 = FP * (blockIdx.x % tiles);
+    const int slot = threadIdx.x >> 8, tid = threadIdx.x & 255;
+    // each thread owns outputs (r, 2jc), (r, 2jc+1) for i = tid < FP * FP / 2
+    cpx<T> acc0 = mk<T>(0, 0), acc1 = mk<T>(0, 0);
+    const int rounds = (A.nwav + NSLOT - 1) / NSLOT;
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int z = rd * NSLOT + slot;
+        const bool active = z < A.nwav;
+        const int zz = active ? z : 0;
+        const size_t blk = (size_t)A.block[zz] * N;
+        const cpx<T>* lls = ll_from_alpha ? alpha + blk : llin + (size_t)zz * (N / 4);
+        const int lld = ll_from_alpha ? n : half;
+        if (rd > 0) __syncthreads();
+        if (tid < 2 * MAX_TAPS) tp[slot][tid] = filt[zz * 2 * MAX_TAPS + tid];
+        // inactive slots run on basis 0 and discard the result (keeps the barriers uniform)
+        synth_tile<T, 256, CF>(alpha, blk, lls, lld, n, half, FP, m0, m1, A.flen[zz], tp[slot], in[slot], mid[slot],
+                           tid, [&](int, int, int, cpx<T> e, cpx<T> od) {
+                               if (active) {
+                                   acc0.x += e.x;
+                                   acc0.y += e.y;
+                                   acc1.x += od.x;
+                                   acc1.y += od.y;
+                               }
+                           });
+    }
+    if (tid < FP * FP / 2) {
+        const int r = tid / (FP / 2), c = 2 * (tid % (FP / 2));
+        part[slot][r * FP + c] = acc0;
+        part[slot][r * FP + c + 1] = acc1;
+    }
+    __syncthreads();
+    if (threadIdx.x < FP * FP) {
+        const int r = threadIdx.x / FP, c = threadIdx.x % FP;
+        const size_t o = (size_t)(m0 + r) * n + m1 + c;
+        T sx = 0, sy = 0;
+        if (A.dirac_block >= 0) {
+            const cpx<T> d = alpha[(size_t)A.dirac_block * N + o];
+            sx = d.x;
+            sy = d.y;
+        }
+#pragma unroll
+        for (int sl = 0; sl < NSLOT; ++sl) {
+            sx += part[sl][threadIdx.x].x;
+            sy += part[sl][threadIdx.x].y;
+        }
+        x[o] = mk<T>(scale * sx, scale * sy);
+    }
 }
 
 template <typename T>
@@ -199,21 +314,27 @@ void launch_psi_adj(const Plan& P, const cpx<T>* x, cpx<T>* alpha, hipStream_t s
     const WavArgs A = wav_args(P);
     const T scale = (T)(1.0 / std::sqrt((double)P.q));
     const int64_t N = P.N;
-    if (P.has_dirac)
+    if (P.nwav == 0) {
         hipLaunchKernelGGL(k_scale_copy_c<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, x,
                            alpha, scale, N);
-    if (P.nwav == 0) return;
+        return;
+    }
     const T* filt = (const T*)P.filters;
-    cpx<T>* wt = (cpx<T>*)P.wt;
+    const int ztot = P.nwav + (P.has_dirac ? 1 : 0);
+    // LL ping-pong buffers, one (n/2)^2 slot per basis each
+    cpx<T>* llb[2] = {(cpx<T>*)P.ws2, (cpx<T>*)P.ws2 + (size_t)P.nwav * (N / 4)};
     for (int lev = 0; lev < P.levels; ++lev) {
         const int Ls = P.n >> lev;
-        const dim3 g((Ls * Ls + 255) / 256, 1, P.nwav);
+        const int half = Ls / 2, ap = std::min(AP, half);
+        const int tiles = half / ap;
+        const dim3 g(tiles * tiles, 1, lev == 0 ? ztot : P.nwav);
+        cpx<T>* llout = lev + 1 < P.levels ? llb[lev & 1] : nullptr;
         if (lev == 0)
-            hipLaunchKernelGGL(k_dwt_rows_fwd<T>, g, dim3(256), 0, s, x, 0, wt, filt, A, Ls, scale);
+            hipLaunchKernelGGL(k_wav_fwd_level<T>, g, dim3(256), 0, s, x, (size_t)0, P.n, alpha, llout, filt, A,
+                               Ls, scale);
         else
-            hipLaunchKernelGGL(k_dwt_rows_fwd<T>, g, dim3(256), 0, s, (const cpx<T>*)alpha,
-                               (int)N, wt, filt, A, Ls, (T)1);
-        hipLaunchKernelGGL(k_dwt_cols_fwd<T>, g, dim3(256), 0, s, (const cpx<T>*)wt, alpha, filt, A, Ls);
+            hipLaunchKernelGGL(k_wav_fwd_level<T>, g, dim3(256), 0, s, (const cpx<T>*)llb[(lev - 1) & 1],
+                               (size_t)(N / 4), Ls, alpha, llout, filt, A, Ls, (T)1);
     }
 }
 
@@ -228,19 +349,23 @@ void launch_psi(const Plan& P, const cpx<T>* alpha, cpx<T>* x, hipStream_t s) {
         return;
     }
     const T* filt = (const T*)P.filters;
-    cpx<T>* wt = (cpx<T>*)P.wt;
-    cpx<T>* ll = (cpx<T>*)P.ws2;
-    for (int lev = P.levels - 1; lev >= 0; --lev) {
+    // LL ping-pong buffers, one (n/2)^2 slot per basis each
+    cpx<T>* llb[2] = {(cpx<T>*)P.ws2, (cpx<T>*)P.ws2 + (size_t)P.nwav * (N / 4)};
+    int cur = -1;   // buffer holding the current LL, -1: the alpha block (coarsest level)
+    for (int lev = P.levels - 1; lev >= 1; --lev) {
         const int Ls = P.n >> lev;
-        const dim3 g((Ls * Ls + 255) / 256, 1, P.nwav);
-        const cpx<T>* llsrc = (lev == P.levels - 1) ? nullptr : ll;
-        hipLaunchKernelGGL(k_dwt_cols_inv<T>, g, dim3(256), 0, s, alpha, llsrc, wt, filt, A, Ls);
-        if (lev > 0)
-            hipLaunchKernelGGL(k_dwt_rows_inv<T>, g, dim3(256), 0, s, (const cpx<T>*)wt, ll, filt, A, Ls);
-        else
-            hipLaunchKernelGGL(k_dwt_rows_inv_sum<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
-                               (const cpx<T>*)wt, alpha, x, filt, A, scale);
+        const int po = std::min(SP, Ls);
+        const int tiles = Ls / po;
+        const int dst = cur == 0 ? 1 : 0;
+        const cpx<T>* in = cur < 0 ? alpha : llb[cur];
+        hipLaunchKernelGGL(k_wav_inv_level<T>, dim3(tiles * tiles, 1, P.nwav), dim3(256), 0, s, alpha, in,
+                           cur < 0 ? 1 : 0, llb[dst], filt, A, Ls);
+        cur = dst;
     }
+    const cpx<T>* in = cur < 0 ? alpha : llb[cur];
+    const int tiles = P.n / FP;
+    hipLaunchKernelGGL(k_wav_inv_final<T>, dim3(tiles * tiles), dim3(256 * NSLOT), 0, s, alpha, in,
+                       cur < 0 ? 1 : 0, x, filt, A, scale);
 }
 
 template void launch_psi_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
