@@ -21,6 +21,9 @@ struct Ops {
     // y = scale * G F Z S x ; y in user order when perm is given, else in sorted order
     void phi(const C* x, C* y, double scale, const int32_t* perm) const {
         launch_fft_rows_fwd<T>(P, x, (C*)P.tmp, s);
+        phi_tail(y, scale, perm);
+    }
+    void phi_tail(C* y, double scale, const int32_t* perm) const {
         launch_fft_cols_fwd<T>(P, (const C*)P.tmp, (C*)P.grid, s);
         launch_degrid<T>(P, (const C*)P.grid, y, perm, scale, s);
     }
@@ -35,6 +38,13 @@ struct Ops {
     void apply_A(const C* v, C* q, double inv_nu2, double* dot) const {
         phi(v, (C*)P.vis, 1.0, nullptr);
         phi_adj((const C*)P.vis, nullptr, q, inv_nu2, v, 2.0, dot);
+    }
+    // conjugate-gradient step: p = r + beta p (beta from the rho partials), then q = A p
+    void apply_A_cg(C* p, const C* r, const double* rho, const double* rho_new, int count, C* q,
+                    double inv_nu2, double* dot) const {
+        launch_fft_rows_fwd_cg<T>(P, p, r, rho, rho_new, count, (C*)P.tmp, s);
+        phi_tail((C*)P.vis, 1.0, nullptr);
+        phi_adj((const C*)P.vis, nullptr, q, inv_nu2, p, 2.0, dot);
     }
 };
 
@@ -96,12 +106,14 @@ struct Sdmm {
         // Global update (step 5): CG on (Phi~^dag Phi~ + 2I) x = x1 + x2 + x3, warm start.
         op.apply_A(xh, q, inv_nu2, nullptr);
         const int nb = launch_cg_init<T>(x1, x2, x3, q, r, p, N, part(0), s);
+        // step c: q = A p (for c > 0 the row pass first forms p = r + beta p), then
+        // x += alpha p, r -= alpha q; rho of step c is in buffer c & 1
         for (int c = 0; c < prm->cg_iter; ++c) {
             double* rho = part(c & 1);
             double* rho_next = part((c + 1) & 1);
-            op.apply_A(p, q, inv_nu2, part(2));
+            if (c == 0) op.apply_A(p, q, inv_nu2, part(2));
+            else op.apply_A_cg(p, r, part((c - 1) & 1), rho, nb, q, inv_nu2, part(2));
             launch_cg_xr<T>(xh, r, p, q, rho, nb, part(2), rows_blocks, N, rho_next, s);
-            launch_cg_p<T>(p, r, rho, rho_next, nb, N, s);
         }
         // i = 1 (on s2): l1 prior on Psi^dag x_hat
         (void)hipEventRecord(fork, s);

@@ -142,6 +142,10 @@ struct Plan {
 // ---------------------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files, instantiated for float and double).
 template <typename T> void launch_fft_rows_fwd(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s);
+// Row pass on p = r + beta p (beta = rho_new / rho from partial sums), p updated in place.
+template <typename T>
+void launch_fft_rows_fwd_cg(const Plan& P, cpx<T>* p, const cpx<T>* r, const double* rho_part,
+                            const double* rhonew_part, int count, cpx<T>* tmp, hipStream_t s);
 template <typename T> void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s);
 template <typename T> void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s);
 // x = c1 * (S Z^T F^dag rows)(tmp) + c2 * v   (v may be null); optional partial Re<v, x>
@@ -190,8 +194,6 @@ template <typename T> int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, co
                                        const double* rho_part, int rho_count, const double* pq_part,
                                        int pq_count, int64_t n, double* part, hipStream_t s);
 // p = r + (rho_new / rho) p, both from partials
-template <typename T> void launch_cg_p(cpx<T>* p, const cpx<T>* r, const double* rho_part,
-                                       const double* rhonew_part, int count, int64_t n, hipStream_t s);
 // power-iteration normalisation v = w / ||w|| (||w||^2 from partials), sc[LAMBDA] = ||w||
 template <typename T> void launch_power_normalise(cpx<T>* v, const cpx<T>* w, const double* part,
                                                   int count, double* sc, int64_t n, hipStream_t s);

@@ -160,7 +160,7 @@ PURIFY_RADICES(double, 4, 1, 16, 1, 1)
 PURIFY_RADICES(double, 5, 2, 16, 2, 1)
 PURIFY_RADICES(double, 6, 2, 8, 8, 1)
 PURIFY_RADICES(double, 7, 2, 16, 8, 1)
-PURIFY_RADICES(double, 8, 2, 16, 16, 1)
+PURIFY_RADICES(double, 8, 3, 8, 8, 4)
 PURIFY_RADICES(double, 9, 3, 16, 16, 2)
 PURIFY_RADICES(double, 10, 3, 16, 16, 4)
 PURIFY_RADICES(double, 11, 3, 16, 16, 8)
@@ -293,28 +293,77 @@ template <typename T, int LOGN>
 constexpr int table_elems() { return twiddles_in_lds<T, LOGN>() ? (1 << LOGN) : 0; }
 
 // ---------------------------------------------------------------------------------------
+// Sum of a partial-sum buffer by one workgroup of any size, in a fixed order (every
+// workgroup gets the identical value).
+__device__ __forceinline__ double sum_parts_dyn(const double* __restrict__ part, int count, double* red) {
+    double acc = 0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) acc += part[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    double t = 0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) t += red[i];
+    __syncthreads();
+    return t;
+}
+
+// Optional conjugate-gradient direction update folded into the row pass: the input is
+// p = r + beta p_old with beta = rho_new / rho (0 when rho == 0), summed from the partial
+// buffers; p is written back in place.
+template <typename T>
+struct CgDir {
+    const cpx<T>* r = nullptr;        // null: plain transform of x
+    const double* rho_part = nullptr;
+    const double* rhonew_part = nullptr;
+    int count = 0;
+};
+
 // rows_fwd: thread (b, r, tl), line 2b + r; tmp[row][2k' + r] = (-1)^k' i^r FFT(s x tw2^r)[k']
 template <typename T, int LOGN, int B>
 __global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN>::TL))
-k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __restrict__ deap,
-               const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2) {
+k_fft_rows_fwd(cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __restrict__ deap,
+               const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2, CgDir<T> cg) {
     using PL = Plan1D<T, LOGN>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[16];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int tl = threadIdx.x % PL::TL, r = (threadIdx.x / PL::TL) & 1, lr = threadIdx.x / (2 * PL::TL);
     cpx<T>* line = base + table_elems<T, LOGN>() + (2 * lr + r) * PL::LS;
     const int row = blockIdx.x * B + lr;
     const T srow = deap[row];
-    const cpx<T>* xr = x + (size_t)row * N;
+    cpx<T>* xr = x + (size_t)row * N;
     cpx<T>* outr = tmp + (size_t)row * K;
+    T beta = 0;
+    if (cg.r) {
+        const double rho = sum_parts_dyn(cg.rho_part, cg.count, red);
+        const double rn = sum_parts_dyn(cg.rhonew_part, cg.count, red);
+        beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
+    }
     __syncthreads();
     cpx<T> v[PL::RMAX];
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
         const int p = PL::in_pos(tl, i);
-        cpx<T> a = (srow * deap[p]) * xr[p];
+        cpx<T> a = xr[p];
+        if (cg.r) a = cg.r[(size_t)row * N + p] + beta * a;
+        v[i] = a;
+    }
+    if (cg.r) {
+        // both parity groups read the row; one writes the new direction once all have read
+        __syncthreads();
+        if (r == 0) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) xr[PL::in_pos(tl, i)] = v[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int p = PL::in_pos(tl, i);
+        cpx<T> a = (srow * deap[p]) * v[i];
         if (r) a = a * tw2[p];
         v[i] = a;
     }
@@ -477,7 +526,7 @@ size_t lds_bytes(int lines) {
 }
 
 template <typename T, int LOGN>
-void rows_fwd_impl(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s) {
+void rows_fwd_impl(const Plan& P, cpx<T>* x, cpx<T>* tmp, CgDir<T> cg, hipStream_t s) {
     constexpr int B = rows_per_wg<T, LOGN>();
     constexpr int NT = 2 * B * Plan1D<T, LOGN>::TL;
     constexpr int N = 1 << LOGN;
@@ -485,7 +534,7 @@ void rows_fwd_impl(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s) {
     auto f = k_fft_rows_fwd<T, LOGN, B>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, x, tmp, (const T*)P.deap,
-                       (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2);
+                       (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, cg);
 }
 template <typename T, int LOGN>
 void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
@@ -546,7 +595,17 @@ int ilog2(int n) {
 
 template <typename T>
 void launch_fft_rows_fwd(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s) {
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_fwd_impl<T, L_>(P, x, tmp, s)));
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_fwd_impl<T, L_>(P, const_cast<cpx<T>*>(x), tmp, CgDir<T>{}, s)));
+}
+template <typename T>
+void launch_fft_rows_fwd_cg(const Plan& P, cpx<T>* p, const cpx<T>* r, const double* rho_part,
+                            const double* rhonew_part, int count, cpx<T>* tmp, hipStream_t s) {
+    CgDir<T> cg;
+    cg.r = r;
+    cg.rho_part = rho_part;
+    cg.rhonew_part = rhonew_part;
+    cg.count = count;
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_fwd_impl<T, L_>(P, p, tmp, cg, s)));
 }
 template <typename T>
 void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
@@ -570,6 +629,10 @@ int fft_rows_adj_blocks(const Plan& P) {
 
 template void launch_fft_rows_fwd<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
 template void launch_fft_rows_fwd<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
+template void launch_fft_rows_fwd_cg<float>(const Plan&, cpx<float>*, const cpx<float>*, const double*,
+                                            const double*, int, cpx<float>*, hipStream_t);
+template void launch_fft_rows_fwd_cg<double>(const Plan&, cpx<double>*, const cpx<double>*, const double*,
+                                             const double*, int, cpx<double>*, hipStream_t);
 template void launch_fft_cols_fwd<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
 template void launch_fft_cols_fwd<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
 template void launch_fft_cols_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);

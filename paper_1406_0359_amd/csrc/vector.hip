@@ -188,17 +188,6 @@ k_cg_xr(cpx<T>* __restrict__ x, cpx<T>* __restrict__ r, const cpx<T>* __restrict
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// p = r + beta p, beta = rho_new / rho (0 when rho == 0)
-template <typename T>
-__global__ void __launch_bounds__(VT)
-k_cg_p(cpx<T>* __restrict__ p, const cpx<T>* __restrict__ r, const double* __restrict__ rho_part,
-       const double* __restrict__ rhonew_part, int count, int64_t n) {
-    const double rho = sum_partials(rho_part, count);
-    const double rn = sum_partials(rhonew_part, count);
-    const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
-    GRID_STRIDE(i, n) p[i] = r[i] + beta * p[i];
-}
-
 // i = 1 of Algorithm 1: u = v1 + z1 ; r1 = soft(u, gamma w) ; z1 = u - r1 ; v1 <- r1 - z1 ;
 // partial sum_j w_j |v1_j| (objective ||W Psi^dag x_hat||_1, before the update).
 template <typename T>
@@ -365,12 +354,6 @@ int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q, const d
     return b;
 }
 template <typename T>
-void launch_cg_p(cpx<T>* p, const cpx<T>* r, const double* rho_part, const double* rhonew_part,
-                 int count, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_p<T>, dim3(red_blocks(n)), dim3(VT), 0, s, p, r, rho_part, rhonew_part,
-                       count, n);
-}
-template <typename T>
 int launch_prox_l1(cpx<T>* v1, cpx<T>* z1, const double* w, double gamma, int64_t n, double* part,
                    hipStream_t s) {
     const int b = red_blocks(n);
@@ -420,8 +403,6 @@ void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc, int 
                                    cpx<T>*, int64_t, double*, hipStream_t);                              \
     template int launch_cg_xr<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const cpx<T>*, const double*, int,     \
                                  const double*, int, int64_t, double*, hipStream_t);                     \
-    template void launch_cg_p<T>(cpx<T>*, const cpx<T>*, const double*, const double*, int, int64_t,      \
-                                 hipStream_t);                                                           \
     template void launch_power_normalise<T>(cpx<T>*, const cpx<T>*, const double*, int, double*, int64_t, \
                                             hipStream_t);                                                \
     template int launch_prox_l1<T>(cpx<T>*, cpx<T>*, const double*, double, int64_t, double*, hipStream_t); \
