@@ -42,6 +42,7 @@ def stage_bytes(plan, stage: str) -> float:
         "fft_cols": 2 * N * c + 4 * N * c,         # read K x n, write K x K
         "degrid": 4 * N * c + M * (coord + c),     # read grid, coords; write y
         "grid": M * (coord + c) + 4 * N * c,       # read y, coords; write grid
+        "gtg": 4 * N * c + M * coord + 4 * N * c,  # read grid, coords; write grid
         "ifft_cols": 4 * N * c + 2 * N * c,
         "ifft_rows": 2 * N * c + N * c,
         "psi_adj": N * c + q * N * c,
@@ -54,14 +55,15 @@ def stage_bytes(plan, stage: str) -> float:
 
 # launches of each kernel stage per SDMM iteration with cg CG steps
 def launches_per_iter(cg: int) -> dict:
-    a = cg + 1            # A-applications in CG (warm-start residual + cg steps)
-    return {"fft_rows": a + 1, "fft_cols": a + 1, "degrid": a + 1, "grid": a + 1,
+    a = cg + 1            # A-applications in CG (warm-start residual + cg steps), each with
+                          # G^T G fused; Phi and Phi^dagger once more for the l2-ball branch
+    return {"fft_rows": a + 1, "fft_cols": a + 1, "degrid": 1, "grid": 1, "gtg": a,
             "ifft_cols": a + 1, "ifft_rows": a + 1, "psi_adj": 1, "psi": 1}
 
 
 KERNEL_NAME = {
     "fft_rows": "k_fft_rows_fwd", "fft_cols": "k_fft_cols_fwd", "degrid": "k_degrid",
-    "grid": "k_grid", "ifft_cols": "k_fft_cols_adj", "ifft_rows": "k_fft_rows_adj",
+    "grid": "k_grid", "gtg": "k_grid (G^T G)", "ifft_cols": "k_fft_cols_adj", "ifft_rows": "k_fft_rows_adj",
 }
 
 
@@ -69,7 +71,7 @@ def stage_table(plan, reps: int = 50) -> dict:
     """Per-stage average launch time on the plan's internal buffers; call after a solve so
     they hold real data (gridding skips tiles whose visibilities are all zero)."""
     out = {}
-    for st in ["fft_rows", "fft_cols", "degrid", "grid", "ifft_cols", "ifft_rows", "phi",
+    for st in ["fft_rows", "fft_cols", "degrid", "grid", "gtg", "ifft_cols", "ifft_rows", "phi",
                "phi_adj", "psi_adj", "psi"]:
         plan.time_stage(st, 3)
         ms = plan.time_stage(st, reps)

@@ -154,7 +154,9 @@ typedef enum {
     PURIFY_STAGE_PHI = 6,          /* whole Phi                                                */
     PURIFY_STAGE_PHI_ADJ = 7,      /* whole Phi^dagger                                         */
     PURIFY_STAGE_PSI_ADJ = 8,      /* whole Psi^dagger                                         */
-    PURIFY_STAGE_PSI = 9           /* whole Psi                                                */
+    PURIFY_STAGE_PSI = 9,          /* whole Psi                                                */
+    PURIFY_STAGE_GTG = 10          /* G^T G in one launch (interpolate + grid), as in the
+                                      normal operator Phi^dagger Phi of the CG update  (K x K -> K x K) */
 } purify_stage;
 
 /* Time `reps` back-to-back launches of one stage on the plan's internal buffers (their

@@ -35,16 +35,28 @@ struct Ops {
         launch_fft_rows_adj<T>(P, (const C*)P.tmp, x, c1, v, c2, dot, s);
     }
     // q = (Phi~^dag Phi~ + 2 I) v, Phi~ = Phi / nu
+    // (G^T G fused: the visibilities of Phi v are interpolated inside the gridding launch)
     void apply_A(const C* v, C* q, double inv_nu2, double* dot) const {
-        phi(v, (C*)P.vis, 1.0, nullptr);
-        phi_adj((const C*)P.vis, nullptr, q, inv_nu2, v, 2.0, dot);
+        launch_fft_rows_fwd<T>(P, v, (C*)P.tmp, s);
+        normal_tail(v, q, inv_nu2, 2.0, dot);
+    }
+    // q = Phi^dag Phi v
+    void normal(const C* v, C* q) const {
+        launch_fft_rows_fwd<T>(P, v, (C*)P.tmp, s);
+        normal_tail(nullptr, q, 1.0, 0.0, nullptr);
     }
     // conjugate-gradient step: p = r + beta p (beta from the rho partials), then q = A p
     void apply_A_cg(C* p, const C* r, const double* rho, const double* rho_new, int count, C* q,
                     double inv_nu2, double* dot) const {
         launch_fft_rows_fwd_cg<T>(P, p, r, rho, rho_new, count, (C*)P.tmp, s);
-        phi_tail((C*)P.vis, 1.0, nullptr);
-        phi_adj((const C*)P.vis, nullptr, q, inv_nu2, p, 2.0, dot);
+        normal_tail(p, q, inv_nu2, 2.0, dot);
+    }
+    // after the row pass of v: q = c1 Phi^dag Phi v + c2 v
+    void normal_tail(const C* v, C* q, double c1, double c2, double* dot) const {
+        launch_fft_cols_fwd<T>(P, (const C*)P.tmp, (C*)P.grid, s);
+        launch_gtg<T>(P, (const C*)P.grid, (C*)P.grid2, s);
+        launch_fft_cols_adj<T>(P, (const C*)P.grid2, (C*)P.tmp, s);
+        launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, c1, v, c2, dot, s);
     }
 };
 
@@ -83,8 +95,7 @@ struct Sdmm {
         const Ops<T> op{P, s};
         C* v = (C*)P.p;
         C* w = (C*)P.qv;
-        op.phi(v, (C*)P.vis, 1.0, nullptr);
-        op.phi_adj((const C*)P.vis, nullptr, w, 1.0, nullptr, 0.0, nullptr);
+        op.normal(v, w);
         const int nb = launch_norm2_part<T>(w, P.N, part(6), s);
         launch_power_normalise<T>(v, w, part(6), nb, P.sc, P.N, s);
     }
@@ -277,6 +288,7 @@ void run_stage(const Plan& P, int stage, hipStream_t s) {
         case PURIFY_STAGE_FFT_COLS: launch_fft_cols_fwd<T>(P, (const C*)P.tmp, (C*)P.grid, s); break;
         case PURIFY_STAGE_DEGRID: launch_degrid<T>(P, (const C*)P.grid, (C*)P.vis, nullptr, 1.0, s); break;
         case PURIFY_STAGE_GRID: launch_grid<T>(P, (const C*)P.vis, nullptr, (C*)P.grid, s); break;
+        case PURIFY_STAGE_GTG: launch_gtg<T>(P, (const C*)P.grid, (C*)P.grid2, s); break;
         case PURIFY_STAGE_IFFT_COLS: launch_fft_cols_adj<T>(P, (const C*)P.grid, (C*)P.tmp, s); break;
         case PURIFY_STAGE_IFFT_ROWS:
             launch_fft_rows_adj<T>(P, (const C*)P.tmp, (C*)P.qv, 1.0, nullptr, 0.0, nullptr, s);
@@ -460,7 +472,7 @@ purify_status purify_sdmm_solve(purify_plan* plan, const void* y, const purify_s
 purify_status purify_time_stage(purify_plan* plan, int32_t stage, int32_t reps, void* stream,
                                 double* ms_per_launch) {
     CHECK_PLAN(plan);
-    if (stage < 0 || stage > PURIFY_STAGE_PSI || reps < 1 || !ms_per_launch) {
+    if (stage < 0 || stage > PURIFY_STAGE_GTG || reps < 1 || !ms_per_launch) {
         set_error("invalid stage or reps");
         return PURIFY_E_INVALID;
     }

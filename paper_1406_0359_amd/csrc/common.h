@@ -123,7 +123,8 @@ struct Plan {
     void* filters = nullptr;     // MAX_WAV * 2 * MAX_TAPS reals (h then g)
     void* kbpoly = nullptr;      // J * (KBDeg + 1) reals: per-tap polynomial coefficients
     void* wtab = nullptr;        // FP64 plans: M x 2J tap weights (sorted order), else null
-    void* grid = nullptr;        // K x K complex, layout [k2][k1]
+    void* grid = nullptr;        // K x K complex, row-major G[k1][k2]
+    void* grid2 = nullptr;       // K x K complex: G^T G output of the normal operator
     void* tmp = nullptr;         // K x n complex, layout [k2][j1]
     double* part = nullptr;      // NUM_PARTIAL_BUFS * MAX_PARTIALS
     double* sc = nullptr;        // SL_COUNT scalars
@@ -160,6 +161,8 @@ template <typename T> void launch_degrid(const Plan& P, const cpx<T>* grid, cpx<
 // G^T: grid = sum psi psi y[perm ? perm[m] : m]
 template <typename T> void launch_grid(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* grid,
                                        hipStream_t s);
+// gout = G^T G gin (visibility values interpolated from gin and gridded in one launch)
+template <typename T> void launch_gtg(const Plan& P, const cpx<T>* gin, cpx<T>* gout, hipStream_t s);
 
 template <typename T> void launch_psi_adj(const Plan& P, const cpx<T>* x, cpx<T>* alpha, hipStream_t s);
 template <typename T> void launch_psi(const Plan& P, const cpx<T>* alpha, cpx<T>* x, hipStream_t s);

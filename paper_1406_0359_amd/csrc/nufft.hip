@@ -72,23 +72,13 @@ __device__ __forceinline__ void visibility_weights(const T* __restrict__ wtab, c
     }
 }
 
-// G: one thread per visibility (tile-sorted order), J x J gather from the row-major grid
-// G[k1][k2].  J = 0: runtime Jr.
+// sum_a wa[a] sum_b wb[b] G[k1 + a][k2 + b] (cyclic), the J x J gather of one visibility
 template <typename T, int J>
-__global__ void __launch_bounds__(256)
-k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
-         const int32_t* __restrict__ base, const T* __restrict__ frac, const T* __restrict__ kbc,
-         const T* __restrict__ wtab, int M, int K, T scale, int Jr) {
+__device__ __forceinline__ cpx<T> interpolate(const cpx<T>* __restrict__ grid, int k1, int k2, const T* wa,
+                                              const T* wb, int K, int Jr) {
     constexpr int JJ = J > 0 ? J : KB_MAX_J;
-    constexpr int UNR = J > 0 ? J : 1;   // generic width: plain loops
+    constexpr int UNR = J > 0 ? J : 1;
     const int Jn = J > 0 ? J : Jr;
-    const int m = blockIdx.x * 256 + threadIdx.x;
-    if (m >= M) return;
-    const int b = base[m];
-    const int k1 = b & 0xFFFF, k2 = (b >> 16) & 0xFFFF;
-    const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[m];
-    T wa[JJ], wb[JJ];
-    visibility_weights<T, J>(wtab, kbc, m, f, wa, wb, Jr);
     const int mask = K - 1;
     T ax = 0, ay = 0;
 #pragma unroll UNR
@@ -106,7 +96,26 @@ k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t*
         ax += wa[a] * rx;
         ay += wa[a] * ry;
     }
-    y[perm ? perm[m] : m] = mk<T>(scale * ax, scale * ay);
+    return mk<T>(ax, ay);
+}
+
+// G: one thread per visibility (tile-sorted order), J x J gather from the row-major grid
+// G[k1][k2].  J = 0: runtime Jr.
+template <typename T, int J>
+__global__ void __launch_bounds__(256)
+k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
+         const int32_t* __restrict__ base, const T* __restrict__ frac, const T* __restrict__ kbc,
+         const T* __restrict__ wtab, int M, int K, T scale, int Jr) {
+    constexpr int JJ = J > 0 ? J : KB_MAX_J;
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= M) return;
+    const int b = base[m];
+    const int k1 = b & 0xFFFF, k2 = (b >> 16) & 0xFFFF;
+    const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[m];
+    T wa[JJ], wb[JJ];
+    visibility_weights<T, J>(wtab, kbc, m, f, wa, wb, Jr);
+    const cpx<T> v = interpolate<T, J>(grid, k1, k2, wa, wb, K, Jr);
+    y[perm ? perm[m] : m] = mk<T>(scale * v.x, scale * v.y);
 }
 
 // Gridding accumulates in LDS with integer atomics on a fixed-point representation:
@@ -155,17 +164,28 @@ __device__ __forceinline__ double wave_max(double v) {
 // atomics: the sum does not depend on the order of the adds).  A whole tile is written to
 // the grid; a part stores its integer partial tile and scale exponent in its own slot, and
 // k_grid_merge sums the parts of each split tile in part order.
-template <typename T, int J, int TT, int NT, int CHR>
+//
+// GTG: the unit's visibility values are not read from y but interpolated from the grid
+// `gin` (the same J x J gather as G), so one launch applies G^T G (gin and grid distinct).
+template <typename T, int J, int TT, int NT, int CHR, bool GTG>
 __global__ void __launch_bounds__(NT)
-k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int32_t* __restrict__ base,
+k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32_t* __restrict__ perm, const int32_t* __restrict__ base,
        const T* __restrict__ frac, const T* __restrict__ kbc, const T* __restrict__ wtab,
        const int32_t* __restrict__ work, typename FixedAcc<T>::I* __restrict__ partial,
        int32_t* __restrict__ pexp, cpx<T>* __restrict__ grid, int K, int nT, int Jr) {
     using Acc = FixedAcc<T>;
     constexpr int JJ = J > 0 ? J : KB_MAX_J;
     constexpr int UNR = J > 0 ? J : 1;
+    // GTG: window of gin covering every footprint of the unit's visibilities (own and
+    // spill-in), rows/cols [tile origin - (J-1), tile end + J - 1)
+    constexpr int WS = TT + 2 * (JJ - 1);
+    constexpr int WPT = (WS * WS + NT - 1) / NT;
+    // FP64: the window goes straight from global memory to LDS (global_load_lds, one 16-byte
+    // element per lane at consecutive LDS slots of the wave), keeping it out of registers
+    constexpr bool DMA = GTG && sizeof(T) == 8;
     __shared__ typename Acc::I acc[2 * TT * TT];
     __shared__ double red[NT / 64];
+    __shared__ cpx<T> win[GTG ? WPT * NT : 1];
     const int32_t* w = work + GRID_REC * blockIdx.x;
     const int tile = w[0], slot = w[1], cover = w[2], total = w[3];
     int rs[5], cum[6];
@@ -178,6 +198,11 @@ k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int
     const int t1o = (tile % nT) * TT, t2o = (tile / nT) * TT;
     const int mask = K - 1;
     const int Jn = J > 0 ? J : Jr;
+    if (total == 0 && slot < 0) {   // no visibility reaches the tile
+        for (int i = threadIdx.x; i < TT * TT; i += NT)
+            grid[(size_t)(t1o + i / TT) * K + t2o + i % TT] = mk<T>(0, 0);
+        return;
+    }
     for (int i = threadIdx.x; i < 2 * TT * TT; i += NT) acc[i] = 0;
     const int ch = (total + NT - 1) / NT;
     const int j0 = (int)threadIdx.x * ch;
@@ -188,15 +213,80 @@ k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int
             if (j >= cum[r]) idx = rs[r] + (j - cum[r]);
         return idx;
     };
-    // largest component magnitude of y over the unit's items (a separate pass only when a
-    // thread's chunk does not fit in one batch)
+    const int wo1 = (t1o - (Jn - 1)) & mask, wo2 = (t2o - (Jn - 1)) & mask;   // window origin
+    cpx<T> wreg[GTG && !DMA ? WPT : 1];
+    if constexpr (GTG) {
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+            const int i = threadIdx.x + k * NT;
+            if (i < WS * WS) {
+                const cpx<T>* src = gin + (size_t)((wo1 + i / WS) & mask) * K + ((wo2 + i % WS) & mask);
+                if constexpr (DMA)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void*)src,
+                        (__attribute__((address_space(3))) void*)(win + (threadIdx.x & ~63u) + k * NT), 16, 0, 0);
+                else
+                    wreg[k] = *src;
+            }
+        }
+    }
+    bool staged = false;
+#define PURIFY_STAGE_WINDOW()                                  \
+    do {                                                       \
+        if constexpr (!DMA) {                                  \
+            _Pragma("unroll") for (int k = 0; k < WPT; ++k) {  \
+                const int i = threadIdx.x + k * NT;            \
+                if (i < WS * WS) win[i] = wreg[k];             \
+            }                                                  \
+        }                                                      \
+        __syncthreads();                                       \
+        staged = true;                                         \
+    } while (0)
+    // the visibility value: y (gridding) or the J x J interpolation from the window (G^T G,
+    // same arithmetic order as the G kernel)
+    auto value = [&](int idx, int bk, const T* wa, const T* wb) {
+        if constexpr (GTG) {
+            const int k1 = bk & 0xFFFF, k2 = (bk >> 16) & 0xFFFF;
+            T ax = 0, ay = 0;
+#pragma unroll UNR
+            for (int a = 0; a < JJ; ++a) {
+                if (a >= Jn) break;
+                const cpx<T>* row = win + ((k1 + a - wo1) & mask) * WS;
+                T rx = 0, ry = 0;
+#pragma unroll UNR
+                for (int bb = 0; bb < JJ; ++bb) {
+                    if (bb >= Jn) break;
+                    const cpx<T> g = row[(k2 + bb - wo2) & mask];
+                    rx += wb[bb] * g.x;
+                    ry += wb[bb] * g.y;
+                }
+                ax += wa[a] * rx;
+                ay += wa[a] * ry;
+            }
+            return mk<T>(ax, ay);
+        } else {
+            return y[perm ? perm[idx] : idx];
+        }
+    };
+    // largest component magnitude of the values over the unit's items (a separate pass only
+    // when a thread's chunk does not fit in one batch)
     double ym = 0.0;
+    if constexpr (GTG) {
+        if (ch > CHR) PURIFY_STAGE_WINDOW();
+    }
     if (ch > CHR) {
         for (int s = 0; s < ch; ++s) {
             const int j = j0 + s;
             if (j < total) {
                 const int idx = item(j);
-                const cpx<T> v = y[perm ? perm[idx] : idx];
+                cpx<T> v;
+                if constexpr (GTG) {
+                    T wa[JJ], wb[JJ];
+                    visibility_weights<T, J>(wtab, kbc, idx, reinterpret_cast<const cpx<T>*>(frac)[idx], wa, wb, Jr);
+                    v = value(idx, base[idx], wa, wb);
+                } else {
+                    v = value(idx, 0, nullptr, nullptr);
+                }
                 ym = fmax(ym, fmax(fabs((double)v.x), fabs((double)v.y)));
             }
         }
@@ -217,10 +307,21 @@ k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int
                 const int idx = item(j);
                 bk[c] = base[idx];
                 const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[idx];
-                vv[c] = y[perm ? perm[idx] : idx];
                 visibility_weights<T, J>(wtab, kbc, idx, f, wa[c], wb[c], Jr);
-                if (ch <= CHR) ym = fmax(ym, fmax(fabs((double)vv[c].x), fabs((double)vv[c].y)));
+                if constexpr (!GTG) vv[c] = value(idx, bk[c], wa[c], wb[c]);
             }
+        }
+        if constexpr (GTG) {
+            // the window's loads were issued before this batch's coordinate and weight loads
+            if (!staged) PURIFY_STAGE_WINDOW();
+#pragma unroll
+            for (int c = 0; c < CHR; ++c)
+                if (ok[c]) vv[c] = value(0, bk[c], wa[c], wb[c]);
+        }
+        if (ch <= CHR) {
+#pragma unroll
+            for (int c = 0; c < CHR; ++c)
+                if (ok[c]) ym = fmax(ym, fmax(fabs((double)vv[c].x), fabs((double)vv[c].y)));
         }
         if (s0 == 0) {
             ym = wave_max(ym);
@@ -275,6 +376,8 @@ k_grid(const cpx<T>* __restrict__ y, const int32_t* __restrict__ perm, const int
     if (threadIdx.x == 0) pexp[slot] = e;
 }
 
+#undef PURIFY_STAGE_WINDOW
+
 // Sum of the partial tiles of each split tile (one workgroup per split tile), in part order
 // and in double, then written to the grid.
 template <typename T, int TT>
@@ -297,8 +400,8 @@ k_grid_merge(const int32_t* __restrict__ merge, const typename FixedAcc<T>::I* _
     }
 }
 
-template <typename T, int TT, int NT>
-void grid_tt(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* grid, hipStream_t s) {
+template <typename T, int TT, int NT, bool GTG>
+void grid_tt(const Plan& P, const cpx<T>* y, const cpx<T>* gin, const int32_t* perm, cpx<T>* grid, hipStream_t s) {
     const dim3 g(P.nwork), b(NT);
     using I = typename FixedAcc<T>::I;
     constexpr int C = sizeof(T) == 8 ? 2 : 4;   // items per batch (register budget)
@@ -307,10 +410,10 @@ void grid_tt(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* grid, 
     const T* kbc = (const T*)P.kbpoly;
     const T* wt = (const T*)P.wtab;
     switch (P.J) {
-        case 4: hipLaunchKernelGGL((k_grid<T, 4, TT, NT, C>), g, b, 0, s, y, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, 4); break;
-        case 6: hipLaunchKernelGGL((k_grid<T, 6, TT, NT, C>), g, b, 0, s, y, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, 6); break;
-        case 8: hipLaunchKernelGGL((k_grid<T, 8, TT, NT, C>), g, b, 0, s, y, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, 8); break;
-        default: hipLaunchKernelGGL((k_grid<T, 0, TT, NT, 1>), g, b, 0, s, y, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, P.J); break;
+        case 4: hipLaunchKernelGGL((k_grid<T, 4, TT, NT, C, GTG>), g, b, 0, s, y, gin, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, 4); break;
+        case 6: hipLaunchKernelGGL((k_grid<T, 6, TT, NT, C, GTG>), g, b, 0, s, y, gin, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, 6); break;
+        case 8: hipLaunchKernelGGL((k_grid<T, 8, TT, NT, C, GTG>), g, b, 0, s, y, gin, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, 8); break;
+        default: hipLaunchKernelGGL((k_grid<T, 0, TT, NT, 1, GTG>), g, b, 0, s, y, gin, perm, P.base, fr, kbc, wt, P.gwork, scr, P.gexp, grid, P.K, P.nT, P.J); break;
     }
     if (P.nmerge > 0)
         hipLaunchKernelGGL((k_grid_merge<T, TT>), dim3(P.nmerge), dim3(256), 0, s, P.gmerge, scr, P.gexp, grid, P.K, P.nT);
@@ -335,13 +438,21 @@ void launch_degrid(const Plan& P, const cpx<T>* grid, cpx<T>* y, const int32_t* 
 
 template <typename T>
 void launch_grid(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* grid, hipStream_t s) {
-    if (P.TT == 16) grid_tt<T, 16, 256>(P, y, perm, grid, s);
-    else grid_tt<T, 32, 256>(P, y, perm, grid, s);
+    if (P.TT == 16) grid_tt<T, 16, 256, false>(P, y, nullptr, perm, grid, s);
+    else grid_tt<T, 32, 256, false>(P, y, nullptr, perm, grid, s);
+}
+
+template <typename T>
+void launch_gtg(const Plan& P, const cpx<T>* gin, cpx<T>* gout, hipStream_t s) {
+    if (P.TT == 16) grid_tt<T, 16, 256, true>(P, nullptr, gin, nullptr, gout, s);
+    else grid_tt<T, 32, 256, true>(P, nullptr, gin, nullptr, gout, s);
 }
 
 template void launch_degrid<float>(const Plan&, const cpx<float>*, cpx<float>*, const int32_t*, double, hipStream_t);
 template void launch_degrid<double>(const Plan&, const cpx<double>*, cpx<double>*, const int32_t*, double, hipStream_t);
 template void launch_grid<float>(const Plan&, const cpx<float>*, const int32_t*, cpx<float>*, hipStream_t);
 template void launch_grid<double>(const Plan&, const cpx<double>*, const int32_t*, cpx<double>*, hipStream_t);
+template void launch_gtg<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
+template void launch_gtg<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
 
 }  // namespace purify

@@ -291,6 +291,7 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
     P.filters = carve((size_t)MAX_WAV * 2 * MAX_TAPS * es);
     P.kbpoly = carve((size_t)KB_MAX_COEF * es);
     P.grid = carve(K * K * ce);
+    P.grid2 = carve(K * K * ce);
     P.tmp = carve(K * P.n * ce);
     P.part = (double*)carve((size_t)NUM_PARTIAL_BUFS * MAX_PARTIALS * sizeof(double));
     P.sc = (double*)carve(SL_COUNT * sizeof(double));
