@@ -143,6 +143,41 @@ def precision_form(torch, purify, synth, solve_iters: int) -> dict:
     }
 
 
+COUNTER_FILE = os.path.join(ROOT, "profiles", "k_grid_gtg_sara256_counters.md")
+COUNTER_SOURCE = os.path.join(ROOT, "paper_1406_0359_amd", "csrc", "nufft.hip")
+
+
+def measured_traffic(stage: str):
+    """HBM bytes per launch of the G^T G kernel from the committed counter summary (two
+    rocprofv3 --pmc runs, FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy kernel of
+    known size).  None unless the summary covers `stage` and the kernel source it was taken
+    on is the current one."""
+    if stage != "gtg" or not os.path.exists(COUNTER_FILE):
+        return None
+    fields = {}
+    for ln in open(COUNTER_FILE):
+        if ":" in ln and ln.split(":", 1)[0].strip() in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            k, v = ln.split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    import hashlib
+    sha = hashlib.sha256(open(COUNTER_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def copy_calibration(torch, mib: int) -> dict:
+    """Ten launches of a plain elementwise kernel (negation, float32) that reads and writes
+    mib MiB once each: the reference for scaling hardware byte counters."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(10):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    return {"read": 4 * n, "write": 4 * n, "launches": 10}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +187,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--extra-iters", type=int, default=30)
+    ap.add_argument("--kernel-only", default="", metavar="STAGE",
+                    help="only time one stage of the 256x256 FP64 plan on real data (no solve, no "
+                         "graphs; for hardware-counter runs) and print its line")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the run, negate a float32 tensor of MIB MiB into another 10 times "
+                         "(a plain read-once/write-once kernel of known size that calibrates the "
+                         "HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs every solve on a single "
@@ -167,6 +209,18 @@ def main():
     w = synth.WORKLOADS["sara256"]
     p, plan0 = make_gpu_problem(w, torch, purify, synth, "fp64")
     y = plan0.as_vec(p.y)
+    if args.kernel_only:
+        # stage inputs from one Phi and one Phi^dagger of the problem's data
+        plan0.phi_adj(y, out=None)
+        plan0.phi(plan0.as_vec(p.x_true))
+        plan0.time_stage("degrid", 1)
+        ms = plan0.time_stage(args.kernel_only, 20)
+        line = {"stage": args.kernel_only, "ms_per_launch": ms,
+                "bytes_per_launch": stage_bytes(plan0, args.kernel_only), "launches": 20}
+        if args.copy_calibration > 0:
+            line["copy_calibration_bytes"] = copy_calibration(torch, args.copy_calibration)
+        print(json.dumps(line))
+        return
 
     def step():
         plan = purify.Plan(w.n, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels,
@@ -192,7 +246,7 @@ def main():
     dom = max((k for k in share if k in KERNEL_NAME), key=lambda k: share[k])
     d = st[dom]
     roofline = {"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["frac"], "traffic": None, "kernel": KERNEL_NAME[dom],
+                "frac": d["frac"], "traffic": measured_traffic(dom), "kernel": KERNEL_NAME[dom],
                 "bytes_per_launch": d["bytes"], "ms_per_launch": d["ms"]}
 
     line = {
@@ -215,6 +269,8 @@ def main():
     line["also"] = also
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, p, args.cpu_iters)
+    if args.copy_calibration > 0:
+        line["copy_calibration_bytes"] = copy_calibration(torch, args.copy_calibration)
     print(json.dumps(line))
 
 

@@ -124,3 +124,25 @@ def test_sdmm_bitwise_repeatable_and_graph_equals_eager(prec):
     assert np.array_equal(to_np(a.x), to_np(b.x))
     assert np.array_equal(to_np(a.x), to_np(c.x))
     assert np.array_equal(a.history, c.history)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
+def test_sdmm_heavy_tiles_split_gridding_units(prec, tol):
+    # 128 x 128 image, 100 000 visibilities concentrated at low spatial frequencies: the
+    # densest gridding tiles exceed one work unit and are split over several workgroups
+    # (partial tiles summed by the merge kernel), in Phi^dagger and in the fused G^T G of
+    # the CG update.  nu and gamma are fixed so both sides run the same iteration.
+    w, p = _problem("small64", n=128, M=100000)
+    nu, gamma, iters = 300.0, 1e-3, 3
+    op = Nufft(128, p.uv, w.J)
+    sa = Sara(128, w.dict_mask, w.levels)
+    ref = sdmm(op.phi, op.phi_adj, sa.psi, sa.psi_adj, p.y, p.epsilon, (128, 128), iters=iters,
+               cg_iters=w.cg_iters, nu=nu, gamma=gamma)
+    plan = purify.Plan(128, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels, precision=prec,
+                       device=DEV)
+    res = plan.sdmm(plan.as_vec(p.y), p.epsilon, max_iter=iters, nu=nu, gamma=gamma,
+                    record_history=True)
+    h = res.history
+    assert _hist_rel(h[:, 0], ref.objective) < tol
+    assert _hist_rel(h[:, 1], ref.residual) < tol
+    assert rel_l2(to_np(res.x), ref.x) < tol
