@@ -139,36 +139,38 @@ __device__ __forceinline__ void reg_dft(cpx<T>* v) {
 
 // ---------------------------------------------------------------------------------------
 // Radix plans: product of the radices is n; RMAX elements live in registers per thread.
-template <typename T, int LOGN>
-struct Radices;
-#define PURIFY_RADICES(TY, LG, NP_, R0, R1, R2)              \
+// AX = 0: row passes, AX = 1: column passes (which reuse the row plan unless listed).
+template <typename T, int LOGN, int AX>
+struct Radices : Radices<T, LOGN, 0> {};
+#define PURIFY_RADICES_AX(TY, LG, AX, NP_, R0, R1, R2)       \
     template <>                                               \
-    struct Radices<TY, LG> {                                  \
+    struct Radices<TY, LG, AX> {                              \
         static constexpr int NP = NP_;                        \
         static constexpr int r[3] = {R0, R1, R2};             \
     };
+#define PURIFY_RADICES(TY, LG, NP_, R0, R1, R2) PURIFY_RADICES_AX(TY, LG, 0, NP_, R0, R1, R2)
 PURIFY_RADICES(float, 4, 1, 16, 1, 1)
 PURIFY_RADICES(float, 5, 1, 32, 1, 1)
 PURIFY_RADICES(float, 6, 2, 8, 8, 1)
-PURIFY_RADICES(float, 7, 2, 16, 8, 1)
-PURIFY_RADICES(float, 8, 2, 16, 16, 1)
-PURIFY_RADICES(float, 9, 2, 32, 16, 1)
-PURIFY_RADICES(float, 10, 2, 32, 32, 1)
+PURIFY_RADICES(float, 7, 3, 8, 4, 4)
+PURIFY_RADICES(float, 8, 3, 8, 8, 4)
+PURIFY_RADICES(float, 9, 3, 8, 8, 8)
+PURIFY_RADICES(float, 10, 3, 8, 8, 16)
 PURIFY_RADICES(float, 11, 3, 32, 16, 4)
 PURIFY_RADICES(float, 12, 3, 16, 16, 16)
 PURIFY_RADICES(double, 4, 1, 16, 1, 1)
 PURIFY_RADICES(double, 5, 2, 16, 2, 1)
 PURIFY_RADICES(double, 6, 2, 8, 8, 1)
-PURIFY_RADICES(double, 7, 2, 16, 8, 1)
+PURIFY_RADICES(double, 7, 3, 8, 4, 4)
 PURIFY_RADICES(double, 8, 3, 8, 8, 4)
-PURIFY_RADICES(double, 9, 3, 16, 16, 2)
+PURIFY_RADICES(double, 9, 3, 8, 8, 8)
 PURIFY_RADICES(double, 10, 3, 16, 16, 4)
 PURIFY_RADICES(double, 11, 3, 16, 16, 8)
 PURIFY_RADICES(double, 12, 3, 16, 16, 16)
 
-template <typename T, int LOGN>
+template <typename T, int LOGN, int AX>
 struct Plan1D {
-    using Rd = Radices<T, LOGN>;
+    using Rd = Radices<T, LOGN, AX>;
     static constexpr int N = 1 << LOGN;
     static constexpr int NP = Rd::NP;
     static constexpr int R0 = Rd::r[0];
@@ -186,10 +188,10 @@ struct Plan1D {
     }
 };
 
-template <typename T, int LOGN, int P, bool INV>
+template <typename T, int LOGN, int AX, int P, bool INV>
 __device__ __forceinline__ void fft_pass(cpx<T>* v, cpx<T>* line, int tl, const cpx<T>* W) {
-    using PL = Plan1D<T, LOGN>;
-    using Rd = Radices<T, LOGN>;
+    using PL = Plan1D<T, LOGN, AX>;
+    using Rd = Radices<T, LOGN, AX>;
     constexpr int N = PL::N;
     constexpr int R = Rd::r[P];
     constexpr int NB = PL::RMAX / R;   // butterflies per thread in this pass
@@ -230,12 +232,12 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, cpx<T>* line, int tl, const 
 }
 
 // Run every pass on this thread's registers; `line` is this line's LDS buffer.
-template <typename T, int LOGN, bool INV>
+template <typename T, int LOGN, int AX, bool INV>
 __device__ __forceinline__ void line_fft(cpx<T>* v, cpx<T>* line, int tl, const cpx<T>* W) {
-    using Rd = Radices<T, LOGN>;
-    fft_pass<T, LOGN, 0, INV>(v, line, tl, W);
-    if constexpr (Rd::NP > 1) fft_pass<T, LOGN, 1, INV>(v, line, tl, W);
-    if constexpr (Rd::NP > 2) fft_pass<T, LOGN, 2, INV>(v, line, tl, W);
+    using Rd = Radices<T, LOGN, AX>;
+    fft_pass<T, LOGN, AX, 0, INV>(v, line, tl, W);
+    if constexpr (Rd::NP > 1) fft_pass<T, LOGN, AX, 1, INV>(v, line, tl, W);
+    if constexpr (Rd::NP > 2) fft_pass<T, LOGN, AX, 2, INV>(v, line, tl, W);
 }
 
 template <typename T>
@@ -252,11 +254,11 @@ __device__ __forceinline__ int xcd_block() {
 
 // Workgroup shapes.  Each n-point line transform uses TL threads; the two output parities of
 // a line are separate thread groups.  Row passes: B rows per workgroup (64-128 threads).
-// Column passes: C adjacent columns (contiguous runs of C elements), at most 256 threads,
+// Column passes: C adjacent columns (contiguous runs of C elements), at most 1024 threads,
 // at least ~256 workgroups, and LDS (2C lines + twiddle table) within 160 KB.
 template <typename T, int LOGN>
 constexpr int rows_per_wg() {
-    constexpr int tl = Plan1D<T, LOGN>::TL;
+    constexpr int tl = Plan1D<T, LOGN, 0>::TL;
     int b = 64 / (2 * tl);
     if (b < 1) b = 1;
     if (b > (1 << LOGN)) b = 1 << LOGN;
@@ -270,9 +272,9 @@ constexpr bool twiddles_in_lds() {
 template <typename T, int LOGN>
 constexpr int cols_per_wg() {
     constexpr int N = 1 << LOGN;
-    constexpr int tl = Plan1D<T, LOGN>::TL;
-    int c = 128 / tl;
-    if (c > (2 * N) / 256) c = (2 * N) / 256;
+    constexpr int tl = Plan1D<T, LOGN, 1>::TL;
+    int c = 512 / tl;
+    if (c > (4 * N) / 256) c = (4 * N) / 256;
     if (c > 8) c = 8;
     if (c < 1) c = 1;
     const int tab = twiddles_in_lds<T, LOGN>() ? N : 0;
@@ -322,10 +324,10 @@ struct CgDir {
 
 // rows_fwd: thread (b, r, tl), line 2b + r; tmp[row][2k' + r] = (-1)^k' i^r FFT(s x tw2^r)[k']
 template <typename T, int LOGN, int B>
-__global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN>::TL))
+__global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN, 0>::TL))
 k_fft_rows_fwd(cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __restrict__ deap,
                const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2, CgDir<T> cg) {
-    using PL = Plan1D<T, LOGN>;
+    using PL = Plan1D<T, LOGN, 0>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -337,21 +339,23 @@ k_fft_rows_fwd(cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __rest
     const T srow = deap[row];
     cpx<T>* xr = x + (size_t)row * N;
     cpx<T>* outr = tmp + (size_t)row * K;
+    // the row's loads are issued before the partial sums are read, so both are in flight
+    cpx<T> v[PL::RMAX], rv[PL::RMAX];
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int p = PL::in_pos(tl, i);
+        v[i] = xr[p];
+        if (cg.r) rv[i] = cg.r[(size_t)row * N + p];
+    }
     T beta = 0;
     if (cg.r) {
         const double rho = sum_parts_dyn(cg.rho_part, cg.count, red);
         const double rn = sum_parts_dyn(cg.rhonew_part, cg.count, red);
         beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) v[i] = rv[i] + beta * v[i];
     }
     __syncthreads();
-    cpx<T> v[PL::RMAX];
-#pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        const int p = PL::in_pos(tl, i);
-        cpx<T> a = xr[p];
-        if (cg.r) a = cg.r[(size_t)row * N + p] + beta * a;
-        v[i] = a;
-    }
     if (cg.r) {
         // both parity groups read the row; one writes the new direction once all have read
         __syncthreads();
@@ -367,7 +371,7 @@ k_fft_rows_fwd(cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __rest
         if (r) a = a * tw2[p];
         v[i] = a;
     }
-    line_fft<T, LOGN, false>(v, line, tl, W);
+    line_fft<T, LOGN, 0, false>(v, line, tl, W);
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
         const int kp = PL::out_pos(tl, i);
@@ -379,10 +383,10 @@ k_fft_rows_fwd(cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __rest
 
 // cols_fwd: thread (c, r, tl) with c fastest (coalesced runs of C columns)
 template <typename T, int LOGN, int C>
-__global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN>::TL))
+__global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN, 1>::TL))
 k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const cpx<T>* __restrict__ tw,
                const cpx<T>* __restrict__ tw2) {
-    using PL = Plan1D<T, LOGN>;
+    using PL = Plan1D<T, LOGN, 1>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -399,7 +403,7 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
         if (r) a = a * tw2[p];
         v[i] = a;
     }
-    line_fft<T, LOGN, false>(v, line, tl, W);
+    line_fft<T, LOGN, 1, false>(v, line, tl, W);
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
         const int kp = PL::out_pos(tl, i);
@@ -412,10 +416,10 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
 // cols_adj: parity lines transformed in parallel, results meet in LDS, then
 // tmp[j][col] = A[j] + (-i) exp(pi i j / n) B[j]
 template <typename T, int LOGN, int C>
-__global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN>::TL))
+__global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN, 1>::TL))
 k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const cpx<T>* __restrict__ tw,
                const cpx<T>* __restrict__ tw2) {
-    using PL = Plan1D<T, LOGN>;
+    using PL = Plan1D<T, LOGN, 1>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -432,7 +436,7 @@ k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const 
         const cpx<T> u = grid[(size_t)(2 * kp + r) * K + col];
         v[i] = (kp & 1) ? neg(u) : u;
     }
-    line_fft<T, LOGN, true>(v, line, tl, W);
+    line_fft<T, LOGN, 1, true>(v, line, tl, W);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
@@ -463,11 +467,11 @@ __device__ __forceinline__ double block_sum_dyn(double v, double* red) {
 // rows_adj: thread (b, tl, r) with r fastest; parity lines in parallel, combined in LDS;
 // x[row][j] = c1 s_row s_j (A[j] + (-i) exp(pi i j/n) B[j]) + c2 v, partial Re<v, x>
 template <typename T, int LOGN, int B>
-__global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN>::TL))
+__global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN, 0>::TL))
 k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* __restrict__ deap,
                const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2, T c1,
                const cpx<T>* __restrict__ vin, T c2, double* __restrict__ dot_part) {
-    using PL = Plan1D<T, LOGN>;
+    using PL = Plan1D<T, LOGN, 0>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -486,7 +490,7 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
         const cpx<T> u = inr[2 * kp + r];
         v[i] = (kp & 1) ? neg(u) : u;
     }
-    line_fft<T, LOGN, true>(v, line, tl, W);
+    line_fft<T, LOGN, 0, true>(v, line, tl, W);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
@@ -519,18 +523,18 @@ void set_lds_limit(F* f, size_t bytes) {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename T, int LOGN>
+template <typename T, int LOGN, int AX>
 size_t lds_bytes(int lines) {
-    using PL = Plan1D<T, LOGN>;
+    using PL = Plan1D<T, LOGN, AX>;
     return (size_t)(table_elems<T, LOGN>() + lines * PL::LS) * sizeof(cpx<T>);
 }
 
 template <typename T, int LOGN>
 void rows_fwd_impl(const Plan& P, cpx<T>* x, cpx<T>* tmp, CgDir<T> cg, hipStream_t s) {
     constexpr int B = rows_per_wg<T, LOGN>();
-    constexpr int NT = 2 * B * Plan1D<T, LOGN>::TL;
+    constexpr int NT = 2 * B * Plan1D<T, LOGN, 0>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = lds_bytes<T, LOGN>(2 * B);
+    const size_t lds = lds_bytes<T, LOGN, 0>(2 * B);
     auto f = k_fft_rows_fwd<T, LOGN, B>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, x, tmp, (const T*)P.deap,
@@ -539,9 +543,9 @@ void rows_fwd_impl(const Plan& P, cpx<T>* x, cpx<T>* tmp, CgDir<T> cg, hipStream
 template <typename T, int LOGN>
 void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
     constexpr int C = cols_per_wg<T, LOGN>();
-    constexpr int NT = 2 * C * Plan1D<T, LOGN>::TL;
+    constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = lds_bytes<T, LOGN>(2 * C);
+    const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
     auto f = k_fft_cols_fwd<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, tmp, grid, (const cpx<T>*)P.tw,
@@ -550,9 +554,9 @@ void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s
 template <typename T, int LOGN>
 void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s) {
     constexpr int C = cols_per_wg<T, LOGN>();
-    constexpr int NT = 2 * C * Plan1D<T, LOGN>::TL;
+    constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = lds_bytes<T, LOGN>(2 * C);
+    const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
     auto f = k_fft_cols_adj<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, grid, tmp, (const cpx<T>*)P.tw,
@@ -562,9 +566,9 @@ template <typename T, int LOGN>
 void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* v,
                    double c2, double* dot_part, hipStream_t s) {
     constexpr int B = rows_per_wg<T, LOGN>();
-    constexpr int NT = 2 * B * Plan1D<T, LOGN>::TL;
+    constexpr int NT = 2 * B * Plan1D<T, LOGN, 0>::TL;
     constexpr int N = 1 << LOGN;
-    const size_t lds = lds_bytes<T, LOGN>(2 * B);
+    const size_t lds = lds_bytes<T, LOGN, 0>(2 * B);
     auto f = k_fft_rows_adj<T, LOGN, B>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, tmp, x, (const T*)P.deap,

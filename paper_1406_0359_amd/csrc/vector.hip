@@ -174,13 +174,23 @@ __global__ void __launch_bounds__(VT)
 k_cg_xr(cpx<T>* __restrict__ x, cpx<T>* __restrict__ r, const cpx<T>* __restrict__ p,
         const cpx<T>* __restrict__ q, const double* __restrict__ rho_part, int rho_count,
         const double* __restrict__ pq_part, int pq_count, int64_t n, double* part) {
+    // first element's operands are loaded before the partial sums are read (both in flight)
+    const int64_t i0 = (int64_t)blockIdx.x * VT + threadIdx.x;
+    cpx<T> x0, r0, p0, q0;
+    if (i0 < n) {
+        x0 = x[i0];
+        r0 = r[i0];
+        p0 = p[i0];
+        q0 = q[i0];
+    }
     const double rho = sum_partials(rho_part, rho_count);
     const double pq = sum_partials(pq_part, pq_count);
     const T alpha = (T)(rho == 0.0 ? 0.0 : rho / pq);
     double acc = 0;
     GRID_STRIDE(i, n) {
-        x[i] = x[i] + alpha * p[i];
-        const cpx<T> v = r[i] - alpha * q[i];
+        const bool first = i == i0;
+        x[i] = (first ? x0 : x[i]) + alpha * (first ? p0 : p[i]);
+        const cpx<T> v = (first ? r0 : r[i]) - alpha * (first ? q0 : q[i]);
         r[i] = v;
         acc += (double)v.x * v.x + (double)v.y * v.y;
     }
@@ -254,6 +264,13 @@ __global__ void __launch_bounds__(VT)
 k_prox_ball(cpx<T>* __restrict__ v3, cpx<T>* __restrict__ z3, const cpx<T>* __restrict__ yt,
             const double* __restrict__ part_d, const double* __restrict__ part_res, int count,
             double eps, double* sc, double* hist, int hist_cap, int64_t n) {
+    // first element's operands are loaded before the partial sums are read (both in flight)
+    const int64_t i0 = (int64_t)blockIdx.x * VT + threadIdx.x;
+    cpx<T> y0, u0;
+    if (i0 < n) {
+        y0 = yt[i0];
+        u0 = v3[i0] + z3[i0];
+    }
     const double d2 = sum_partials(part_d, count);
     const double nd = sqrt(d2);
     const T s = (T)((nd == 0.0 || eps >= nd) ? 1.0 : eps / nd);
@@ -267,8 +284,8 @@ k_prox_ball(cpx<T>* __restrict__ v3, cpx<T>* __restrict__ z3, const cpx<T>* __re
         }
     }
     GRID_STRIDE(i, n) {
-        const cpx<T> y = yt[i];
-        const cpx<T> u = v3[i] + z3[i];
+        const cpx<T> y = i == i0 ? y0 : yt[i];
+        const cpx<T> u = i == i0 ? u0 : v3[i] + z3[i];
         const cpx<T> r3 = y + s * (u - y);
         const cpx<T> z = u - r3;
         z3[i] = z;
