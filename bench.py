@@ -166,6 +166,65 @@ def measured_traffic(stage: str):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def serving(torch, purify, synth, count: int, max_active: int) -> dict:
+    """Serving form on a seeded stream of ``count`` requests (sizes 128^2..1024^2 in the ratio
+    8:4:2:1, M/N ~ U[0.2, 2], ISNR ~ U[20, 40] dB, SARA, halting on, T_max = 300): the FP64
+    one-at-a-time GPU baseline (plan + solve per request, in order, on one stream), then the
+    FP32 server fed by Poisson arrivals at twice the baseline's solves/s.  Latency is arrival
+    to result on the host."""
+    reqs = synth.serving_requests(count)
+    for p in reqs:       # noiseless visibilities from the FP64 operator, then the request's noise
+        n = p.x_true.shape[0]
+        pl = purify.Plan(n, p.uv, precision="fp64", device="cuda:0")
+        y0 = pl.phi(pl.as_vec(p.x_true)).cpu().numpy()
+        synth.add_noise(p, y0, p.extra["isnr_db"])
+        del pl
+    kw = dict(max_iter=300, cg_iter=10, halting=True, xi=1e-4, slack=1e-3, check_every=10)
+    torch.cuda.synchronize()
+    base_ms, base_snr = [], []
+    t0 = time.perf_counter()
+    for p in reqs:
+        ts = time.perf_counter()
+        n = p.x_true.shape[0]
+        pl = purify.Plan(n, p.uv, precision="fp64", device="cuda:0")
+        r = pl.sdmm(pl.as_vec(p.y), p.epsilon, **kw)
+        x = r.x.cpu().numpy()
+        base_ms.append((time.perf_counter() - ts) * 1e3)
+        base_snr.append(synth.snr_db(p.x_true, x))
+        del pl, r
+    base_s = time.perf_counter() - t0
+    base_rate = count / base_s
+
+    free, _ = torch.cuda.mem_get_info()
+    arena = int(min(200e9, free - 16e9))
+    srv = purify.Server(arena, max_active=max_active, device="cuda:0")
+    arrivals = synth.poisson_arrivals(count, 2.0 * base_rate)
+    tickets = []
+    t0 = time.perf_counter()
+    for p, at in zip(reqs, arrivals):
+        now = time.perf_counter() - t0
+        if at > now:
+            time.sleep(at - now)
+        tickets.append(srv.submit(p.x_true.shape[0], p.uv, p.y.astype(np.complex64), p.epsilon,
+                                  precision="fp32", **kw))
+    res = [srv.wait(t) for t in tickets]
+    t_end = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([r.latency_ms for r in res])
+    dsnr = [abs(synth.snr_db(p.x_true, r.x) - s) for p, r, s in zip(reqs, res, base_snr)]
+    return {
+        "requests": count, "per_size": dict(zip([f"{s}^2" for s in synth.SERVING_SIZES],
+                                                 synth.serving_counts(count))),
+        "served_fp32_solves_s": count / t_end, "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)), "arrival_rate_per_s": 2.0 * base_rate,
+        "baseline_fp64_one_at_a_time_solves_s": base_rate,
+        "baseline_p50_ms": float(np.percentile(base_ms, 50)), "baseline_p99_ms": float(np.percentile(base_ms, 99)),
+        "max_abs_snr_diff_db": float(max(dsnr)), "mean_snr_db": float(np.mean(base_snr)),
+        "mean_iterations": float(np.mean([r.iterations for r in res])),
+        "max_active": max_active, "arena_gb": arena / 1e9,
+    }
+
+
 def copy_calibration(torch, mib: int) -> dict:
     """Ten launches of a plain elementwise kernel (negation, float32) that reads and writes
     mib MiB once each: the reference for scaling hardware byte counters."""
@@ -187,6 +246,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--extra-iters", type=int, default=30)
+    ap.add_argument("--serving-requests", type=int, default=30,
+                    help="requests in the serving-form stream (0: skip; 512 is the full stream)")
+    ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--kernel-only", default="", metavar="STAGE",
                     help="only time one stage of the 256x256 FP64 plan on real data (no solve, no "
                          "graphs; for hardware-counter runs) and print its line")
@@ -266,6 +328,11 @@ def main():
             also["sara1024_fp32"] = precision_form(torch, purify, synth, args.extra_iters)
         except Exception as e:  # report, do not hide the main line
             also["sara1024_fp32_error"] = repr(e)
+    if args.serving_requests > 0:
+        try:
+            also["serving"] = serving(torch, purify, synth, args.serving_requests, args.serving_slots)
+        except Exception as e:  # report, do not hide the main line
+            also["serving_error"] = repr(e)
     line["also"] = also
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, p, args.cpu_iters)

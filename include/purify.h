@@ -165,6 +165,50 @@ typedef enum {
 purify_status purify_time_stage(purify_plan* plan, int32_t stage, int32_t reps, void* stream,
                                 double* ms_per_launch);
 
+/* ---------------------------------------------------------------------------------------
+ * Serving form: a persistent request loop that runs the SDMM solves of independent imaging
+ * requests (any size and visibility count the plan accepts) concurrently on the current
+ * device.  The caller owns one device arena (the HBM budget); each admitted request gets a
+ * block of it (plan workspace + visibilities + image, purify_plan_workspace_bytes + M + N
+ * complex, 256-byte aligned) until its result is on the host.  Up to max_active requests
+ * run at once, each on its own stream with its own graph-replayed iteration, so their
+ * kernels overlap on the device; waiting requests are admitted as slots and arena memory
+ * free up (oldest first; a later request that fits may overtake a waiting one at most
+ * 2 * max_active times).  A served result is identical to purify_sdmm_solve of the same
+ * request on its own.  Calls are thread-safe.
+ * ------------------------------------------------------------------------------------- */
+typedef struct purify_server purify_server;
+
+typedef struct {
+    void* arena;          /* device, 256-byte aligned, owned by the caller, kept alive until
+                             purify_server_destroy returns */
+    size_t arena_bytes;   /* HBM budget: requests whose block exceeds it are rejected */
+    int32_t max_active;   /* requests solved at once (worker slots, one stream each), 1..64 */
+} purify_server_desc;
+
+/* Start the server's worker slots on the current device. */
+purify_status purify_server_create(const purify_server_desc* desc, purify_server** out);
+
+/* Queue one solve.  desc: as for purify_plan_create (desc->uv host, M x 2, copied).  y: host,
+ * M complex of desc->precision in uv order (copied).  params: as for purify_sdmm_solve, with
+ * history and weights NULL.  *ticket identifies the request.  Returns at once. */
+purify_status purify_server_submit(purify_server* server, const purify_plan_desc* desc, const void* y,
+                                   const purify_sdmm_params* params, int64_t* ticket);
+
+/* State of a request: 0 waiting, 1 running, 2 done, -1 unknown ticket. */
+int32_t purify_server_poll(purify_server* server, int64_t ticket);
+
+/* Block until the request is done, then release it.  x: host, N complex of the request's
+ * precision (or NULL); info as for purify_sdmm_solve (or NULL); timings: host, 3 doubles or
+ * NULL: milliseconds waiting for admission, running (plan creation, solve, result
+ * download), and from submission to the result on the host.  Returns the solve's status. */
+purify_status purify_server_wait(purify_server* server, int64_t ticket, void* x, purify_sdmm_info* info,
+                                 double* timings);
+
+/* Finish every queued request, stop the workers and free the server (uncollected results
+ * are dropped).  The arena may be freed afterwards. */
+void purify_server_destroy(purify_server* server);
+
 /* Host-side introspection (no GPU needed). */
 /* Daubechies Db-b lowpass filter the library uses (extremal phase, sum h = sqrt 2), computed
  * by its own spectral factorisation.  Writes min(2b, cap) doubles to h (host); returns 2b,

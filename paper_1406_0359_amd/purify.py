@@ -61,6 +61,10 @@ class SdmmInfo(ctypes.Structure):
     ]
 
 
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -89,6 +93,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "purify_daubechies_filter": (i32, [i32, ctypes.POINTER(dbl), i32]),
         "purify_kb_kernel": (i32, [i32, dbl, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
         "purify_deapodisation": (i32, [i32, i32, i32, dbl, ctypes.POINTER(dbl)]),
+        "purify_server_create": (i32, [ctypes.POINTER(ServerDesc), ctypes.POINTER(vp)]),
+        "purify_server_submit": (i32, [vp, pdesc, vp, ctypes.POINTER(SdmmParams), ctypes.POINTER(i64)]),
+        "purify_server_poll": (i32, [vp, i64]),
+        "purify_server_wait": (i32, [vp, i64, vp, ctypes.POINTER(SdmmInfo), ctypes.POINTER(dbl)]),
+        "purify_server_destroy": (None, [vp]),
         "purify_status_string": (ctypes.c_char_p, [i32]),
         "purify_last_error": (ctypes.c_char_p, []),
         "purify_version": (ctypes.c_char_p, []),
@@ -293,3 +302,84 @@ class Plan:
         _check(self.lib.purify_time_stage(self.handle, STAGES[stage], reps, self._stream(),
                                           ctypes.byref(ms)), "purify_time_stage")
         return ms.value
+
+
+@dataclass
+class ServedResult:
+    x: np.ndarray                # host complex (n, n); the image is x.real
+    iterations: int
+    converged: bool
+    objective: float
+    residual: float
+    nu: float
+    gamma: float
+    queue_ms: float              # submission -> admission
+    run_ms: float                # admission -> result on the host (plan, solve, download)
+    latency_ms: float            # submission -> result on the host
+
+
+class Server:
+    """Serving form: solves of independent requests (mixed sizes) run concurrently on one GPU.
+
+    The HBM budget is one device arena (a torch uint8 tensor of ``arena_bytes``) from which
+    every admitted request gets its plan workspace, visibilities and image; ``max_active``
+    requests run at once, each on its own stream.  ``submit`` returns a ticket at once;
+    ``wait`` blocks until that request's image is on the host.
+    """
+
+    def __init__(self, arena_bytes: int, max_active: int = 4, device="cuda:0"):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        d = ServerDesc()
+        d.arena, d.arena_bytes, d.max_active = self.arena.data_ptr(), int(arena_bytes), max_active
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.purify_server_create(ctypes.byref(d), ctypes.byref(h)), "purify_server_create")
+        self.handle = h
+        self._meta = {}
+
+    def submit(self, n: int, uv, y, epsilon: float, J: int = 6, dict_mask: int = DICT_SARA,
+               levels: int = 4, precision: str = "fp32", max_iter: int = 300, cg_iter: int = 10,
+               halting: bool = True, xi: float = 1e-4, slack: float = 1e-3, check_every: int = 10,
+               nu: float = 0.0, nu_iter: int = 100, gamma: float = 0.0, graph: bool = True) -> int:
+        prec = FP64 if precision in ("fp64", FP64) else FP32
+        uv = np.ascontiguousarray(uv, dtype=np.float64).reshape(-1, 2)
+        yh = np.ascontiguousarray(y, dtype=np.complex128 if prec == FP64 else np.complex64).ravel()
+        if yh.size != uv.shape[0]:
+            raise ValueError("y must have one value per uv point")
+        d = _desc(n, uv, J, 0.0, dict_mask, levels, prec)
+        p = SdmmParams()
+        p.epsilon, p.gamma, p.nu, p.xi, p.slack = epsilon, gamma, nu, xi, slack
+        p.max_iter, p.cg_iter, p.check_every = max_iter, cg_iter, check_every
+        p.halting, p.nu_iter = int(bool(halting)), nu_iter
+        p.flags = 0 if graph else SDMM_NO_GRAPH
+        t = ctypes.c_int64()
+        _check(self.lib.purify_server_submit(self.handle, ctypes.byref(d), yh.ctypes.data, ctypes.byref(p),
+                                             ctypes.byref(t)), "purify_server_submit")
+        self._meta[t.value] = (n, prec)
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        return int(self.lib.purify_server_poll(self.handle, ticket))
+
+    def wait(self, ticket: int) -> ServedResult:
+        n, prec = self._meta.pop(ticket)
+        x = np.zeros((n, n), dtype=np.complex128 if prec == FP64 else np.complex64)
+        info = SdmmInfo()
+        tm = np.zeros(3)
+        _check(self.lib.purify_server_wait(self.handle, ticket, x.ctypes.data, ctypes.byref(info), _dptr(tm)),
+               "purify_server_wait")
+        return ServedResult(x, info.iterations, bool(info.converged), info.objective, info.residual,
+                            info.nu, info.gamma, float(tm[0]), float(tm[1]), float(tm[2]))
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.purify_server_destroy(h)
+            self.handle = None
+
+    def __del__(self):
+        self.close()

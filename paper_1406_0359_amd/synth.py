@@ -183,3 +183,49 @@ def snr_db(x_true: np.ndarray, x_hat: np.ndarray) -> float:
     x_true = np.asarray(x_true, dtype=np.float64)
     err = x_true - np.real(np.asarray(x_hat))
     return 20.0 * math.log10(np.linalg.norm(x_true) / np.linalg.norm(err))
+
+
+# Serving stream: solves of mixed sizes in the ratio 8:4:2:1 (shuffled), M/N ~ U[0.2, 2] and
+# input SNR ~ U[20, 40] dB per request, Poisson arrivals.
+SERVING_SIZES = (128, 256, 512, 1024)
+SERVING_MIX = (8, 4, 2, 1)
+SERVING_INDEX = 3
+
+
+def serving_counts(count: int) -> list:
+    """Requests per size for a stream of ``count``: the 8:4:2:1 shares by largest remainder
+    (512 -> 273/137/68/34)."""
+    tot = sum(SERVING_MIX)
+    exact = [count * m / tot for m in SERVING_MIX]
+    per = [int(e) for e in exact]
+    order = sorted(range(len(per)), key=lambda i: -(exact[i] - per[i]))
+    for i in order[: count - sum(per)]:
+        per[i] += 1
+    return per
+
+
+def serving_requests(count: int) -> list:
+    """``count`` requests (Problem, noise not yet added: the caller's operator gives the
+    noiseless visibilities; the request's ISNR is in ``extra['isnr_db']``)."""
+    rng = rng_for(SERVING_INDEX, 0)
+    sizes = np.repeat(np.array(SERVING_SIZES), serving_counts(count))
+    rng.shuffle(sizes)
+    out = []
+    for i, n in enumerate(sizes.tolist()):
+        r = np.random.default_rng(SEED_BASE + 100 * SERVING_INDEX + 10 + i)
+        M = int(round(r.uniform(0.2, 2.0) * n * n))
+        isnr = float(r.uniform(20.0, 40.0))
+        w = Workload(f"serve{i}", n=n, M=M, J=6, dict_mask=0x1FF, levels=4, iters=300, blobs=40,
+                     isnr_db=isnr, index=SERVING_INDEX, precision="fp32")
+        img = blob_image(n, w.blobs, r)
+        uv = uv_coverage(M, 2 * n, r, 0.0)
+        nz = unit_complex_noise(M, r)
+        out.append(Problem(w, img, uv, nz, extra={"isnr_db": isnr}))
+    return out
+
+
+def poisson_arrivals(count: int, rate: float) -> np.ndarray:
+    """Arrival times (seconds from the first) of a Poisson stream of ``rate`` per second."""
+    gaps = rng_for(SERVING_INDEX, 1).exponential(1.0 / rate, size=count)
+    gaps[0] = 0.0
+    return np.cumsum(gaps)
