@@ -166,6 +166,39 @@ def measured_traffic(stage: str):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def large_solve(torch, purify, synth, iters: int) -> dict:
+    """The 4096^2 single solve (M = 10^7, J = 8, SARA, 5 levels, FP32 with FP64 reductions):
+    per-operator rates and SDMM iterations per second (nu, gamma and the plan excluded)."""
+    w = synth.WORKLOADS["sara4096"]
+    t0 = time.perf_counter()
+    p = synth.make_inputs(w)
+    t_inputs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = purify.Plan(w.n, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels, precision="fp32",
+                       device="cuda:0")
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    y0 = plan.phi(plan.as_vec(p.x_true)).cpu().numpy().astype(np.complex128)
+    synth.add_noise(p, y0)
+    y = plan.as_vec(p.y)
+    r0 = plan.sdmm(y, p.epsilon, max_iter=2, nu_iter=100)
+    torch.cuda.synchronize()
+    st = stage_table(plan, reps=5)
+    t0 = time.perf_counter()
+    r = plan.sdmm(y, p.epsilon, max_iter=iters, nu=r0.nu)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {
+        "workload": "sara4096 FP32 (n=4096, M=10^7, J=8, SARA 9 bases, L=5; 512 blobs + 1/f^2 field)",
+        "sdmm_iters_s": iters / dt, "solve_iters": iters, "snr_db": synth.snr_db(p.x_true, r.x.cpu().numpy()),
+        "residual_over_eps": r.residual / p.epsilon,
+        "phi_gvis_s": w.M / (st["phi"]["ms"] * 1e-3) / 1e9,
+        "phi_adj_gvis_s": w.M / (st["phi_adj"]["ms"] * 1e-3) / 1e9,
+        "psi_adj_GBs": st["psi_adj"]["GBs"], "psi_GBs": st["psi"]["GBs"],
+        "host_inputs_s": t_inputs, "plan_s": t_plan, "stages": st,
+    }
+
+
 def serving(torch, purify, synth, count: int, max_active: int) -> dict:
     """Serving form on a seeded stream of ``count`` requests (sizes 128^2..1024^2 in the ratio
     8:4:2:1, M/N ~ U[0.2, 2], ISNR ~ U[20, 40] dB, SARA, halting on, T_max = 300): the FP64
@@ -246,6 +279,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--extra-iters", type=int, default=30)
+    ap.add_argument("--large-iters", type=int, default=20,
+                    help="SDMM iterations timed on the 4096^2 solve (0: skip it)")
     ap.add_argument("--serving-requests", type=int, default=30,
                     help="requests in the serving-form stream (0: skip; 512 is the full stream)")
     ap.add_argument("--serving-slots", type=int, default=8)
@@ -328,6 +363,11 @@ def main():
             also["sara1024_fp32"] = precision_form(torch, purify, synth, args.extra_iters)
         except Exception as e:  # report, do not hide the main line
             also["sara1024_fp32_error"] = repr(e)
+    if args.large_iters > 0:
+        try:
+            also["sara4096_fp32"] = large_solve(torch, purify, synth, args.large_iters)
+        except Exception as e:  # report, do not hide the main line
+            also["sara4096_fp32_error"] = repr(e)
     if args.serving_requests > 0:
         try:
             also["serving"] = serving(torch, purify, synth, args.serving_requests, args.serving_slots)

@@ -126,6 +126,85 @@ k_wav_fwd_level(const cpx<T>* __restrict__ src, size_t src_bstride, int src_ld, 
     }
 }
 
+// The finest analysis level of every basis at once: all bases read the same image window,
+// so a workgroup loads the (2 AP + Fmax - 2)^2 window of its tile once (polyphase rows, as
+// above) and runs each basis' two axis passes on it in turn, instead of each basis' own
+// workgroup re-reading the image.  The Dirac block is the scaled tile of the image.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_wav_fwd_level0_all(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ alpha, cpx<T>* __restrict__ llout,
+                     const T* __restrict__ filt, WavArgs A, T scale, int Fmax) {
+    constexpr int IS = AR + 1, MS = 2 * AP + 1;
+    __shared__ cpx<T> in[AR * IS];
+    __shared__ cpx<T> mid[AR * MS];
+    __shared__ T tp[MAX_WAV][2 * MAX_TAPS];
+    const int n = A.n, Ls = n;
+    const size_t N = (size_t)n * n;
+    const int half = Ls >> 1;
+    const int tiles = half / AP;
+    const int ti1 = blockIdx.x / tiles, ti2 = blockIdx.x % tiles;
+    const int r0 = 2 * AP * ti1, c0 = 2 * AP * ti2;
+    const int R = 2 * AP + Fmax - 2, RH = R >> 1;
+    for (int i = threadIdx.x; i < A.nwav * 2 * MAX_TAPS; i += 256)
+        tp[i / (2 * MAX_TAPS)][i % (2 * MAX_TAPS)] = filt[i];
+    for (int i = threadIdx.x; i < R * R; i += 256) {
+        const int a = i / R, b = i - a * R;
+        in[a * IS + (b & 1) * RH + (b >> 1)] = x[(size_t)((r0 + a) & (Ls - 1)) * n + ((c0 + b) & (Ls - 1))];
+    }
+    if (A.dirac_block >= 0) {
+        cpx<T>* d = alpha + (size_t)A.dirac_block * N;
+        for (int i = threadIdx.x; i < 4 * AP * AP; i += 256) {
+            const size_t o = (size_t)(r0 + i / (2 * AP)) * n + c0 + i % (2 * AP);
+            d[o] = scale * x[o];
+        }
+    }
+    __syncthreads();
+    for (int z = 0; z < A.nwav; ++z) {
+        const size_t blk = (size_t)A.block[z] * N;
+        const int F = A.flen[z];
+        const int Rz = 2 * AP + F - 2;   // this basis uses the window's first Rz rows / cols
+        const T* h = tp[z];
+        const T* g = h + MAX_TAPS;
+        for (int i = threadIdx.x; i < Rz * AP; i += 256) {
+            const int a = i / AP, oi = i - a * AP;
+            const cpx<T>* row = in + a * IS + oi;
+            T lx = 0, ly = 0, hx = 0, hy = 0;
+#pragma unroll
+            for (int k = 0; k < MAX_TAPS; ++k) {
+                if (k >= F) break;
+                const cpx<T> v = row[(k & 1) * RH + (k >> 1)];
+                lx += h[k] * v.x;
+                ly += h[k] * v.y;
+                hx += g[k] * v.x;
+                hy += g[k] * v.y;
+            }
+            mid[a * MS + oi] = mk<T>(lx, ly);
+            mid[a * MS + AP + oi] = mk<T>(hx, hy);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 2 * AP * AP; i += 256) {
+            const int oi = i / (2 * AP), o1 = i - oi * (2 * AP);
+            const cpx<T>* col = mid + 2 * oi * MS + o1;
+            T lx = 0, ly = 0, hx = 0, hy = 0;
+#pragma unroll
+            for (int k = 0; k < MAX_TAPS; ++k) {
+                if (k >= F) break;
+                const cpx<T> v = col[k * MS];
+                lx += h[k] * v.x;
+                ly += h[k] * v.y;
+                hx += g[k] * v.x;
+                hy += g[k] * v.y;
+            }
+            const int row = AP * ti1 + oi;
+            const int cl = (o1 >= AP ? half + o1 - AP : o1) + AP * ti2;
+            if (o1 < AP && llout) llout[(size_t)z * (N / 4) + (size_t)row * half + cl] = mk<T>(scale * lx, scale * ly);
+            else alpha[blk + (size_t)row * n + cl] = mk<T>(scale * lx, scale * ly);
+            alpha[blk + (size_t)(half + row) * n + cl] = mk<T>(scale * hx, scale * hy);
+        }
+        __syncthreads();
+    }
+}
+
 // Synthesis of one level on a po x po output tile (po = min(SP, Ls)) of one basis: loads
 // the window of the four subbands the tile reaches (po/2 + F/2 - 1 positions per axis per
 // subband, periodic) into `in`, undoes axis 0 into `mid`, then axis 1; returns the thread's
@@ -169,8 +248,14 @@ __device__ __forceinline__ void synth_tile(const cpx<T>* __restrict__ alpha, siz
         mid[(2 * jr + 1) * WS + v] = mk<T>(ox, oy);
     }
     __syncthreads();
-    // undo axis 1: row r, output columns 2j, 2j+1
-    for (int i = tid; i < po * hp; i += NTH) {
+    // undo axis 1: row r, output columns 2j, 2j+1 (a thread's k-th pair is i = tid + k NTH;
+    // the unrolled k is a compile-time index for the caller's accumulators)
+    constexpr int PMAX = CMAX - MAX_TAPS / 2 + 1;          // largest po / 2
+    constexpr int KMAX = (2 * PMAX * PMAX + NTH - 1) / NTH;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int i = tid + k * NTH;
+        if (i >= po * hp) break;
         const int r = i / hp, jc = i - r * hp;
         T ex = 0, ey = 0, ox = 0, oy = 0;
 #pragma unroll
@@ -185,7 +270,7 @@ __device__ __forceinline__ void synth_tile(const cpx<T>* __restrict__ alpha, siz
             ox += ho * lo.x + go * hv.x;
             oy += ho * lo.y + go * hv.y;
         }
-        emit(i, r, 2 * jc, mk<T>(ex, ey), mk<T>(ox, oy));
+        emit(k, r, 2 * jc, mk<T>(ex, ey), mk<T>(ox, oy));
     }
 }
 
@@ -219,17 +304,16 @@ k_wav_inv_level(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ lli
                        });
 }
 
-// Finest synthesis level: the image tile (16 x 16) sums every basis plus the Dirac block,
-// times `scale`.  NSLOT groups of 256 threads synthesise different bases concurrently and
-// their partial sums are added in slot order (a fixed order: deterministic).
-constexpr int FP = 16;
-constexpr int NSLOT = 4;
-template <typename T>
+// Finest synthesis level: an FP x FP image tile sums every basis plus the Dirac block, times
+// `scale`.  NSLOT groups of 256 threads synthesise different bases concurrently and their
+// partial sums are added in slot order (a fixed order: deterministic).
+template <typename T, int FP, int NSLOT>
 __global__ void __launch_bounds__(256 * NSLOT)
 k_wav_inv_final(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ llin, int ll_from_alpha,
                 cpx<T>* __restrict__ x, const T* __restrict__ filt, WavArgs A, T scale) {
     constexpr int CF = FP / 2 + MAX_TAPS / 2 - 1;
     constexpr int WS = 2 * CF + 1;
+    constexpr int PAIRS = (FP * FP / 2 + 255) / 256;   // output pairs per thread
     __shared__ cpx<T> in[NSLOT][2 * CF * WS];
     __shared__ cpx<T> mid[NSLOT][FP * WS];
     __shared__ T tp[NSLOT][2 * MAX_TAPS];
@@ -240,8 +324,10 @@ k_wav_inv_final(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ lli
     const int tiles = n / FP;
     const int m0 = FP * (blockIdx.x / tiles), m1 = FP * (blockIdx.x % tiles);
     const int slot = threadIdx.x >> 8, tid = threadIdx.x & 255;
-    // each thread owns outputs (r, 2jc), (r, 2jc+1) for i = tid < FP * FP / 2
-    cpx<T> acc0 = mk<T>(0, 0), acc1 = mk<T>(0, 0);
+    // thread tid owns the output pairs i = tid + 256 k: row i / (FP/2), columns 2 (i % (FP/2)) + {0, 1}
+    cpx<T> acc0[PAIRS], acc1[PAIRS];
+#pragma unroll
+    for (int k = 0; k < PAIRS; ++k) acc0[k] = acc1[k] = mk<T>(0, 0);
     const int rounds = (A.nwav + NSLOT - 1) / NSLOT;
     for (int rd = 0; rd < rounds; ++rd) {
         const int z = rd * NSLOT + slot;
@@ -254,23 +340,27 @@ k_wav_inv_final(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ lli
         if (tid < 2 * MAX_TAPS) tp[slot][tid] = filt[zz * 2 * MAX_TAPS + tid];
         // inactive slots run on basis 0 and discard the result (keeps the barriers uniform)
         synth_tile<T, 256, CF>(alpha, blk, lls, lld, n, half, FP, m0, m1, A.flen[zz], tp[slot], in[slot], mid[slot],
-                           tid, [&](int, int, int, cpx<T> e, cpx<T> od) {
-                               if (active) {
-                                   acc0.x += e.x;
-                                   acc0.y += e.y;
-                                   acc1.x += od.x;
-                                   acc1.y += od.y;
-                               }
-                           });
+                               tid, [&](int k, int, int, cpx<T> e, cpx<T> od) {
+                                   if (active) {
+                                       acc0[k].x += e.x;
+                                       acc0[k].y += e.y;
+                                       acc1[k].x += od.x;
+                                       acc1[k].y += od.y;
+                                   }
+                               });
     }
-    if (tid < FP * FP / 2) {
-        const int r = tid / (FP / 2), c = 2 * (tid % (FP / 2));
-        part[slot][r * FP + c] = acc0;
-        part[slot][r * FP + c + 1] = acc1;
+#pragma unroll
+    for (int k = 0; k < PAIRS; ++k) {
+        const int i = tid + 256 * k;
+        if (i < FP * FP / 2) {
+            const int r = i / (FP / 2), c = 2 * (i % (FP / 2));
+            part[slot][r * FP + c] = acc0[k];
+            part[slot][r * FP + c + 1] = acc1[k];
+        }
     }
     __syncthreads();
-    if (threadIdx.x < FP * FP) {
-        const int r = threadIdx.x / FP, c = threadIdx.x % FP;
+    for (int i = threadIdx.x; i < FP * FP; i += 256 * NSLOT) {
+        const int r = i / FP, c = i % FP;
         const size_t o = (size_t)(m0 + r) * n + m1 + c;
         T sx = 0, sy = 0;
         if (A.dirac_block >= 0) {
@@ -280,8 +370,8 @@ k_wav_inv_final(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ lli
         }
 #pragma unroll
         for (int sl = 0; sl < NSLOT; ++sl) {
-            sx += part[sl][threadIdx.x].x;
-            sy += part[sl][threadIdx.x].y;
+            sx += part[sl][i].x;
+            sy += part[sl][i].y;
         }
         x[o] = mk<T>(scale * sx, scale * sy);
     }
@@ -329,7 +419,14 @@ void launch_psi_adj(const Plan& P, const cpx<T>* x, cpx<T>* alpha, hipStream_t s
         const int tiles = half / ap;
         const dim3 g(tiles * tiles, 1, lev == 0 ? ztot : P.nwav);
         cpx<T>* llout = lev + 1 < P.levels ? llb[lev & 1] : nullptr;
-        if (lev == 0)
+        // large images: one pass over the image for all bases (small ones need the bases'
+        // separate workgroups to fill the device)
+        if (lev == 0 && ap == AP && tiles * tiles >= 1024) {
+            int Fmax = 2;
+            for (int i = 0; i < P.nwav; ++i) Fmax = std::max(Fmax, A.flen[i]);
+            hipLaunchKernelGGL(k_wav_fwd_level0_all<T>, dim3(tiles * tiles), dim3(256), 0, s, x, alpha, llout,
+                               filt, A, scale, Fmax);
+        } else if (lev == 0)
             hipLaunchKernelGGL(k_wav_fwd_level<T>, g, dim3(256), 0, s, x, (size_t)0, P.n, alpha, llout, filt, A,
                                Ls, scale);
         else
@@ -363,8 +460,18 @@ void launch_psi(const Plan& P, const cpx<T>* alpha, cpx<T>* x, hipStream_t s) {
         cur = dst;
     }
     const cpx<T>* in = cur < 0 ? alpha : llb[cur];
-    const int tiles = P.n / FP;
-    hipLaunchKernelGGL(k_wav_inv_final<T>, dim3(tiles * tiles), dim3(256 * NSLOT), 0, s, alpha, in,
+    // FP32 on large images: 32 x 32 tiles (half the window overhead of 16 x 16); the FP64
+    // windows of a 32 x 32 tile would not fit in LDS four bases at a time
+    if constexpr (sizeof(T) == 4) {
+        if (P.n >= 512) {
+            const int tiles = P.n / 32;
+            hipLaunchKernelGGL((k_wav_inv_final<T, 32, 4>), dim3(tiles * tiles), dim3(1024), 0, s, alpha, in,
+                               cur < 0 ? 1 : 0, x, filt, A, scale);
+            return;
+        }
+    }
+    const int tiles = P.n / 16;
+    hipLaunchKernelGGL((k_wav_inv_final<T, 16, 4>), dim3(tiles * tiles), dim3(1024), 0, s, alpha, in,
                        cur < 0 ? 1 : 0, x, filt, A, scale);
 }
 
