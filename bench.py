@@ -10,8 +10,11 @@ Also reported:
   launch time (HIP events on the stream it runs on), against 8 TB/s HBM;
 * ``cpu_baseline``: the FP64 NumPy/SciPy oracle on the same workload, timed on a bounded
   sample (setup + a few SDMM iterations, extrapolated to the 300-iteration solve);
-* ``also``: per-stage timings and the 1024 x 1024 FP32 precision-form workload (M = 2N):
-  Phi / Phi^dagger Gvis/s, Psi / Psi^dagger GB/s and SDMM iterations per second.
+* ``steady_state``: the marginal SDMM iterations per second on an existing plan;
+* ``also``: per-stage timings; the 1024 x 1024 FP32 precision-form workload (M = 2N):
+  Phi / Phi^dagger Gvis/s, Psi / Psi^dagger GB/s and SDMM iterations per second; the
+  4096 x 4096 single solve (M = 10^7, J = 8, 5 levels, FP32); and the serving form (FP32
+  server on a Poisson stream of mixed-size requests against the FP64 one-at-a-time solves).
 """
 from __future__ import annotations
 
@@ -336,6 +339,15 @@ def main():
     value = args.steps * w.iters / dt
     snr = synth.snr_db(p.x_true, res.x.cpu().numpy())
 
+    # steady state: the marginal cost of 300 more iterations on the same plan (nu given)
+    def timed_solve(k):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plan.sdmm(y, p.epsilon, max_iter=k, cg_iter=w.cg_iters, nu=res.nu)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+    steady = w.iters / (timed_solve(10 + w.iters) - timed_solve(10))
+
     # per-stage timing (HIP events on the plan's stream) and the dominant kernel
     st = stage_table(plan)
     per_iter = launches_per_iter(w.cg_iters)
@@ -355,6 +367,8 @@ def main():
                                "300 SDMM iters, CG 10, FP64; step = plan + nu + gamma + solve",
                    "global_batch": 1, "parallelism": "single GPU"},
         "snr_db": snr, "residual_over_eps": res.residual / p.epsilon,
+        "steady_state": {"value": steady, "unit": "iters/s",
+                         "what": "marginal SDMM iterations/s on the plan (no plan, nu or gamma)"},
         "roofline": roofline,
     }
     also = {"sara256_stages": st}
