@@ -114,8 +114,9 @@ struct Sdmm {
         C *z1 = (C*)P.z1, *v1 = (C*)P.v1, *z2 = (C*)P.z2, *z3 = (C*)P.z3, *v3 = (C*)P.v3;
         const C* yt = (const C*)P.ytil;
         const int rows_blocks = fft_rows_adj_blocks<T>(P);
-        // Global update (step 5): CG on (Phi~^dag Phi~ + 2I) x = x1 + x2 + x3, warm start.
-        op.apply_A(xh, q, inv_nu2, nullptr);
+        // Global update (step 5): CG on (Phi~^dag Phi~ + 2I) x = x1 + x2 + x3, warm start;
+        // q = A x_hat of the warm start was formed at the end of the previous iteration (or
+        // by enqueue_prologue), beside branch i = 1.
         const int nb = launch_cg_init<T>(x1, x2, x3, q, r, p, N, part(0), s);
         // step c: q = A p (for c > 0 the row pass first forms p = r + beta p), then
         // x += alpha p, r -= alpha q; rho of step c is in buffer c & 1
@@ -141,8 +142,17 @@ struct Sdmm {
         const int nb3 = launch_ball_part<T>(v3, z3, yt, M, part(4), part(5), s);
         launch_prox_ball<T>(v3, z3, yt, part(4), part(5), nb3, eps_t, sc, P.hist, P.hist_cap, M, s);
         op.phi_adj(v3, nullptr, x3, inv_nu, nullptr, 0.0, nullptr);
+        // the next iteration's warm-start product A x_hat needs only x_hat: it runs here,
+        // overlapping branch i = 1 on the other stream
+        op.apply_A(xh, q, inv_nu2, nullptr);
         (void)hipStreamWaitEvent(s, join, 0);
         launch_iter_advance(sc, s);
+    }
+
+    // q = A x_hat for the first iteration's warm start.
+    void enqueue_prologue(hipStream_t s) const {
+        const Ops<T> op{P, s};
+        op.apply_A((const C*)P.xh, (C*)P.qv, inv_nu2, nullptr);
     }
 };
 
@@ -224,6 +234,7 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     launch_fill<T>((C*)P.z1, zero, D, cs);
     launch_fill<T>((C*)P.z3, zero, M, cs);
     PURIFY_HIP(hipMemsetAsync(sc, 0, SL_COUNT * sizeof(double), cs));
+    S.enqueue_prologue(cs);
 
     if (use_graph) {
         PURIFY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
