@@ -111,6 +111,7 @@ struct Plan {
     int32_t* tilecover = nullptr;  // nT^2: max number of visibilities covering one cell of the tile
     int32_t* gwork = nullptr;    // gridding work-unit records, GRID_REC ints each
     int nwork = 0;
+    bool strip_xcd = false;      // work unit w handles a tile of strip t2 with t2 % 8 == w % 8
     int grid_unit = 0;           // visibility passes per gridding work unit before a split
     int32_t* gmerge = nullptr;   // split tiles {tile, parts, first partial slot}
     int nmerge = 0, gmerge_cap = 0;

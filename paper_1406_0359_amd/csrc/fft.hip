@@ -252,6 +252,16 @@ __device__ __forceinline__ int xcd_block() {
     return (b % 8) * (nb / 8) + b / 8;
 }
 
+// Column group of this workgroup when the grid's gridding tiles are strips of `sg` column
+// groups: workgroup b runs on XCD b % 8 and takes the strips congruent to b % 8 (mod 8), the
+// same strips whose tiles the gridding kernel runs on that XCD, so the grid stays in that
+// XCD's L2 between the column passes and the gridding.  sg = 0: xcd_block().
+__device__ __forceinline__ int strip_block(int sg) {
+    if (sg <= 0) return xcd_block();
+    const int e = blockIdx.x % 8, k = blockIdx.x / 8;
+    return (e + 8 * (k / sg)) * sg + k % sg;
+}
+
 // Workgroup shapes.  Each n-point line transform uses TL threads; the two output parities of
 // a line are separate thread groups.  Row passes: B rows per workgroup (64-128 threads).
 // Column passes: C adjacent columns (contiguous runs of C elements), at most 1024 threads,
@@ -385,7 +395,7 @@ k_fft_rows_fwd(cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __rest
 template <typename T, int LOGN, int C>
 __global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN, 1>::TL))
 k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const cpx<T>* __restrict__ tw,
-               const cpx<T>* __restrict__ tw2) {
+               const cpx<T>* __restrict__ tw2, int sg) {
     using PL = Plan1D<T, LOGN, 1>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
@@ -393,7 +403,7 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int c = threadIdx.x % C, r = (threadIdx.x / C) & 1, tl = threadIdx.x / (2 * C);
     cpx<T>* line = base + table_elems<T, LOGN>() + (2 * c + r) * PL::LS;
-    const int col = xcd_block() * C + c;
+    const int col = strip_block(sg) * C + c;
     __syncthreads();
     cpx<T> v[PL::RMAX];
 #pragma unroll
@@ -418,7 +428,7 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
 template <typename T, int LOGN, int C>
 __global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN, 1>::TL))
 k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const cpx<T>* __restrict__ tw,
-               const cpx<T>* __restrict__ tw2) {
+               const cpx<T>* __restrict__ tw2, int sg) {
     using PL = Plan1D<T, LOGN, 1>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
@@ -427,7 +437,7 @@ k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const 
     const int c = threadIdx.x % C, r = (threadIdx.x / C) & 1, tl = threadIdx.x / (2 * C);
     cpx<T>* lines = base + table_elems<T, LOGN>();
     cpx<T>* line = lines + (2 * c + r) * PL::LS;
-    const int col = xcd_block() * C + c;
+    const int col = strip_block(sg) * C + c;
     __syncthreads();
     cpx<T> v[PL::RMAX];
 #pragma unroll
@@ -516,6 +526,12 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
     }
 }
 
+// Column groups per gridding-tile strip when the plan's work list is strip-ordered (see
+// strip_block), else 0.
+int strip_groups(const Plan& P, int C) {
+    return (P.strip_xcd && P.TT % C == 0) ? P.TT / C : 0;
+}
+
 template <typename F>
 void set_lds_limit(F* f, size_t bytes) {
     if (bytes > 65536)
@@ -549,7 +565,7 @@ void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s
     auto f = k_fft_cols_fwd<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, tmp, grid, (const cpx<T>*)P.tw,
-                       (const cpx<T>*)P.tw2);
+                       (const cpx<T>*)P.tw2, strip_groups(P, C));
 }
 template <typename T, int LOGN>
 void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s) {
@@ -560,7 +576,7 @@ void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s
     auto f = k_fft_cols_adj<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, grid, tmp, (const cpx<T>*)P.tw,
-                       (const cpx<T>*)P.tw2);
+                       (const cpx<T>*)P.tw2, strip_groups(P, C));
 }
 template <typename T, int LOGN>
 void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* v,

@@ -188,6 +188,7 @@ k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32
     __shared__ cpx<T> win[GTG ? WPT * NT : 1];
     const int32_t* w = work + GRID_REC * blockIdx.x;
     const int tile = w[0], slot = w[1], cover = w[2], total = w[3];
+    if (tile < 0) return;   // padding unit of the strip-ordered work list
     int rs[5], cum[6];
     cum[0] = 0;
 #pragma unroll

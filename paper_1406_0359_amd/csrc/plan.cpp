@@ -530,6 +530,38 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
             set_error("internal: gridding work list exceeds its bound");
             return PURIFY_E_INVALID;
         }
+        // Strip order: workgroups are dispatched round-robin over the 8 XCDs, so unit w runs on
+        // XCD w % 8.  Give unit w a tile of a strip t2 = w (mod 8) (each XCD's units keep the
+        // heaviest-first order, empty units pad the shorter lists), matching the column FFT
+        // passes' strip_block mapping: the grid columns a tile reads and writes stay in one
+        // XCD's L2.  Kept only if the padding fits the work list's capacity.
+        P.strip_xcd = false;
+        if (nT % 8 == 0) {
+            std::vector<std::vector<int32_t>> q(8);
+            for (size_t u = 0; u < work.size() / GRID_REC; ++u) {
+                const int32_t* rec = &work[u * GRID_REC];
+                const int e = (rec[0] / nT) % 8;
+                q[e].insert(q[e].end(), rec, rec + GRID_REC);
+            }
+            size_t longest = 0;
+            for (const auto& v : q) longest = std::max(longest, v.size() / GRID_REC);
+            if (8 * longest <= work_cap) {
+                std::vector<int32_t> ord;
+                ord.reserve(8 * longest * GRID_REC);
+                for (size_t k = 0; k < longest; ++k)
+                    for (int e = 0; e < 8; ++e) {
+                        if (k < q[e].size() / GRID_REC) {
+                            ord.insert(ord.end(), q[e].begin() + k * GRID_REC, q[e].begin() + (k + 1) * GRID_REC);
+                        } else {
+                            int32_t empty[GRID_REC] = {};
+                            empty[0] = -1;   // no tile: the workgroup exits at once
+                            ord.insert(ord.end(), empty, empty + GRID_REC);
+                        }
+                    }
+                work.swap(ord);
+                P.strip_xcd = true;
+            }
+        }
         P.nwork = (int)(work.size() / GRID_REC);
         P.nmerge = (int)(merge.size() / 3);
     }
