@@ -112,6 +112,9 @@ struct Plan {
     int32_t* gwork = nullptr;    // gridding work-unit records, GRID_REC ints each
     int nwork = 0;
     bool strip_xcd = false;      // work unit w handles a tile of strip t2 with t2 % 8 == w % 8
+    int32_t* dchunk = nullptr;   // degridding: {first visibility, count} per workgroup (strip order)
+    int ndchunk = 0, dchunk_cap = 0;   // 0 workgroups listed: plain 256-visibility blocks
+    bool degrid_tiles = false;   // G by gridding work units with an LDS window of the grid
     int grid_unit = 0;           // visibility passes per gridding work unit before a split
     int32_t* gmerge = nullptr;   // split tiles {tile, parts, first partial slot}
     int nmerge = 0, gmerge_cap = 0;

@@ -105,10 +105,16 @@ template <typename T, int J>
 __global__ void __launch_bounds__(256)
 k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
          const int32_t* __restrict__ base, const T* __restrict__ frac, const T* __restrict__ kbc,
-         const T* __restrict__ wtab, int M, int K, T scale, int Jr) {
+         const T* __restrict__ wtab, int M, int K, T scale, int Jr, const int32_t* __restrict__ chunks) {
     constexpr int JJ = J > 0 ? J : KB_MAX_J;
-    const int m = blockIdx.x * 256 + threadIdx.x;
-    if (m >= M) return;
+    int m;
+    if (chunks) {   // strip-ordered chunk {first, count} of this workgroup
+        if ((int)threadIdx.x >= chunks[2 * blockIdx.x + 1]) return;
+        m = chunks[2 * blockIdx.x] + threadIdx.x;
+    } else {
+        m = blockIdx.x * 256 + threadIdx.x;
+        if (m >= M) return;
+    }
     const int b = base[m];
     const int k1 = b & 0xFFFF, k2 = (b >> 16) & 0xFFFF;
     const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[m];
@@ -116,6 +122,72 @@ k_degrid(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t*
     visibility_weights<T, J>(wtab, kbc, m, f, wa, wb, Jr);
     const cpx<T> v = interpolate<T, J>(grid, k1, k2, wa, wb, K, Jr);
     y[perm ? perm[m] : m] = mk<T>(scale * v.x, scale * v.y);
+}
+
+// G by tiles: one work unit of the gridding work list (a tile, or part of a heavy one) per
+// workgroup; the unit's own visibilities (its shares of the tile's interior and spilling
+// ranges; spill-ins belong to other tiles) interpolate from the (TT + J - 1)^2 window of the
+// grid that holds all their footprints, staged once in LDS (FP64 with global_load_lds).  Each
+// visibility is handled once; the strip-ordered work list keeps a unit on the XCD whose L2
+// holds its grid columns.
+template <typename T, int J, int TT, int NT>
+__global__ void __launch_bounds__(NT)
+k_degrid_tiles(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const int32_t* __restrict__ perm,
+               const int32_t* __restrict__ base, const T* __restrict__ frac, const T* __restrict__ kbc,
+               const T* __restrict__ wtab, const int32_t* __restrict__ work, int K, int nT, T scale, int Jr) {
+    constexpr int JJ = J > 0 ? J : KB_MAX_J;
+    constexpr int UNR = J > 0 ? J : 1;
+    constexpr int WS = TT + JJ - 1;
+    constexpr int WPT = (WS * WS + NT - 1) / NT;
+    constexpr bool DMA = sizeof(T) == 8;
+    __shared__ cpx<T> win[WPT * NT];
+    const int32_t* w = work + GRID_REC * blockIdx.x;
+    const int tile = w[0];
+    if (tile < 0) return;
+    const int s0 = w[4], n0 = w[5] - w[4], s1 = w[6], total = n0 + (w[7] - w[6]);
+    if (total == 0) return;
+    const int t1o = (tile % nT) * TT, t2o = (tile / nT) * TT;
+    const int mask = K - 1;
+    const int Jn = J > 0 ? J : Jr;
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) {
+        const int i = threadIdx.x + k * NT;
+        if (i < WS * WS) {
+            const cpx<T>* src = grid + (size_t)((t1o + i / WS) & mask) * K + ((t2o + i % WS) & mask);
+            if constexpr (DMA)
+                __builtin_amdgcn_global_load_lds(
+                    (const void*)src, (__attribute__((address_space(3))) void*)(win + (threadIdx.x & ~63u) + k * NT),
+                    16, 0, 0);
+            else
+                win[i] = *src;
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < total; j += NT) {
+        const int idx = j < n0 ? s0 + j : s1 + (j - n0);
+        const int bk = base[idx];
+        const cpx<T> f = reinterpret_cast<const cpx<T>*>(frac)[idx];
+        T wa[JJ], wb[JJ];
+        visibility_weights<T, J>(wtab, kbc, idx, f, wa, wb, Jr);
+        const cpx<T>* w0 = win + (((bk & 0xFFFF) - t1o) & mask) * WS + ((((bk >> 16) & 0xFFFF) - t2o) & mask);
+        T ax = 0, ay = 0;
+#pragma unroll UNR
+        for (int a = 0; a < JJ; ++a) {
+            if (a >= Jn) break;
+            const cpx<T>* row = w0 + a * WS;
+            T rx = 0, ry = 0;
+#pragma unroll UNR
+            for (int bb = 0; bb < JJ; ++bb) {
+                if (bb >= Jn) break;
+                const cpx<T> g = row[bb];
+                rx += wb[bb] * g.x;
+                ry += wb[bb] * g.y;
+            }
+            ax += wa[a] * rx;
+            ay += wa[a] * ry;
+        }
+        y[perm ? perm[idx] : idx] = mk<T>(scale * ax, scale * ay);
+    }
 }
 
 // Gridding accumulates in LDS with integer atomics on a fixed-point representation:
@@ -422,18 +494,39 @@ void grid_tt(const Plan& P, const cpx<T>* y, const cpx<T>* gin, const int32_t* p
 
 }  // namespace
 
+template <typename T, int TT>
+void degrid_tiles_tt(const Plan& P, const cpx<T>* grid, cpx<T>* y, const int32_t* perm, double scale,
+                     hipStream_t s) {
+    const dim3 g(P.nwork), b(256);
+    const T* fr = (const T*)P.frac;
+    const T* kbc = (const T*)P.kbpoly;
+    const T* wt = (const T*)P.wtab;
+    switch (P.J) {
+        case 4: hipLaunchKernelGGL((k_degrid_tiles<T, 4, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, P.gwork, P.K, P.nT, (T)scale, 4); break;
+        case 6: hipLaunchKernelGGL((k_degrid_tiles<T, 6, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, P.gwork, P.K, P.nT, (T)scale, 6); break;
+        case 8: hipLaunchKernelGGL((k_degrid_tiles<T, 8, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, P.gwork, P.K, P.nT, (T)scale, 8); break;
+        default: hipLaunchKernelGGL((k_degrid_tiles<T, 0, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, P.gwork, P.K, P.nT, (T)scale, P.J); break;
+    }
+}
+
 template <typename T>
 void launch_degrid(const Plan& P, const cpx<T>* grid, cpx<T>* y, const int32_t* perm, double scale,
                    hipStream_t s) {
+    if (P.degrid_tiles) {
+        if (P.TT == 16) degrid_tiles_tt<T, 16>(P, grid, y, perm, scale, s);
+        else degrid_tiles_tt<T, 32>(P, grid, y, perm, scale, s);
+        return;
+    }
     const int M = (int)P.M;
-    const dim3 g((M + 255) / 256), b(256);
+    const int32_t* ch = P.ndchunk > 0 ? P.dchunk : nullptr;
+    const dim3 g(ch ? P.ndchunk : (M + 255) / 256), b(256);
     const T* fr = (const T*)P.frac;
     const T* kbc = (const T*)P.kbpoly;
     switch (P.J) {
-        case 4: hipLaunchKernelGGL((k_degrid<T, 4>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, 4); break;
-        case 6: hipLaunchKernelGGL((k_degrid<T, 6>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, 6); break;
-        case 8: hipLaunchKernelGGL((k_degrid<T, 8>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, 8); break;
-        default: hipLaunchKernelGGL((k_degrid<T, 0>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, P.J); break;
+        case 4: hipLaunchKernelGGL((k_degrid<T, 4>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, 4, ch); break;
+        case 6: hipLaunchKernelGGL((k_degrid<T, 6>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, 6, ch); break;
+        case 8: hipLaunchKernelGGL((k_degrid<T, 8>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, 8, ch); break;
+        default: hipLaunchKernelGGL((k_degrid<T, 0>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, (const T*)P.wtab, M, P.K, (T)scale, P.J, ch); break;
     }
 }
 

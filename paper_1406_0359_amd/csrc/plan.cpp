@@ -284,6 +284,10 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
         const size_t ib = P.precision == PURIFY_FP64 ? 8 : 4;
         P.gscratch = carve(parts_max * 2 * (size_t)P.TT * P.TT * ib);
         P.gexp = (int32_t*)carve(parts_max * sizeof(int32_t));
+        // degridding chunk table: at most twice the blocks of a plain launch plus one partial
+        // chunk per strip and padding (larger strip-ordered tables fall back to plain blocks)
+        P.dchunk_cap = (int)std::min<int64_t>((int64_t)2 * ((M + 255) / 256) + P.nT + 64, INT32_MAX / 2);
+        P.dchunk = (int32_t*)carve((size_t)P.dchunk_cap * 2 * sizeof(int32_t));
     }
     P.deap = carve(P.n * es);
     P.tw = carve(P.n * ce);
@@ -565,6 +569,48 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
         P.nwork = (int)(work.size() / GRID_REC);
         P.nmerge = (int)(merge.size() / 3);
     }
+    // G by work units (k_degrid_tiles) when the units' grid windows, (TT + J - 1)^2 cells each,
+    // add up to at most half the J^2 taps the visibilities gather (dense coverage); sparse
+    // coverage keeps one thread per visibility gathering straight from the grid.
+    {
+        int64_t busy = 0;
+        for (size_t u = 0; u < work.size() / GRID_REC; ++u) {
+            const int32_t* rec = &work[u * GRID_REC];
+            if (rec[0] >= 0 && (rec[5] - rec[4]) + (rec[7] - rec[6]) > 0) ++busy;
+        }
+        const int64_t ws = TT + J - 1;
+        P.degrid_tiles = busy * ws * ws * 2 <= (int64_t)M * J * J;
+    }
+    // Degridding in the same strip order: workgroup b (XCD b % 8) takes up to 256 visibilities
+    // of a strip t2 = b (mod 8), so it reads the grid columns the column FFT pass left in its
+    // XCD's L2.  Strip t2 holds the visibilities of tiles t2 * nT .. t2 * nT + nT - 1.
+    std::vector<int32_t> dch;
+    P.ndchunk = 0;
+    if (nT % 8 == 0) {
+        std::vector<std::vector<int32_t>> q(8);
+        for (int s2 = 0; s2 < nT; ++s2) {
+            const int a0 = off[4 * (s2 * nT)], a1 = off[4 * ((s2 + 1) * nT)];
+            for (int a = a0; a < a1; a += 256) {
+                q[s2 % 8].push_back(a);
+                q[s2 % 8].push_back(std::min(256, a1 - a));
+            }
+        }
+        size_t longest = 0;
+        for (const auto& v : q) longest = std::max(longest, v.size() / 2);
+        if (8 * longest <= (size_t)P.dchunk_cap) {
+            for (size_t k = 0; k < longest; ++k)
+                for (int e = 0; e < 8; ++e) {
+                    if (k < q[e].size() / 2) {
+                        dch.push_back(q[e][2 * k]);
+                        dch.push_back(q[e][2 * k + 1]);
+                    } else {
+                        dch.push_back(0);
+                        dch.push_back(0);
+                    }
+                }
+            P.ndchunk = (int)(dch.size() / 2);
+        }
+    }
 
     // FP64 tap weights in sorted order: w[p][a] = psi(f1 + J/2 - 1 - a), w[p][J + a] likewise
     // for axis 2, from the same per-tap polynomials the FP32 kernels evaluate.
@@ -600,6 +646,7 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     PURIFY_HIP(up(P.tileoff, off.data(), off.size() * 4));
     PURIFY_HIP(up(P.tilecover, cover.data(), cover.size() * 4));
     PURIFY_HIP(up(P.gwork, work.data(), work.size() * sizeof(int32_t)));
+    if (!dch.empty()) PURIFY_HIP(up(P.dchunk, dch.data(), dch.size() * sizeof(int32_t)));
     if (!merge.empty()) PURIFY_HIP(up(P.gmerge, merge.data(), merge.size() * sizeof(int32_t)));
     PURIFY_HIP(up_real(P.frac, sfr));
     PURIFY_HIP(up_real(P.deap, deap));
