@@ -104,6 +104,10 @@ purify_status purify_psi_adj(const purify_plan* plan, const void* x, void* alpha
 /* purify_sdmm_params.flags: enqueue every kernel eagerly instead of replaying one captured
  * HIP graph per SDMM iteration (same kernels, same results; for debugging and tests). */
 #define PURIFY_SDMM_NO_GRAPH 1
+/* purify_sdmm_params.flags: x_out holds the starting point x_hat(0) on entry (Algorithm 1,
+ * step 1 with a given x_hat(0): z_i = 0, x_i = L_i^dagger L_i x_hat(0)); without it
+ * x_hat(0) = 0.  x_out then receives the result as usual. */
+#define PURIFY_SDMM_WARM_START 2
 
 typedef struct {
     double epsilon;       /* l2 bound of eq. (2) on ||y - Phi x||, unnormalised units */
@@ -142,6 +146,41 @@ typedef struct {
  * (synchronous). */
 purify_status purify_sdmm_solve(purify_plan* plan, const void* y, const purify_sdmm_params* params,
                                 void* x_out, purify_sdmm_info* info, void* stream);
+
+/* Reweighted l1 (SARA, Section 2.2): a sequence of weighted-l1 problems, each weight roughly
+ * the inverse magnitude of the previous solution's coefficient.  Solve 0 uses params->weights
+ * (NULL: W = I); solve k >= 1 uses w_j = delta_k / (delta_k + |(Psi^dagger x(k-1))_j|), is warm
+ * started from x(k-1) (PURIFY_SDMM_WARM_START) and reuses solve 0's nu and gamma.
+ * delta_1 = max(delta0, delta_min), delta0 <= 0 meaning the standard deviation of the
+ * coefficients Psi^dagger x(0); delta_{k+1} = max(decay delta_k, delta_min), delta_min < 0
+ * meaning sigma / nu with sigma = epsilon / sqrt(M + 2 sqrt(M)) (the noise level of the
+ * chi-square bound epsilon).  The loop ends after solve k when
+ * ||x(k) - x(k-1)|| / ||x(k-1)|| < rel_var, or after `reweights` weighted solves. */
+typedef struct {
+    double delta0;      /* <= 0: standard deviation of Psi^dagger x(0) */
+    double decay;       /* 0 < decay <= 1 */
+    double delta_min;   /* floor on delta; < 0: sigma / nu as above */
+    double rel_var;     /* relative-variation stopping bound, >= 0 (0: run every reweight) */
+    int32_t reweights;  /* weighted solves after solve 0, >= 0 */
+} purify_reweight_params;
+
+typedef struct {
+    int32_t solves;            /* SDMM solves run, solve 0 included */
+    int32_t total_iterations;  /* SDMM iterations over all solves */
+    double delta;              /* delta of the last weighted solve (0 if none ran) */
+    double rel_var;            /* relative variation after the last weighted solve (-1 if none) */
+} purify_reweight_info;
+
+/* Reweighted SDMM.  y: device, M complex in uv order.  params: as for purify_sdmm_solve
+ * (flags apply to every solve; PURIFY_SDMM_WARM_START also to solve 0; history, if given,
+ * keeps the rows of the last solve).  weights: device, D doubles owned by the caller
+ * (purify_plan_dict_size), overwritten with each solve's weights (may be params->weights);
+ * may be NULL when rw->reweights = 0.  x_io: device, N complex; x(0) on entry when
+ * PURIFY_SDMM_WARM_START is set; receives the last solution.  info: the last solve's.
+ * Synchronous, one call per plan at a time. */
+purify_status purify_sdmm_reweighted(purify_plan* plan, const void* y, const purify_sdmm_params* params,
+                                     const purify_reweight_params* rw, double* weights, void* x_io,
+                                     purify_sdmm_info* info, purify_reweight_info* rw_info, void* stream);
 
 /* Kernel stages that purify_time_stage can time (one launch = one application). */
 typedef enum {

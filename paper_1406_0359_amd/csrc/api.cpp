@@ -1,4 +1,5 @@
 // C ABI of libpurify (declared in include/purify.h) and the SDMM driver (Algorithm 1).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -162,9 +163,11 @@ purify_status capture(hipStream_t cs, hipGraph_t* g, hipGraphExec_t* x) {
     return PURIFY_OK;
 }
 
+// x_in: x_hat(0) (device, N complex) or null for x_hat(0) = 0; x_out: receives x_hat, or null
+// to leave it in the plan's x_hat buffer only (x_in and x_out may be the same vector).
 template <typename T>
-purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* prm, void* x_out,
-                        purify_sdmm_info* info, hipStream_t s) {
+purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* prm, const void* x_in,
+                        void* x_out, purify_sdmm_info* info, hipStream_t s) {
     using C = cpx<T>;
     const int64_t N = P.N, M = P.M, D = P.D;
     const C zero = mk<T>(0, 0);
@@ -229,8 +232,19 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     }
     S.gamma = gamma;
 
-    // Algorithm 1 initialisation: x_hat = 0, z_i = 0, and x_i = L_i^dag L_i x_hat = 0.
-    for (void* v : {P.xh, P.x1, P.x2, P.x3, P.z2}) launch_fill<T>((C*)v, zero, N, cs);
+    // Algorithm 1 initialisation: z_i = 0, r_i = L_i x_hat(0), x_i = L_i^dag r_i; with
+    // x_hat(0) = 0 every x_i is 0, else x1 = Psi Psi^dag x_hat, x2 = x_hat, x3 = Phi~^dag Phi~ x_hat.
+    if (x_in) {
+        PURIFY_HIP(hipMemcpyAsync(P.xh, x_in, (size_t)N * sizeof(C), hipMemcpyDeviceToDevice, cs));
+        launch_psi_adj<T>(P, (const C*)P.xh, (C*)P.v1, cs);
+        launch_psi<T>(P, (const C*)P.v1, (C*)P.x1, cs);
+        PURIFY_HIP(hipMemcpyAsync(P.x2, P.xh, (size_t)N * sizeof(C), hipMemcpyDeviceToDevice, cs));
+        launch_fft_rows_fwd<T>(P, (const C*)P.xh, (C*)P.tmp, cs);
+        opc.normal_tail(nullptr, (C*)P.x3, S.inv_nu2, 0.0, nullptr);
+        launch_fill<T>((C*)P.z2, zero, N, cs);
+    } else {
+        for (void* v : {P.xh, P.x1, P.x2, P.x3, P.z2}) launch_fill<T>((C*)v, zero, N, cs);
+    }
     launch_fill<T>((C*)P.z1, zero, D, cs);
     launch_fill<T>((C*)P.z3, zero, M, cs);
     PURIFY_HIP(hipMemsetAsync(sc, 0, SL_COUNT * sizeof(double), cs));
@@ -264,7 +278,7 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
             }
         }
     }
-    PURIFY_HIP(hipMemcpyAsync(x_out, P.xh, (size_t)N * sizeof(C), hipMemcpyDeviceToDevice, cs));
+    if (x_out) PURIFY_HIP(hipMemcpyAsync(x_out, P.xh, (size_t)N * sizeof(C), hipMemcpyDeviceToDevice, cs));
     double scal[SL_COUNT];
     PURIFY_HIP(hipMemcpyAsync(scal, sc, sizeof(scal), hipMemcpyDeviceToHost, cs));
     if (prm->history) {
@@ -288,6 +302,78 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
         return PURIFY_E_NONFINITE;
     }
     return PURIFY_OK;
+}
+
+// Reweighted l1 (SARA, Section 2.2): solve 0 with the caller's W, then weighted solves with
+// w_j = delta / (delta + |(Psi^dag x_prev)_j|), each warm started from the previous x_hat
+// with the nu and gamma of solve 0.  delta_1 = max(delta0 or the standard deviation of
+// Psi^dag x(0), delta_min), then delta <- max(decay delta, delta_min); stop when the relative
+// variation ||x(k) - x(k-1)|| / ||x(k-1)|| drops below rel_var.  Statistics are summed by
+// the reduction kernels; the host only reads the resulting scalars between solves.
+template <typename T>
+purify_status reweighted_impl(Plan& P, const void* y, const purify_sdmm_params* prm,
+                              const purify_reweight_params* rw, double* weights, void* x_io,
+                              purify_sdmm_info* info, purify_reweight_info* rinfo, hipStream_t s) {
+    using C = cpx<T>;
+    const int64_t N = P.N, D = P.D, M = P.M;
+    purify_sdmm_info inf{};
+    purify_reweight_info out{};
+    out.solves = 1;
+    out.rel_var = -1.0;
+    const bool warm0 = (prm->flags & PURIFY_SDMM_WARM_START) != 0;
+    purify_status st = sdmm_impl<T>(P, y, prm, warm0 ? x_io : nullptr, x_io, &inf, s);
+    out.total_iterations = inf.iterations;
+    if (st == PURIFY_OK && rw->reweights > 0) {
+        purify_sdmm_params pk = *prm;
+        pk.nu = inf.nu;
+        pk.gamma = inf.gamma;
+        pk.weights = weights;
+        pk.flags = prm->flags | PURIFY_SDMM_WARM_START;
+        const double floor = rw->delta_min >= 0
+                                 ? rw->delta_min
+                                 : prm->epsilon / std::sqrt((double)M + 2.0 * std::sqrt((double)M)) / inf.nu;
+        double* sc = P.sc;
+        launch_psi_adj<T>(P, (const C*)x_io, (C*)P.v1, s);
+        double delta = rw->delta0;
+        if (!(delta > 0)) {   // standard deviation of the coefficients, two passes
+            const int nb = launch_sum_part<T>((const C*)P.v1, D, part_buf(P, 0), part_buf(P, 1), s);
+            launch_finalize(part_buf(P, 0), nb, sc, SL_RW_A, FIN_STORE, 0.0, nullptr, 0, s);
+            launch_finalize(part_buf(P, 1), nb, sc, SL_RW_B, FIN_STORE, 0.0, nullptr, 0, s);
+            const int nb2 = launch_dev2_part<T>((const C*)P.v1, D, sc, SL_RW_A, SL_RW_B, part_buf(P, 2), s);
+            launch_finalize(part_buf(P, 2), nb2, sc, SL_RW_C, FIN_STORE, 0.0, nullptr, 0, s);
+            double dev2 = 0;
+            PURIFY_HIP(hipMemcpyAsync(&dev2, sc + SL_RW_C, sizeof(double), hipMemcpyDeviceToHost, s));
+            PURIFY_HIP(hipStreamSynchronize(s));
+            delta = std::sqrt(dev2 / (double)D);
+        }
+        delta = std::max(delta, floor);
+        for (int k = 1; k <= rw->reweights; ++k) {
+            launch_reweight<T>((const C*)P.v1, D, delta, weights, s);
+            st = sdmm_impl<T>(P, y, &pk, x_io, nullptr, &inf, s);
+            ++out.solves;
+            out.total_iterations += inf.iterations;
+            out.delta = delta;
+            if (st != PURIFY_OK) break;
+            const int nb = launch_diff2_part<T>((const C*)P.xh, (const C*)x_io, N, part_buf(P, 0),
+                                                part_buf(P, 1), s);
+            launch_finalize(part_buf(P, 0), nb, sc, SL_RW_A, FIN_STORE, 0.0, nullptr, 0, s);
+            launch_finalize(part_buf(P, 1), nb, sc, SL_RW_B, FIN_STORE, 0.0, nullptr, 0, s);
+            double ab[2] = {0, 0};
+            static_assert(SL_RW_B == SL_RW_A + 1, "adjacent slots");
+            PURIFY_HIP(hipMemcpyAsync(ab, sc + SL_RW_A, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            PURIFY_HIP(hipMemcpyAsync(x_io, P.xh, (size_t)N * sizeof(C), hipMemcpyDeviceToDevice, s));
+            PURIFY_HIP(hipStreamSynchronize(s));
+            const double d = std::sqrt(ab[0]), o = std::sqrt(ab[1]);
+            const double rv = o > 0 ? d / o : (d == 0 ? 0.0 : INFINITY);
+            out.rel_var = rv;
+            if (rv < rw->rel_var) break;
+            delta = std::max(rw->decay * delta, floor);
+            launch_psi_adj<T>(P, (const C*)x_io, (C*)P.v1, s);
+        }
+    }
+    if (info) *info = inf;
+    if (rinfo) *rinfo = out;
+    return st;
 }
 
 template <typename T>
@@ -474,8 +560,35 @@ purify_status purify_sdmm_solve(purify_plan* plan, const void* y, const purify_s
     }
     Plan& P = plan->P;
     hipStream_t s = (hipStream_t)stream;
-    purify_status st = f64(P) ? sdmm_impl<double>(P, y, params, x_out, info, s)
-                              : sdmm_impl<float>(P, y, params, x_out, info, s);
+    const void* x_in = (params->flags & PURIFY_SDMM_WARM_START) ? x_out : nullptr;
+    purify_status st = f64(P) ? sdmm_impl<double>(P, y, params, x_in, x_out, info, s)
+                              : sdmm_impl<float>(P, y, params, x_in, x_out, info, s);
+    if (st == PURIFY_OK) CHECK_LAUNCH();
+    return st;
+}
+
+purify_status purify_sdmm_reweighted(purify_plan* plan, const void* y, const purify_sdmm_params* params,
+                                     const purify_reweight_params* rw, double* weights, void* x_io,
+                                     purify_sdmm_info* info, purify_reweight_info* rw_info, void* stream) {
+    CHECK_PLAN(plan);
+    if (!y || !params || !rw || !x_io || (rw->reweights > 0 && !weights)) {
+        set_error("null argument");
+        return PURIFY_E_INVALID;
+    }
+    if (params->max_iter < 1 || params->cg_iter < 1 || !(params->epsilon >= 0) ||
+        (params->nu <= 0 && params->nu_iter < 1)) {
+        set_error("invalid SDMM parameters (max_iter, cg_iter >= 1; epsilon >= 0; nu_iter >= 1 when nu <= 0)");
+        return PURIFY_E_INVALID;
+    }
+    if (rw->reweights < 0 || !(rw->decay > 0 && rw->decay <= 1) || !std::isfinite(rw->delta0) ||
+        !std::isfinite(rw->delta_min) || !(rw->rel_var >= 0)) {
+        set_error("invalid reweighting parameters (reweights >= 0, 0 < decay <= 1, finite deltas, rel_var >= 0)");
+        return PURIFY_E_INVALID;
+    }
+    Plan& P = plan->P;
+    hipStream_t s = (hipStream_t)stream;
+    purify_status st = f64(P) ? reweighted_impl<double>(P, y, params, rw, weights, x_io, info, rw_info, s)
+                              : reweighted_impl<float>(P, y, params, rw, weights, x_io, info, rw_info, s);
     if (st == PURIFY_OK) CHECK_LAUNCH();
     return st;
 }

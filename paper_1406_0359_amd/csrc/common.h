@@ -71,6 +71,7 @@ constexpr int MAX_TAPS = 16;
 enum Slot : int {
     SL_RHO = 0, SL_PQ, SL_ALPHA, SL_BETA, SL_RHONEW,
     SL_OBJ, SL_RES2, SL_D2, SL_BALL, SL_LAMBDA, SL_INVLAMBDA, SL_MAXABS, SL_NONFINITE, SL_ITER,
+    SL_RW_A, SL_RW_B, SL_RW_C,   // reweighting statistics (sums of the reweighting kernels)
     SL_COUNT = 32
 };
 
@@ -218,6 +219,17 @@ template <typename T> void launch_permute_scale(const cpx<T>* y_user, const int3
                                                 cpx<T>* y_sorted, int64_t n, hipStream_t s);
 template <typename T> void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc,
                                                 int slot, int64_t n, hipStream_t s);
+// Reweighting (SARA): partials of sum Re v and sum Im v
+template <typename T> int launch_sum_part(const cpx<T>* v, int64_t n, double* part_re, double* part_im,
+                                          hipStream_t s);
+// partials of sum |v_j - mean|^2, mean = (sc[slot_re] + i sc[slot_im]) / n
+template <typename T> int launch_dev2_part(const cpx<T>* v, int64_t n, const double* sc, int slot_re,
+                                           int slot_im, double* part, hipStream_t s);
+// w_j = delta / (delta + |a_j|) (1 where that denominator is 0)
+template <typename T> void launch_reweight(const cpx<T>* a, int64_t n, double delta, double* w, hipStream_t s);
+// partials of ||a - b||^2 and ||b||^2
+template <typename T> int launch_diff2_part(const cpx<T>* a, const cpx<T>* b, int64_t n, double* part_d,
+                                            double* part_b, hipStream_t s);
 
 // error helper
 void set_error(const std::string& msg);

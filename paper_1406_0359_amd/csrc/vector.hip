@@ -328,6 +328,71 @@ k_scale_by_slot(cpx<T>* __restrict__ dst, const cpx<T>* __restrict__ src, const 
     if (i < n) dst[i] = (T)sc[slot] * src[i];
 }
 
+// Reweighting statistics: partial sums of Re and Im (the mean of the coefficients)
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_sum(const cpx<T>* __restrict__ v, int64_t n, double* part_re, double* part_im) {
+    double ar = 0, ai = 0;
+    GRID_STRIDE(i, n) {
+        const cpx<T> a = v[i];
+        ar += (double)a.x;
+        ai += (double)a.y;
+    }
+    const double tr = block_sum(ar);
+    const double ti = block_sum(ai);
+    if (threadIdx.x == 0) {
+        part_re[blockIdx.x] = tr;
+        part_im[blockIdx.x] = ti;
+    }
+}
+
+// partial sums of |v_j - mean|^2 (second pass of the standard deviation)
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_dev2(const cpx<T>* __restrict__ v, int64_t n, const double* __restrict__ sc, int slot_re, int slot_im,
+       double* part) {
+    const double mr = sc[slot_re] / (double)n, mi = sc[slot_im] / (double)n;
+    double acc = 0;
+    GRID_STRIDE(i, n) {
+        const cpx<T> a = v[i];
+        const double dr = (double)a.x - mr, di = (double)a.y - mi;
+        acc += dr * dr + di * di;
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// w_j = delta / (delta + |a_j|): delta times the slope of log(delta + s) at s = |a_j|
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_reweight(const cpx<T>* __restrict__ a, int64_t n, double delta, double* __restrict__ w) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i >= n) return;
+    const cpx<T> v = a[i];
+    const double den = delta + sqrt((double)v.x * v.x + (double)v.y * v.y);
+    w[i] = den > 0.0 ? delta / den : 1.0;
+}
+
+// partial sums of ||a - b||^2 and ||b||^2 (relative variation between successive solves)
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_diff2(const cpx<T>* __restrict__ a, const cpx<T>* __restrict__ b, int64_t n, double* part_d,
+        double* part_b) {
+    double ad = 0, ab = 0;
+    GRID_STRIDE(i, n) {
+        const cpx<T> u = a[i], v = b[i];
+        const double dr = (double)u.x - v.x, di = (double)u.y - v.y;
+        ad += dr * dr + di * di;
+        ab += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    const double td = block_sum(ad);
+    const double tb = block_sum(ab);
+    if (threadIdx.x == 0) {
+        part_d[blockIdx.x] = td;
+        part_b[blockIdx.x] = tb;
+    }
+}
+
 }  // namespace
 
 template <typename T>
@@ -412,6 +477,31 @@ void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc, int 
     hipLaunchKernelGGL(k_scale_by_slot<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, dst, src, sc, slot, n);
 }
 
+template <typename T>
+int launch_sum_part(const cpx<T>* v, int64_t n, double* part_re, double* part_im, hipStream_t s) {
+    const int b = red_blocks(n);
+    hipLaunchKernelGGL(k_sum<T>, dim3(b), dim3(VT), 0, s, v, n, part_re, part_im);
+    return b;
+}
+template <typename T>
+int launch_dev2_part(const cpx<T>* v, int64_t n, const double* sc, int slot_re, int slot_im, double* part,
+                     hipStream_t s) {
+    const int b = red_blocks(n);
+    hipLaunchKernelGGL(k_dev2<T>, dim3(b), dim3(VT), 0, s, v, n, sc, slot_re, slot_im, part);
+    return b;
+}
+template <typename T>
+void launch_reweight(const cpx<T>* a, int64_t n, double delta, double* w, hipStream_t s) {
+    hipLaunchKernelGGL(k_reweight<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, a, n, delta, w);
+}
+template <typename T>
+int launch_diff2_part(const cpx<T>* a, const cpx<T>* b, int64_t n, double* part_d, double* part_b,
+                      hipStream_t s) {
+    const int nb = red_blocks(n);
+    hipLaunchKernelGGL(k_diff2<T>, dim3(nb), dim3(VT), 0, s, a, b, n, part_d, part_b);
+    return nb;
+}
+
 #define PURIFY_INST_VEC(T)                                                                              \
     template void launch_fill<T>(cpx<T>*, cpx<T>, int64_t, hipStream_t);                                \
     template int launch_norm2_part<T>(const cpx<T>*, int64_t, double*, hipStream_t);                     \
@@ -430,7 +520,11 @@ void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc, int 
                                       double, double*, double*, int, int64_t, hipStream_t);             \
     template void launch_permute_scale<T>(const cpx<T>*, const int32_t*, double, cpx<T>*, int64_t,       \
                                           hipStream_t);                                                  \
-    template void launch_scale_by_slot<T>(cpx<T>*, const cpx<T>*, const double*, int, int64_t, hipStream_t);
+    template void launch_scale_by_slot<T>(cpx<T>*, const cpx<T>*, const double*, int, int64_t, hipStream_t); \
+    template int launch_sum_part<T>(const cpx<T>*, int64_t, double*, double*, hipStream_t);               \
+    template int launch_dev2_part<T>(const cpx<T>*, int64_t, const double*, int, int, double*, hipStream_t); \
+    template void launch_reweight<T>(const cpx<T>*, int64_t, double, double*, hipStream_t);               \
+    template int launch_diff2_part<T>(const cpx<T>*, const cpx<T>*, int64_t, double*, double*, hipStream_t);
 
 PURIFY_INST_VEC(float)
 PURIFY_INST_VEC(double)

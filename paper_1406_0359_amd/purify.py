@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libpurify.so")
 FP64, FP32 = 0, 1
 DICT_SARA = 0x1FF
 SDMM_NO_GRAPH = 1
+SDMM_WARM_START = 2
 
 STAGES = {
     "fft_rows": 0, "fft_cols": 1, "degrid": 2, "grid": 3, "ifft_cols": 4, "ifft_rows": 5,
@@ -61,6 +62,20 @@ class SdmmInfo(ctypes.Structure):
     ]
 
 
+class ReweightParams(ctypes.Structure):
+    _fields_ = [
+        ("delta0", ctypes.c_double), ("decay", ctypes.c_double), ("delta_min", ctypes.c_double),
+        ("rel_var", ctypes.c_double), ("reweights", ctypes.c_int32),
+    ]
+
+
+class ReweightInfo(ctypes.Structure):
+    _fields_ = [
+        ("solves", ctypes.c_int32), ("total_iterations", ctypes.c_int32),
+        ("delta", ctypes.c_double), ("rel_var", ctypes.c_double),
+    ]
+
+
 class ServerDesc(ctypes.Structure):
     _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32)]
 
@@ -89,6 +104,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "purify_psi_adj": (i32, [vp, vp, vp, vp]),
         "purify_sdmm_solve": (i32, [vp, vp, ctypes.POINTER(SdmmParams), vp,
                                     ctypes.POINTER(SdmmInfo), vp]),
+        "purify_sdmm_reweighted": (i32, [vp, vp, ctypes.POINTER(SdmmParams), ctypes.POINTER(ReweightParams),
+                                         vp, vp, ctypes.POINTER(SdmmInfo), ctypes.POINTER(ReweightInfo), vp]),
         "purify_time_stage": (i32, [vp, i32, i32, vp, ctypes.POINTER(dbl)]),
         "purify_daubechies_filter": (i32, [i32, ctypes.POINTER(dbl), i32]),
         "purify_kb_kernel": (i32, [i32, dbl, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
@@ -182,6 +199,17 @@ class SolveResult:
     history: Optional[np.ndarray]
 
 
+@dataclass
+class ReweightResult:
+    x: "object"                  # torch complex tensor (n, n): the last solve's x_hat
+    weights: "object"            # torch float64 (D,): the last weighted solve's weights
+    solves: int                  # SDMM solves, solve 0 included
+    total_iterations: int
+    delta: float                 # delta of the last weighted solve
+    rel_var: float               # relative variation after it (-1 if none ran)
+    last: SolveResult            # info of the last solve
+
+
 class Plan:
     """A measurement operator / dictionary / solver plan on one GPU.
 
@@ -269,24 +297,40 @@ class Plan:
                "purify_psi_adj")
         return a
 
-    def sdmm(self, y, epsilon: float, max_iter: int = 300, cg_iter: int = 10,
-             gamma: float = 0.0, nu: float = 0.0, nu_iter: int = 100, halting: bool = False,
-             xi: float = 1e-4, slack: float = 1e-3, check_every: int = 10, weights=None,
-             record_history: bool = False, graph: bool = True, out=None) -> SolveResult:
-        """SDMM (Algorithm 1) for eq. (3) with R = 1; returns x_hat and solver info."""
-        x = self.empty(self.n, self.n) if out is None else out
+    def _params(self, epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack,
+                check_every, weights, graph, warm, hist):
         p = SdmmParams()
         p.epsilon, p.gamma, p.nu, p.xi, p.slack = epsilon, gamma, nu, xi, slack
         p.max_iter, p.cg_iter, p.check_every = max_iter, cg_iter, check_every
         p.halting, p.nu_iter = int(bool(halting)), nu_iter
-        p.flags = 0 if graph else SDMM_NO_GRAPH
+        p.flags = (0 if graph else SDMM_NO_GRAPH) | (SDMM_WARM_START if warm else 0)
         if weights is not None:
-            if (weights.dtype != self.torch.float64 or weights.numel() != self.D
-                    or weights.device != self.device or not weights.is_contiguous()):
-                raise ValueError("weights must be a contiguous float64 device tensor of size D")
-            p.weights = weights.data_ptr()
-        hist = np.zeros(2 * max_iter) if record_history else None
+            p.weights = self._weights(weights)
         p.history = _dptr(hist) if hist is not None else None
+        return p
+
+    def _weights(self, w):
+        if (not isinstance(w, self.torch.Tensor) or w.dtype != self.torch.float64 or w.numel() != self.D
+                or w.device != self.device or not w.is_contiguous()):
+            raise ValueError("weights must be a contiguous float64 device tensor of size D")
+        return w.data_ptr()
+
+    def _start(self, x0, out):
+        x = self.empty(self.n, self.n) if out is None else out
+        if x0 is not None:
+            x.copy_(self.as_vec(x0).reshape(x.shape))
+        return x
+
+    def sdmm(self, y, epsilon: float, max_iter: int = 300, cg_iter: int = 10,
+             gamma: float = 0.0, nu: float = 0.0, nu_iter: int = 100, halting: bool = False,
+             xi: float = 1e-4, slack: float = 1e-3, check_every: int = 10, weights=None,
+             record_history: bool = False, graph: bool = True, x0=None, out=None) -> SolveResult:
+        """SDMM (Algorithm 1) for eq. (3) with R = 1; returns x_hat and solver info.
+        x0: starting point x_hat(0) (default 0)."""
+        x = self._start(x0, out)
+        hist = np.zeros(2 * max_iter) if record_history else None
+        p = self._params(epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack, check_every,
+                         weights, graph, x0 is not None, hist)
         info = SdmmInfo()
         _check(self.lib.purify_sdmm_solve(self.handle, self._vec(y, self.M, "y"), ctypes.byref(p),
                                           self._vec(x, self.n * self.n, "x"), ctypes.byref(info),
@@ -295,6 +339,30 @@ class Plan:
             hist = hist[: 2 * info.iterations].reshape(-1, 2)
         return SolveResult(x, info.iterations, bool(info.converged), info.objective,
                            info.residual, info.nu, info.gamma, hist)
+
+    def sdmm_reweighted(self, y, epsilon: float, reweights: int = 5, delta0: float = 0.0,
+                        decay: float = 0.1, delta_min: float = -1.0, rel_var: float = 1e-3,
+                        max_iter: int = 300, cg_iter: int = 10, gamma: float = 0.0, nu: float = 0.0,
+                        nu_iter: int = 100, halting: bool = False, xi: float = 1e-4, slack: float = 1e-3,
+                        check_every: int = 10, weights=None, graph: bool = True, x0=None,
+                        out=None) -> "ReweightResult":
+        """Reweighted l1 (SARA): solve 0 with `weights` (None: W = I), then up to `reweights`
+        weighted solves (purify_sdmm_reweighted)."""
+        x = self._start(x0, out)
+        w = self.torch.empty(self.D, dtype=self.torch.float64, device=self.device)
+        p = self._params(epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack, check_every,
+                         weights, graph, x0 is not None, None)
+        rw = ReweightParams()
+        rw.delta0, rw.decay, rw.delta_min, rw.rel_var, rw.reweights = delta0, decay, delta_min, rel_var, reweights
+        info, rinfo = SdmmInfo(), ReweightInfo()
+        _check(self.lib.purify_sdmm_reweighted(self.handle, self._vec(y, self.M, "y"), ctypes.byref(p),
+                                               ctypes.byref(rw), w.data_ptr(),
+                                               self._vec(x, self.n * self.n, "x"), ctypes.byref(info),
+                                               ctypes.byref(rinfo), self._stream()),
+               "purify_sdmm_reweighted")
+        return ReweightResult(x, w, rinfo.solves, rinfo.total_iterations, rinfo.delta, rinfo.rel_var,
+                              SolveResult(x, info.iterations, bool(info.converged), info.objective,
+                                          info.residual, info.nu, info.gamma, None))
 
     def time_stage(self, stage: str, reps: int = 20) -> float:
         """Average milliseconds per launch of one stage (HIP events on the current stream)."""
