@@ -78,8 +78,11 @@ class SdmmResult:
 def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
          cg_iters: int = 10, gamma: Optional[float] = None, nu: Optional[float] = None,
          weights=None, halting: bool = False, xi: float = 1e-4, slack: float = 1e-3,
-         nu_iters: int = 100, x0=None) -> SdmmResult:
-    """Run SDMM (Algorithm 1, R = 1, S = 3) and return x_hat (complex; the image is Re)."""
+         nu_iters: int = 100, x0=None, normal=None) -> SdmmResult:
+    """Run SDMM (Algorithm 1, R = 1, S = 3) and return x_hat (complex; the image is Re).
+    normal: a stored form of Phi^dagger Phi for the global update's conjugate-gradient
+    operator (Section 3), e.g. the Toeplitz operator of oracle.toeplitz; None applies Phi
+    and Phi^dagger.  nu, the proximity steps and x_i = L_i^dagger L_i x_hat(0) always use Phi."""
     if nu is None or nu <= 0:
         nu, _ = operator_norm(lambda v: phi_adj(phi(v)), shape, nu_iters)
     yt = np.asarray(y, dtype=np.complex128) / nu
@@ -88,7 +91,10 @@ def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
     Pt = lambda v: phi_adj(v) / nu
     if gamma is None or gamma <= 0:
         gamma = 1e-3 * float(np.max(np.abs(psi_adj(Pt(yt)))))
-    A = lambda v: Pt(P(v)) + 2.0 * v
+    if normal is None:
+        A = lambda v: Pt(P(v)) + 2.0 * v
+    else:
+        A = lambda v: normal(v) / (nu * nu) + 2.0 * v
 
     xh = np.zeros(shape, dtype=np.complex128) if x0 is None else np.array(x0, np.complex128)
     v1 = psi_adj(xh)
