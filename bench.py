@@ -13,8 +13,11 @@ Also reported:
 * ``steady_state``: the marginal SDMM iterations per second on an existing plan;
 * ``also``: per-stage timings; the 1024 x 1024 FP32 precision-form workload (M = 2N):
   Phi / Phi^dagger Gvis/s, Psi / Psi^dagger GB/s and SDMM iterations per second; the
-  4096 x 4096 single solve (M = 10^7, J = 8, 5 levels, FP32); and the serving form (FP32
-  server on a Poisson stream of mixed-size requests against the FP64 one-at-a-time solves).
+  4096 x 4096 single solve (M = 10^7, J = 8, 5 levels, FP32); the serving form (FP32
+  server on a Poisson stream of mixed-size requests against the FP64 one-at-a-time solves);
+  and, at 256^2 and 1024^2, the same solve with the stored (Toeplitz) normal operator in
+  CG (Section 3's precomputed composite operator): its iteration rate, stage times and its
+  image against the exact solve's.
 """
 from __future__ import annotations
 
@@ -50,7 +53,11 @@ def stage_bytes(plan, stage: str) -> float:
         "ifft_rows": 2 * N * c + N * c,
         "psi_adj": N * c + q * N * c,
         "psi": q * N * c + N * c,
+        # stored normal operator: column stage reads n x K and the real K x K spectrum, writes
+        # n x K; the whole operator adds a row pass each way
+        "toep_cols": 2 * N * c + 4 * N * (c // 2) + 2 * N * c,
     }
+    tbl["toep_normal"] = (N * c + 2 * N * c) + tbl["toep_cols"] + (2 * N * c + N * c)
     tbl["phi"] = tbl["fft_rows"] + tbl["fft_cols"] + tbl["degrid"]
     tbl["phi_adj"] = tbl["grid"] + tbl["ifft_cols"] + tbl["ifft_rows"]
     return float(tbl[stage])
@@ -135,7 +142,10 @@ def precision_form(torch, purify, synth, solve_iters: int) -> dict:
     res = plan.sdmm(y, p.epsilon, max_iter=solve_iters, nu_iter=100)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    toep = toeplitz_form(torch, plan, y, p.epsilon, res.nu, solve_iters, w.cg_iters, p.x_true, synth,
+                         res.x.cpu().numpy())
     return {
+        "toeplitz": toep,
         "workload": "sara1024 FP32 (n=1024, M=2097152, SARA 9 bases, L=4, J=6)",
         "phi_gvis_s": w.M / (st["phi"]["ms"] * 1e-3) / 1e9,
         "phi_adj_gvis_s": w.M / (st["phi_adj"]["ms"] * 1e-3) / 1e9,
@@ -144,6 +154,33 @@ def precision_form(torch, purify, synth, solve_iters: int) -> dict:
         "solve_iters": solve_iters, "stages": st,
         "residual_over_eps": res.residual / p.epsilon,
     }
+
+
+def toeplitz_form(torch, plan, y, eps, nu, iters, cg, x_true, synth, x_exact) -> dict:
+    """CG with the stored (Toeplitz) normal operator on an existing plan: marginal iterations
+    per second, the stage times, and the image against the exact solve of the same length."""
+    def timed(k):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = plan.sdmm(y, eps, max_iter=k, cg_iter=cg, nu=nu, toeplitz=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+    timed(10)
+    t_short, _ = timed(10)
+    t_long, res = timed(10 + iters)
+    t_full, res = timed(iters)
+    out = {"steady_iters_s": iters / (t_long - t_short)}
+    for st in ("toep_cols", "toep_normal"):
+        plan.time_stage(st, 3)
+        ms = plan.time_stage(st, 50)
+        b = stage_bytes(plan, st)
+        out[st] = {"ms": ms, "bytes": b, "GBs": b / (ms * 1e-3) / 1e9,
+                   "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    xt = res.x.cpu().numpy()
+    out["snr_db"] = synth.snr_db(x_true, xt)
+    out["snr_db_exact"] = synth.snr_db(x_true, x_exact)
+    out["rel_diff_vs_exact"] = float(np.linalg.norm(xt - x_exact) / np.linalg.norm(x_exact))
+    return out
 
 
 COUNTER_FILE = os.path.join(ROOT, "profiles", "k_grid_gtg_sara256_counters.md")
@@ -372,6 +409,11 @@ def main():
         "roofline": roofline,
     }
     also = {"sara256_stages": st}
+    try:
+        also["sara256_toeplitz"] = toeplitz_form(torch, plan, y, p.epsilon, res.nu, w.iters, w.cg_iters,
+                                                 p.x_true, synth, res.x.cpu().numpy())
+    except Exception as e:  # report, do not hide the main line
+        also["sara256_toeplitz_error"] = repr(e)
     if not args.no_extra:
         try:
             also["sara1024_fp32"] = precision_form(torch, purify, synth, args.extra_iters)

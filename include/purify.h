@@ -108,6 +108,12 @@ purify_status purify_psi_adj(const purify_plan* plan, const void* x, void* alpha
  * step 1 with a given x_hat(0): z_i = 0, x_i = L_i^dagger L_i x_hat(0)); without it
  * x_hat(0) = 0.  x_out then receives the result as usual. */
 #define PURIFY_SDMM_WARM_START 2
+/* purify_sdmm_params.flags: the global update's conjugate gradient applies the stored
+ * (Toeplitz) form of Phi^dagger Phi instead of Phi and Phi^dagger (Section 3 suggests
+ * precomputing that composite operator; see purify_phi_normal).  It differs from the
+ * NUFFT's Phi^dagger Phi by the NUFFT's own error; nu, the proximity steps and the
+ * data-fidelity branch still apply Phi and Phi^dagger. */
+#define PURIFY_SDMM_TOEPLITZ 4
 
 typedef struct {
     double epsilon;       /* l2 bound of eq. (2) on ||y - Phi x||, unnormalised units */
@@ -146,6 +152,20 @@ typedef struct {
  * (synchronous). */
 purify_status purify_sdmm_solve(purify_plan* plan, const void* y, const purify_sdmm_params* params,
                                 void* x_out, purify_sdmm_info* info, void* stream);
+
+/* purify_phi_normal modes. */
+#define PURIFY_NORMAL_TOEPLITZ 1
+
+/* out = Phi^dagger Phi x (x, out: device, N complex; both n x n).  mode 0: through the
+ * NUFFT, the interpolation and gridding of G^T G fused in one launch, exactly the operator
+ * of the CG update.  mode PURIFY_NORMAL_TOEPLITZ: the stored form
+ * T = Z^T F^dagger diag(c_hat) F Z, a convolution with the point-spread function
+ * h(d) = sum_m exp(i omega_m . d) on the 2n x 2n circulant embedding, with c_hat the real
+ * part of its spectrum / K^2 (so T is Hermitian).  h comes from the plan's Phi^dagger applied
+ * to modulated unit visibilities (four n x n quadrants of d), so T matches the NUDFT normal
+ * operator to the NUFFT's accuracy.  c_hat is computed on the first call that needs it
+ * (that call is synchronous) and kept in the plan workspace; later calls only enqueue. */
+purify_status purify_phi_normal(purify_plan* plan, const void* x, void* out, int32_t mode, void* stream);
 
 /* Reweighted l1 (SARA, Section 2.2): a sequence of weighted-l1 problems, each weight roughly
  * the inverse magnitude of the previous solution's coefficient.  Solve 0 uses params->weights
@@ -194,8 +214,11 @@ typedef enum {
     PURIFY_STAGE_PHI_ADJ = 7,      /* whole Phi^dagger                                         */
     PURIFY_STAGE_PSI_ADJ = 8,      /* whole Psi^dagger                                         */
     PURIFY_STAGE_PSI = 9,          /* whole Psi                                                */
-    PURIFY_STAGE_GTG = 10          /* G^T G in one launch (interpolate + grid), as in the
+    PURIFY_STAGE_GTG = 10,         /* G^T G in one launch (interpolate + grid), as in the
                                       normal operator Phi^dagger Phi of the CG update  (K x K -> K x K) */
+    PURIFY_STAGE_TOEP_COLS = 11,   /* column stage of the stored normal operator (transform,
+                                      spectrum, adjoint transform, in place)          (n x K -> n x K) */
+    PURIFY_STAGE_TOEP_NORMAL = 12  /* whole stored normal operator T x                (n x n -> n x n) */
 } purify_stage;
 
 /* Time `reps` back-to-back launches of one stage on the plan's internal buffers (their

@@ -52,6 +52,19 @@ struct Ops {
         launch_fft_rows_fwd_cg<T>(P, p, r, rho, rho_new, count, (C*)P.tmp, s);
         normal_tail(p, q, inv_nu2, 2.0, dot);
     }
+    // q = c1 T v + c2 v with T the stored (Toeplitz) form of Phi^dag Phi (chat ready)
+    void toep_A(const C* v, C* q, double c1, double c2, double* dot) const {
+        launch_fft_rows_fwd<T>(P, v, (C*)P.tmp, s, P.unit);
+        launch_fft_cols_toep<T>(P, (C*)P.tmp, s);
+        launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, c1, v, c2, dot, s, P.unit);
+    }
+    // conjugate-gradient step with T: p = r + beta p in the row pass, then q = c1 T p + 2 p
+    void toep_A_cg(C* p, const C* r, const double* rho, const double* rho_new, int count, C* q, double c1,
+                   double* dot) const {
+        launch_fft_rows_fwd_cg<T>(P, p, r, rho, rho_new, count, (C*)P.tmp, s, P.unit);
+        launch_fft_cols_toep<T>(P, (C*)P.tmp, s);
+        launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, c1, p, 2.0, dot, s, P.unit);
+    }
     // after the row pass of v: q = c1 Phi^dag Phi v + c2 v
     void normal_tail(const C* v, C* q, double c1, double c2, double* dot) const {
         launch_fft_cols_fwd<T>(P, (const C*)P.tmp, (C*)P.grid, s);
@@ -62,6 +75,32 @@ struct Ops {
 };
 
 double* part_buf(const Plan& P, int k) { return P.part + (size_t)k * MAX_PARTIALS; }
+
+// Spectrum of the stored normal operator, computed once per plan (first use): for each
+// quadrant shift s in {-n/2, n/2}^2, h_s = Phi^dagger v_s (v_s,m = exp(i omega_m . s)) holds
+// h(p + s); the offsets d = -n are zeroed; chat += Re(exp(-2 pi i k . s / K) F Z h_s) / K^2.
+// Uses the plan's visibility, grid and image scratch; synchronous on s.
+template <typename T>
+purify_status ensure_chat(Plan& P, hipStream_t s) {
+    if (P.chat_ready) return PURIFY_OK;
+    using C = cpx<T>;
+    const int h = P.n / 2;
+    const int sig[4][2] = {{-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
+    for (int q = 0; q < 4; ++q) {
+        launch_modulate<T>(P, sig[q][0] * h, sig[q][1] * h, (C*)P.vis, s);
+        launch_grid<T>(P, (const C*)P.vis, nullptr, (C*)P.grid, s);
+        launch_fft_cols_adj<T>(P, (const C*)P.grid, (C*)P.tmp, s);
+        launch_fft_rows_adj<T>(P, (const C*)P.tmp, (C*)P.qv, 1.0, nullptr, 0.0, nullptr, s);
+        launch_zero_edge<T>((C*)P.qv, P.n, sig[q][0] < 0, sig[q][1] < 0, s);
+        launch_fft_rows_fwd<T>(P, (const C*)P.qv, (C*)P.tmp, s, P.unit);
+        launch_fft_cols_fwd<T>(P, (const C*)P.tmp, (C*)P.grid, s);
+        launch_chat_accum<T>(P, (const C*)P.grid, sig[q][0], sig[q][1], q == 0, s);
+    }
+    PURIFY_HIP(hipGetLastError());
+    PURIFY_HIP(hipStreamSynchronize(s));
+    P.chat_ready = true;
+    return PURIFY_OK;
+}
 
 // RAII holder for the solver's internal streams, events and graphs.
 struct SolveResources {
@@ -88,8 +127,15 @@ struct Sdmm {
     Plan& P;
     const purify_sdmm_params* prm;
     double inv_nu = 1, inv_nu2 = 1, eps_t = 0, gamma = 0;
+    bool toep = false;   // CG operator from the stored normal operator (PURIFY_SDMM_TOEPLITZ)
 
     double* part(int k) const { return part_buf(P, k); }
+
+    // q = A v = Phi~^dag Phi~ v + 2 v (or its stored form), partial <v, q> into dot
+    void A(const Ops<T>& op, const C* v, C* q, double* dot) const {
+        if (toep) op.toep_A(v, q, inv_nu2, 2.0, dot);
+        else op.apply_A(v, q, inv_nu2, dot);
+    }
 
     // One power-iteration step: v <- Phi^dag Phi v / ||Phi^dag Phi v||, lambda in sc.
     void enqueue_power_step(hipStream_t s) const {
@@ -124,7 +170,8 @@ struct Sdmm {
         for (int c = 0; c < prm->cg_iter; ++c) {
             double* rho = part(c & 1);
             double* rho_next = part((c + 1) & 1);
-            if (c == 0) op.apply_A(p, q, inv_nu2, part(2));
+            if (c == 0) A(op, p, q, part(2));
+            else if (toep) op.toep_A_cg(p, r, part((c - 1) & 1), rho, nb, q, inv_nu2, part(2));
             else op.apply_A_cg(p, r, part((c - 1) & 1), rho, nb, q, inv_nu2, part(2));
             launch_cg_xr<T>(xh, r, p, q, rho, nb, part(2), rows_blocks, N, rho_next, s);
         }
@@ -145,7 +192,7 @@ struct Sdmm {
         op.phi_adj(v3, nullptr, x3, inv_nu, nullptr, 0.0, nullptr);
         // the next iteration's warm-start product A x_hat needs only x_hat: it runs here,
         // overlapping branch i = 1 on the other stream
-        op.apply_A(xh, q, inv_nu2, nullptr);
+        A(op, xh, q, nullptr);
         (void)hipStreamWaitEvent(s, join, 0);
         launch_iter_advance(sc, s);
     }
@@ -153,7 +200,7 @@ struct Sdmm {
     // q = A x_hat for the first iteration's warm start.
     void enqueue_prologue(hipStream_t s) const {
         const Ops<T> op{P, s};
-        op.apply_A((const C*)P.xh, (C*)P.qv, inv_nu2, nullptr);
+        A(op, (const C*)P.xh, (C*)P.qv, nullptr);
     }
 };
 
@@ -185,6 +232,11 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     // the solver's streams start after the caller's prior work on s
     PURIFY_HIP(hipEventRecord(R.done, s));
     PURIFY_HIP(hipStreamWaitEvent(cs, R.done, 0));
+    S.toep = (prm->flags & PURIFY_SDMM_TOEPLITZ) != 0;
+    if (S.toep) {
+        const purify_status st = ensure_chat<T>(P, cs);
+        if (st != PURIFY_OK) return st;
+    }
     const Ops<T> opc{P, cs};
     PURIFY_HIP(hipMemsetAsync(sc, 0, SL_COUNT * sizeof(double), cs));
 
@@ -394,6 +446,8 @@ void run_stage(const Plan& P, int stage, hipStream_t s) {
         case PURIFY_STAGE_PHI_ADJ: op.phi_adj((const C*)P.vis, nullptr, (C*)P.qv, 1.0, nullptr, 0.0, nullptr); break;
         case PURIFY_STAGE_PSI_ADJ: launch_psi_adj<T>(P, (const C*)P.xh, (C*)P.v1, s); break;
         case PURIFY_STAGE_PSI: launch_psi<T>(P, (const C*)P.v1, (C*)P.qv, s); break;
+        case PURIFY_STAGE_TOEP_COLS: launch_fft_cols_toep<T>(P, (C*)P.tmp, s); break;
+        case PURIFY_STAGE_TOEP_NORMAL: op.toep_A((const C*)P.xh, (C*)P.qv, 1.0, 0.0, nullptr); break;
         default: break;
     }
 }
@@ -593,15 +647,40 @@ purify_status purify_sdmm_reweighted(purify_plan* plan, const void* y, const pur
     return st;
 }
 
+purify_status purify_phi_normal(purify_plan* plan, const void* x, void* out, int32_t mode, void* stream) {
+    CHECK_PLAN(plan);
+    if (!x || !out || (mode != 0 && mode != PURIFY_NORMAL_TOEPLITZ)) {
+        set_error("null vector or unknown mode");
+        return PURIFY_E_INVALID;
+    }
+    Plan& P = plan->P;
+    hipStream_t s = (hipStream_t)stream;
+    if (mode == PURIFY_NORMAL_TOEPLITZ) {
+        const purify_status st = f64(P) ? ensure_chat<double>(P, s) : ensure_chat<float>(P, s);
+        if (st != PURIFY_OK) return st;
+        if (f64(P)) Ops<double>{P, s}.toep_A((const cpx<double>*)x, (cpx<double>*)out, 1.0, 0.0, nullptr);
+        else Ops<float>{P, s}.toep_A((const cpx<float>*)x, (cpx<float>*)out, 1.0, 0.0, nullptr);
+    } else {
+        if (f64(P)) Ops<double>{P, s}.normal((const cpx<double>*)x, (cpx<double>*)out);
+        else Ops<float>{P, s}.normal((const cpx<float>*)x, (cpx<float>*)out);
+    }
+    CHECK_LAUNCH();
+    return PURIFY_OK;
+}
+
 purify_status purify_time_stage(purify_plan* plan, int32_t stage, int32_t reps, void* stream,
                                 double* ms_per_launch) {
     CHECK_PLAN(plan);
-    if (stage < 0 || stage > PURIFY_STAGE_GTG || reps < 1 || !ms_per_launch) {
+    if (stage < 0 || stage > PURIFY_STAGE_TOEP_NORMAL || reps < 1 || !ms_per_launch) {
         set_error("invalid stage or reps");
         return PURIFY_E_INVALID;
     }
-    const Plan& P = plan->P;
+    Plan& P = plan->P;
     hipStream_t s = (hipStream_t)stream;
+    if (stage == PURIFY_STAGE_TOEP_COLS || stage == PURIFY_STAGE_TOEP_NORMAL) {
+        const purify_status st = f64(P) ? ensure_chat<double>(P, s) : ensure_chat<float>(P, s);
+        if (st != PURIFY_OK) return st;
+    }
     hipEvent_t e0, e1;
     PURIFY_HIP(hipEventCreate(&e0));
     PURIFY_HIP(hipEventCreate(&e1));

@@ -130,7 +130,10 @@ struct Plan {
     void* wtab = nullptr;        // FP64 plans: M x 2J tap weights (sorted order), else null
     void* grid = nullptr;        // K x K complex, row-major G[k1][k2]
     void* grid2 = nullptr;       // K x K complex: G^T G output of the normal operator
-    void* tmp = nullptr;         // K x n complex, layout [k2][j1]
+    void* tmp = nullptr;         // n x K complex, layout [j1][k2]
+    void* unit = nullptr;        // n reals, all 1 (row passes without S)
+    void* chat = nullptr;        // K x K reals: spectrum of the stored normal operator, / K^2
+    bool chat_ready = false;     // chat computed (on the first call that needs it)
     double* part = nullptr;      // NUM_PARTIAL_BUFS * MAX_PARTIALS
     double* sc = nullptr;        // SL_COUNT scalars
     double* hist = nullptr;      // 2 * hist_cap doubles
@@ -147,17 +150,23 @@ struct Plan {
 
 // ---------------------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files, instantiated for float and double).
-template <typename T> void launch_fft_rows_fwd(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s);
+// deap: per-pixel factors of S (n reals of the plan's type); null = the plan's
+// deapodisation, the plan's `unit` table = no S (the stored normal operator)
+template <typename T> void launch_fft_rows_fwd(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s,
+                                               const void* deap = nullptr);
 // Row pass on p = r + beta p (beta = rho_new / rho from partial sums), p updated in place.
 template <typename T>
 void launch_fft_rows_fwd_cg(const Plan& P, cpx<T>* p, const cpx<T>* r, const double* rho_part,
-                            const double* rhonew_part, int count, cpx<T>* tmp, hipStream_t s);
+                            const double* rhonew_part, int count, cpx<T>* tmp, hipStream_t s,
+                            const void* deap = nullptr);
 template <typename T> void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s);
 template <typename T> void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s);
+// column stage of the stored normal operator: forward transform, times chat, adjoint, in place
+template <typename T> void launch_fft_cols_toep(const Plan& P, cpx<T>* tmp, hipStream_t s);
 // x = c1 * (S Z^T F^dag rows)(tmp) + c2 * v   (v may be null); optional partial Re<v, x>
 template <typename T> void launch_fft_rows_adj(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1,
                                                const cpx<T>* v, double c2, double* dot_part,
-                                               hipStream_t s);
+                                               hipStream_t s, const void* deap = nullptr);
 template <typename T> int fft_rows_adj_blocks(const Plan& P);
 
 // G: y[perm ? perm[m] : m] = scale * sum psi psi grid
@@ -219,6 +228,12 @@ template <typename T> void launch_permute_scale(const cpx<T>* y_user, const int3
                                                 cpx<T>* y_sorted, int64_t n, hipStream_t s);
 template <typename T> void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc,
                                                 int slot, int64_t n, hipStream_t s);
+// Stored normal operator: v_m = exp(i omega_m . s) (sorted order); zero row / column 0 of an
+// n x n image; chat (+)= Re(exp(-2 pi i k . s / K) H) / K^2 for s = (sig1, sig2) n / 2
+template <typename T> void launch_modulate(const Plan& P, int s1, int s2, cpx<T>* v, hipStream_t s);
+template <typename T> void launch_zero_edge(cpx<T>* x, int n, bool row, bool col, hipStream_t s);
+template <typename T> void launch_chat_accum(const Plan& P, const cpx<T>* H, int sig1, int sig2, bool first,
+                                             hipStream_t s);
 // Reweighting (SARA): partials of sum Re v and sum Im v
 template <typename T> int launch_sum_part(const cpx<T>* v, int64_t n, double* part_re, double* part_im,
                                           hipStream_t s);

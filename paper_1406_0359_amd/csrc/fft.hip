@@ -460,6 +460,63 @@ k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const 
     }
 }
 
+// Column stage of the stored normal operator T = Z^T F^dagger diag(c_hat) F Z (the Toeplitz
+// form of Phi^dagger Phi, Section 3): per column k2 of tmp, the forward transform along axis 0
+// (n -> K, parity-split as in cols_fwd), the product with the real spectrum c_hat[k1][k2],
+// and the adjoint transform (K -> n, as in cols_adj), in place.  Between the two transforms
+// the spectrum goes through the line buffer, from the forward pass's output order to the
+// adjoint pass's input order; the (-1)^k' factors of the two cancel.
+template <typename T, int LOGN, int C>
+__global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN, 1>::TL))
+k_fft_cols_toep(cpx<T>* __restrict__ tmp, const T* __restrict__ chat, const cpx<T>* __restrict__ tw,
+                const cpx<T>* __restrict__ tw2, int sg) {
+    using PL = Plan1D<T, LOGN, 1>;
+    constexpr int N = PL::N, K = 2 * N;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
+    const int c = threadIdx.x % C, r = (threadIdx.x / C) & 1, tl = threadIdx.x / (2 * C);
+    cpx<T>* lines = base + table_elems<T, LOGN>();
+    cpx<T>* line = lines + (2 * c + r) * PL::LS;
+    const int col = strip_block(sg) * C + c;
+    __syncthreads();
+    cpx<T> v[PL::RMAX];
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int p = PL::in_pos(tl, i);
+        cpx<T> a = tmp[(size_t)p * K + col];
+        if (r) a = a * tw2[p];
+        v[i] = a;
+    }
+    line_fft<T, LOGN, 1, false>(v, line, tl, W);
+    // frequency k1 = 2k' + r holds (-1)^k' i^r v; the adjoint reads (-1)^k' times its input
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int kp = PL::out_pos(tl, i);
+        cpx<T> o = chat[(size_t)(2 * kp + r) * K + col] * v[i];
+        v[i] = r ? mul_i(o) : o;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) v[i] = line[PL::in_pos(tl, i)];
+    __syncthreads();
+    line_fft<T, LOGN, 1, true>(v, line, tl, W);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
+    __syncthreads();
+    const cpx<T>* la = lines + (2 * c) * PL::LS;
+    const cpx<T>* lb = la + PL::LS;
+#pragma unroll
+    for (int q = 0; q < PL::RMAX / 2; ++q) {
+        const int j = r + 2 * tl + q * 2 * PL::TL;
+        tmp[(size_t)j * K + col] = la[j] + mul_mi(mulc(lb[j], tw2[j]));
+    }
+}
+
 __device__ __forceinline__ double block_sum_dyn(double v, double* red) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -546,15 +603,15 @@ size_t lds_bytes(int lines) {
 }
 
 template <typename T, int LOGN>
-void rows_fwd_impl(const Plan& P, cpx<T>* x, cpx<T>* tmp, CgDir<T> cg, hipStream_t s) {
+void rows_fwd_impl(const Plan& P, cpx<T>* x, cpx<T>* tmp, CgDir<T> cg, const T* deap, hipStream_t s) {
     constexpr int B = rows_per_wg<T, LOGN>();
     constexpr int NT = 2 * B * Plan1D<T, LOGN, 0>::TL;
     constexpr int N = 1 << LOGN;
     const size_t lds = lds_bytes<T, LOGN, 0>(2 * B);
     auto f = k_fft_rows_fwd<T, LOGN, B>;
     set_lds_limit(f, lds);
-    hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, x, tmp, (const T*)P.deap,
-                       (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, cg);
+    hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, x, tmp, deap, (const cpx<T>*)P.tw,
+                       (const cpx<T>*)P.tw2, cg);
 }
 template <typename T, int LOGN>
 void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
@@ -579,16 +636,27 @@ void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s
                        (const cpx<T>*)P.tw2, strip_groups(P, C));
 }
 template <typename T, int LOGN>
+void cols_toep_impl(const Plan& P, cpx<T>* tmp, hipStream_t s) {
+    constexpr int C = cols_per_wg<T, LOGN>();
+    constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
+    constexpr int N = 1 << LOGN;
+    const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
+    auto f = k_fft_cols_toep<T, LOGN, C>;
+    set_lds_limit(f, lds);
+    hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, tmp, (const T*)P.chat, (const cpx<T>*)P.tw,
+                       (const cpx<T>*)P.tw2, strip_groups(P, C));
+}
+template <typename T, int LOGN>
 void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* v,
-                   double c2, double* dot_part, hipStream_t s) {
+                   double c2, double* dot_part, const T* deap, hipStream_t s) {
     constexpr int B = rows_per_wg<T, LOGN>();
     constexpr int NT = 2 * B * Plan1D<T, LOGN, 0>::TL;
     constexpr int N = 1 << LOGN;
     const size_t lds = lds_bytes<T, LOGN, 0>(2 * B);
     auto f = k_fft_rows_adj<T, LOGN, B>;
     set_lds_limit(f, lds);
-    hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, tmp, x, (const T*)P.deap,
-                       (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, (T)c1, v, (T)c2, dot_part);
+    hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, tmp, x, deap, (const cpx<T>*)P.tw,
+                       (const cpx<T>*)P.tw2, (T)c1, v, (T)c2, dot_part);
 }
 
 int ilog2(int n) {
@@ -614,18 +682,21 @@ int ilog2(int n) {
 }  // namespace
 
 template <typename T>
-void launch_fft_rows_fwd(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s) {
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_fwd_impl<T, L_>(P, const_cast<cpx<T>*>(x), tmp, CgDir<T>{}, s)));
+void launch_fft_rows_fwd(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s, const void* deap) {
+    const T* dp = (const T*)(deap ? deap : P.deap);
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_fwd_impl<T, L_>(P, const_cast<cpx<T>*>(x), tmp, CgDir<T>{}, dp, s)));
 }
 template <typename T>
 void launch_fft_rows_fwd_cg(const Plan& P, cpx<T>* p, const cpx<T>* r, const double* rho_part,
-                            const double* rhonew_part, int count, cpx<T>* tmp, hipStream_t s) {
+                            const double* rhonew_part, int count, cpx<T>* tmp, hipStream_t s,
+                            const void* deap) {
     CgDir<T> cg;
     cg.r = r;
     cg.rho_part = rho_part;
     cg.rhonew_part = rhonew_part;
     cg.count = count;
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_fwd_impl<T, L_>(P, p, tmp, cg, s)));
+    const T* dp = (const T*)(deap ? deap : P.deap);
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_fwd_impl<T, L_>(P, p, tmp, cg, dp, s)));
 }
 template <typename T>
 void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
@@ -636,9 +707,14 @@ void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStre
     PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_adj_impl<T, L_>(P, grid, tmp, s)));
 }
 template <typename T>
+void launch_fft_cols_toep(const Plan& P, cpx<T>* tmp, hipStream_t s) {
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_toep_impl<T, L_>(P, tmp, s)));
+}
+template <typename T>
 void launch_fft_rows_adj(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* v,
-                         double c2, double* dot_part, hipStream_t s) {
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, x, c1, v, c2, dot_part, s)));
+                         double c2, double* dot_part, hipStream_t s, const void* deap) {
+    const T* dp = (const T*)(deap ? deap : P.deap);
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, x, c1, v, c2, dot_part, dp, s)));
 }
 template <typename T>
 int fft_rows_adj_blocks(const Plan& P) {
@@ -647,20 +723,22 @@ int fft_rows_adj_blocks(const Plan& P) {
     return r;
 }
 
-template void launch_fft_rows_fwd<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
-template void launch_fft_rows_fwd<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
+template void launch_fft_rows_fwd<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t, const void*);
+template void launch_fft_rows_fwd<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t, const void*);
 template void launch_fft_rows_fwd_cg<float>(const Plan&, cpx<float>*, const cpx<float>*, const double*,
-                                            const double*, int, cpx<float>*, hipStream_t);
+                                            const double*, int, cpx<float>*, hipStream_t, const void*);
 template void launch_fft_rows_fwd_cg<double>(const Plan&, cpx<double>*, const cpx<double>*, const double*,
-                                             const double*, int, cpx<double>*, hipStream_t);
+                                             const double*, int, cpx<double>*, hipStream_t, const void*);
 template void launch_fft_cols_fwd<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
 template void launch_fft_cols_fwd<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
 template void launch_fft_cols_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
 template void launch_fft_cols_adj<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
+template void launch_fft_cols_toep<float>(const Plan&, cpx<float>*, hipStream_t);
+template void launch_fft_cols_toep<double>(const Plan&, cpx<double>*, hipStream_t);
 template void launch_fft_rows_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, double,
-                                         const cpx<float>*, double, double*, hipStream_t);
+                                         const cpx<float>*, double, double*, hipStream_t, const void*);
 template void launch_fft_rows_adj<double>(const Plan&, const cpx<double>*, cpx<double>*, double,
-                                          const cpx<double>*, double, double*, hipStream_t);
+                                          const cpx<double>*, double, double*, hipStream_t, const void*);
 template int fft_rows_adj_blocks<float>(const Plan&);
 template int fft_rows_adj_blocks<double>(const Plan&);
 

@@ -297,6 +297,8 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
     P.grid = carve(K * K * ce);
     P.grid2 = carve(K * K * ce);
     P.tmp = carve(K * P.n * ce);
+    P.unit = carve(P.n * es);
+    P.chat = carve(K * K * es);
     P.part = (double*)carve((size_t)NUM_PARTIAL_BUFS * MAX_PARTIALS * sizeof(double));
     P.sc = (double*)carve(SL_COUNT * sizeof(double));
     P.hist_cap = HIST_CAP;
@@ -650,6 +652,8 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     if (!merge.empty()) PURIFY_HIP(up(P.gmerge, merge.data(), merge.size() * sizeof(int32_t)));
     PURIFY_HIP(up_real(P.frac, sfr));
     PURIFY_HIP(up_real(P.deap, deap));
+    const std::vector<double> ones((size_t)n, 1.0);   // lives until the final synchronisation
+    PURIFY_HIP(up_real(P.unit, ones));
     PURIFY_HIP(up_real(P.tw, tw));
     PURIFY_HIP(up_real(P.tw2, tw2));
     PURIFY_HIP(up_real(P.filters, filt));

@@ -21,10 +21,12 @@ FP64, FP32 = 0, 1
 DICT_SARA = 0x1FF
 SDMM_NO_GRAPH = 1
 SDMM_WARM_START = 2
+SDMM_TOEPLITZ = 4
+NORMAL_TOEPLITZ = 1
 
 STAGES = {
     "fft_rows": 0, "fft_cols": 1, "degrid": 2, "grid": 3, "ifft_cols": 4, "ifft_rows": 5,
-    "phi": 6, "phi_adj": 7, "psi_adj": 8, "psi": 9, "gtg": 10,
+    "phi": 6, "phi_adj": 7, "psi_adj": 8, "psi": 9, "gtg": 10, "toep_cols": 11, "toep_normal": 12,
 }
 
 _STATUS = {0: "ok", 1: "invalid argument", 2: "workspace", 3: "device error", 4: "non-finite"}
@@ -106,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(SdmmInfo), vp]),
         "purify_sdmm_reweighted": (i32, [vp, vp, ctypes.POINTER(SdmmParams), ctypes.POINTER(ReweightParams),
                                          vp, vp, ctypes.POINTER(SdmmInfo), ctypes.POINTER(ReweightInfo), vp]),
+        "purify_phi_normal": (i32, [vp, vp, vp, i32, vp]),
         "purify_time_stage": (i32, [vp, i32, i32, vp, ctypes.POINTER(dbl)]),
         "purify_daubechies_filter": (i32, [i32, ctypes.POINTER(dbl), i32]),
         "purify_kb_kernel": (i32, [i32, dbl, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
@@ -297,13 +300,23 @@ class Plan:
                "purify_psi_adj")
         return a
 
+    def normal(self, x, toeplitz: bool = False, out=None):
+        """Phi^dagger Phi x through the NUFFT (fused G^T G), or its stored Toeplitz form."""
+        o = self.empty(self.n, self.n) if out is None else out
+        _check(self.lib.purify_phi_normal(self.handle, self._vec(x, self.n * self.n, "x"),
+                                          self._vec(o, self.n * self.n, "out"),
+                                          NORMAL_TOEPLITZ if toeplitz else 0, self._stream()),
+               "purify_phi_normal")
+        return o
+
     def _params(self, epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack,
-                check_every, weights, graph, warm, hist):
+                check_every, weights, graph, warm, hist, toeplitz=False):
         p = SdmmParams()
         p.epsilon, p.gamma, p.nu, p.xi, p.slack = epsilon, gamma, nu, xi, slack
         p.max_iter, p.cg_iter, p.check_every = max_iter, cg_iter, check_every
         p.halting, p.nu_iter = int(bool(halting)), nu_iter
-        p.flags = (0 if graph else SDMM_NO_GRAPH) | (SDMM_WARM_START if warm else 0)
+        p.flags = ((0 if graph else SDMM_NO_GRAPH) | (SDMM_WARM_START if warm else 0)
+                   | (SDMM_TOEPLITZ if toeplitz else 0))
         if weights is not None:
             p.weights = self._weights(weights)
         p.history = _dptr(hist) if hist is not None else None
@@ -324,13 +337,14 @@ class Plan:
     def sdmm(self, y, epsilon: float, max_iter: int = 300, cg_iter: int = 10,
              gamma: float = 0.0, nu: float = 0.0, nu_iter: int = 100, halting: bool = False,
              xi: float = 1e-4, slack: float = 1e-3, check_every: int = 10, weights=None,
-             record_history: bool = False, graph: bool = True, x0=None, out=None) -> SolveResult:
+             record_history: bool = False, graph: bool = True, x0=None, toeplitz: bool = False,
+             out=None) -> SolveResult:
         """SDMM (Algorithm 1) for eq. (3) with R = 1; returns x_hat and solver info.
-        x0: starting point x_hat(0) (default 0)."""
+        x0: starting point x_hat(0) (default 0).  toeplitz: CG with the stored normal operator."""
         x = self._start(x0, out)
         hist = np.zeros(2 * max_iter) if record_history else None
         p = self._params(epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack, check_every,
-                         weights, graph, x0 is not None, hist)
+                         weights, graph, x0 is not None, hist, toeplitz)
         info = SdmmInfo()
         _check(self.lib.purify_sdmm_solve(self.handle, self._vec(y, self.M, "y"), ctypes.byref(p),
                                           self._vec(x, self.n * self.n, "x"), ctypes.byref(info),
@@ -345,13 +359,13 @@ class Plan:
                         max_iter: int = 300, cg_iter: int = 10, gamma: float = 0.0, nu: float = 0.0,
                         nu_iter: int = 100, halting: bool = False, xi: float = 1e-4, slack: float = 1e-3,
                         check_every: int = 10, weights=None, graph: bool = True, x0=None,
-                        out=None) -> "ReweightResult":
+                        toeplitz: bool = False, out=None) -> "ReweightResult":
         """Reweighted l1 (SARA): solve 0 with `weights` (None: W = I), then up to `reweights`
         weighted solves (purify_sdmm_reweighted)."""
         x = self._start(x0, out)
         w = self.torch.empty(self.D, dtype=self.torch.float64, device=self.device)
         p = self._params(epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack, check_every,
-                         weights, graph, x0 is not None, None)
+                         weights, graph, x0 is not None, None, toeplitz)
         rw = ReweightParams()
         rw.delta0, rw.decay, rw.delta_min, rw.rel_var, rw.reweights = delta0, decay, delta_min, rel_var, reweights
         info, rinfo = SdmmInfo(), ReweightInfo()
