@@ -9,7 +9,9 @@ f3 = indicator of the l2 ball B(y, eps) (on Phi x).  Their proximity operators i
 * prox of the positive-orthant indicator: Re(u) clipped at 0, imaginary part 0 (x is
   iterated in C^N, positivity means x in R_+^N, a subset of C^N);
 * prox of the l2-ball indicator: y + (u - y) min(1, eps / ||u - y||)  (u itself when
-  ||u - y|| = 0).
+  ||u - y|| = 0);
+* with the data split into R blocks (eqs. (4)-(5)), the constraint set is the product of the
+  blocks' balls B(y_i, eps_i) and its projection acts block by block.
 """
 import numpy as np
 
@@ -34,3 +36,13 @@ def project_l2_ball(u: np.ndarray, y: np.ndarray, eps: float) -> np.ndarray:
     if nd == 0.0:
         return np.array(u, dtype=np.complex128)
     return y + d * min(1.0, eps / nd)
+
+
+def project_l2_balls(u: np.ndarray, y: np.ndarray, offsets, eps) -> np.ndarray:
+    """Projection onto the product of the balls B(y_i, eps_i), block i = [offsets[i],
+    offsets[i + 1]) of the visibility vector."""
+    out = np.array(u, dtype=np.complex128)
+    for i in range(len(eps)):
+        a, b = offsets[i], offsets[i + 1]
+        out[a:b] = project_l2_ball(u[a:b], y[a:b], eps[i])
+    return out

@@ -29,7 +29,7 @@ from typing import Callable, List, Optional
 
 import numpy as np
 
-from .prox import project_l2_ball, project_positive, soft_threshold
+from .prox import project_l2_ball, project_l2_balls, project_positive, soft_threshold
 
 
 def operator_norm(normal: Callable[[np.ndarray], np.ndarray], shape, iters: int = 100):
@@ -78,15 +78,23 @@ class SdmmResult:
 def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
          cg_iters: int = 10, gamma: Optional[float] = None, nu: Optional[float] = None,
          weights=None, halting: bool = False, xi: float = 1e-4, slack: float = 1e-3,
-         nu_iters: int = 100, x0=None, normal=None) -> SdmmResult:
+         nu_iters: int = 100, x0=None, normal=None, blocks=None) -> SdmmResult:
     """Run SDMM (Algorithm 1, R = 1, S = 3) and return x_hat (complex; the image is Re).
     normal: a stored form of Phi^dagger Phi for the global update's conjugate-gradient
     operator (Section 3), e.g. the Toeplitz operator of oracle.toeplitz; None applies Phi
-    and Phi^dagger.  nu, the proximity steps and x_i = L_i^dagger L_i x_hat(0) always use Phi."""
+    and Phi^dagger.  nu, the proximity steps and x_i = L_i^dagger L_i x_hat(0) always use Phi.
+    blocks: (offsets, eps_list) splitting the visibilities into R blocks, block i =
+    [offsets[i], offsets[i + 1]) with bound eps_list[i] (eqs. (4)-(5), S = R + 2 functions);
+    `epsilon` is then unused.  Since Phi^dagger of the stacked vector is sum_i Phi_i^dagger,
+    the R data branches together are one projection onto the product of balls followed by one
+    Phi^dagger; halting asks every block's residual to be within its bound."""
     if nu is None or nu <= 0:
         nu, _ = operator_norm(lambda v: phi_adj(phi(v)), shape, nu_iters)
     yt = np.asarray(y, dtype=np.complex128) / nu
     et = epsilon / nu
+    if blocks is not None:
+        offsets = [int(o) for o in blocks[0]]
+        ets = [float(e) / nu for e in blocks[1]]
     P = lambda v: phi(v) / nu
     Pt = lambda v: phi_adj(v) / nu
     if gamma is None or gamma <= 0:
@@ -124,7 +132,7 @@ def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
         # i = 3: data fidelity l2 ball
         v3 = P(xh)
         u = v3 + z3
-        r3 = project_l2_ball(u, yt, et)
+        r3 = project_l2_ball(u, yt, et) if blocks is None else project_l2_balls(u, yt, offsets, ets)
         z3 = u - r3
         x3 = Pt(r3 - z3)
 
@@ -133,8 +141,13 @@ def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
         res.objective.append(f)
         res.residual.append(resid)
         res.iterations = t
+        if blocks is None:
+            feasible = resid <= et * (1.0 + slack)
+        else:
+            feasible = all(np.linalg.norm(yt[a:b] - v3[a:b]) <= e * (1.0 + slack)
+                           for a, b, e in zip(offsets[:-1], offsets[1:], ets))
         if halting and f_prev is not None and f > 0:
-            if abs(f - f_prev) / f < xi and resid <= et * (1.0 + slack):
+            if abs(f - f_prev) / f < xi and feasible:
                 res.converged = True
                 break
         f_prev = f
