@@ -130,6 +130,13 @@ typedef struct {
     const double* weights; /* device, D doubles (diagonal W of eq. (3)), or NULL for W = I */
     double* history;      /* host, 2 * max_iter doubles or NULL: per iteration the objective
                              ||W Psi^dag x_hat||_1 and the residual ||y~ - Phi~ x_hat|| */
+    int32_t nblocks;      /* R: 0 or 1 = one data constraint with `epsilon`; 2..1024 = the data
+                             split into R blocks (eqs. (4)-(5)), one l2 constraint each, S = R + 2
+                             functions; `epsilon` is then unused */
+    const int64_t* block_offsets;  /* host, R + 1 (R >= 2): block i holds the visibilities
+                             [off[i], off[i+1]) of the caller's uv order; off[0] = 0, off[R] = M,
+                             strictly increasing */
+    const double* block_eps;       /* host, R (R >= 2): eps_i >= 0, unnormalised */
 } purify_sdmm_params;
 
 typedef struct {
@@ -142,7 +149,9 @@ typedef struct {
 } purify_sdmm_info;
 
 /* SDMM (Algorithm 1) for eq. (3) with R = 1: f1 = ||W .||_1 on Psi^dagger x, f2 = positive
- * orthant, f3 = l2 ball of radius epsilon about y on Phi x.  The global update solves
+ * orthant, f3 = l2 ball of radius epsilon about y on Phi x (with nblocks = R >= 2: f_{i+2} =
+ * l2 ball of radius eps_i about y_i on Phi_i x, projected block by block; the halting rule
+ * then asks every block's residual to be within eps_i (1 + slack)).  The global update solves
  * (Phi~^dagger Phi~ + 2 I) x = sum_i x_i by cg_iter warm-started conjugate-gradient steps
  * (Section 3), with Phi~ = Phi / nu.  y: device, M complex in uv order.  x_out: device, N
  * complex; receives x_hat (the image is its real part).  Uses the plan's solver state, so
@@ -174,7 +183,7 @@ purify_status purify_phi_normal(purify_plan* plan, const void* x, void* out, int
  * delta_1 = max(delta0, delta_min), delta0 <= 0 meaning the standard deviation of the
  * coefficients Psi^dagger x(0); delta_{k+1} = max(decay delta_k, delta_min), delta_min < 0
  * meaning sigma / nu with sigma = epsilon / sqrt(M + 2 sqrt(M)) (the noise level of the
- * chi-square bound epsilon).  The loop ends after solve k when
+ * chi-square bound epsilon; with visibility blocks, the largest eps_i / sqrt(M_i + 2 sqrt(M_i))).  The loop ends after solve k when
  * ||x(k) - x(k-1)|| / ||x(k-1)|| < rel_var, or after `reweights` weighted solves. */
 typedef struct {
     double delta0;      /* <= 0: standard deviation of Psi^dagger x(0) */
@@ -253,7 +262,7 @@ purify_status purify_server_create(const purify_server_desc* desc, purify_server
 
 /* Queue one solve.  desc: as for purify_plan_create (desc->uv host, M x 2, copied).  y: host,
  * M complex of desc->precision in uv order (copied).  params: as for purify_sdmm_solve, with
- * history and weights NULL.  *ticket identifies the request.  Returns at once. */
+ * history and weights NULL and nblocks <= 1.  *ticket identifies the request.  Returns at once. */
 purify_status purify_server_submit(purify_server* server, const purify_plan_desc* desc, const void* y,
                                    const purify_sdmm_params* params, int64_t* ticket);
 

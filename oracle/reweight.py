@@ -14,7 +14,8 @@ these readings, shared with the GPU library:
 * delta_1 = max(delta0, delta_min), delta0 given or else the standard deviation of the
   coefficients alpha = Psi^dagger x^(0); delta_{k+1} = max(decay * delta_k, delta_min), with
   delta_min given or else sigma~ = sigma / nu, sigma = eps / sqrt(M + 2 sqrt(M)) (the noise
-  level behind the chi-square bound eps, in the units of the normalised problem);
+  level behind the chi-square bound eps, in the units of the normalised problem; with
+  visibility blocks, the largest of the blocks' sigma_i = eps_i / sqrt(M_i + 2 sqrt(M_i)));
 * solve k >= 1 is SDMM warm started from x^(k-1), with the nu and gamma of solve 0;
 * stop after solve k when ||x^(k) - x^(k-1)|| / ||x^(k-1)|| < rel_var (0 when both are zero,
   infinite when only x^(k-1) is), or when k = reweights.
@@ -69,7 +70,13 @@ def reweighted_sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, reweights: in
     out = ReweightResult(x=r0.x, solves=[r0], weights=weights)
     kw = dict(sdmm_kwargs)
     kw["nu"], kw["gamma"] = r0.nu, r0.gamma
-    floor = noise_floor(epsilon, np.size(y), r0.nu) if delta_min is None or delta_min < 0 else delta_min
+    if delta_min is not None and delta_min >= 0:
+        floor = delta_min
+    elif sdmm_kwargs.get("blocks") is not None:
+        offs, eps_b = sdmm_kwargs["blocks"]
+        floor = max(noise_floor(e, offs[i + 1] - offs[i], r0.nu) for i, e in enumerate(eps_b))
+    else:
+        floor = noise_floor(epsilon, np.size(y), r0.nu)
     x = r0.x
     alpha = psi_adj(x)
     delta = float(np.std(alpha)) if delta0 is None or delta0 <= 0 else delta0

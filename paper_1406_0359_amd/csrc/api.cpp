@@ -128,6 +128,7 @@ struct Sdmm {
     const purify_sdmm_params* prm;
     double inv_nu = 1, inv_nu2 = 1, eps_t = 0, gamma = 0;
     bool toep = false;   // CG operator from the stored normal operator (PURIFY_SDMM_TOEPLITZ)
+    int nblk = 0, nchunks = 0;   // visibility blocks (R >= 2) and their reduction chunks
 
     double* part(int k) const { return part_buf(P, k); }
 
@@ -187,8 +188,14 @@ struct Sdmm {
         launch_prox_pos<T>(xh, z2, x2, N, s);
         // i = 3: l2 ball about y~ on Phi~ x_hat
         op.phi(xh, v3, inv_nu, nullptr);
-        const int nb3 = launch_ball_part<T>(v3, z3, yt, M, part(4), part(5), s);
-        launch_prox_ball<T>(v3, z3, yt, part(4), part(5), nb3, eps_t, sc, P.hist, P.hist_cap, M, s);
+        if (nblk > 1) {   // R balls: chunk sums, per-block scales, projection by block
+            launch_ball_part_blk<T>(v3, z3, yt, P.bperm, P.bchunk, nchunks, part(4), part(5), s);
+            launch_ball_fin_blk(part(4), part(5), P.bchunk_off, P.beps, nblk, P.bscale, sc, P.hist, P.hist_cap, s);
+            launch_prox_ball_blk<T>(v3, z3, yt, P.bid, P.bscale, M, s);
+        } else {
+            const int nb3 = launch_ball_part<T>(v3, z3, yt, M, part(4), part(5), s);
+            launch_prox_ball<T>(v3, z3, yt, part(4), part(5), nb3, eps_t, sc, P.hist, P.hist_cap, M, s);
+        }
         op.phi_adj(v3, nullptr, x3, inv_nu, nullptr, 0.0, nullptr);
         // the next iteration's warm-start product A x_hat needs only x_hat: it runs here,
         // overlapping branch i = 1 on the other stream
@@ -203,6 +210,68 @@ struct Sdmm {
         A(op, (const C*)P.xh, (C*)P.qv, nullptr);
     }
 };
+
+// Tables of the visibility blocks for one solve: the block of each sorted visibility, the
+// sorted positions grouped by block, chunks of at least 256 of them per reduction workgroup
+// (at most BLK_CHUNKS in all) and eps_i / nu.  Host work like the plan's binning; synchronous.
+purify_status setup_blocks(const Plan& P, const purify_sdmm_params* prm, double nu, hipStream_t s,
+                           int* nchunks_out) {
+    const int R = prm->nblocks;
+    const int64_t M = P.M;
+    const int64_t* off = prm->block_offsets;
+    std::vector<int32_t> perm((size_t)M), ublk((size_t)M), bid((size_t)M), bperm((size_t)M);
+    PURIFY_HIP(hipMemcpyAsync(perm.data(), P.perm, (size_t)M * 4, hipMemcpyDeviceToHost, s));
+    PURIFY_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < R; ++i)
+        for (int64_t u = off[i]; u < off[i + 1]; ++u) ublk[(size_t)u] = i;
+    std::vector<int64_t> start((size_t)R + 1, 0);
+    for (int64_t m = 0; m < M; ++m) {
+        bid[(size_t)m] = ublk[(size_t)perm[(size_t)m]];
+        ++start[(size_t)bid[(size_t)m] + 1];
+    }
+    for (int i = 0; i < R; ++i) start[(size_t)i + 1] += start[(size_t)i];
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int64_t m = 0; m < M; ++m) bperm[(size_t)fill[(size_t)bid[(size_t)m]]++] = (int32_t)m;
+    const int64_t per = 256 * 4096;
+    const int64_t CH = 256 * std::max<int64_t>(1, (M + per - 1) / per);
+    std::vector<int32_t> chunks, coff((size_t)R + 1, 0);
+    for (int i = 0; i < R; ++i) {
+        coff[(size_t)i] = (int32_t)(chunks.size() / 2);
+        for (int64_t a = start[(size_t)i]; a < start[(size_t)i + 1]; a += CH) {
+            chunks.push_back((int32_t)a);
+            chunks.push_back((int32_t)std::min(a + CH, start[(size_t)i + 1]));
+        }
+    }
+    const int nch = (int)(chunks.size() / 2);
+    coff[(size_t)R] = nch;
+    if (nch > BLK_CHUNKS) {
+        set_error("too many block reduction chunks");
+        return PURIFY_E_INVALID;
+    }
+    std::vector<double> eps((size_t)R);
+    for (int i = 0; i < R; ++i) eps[(size_t)i] = prm->block_eps[i] / nu;
+    PURIFY_HIP(hipMemcpyAsync(P.bid, bid.data(), (size_t)M * 4, hipMemcpyHostToDevice, s));
+    PURIFY_HIP(hipMemcpyAsync(P.bperm, bperm.data(), (size_t)M * 4, hipMemcpyHostToDevice, s));
+    PURIFY_HIP(hipMemcpyAsync(P.bchunk, chunks.data(), chunks.size() * 4, hipMemcpyHostToDevice, s));
+    PURIFY_HIP(hipMemcpyAsync(P.bchunk_off, coff.data(), coff.size() * 4, hipMemcpyHostToDevice, s));
+    PURIFY_HIP(hipMemcpyAsync(P.beps, eps.data(), eps.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    PURIFY_HIP(hipStreamSynchronize(s));
+    *nchunks_out = nch;
+    return PURIFY_OK;
+}
+
+// Check the block description of a solve (R <= 1 needs nothing).
+bool blocks_valid(const purify_sdmm_params* prm, int64_t M) {
+    if (prm->nblocks <= 1) return true;
+    if (prm->nblocks > MAX_BLOCKS || !prm->block_offsets || !prm->block_eps) return false;
+    const int64_t* off = prm->block_offsets;
+    if (off[0] != 0 || off[prm->nblocks] != M) return false;
+    for (int i = 0; i < prm->nblocks; ++i) {
+        if (off[i + 1] <= off[i]) return false;
+        if (!(prm->block_eps[i] >= 0) || !std::isfinite(prm->block_eps[i])) return false;
+    }
+    return true;
+}
 
 purify_status capture(hipStream_t cs, hipGraph_t* g, hipGraphExec_t* x) {
     PURIFY_HIP(hipStreamEndCapture(cs, g));
@@ -265,6 +334,11 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     S.inv_nu = 1.0 / nu;
     S.inv_nu2 = S.inv_nu * S.inv_nu;
     S.eps_t = prm->epsilon * S.inv_nu;
+    if (prm->nblocks > 1) {
+        const purify_status st = setup_blocks(P, prm, nu, cs, &S.nchunks);
+        if (st != PURIFY_OK) return st;
+        S.nblk = prm->nblocks;
+    }
 
     // y~ = y / nu in solver (tile-sorted) order
     launch_permute_scale<T>((const C*)y_user, P.perm, S.inv_nu, (C*)P.ytil, M, cs);
@@ -317,14 +391,18 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
         else S.enqueue_iteration(cs, R.cs2, R.fork, R.join);
         it_done = t + 1;
         if (prm->halting && t >= 1 && ((t + 1) % check == 0 || t + 1 == T_max)) {
-            double h[4];
+            double h[5] = {0, 0, 0, 0, 0};
             const int hi = t % P.hist_cap, hp = (t - 1) % P.hist_cap;
             PURIFY_HIP(hipMemcpyAsync(h, P.hist + 2 * hp, 2 * sizeof(double), hipMemcpyDeviceToHost, cs));
             PURIFY_HIP(hipMemcpyAsync(h + 2, P.hist + 2 * hi, 2 * sizeof(double), hipMemcpyDeviceToHost, cs));
+            if (S.nblk > 1)
+                PURIFY_HIP(hipMemcpyAsync(h + 4, sc + SL_BLK_RATIO, sizeof(double), hipMemcpyDeviceToHost, cs));
             PURIFY_HIP(hipStreamSynchronize(cs));
             const double f = h[2], fp = h[0], res = h[3];
             if (!std::isfinite(f) || !std::isfinite(res)) break;
-            if (f > 0 && std::fabs(f - fp) / f < prm->xi && res <= S.eps_t * (1.0 + prm->slack)) {
+            // every data constraint within its bound (one ball, or each block's)
+            const bool feasible = S.nblk > 1 ? h[4] <= 1.0 + prm->slack : res <= S.eps_t * (1.0 + prm->slack);
+            if (f > 0 && std::fabs(f - fp) / f < prm->xi && feasible) {
                 converged = true;
                 break;
             }
@@ -381,9 +459,16 @@ purify_status reweighted_impl(Plan& P, const void* y, const purify_sdmm_params* 
         pk.gamma = inf.gamma;
         pk.weights = weights;
         pk.flags = prm->flags | PURIFY_SDMM_WARM_START;
-        const double floor = rw->delta_min >= 0
-                                 ? rw->delta_min
-                                 : prm->epsilon / std::sqrt((double)M + 2.0 * std::sqrt((double)M)) / inf.nu;
+        // noise level behind the chi-square bound(s): eps = sigma sqrt(M + 2 sqrt M) per constraint
+        double sigma = prm->epsilon / std::sqrt((double)M + 2.0 * std::sqrt((double)M));
+        if (prm->nblocks > 1) {
+            sigma = 0;
+            for (int i = 0; i < prm->nblocks; ++i) {
+                const double m = (double)(prm->block_offsets[i + 1] - prm->block_offsets[i]);
+                sigma = std::max(sigma, prm->block_eps[i] / std::sqrt(m + 2.0 * std::sqrt(m)));
+            }
+        }
+        const double floor = rw->delta_min >= 0 ? rw->delta_min : sigma / inf.nu;
         double* sc = P.sc;
         launch_psi_adj<T>(P, (const C*)x_io, (C*)P.v1, s);
         double delta = rw->delta0;
@@ -613,6 +698,10 @@ purify_status purify_sdmm_solve(purify_plan* plan, const void* y, const purify_s
         return PURIFY_E_INVALID;
     }
     Plan& P = plan->P;
+    if (!blocks_valid(params, P.M)) {
+        set_error("invalid visibility blocks (2 <= R <= 1024, offsets 0 .. M strictly increasing, eps_i >= 0)");
+        return PURIFY_E_INVALID;
+    }
     hipStream_t s = (hipStream_t)stream;
     const void* x_in = (params->flags & PURIFY_SDMM_WARM_START) ? x_out : nullptr;
     purify_status st = f64(P) ? sdmm_impl<double>(P, y, params, x_in, x_out, info, s)
@@ -640,6 +729,10 @@ purify_status purify_sdmm_reweighted(purify_plan* plan, const void* y, const pur
         return PURIFY_E_INVALID;
     }
     Plan& P = plan->P;
+    if (!blocks_valid(params, P.M)) {
+        set_error("invalid visibility blocks (2 <= R <= 1024, offsets 0 .. M strictly increasing, eps_i >= 0)");
+        return PURIFY_E_INVALID;
+    }
     hipStream_t s = (hipStream_t)stream;
     purify_status st = f64(P) ? reweighted_impl<double>(P, y, params, rw, weights, x_io, info, rw_info, s)
                               : reweighted_impl<float>(P, y, params, rw, weights, x_io, info, rw_info, s);

@@ -72,10 +72,15 @@ enum Slot : int {
     SL_RHO = 0, SL_PQ, SL_ALPHA, SL_BETA, SL_RHONEW,
     SL_OBJ, SL_RES2, SL_D2, SL_BALL, SL_LAMBDA, SL_INVLAMBDA, SL_MAXABS, SL_NONFINITE, SL_ITER,
     SL_RW_A, SL_RW_B, SL_RW_C,   // reweighting statistics (sums of the reweighting kernels)
+    SL_BLK_RATIO,                // visibility blocks: max_i ||y~_i - Phi~_i x|| / eps~_i
     SL_COUNT = 32
 };
 
 constexpr int MAX_PARTIALS = 8192;   // per partial-sum buffer
+// Visibility blocks (eqs. (4)-(5)): at most MAX_BLOCKS data blocks; their ball projections
+// reduce over chunks of each block's visibilities (at most BLK_CHUNKS chunks of at least 256)
+constexpr int MAX_BLOCKS = 1024;
+constexpr int BLK_CHUNKS = 4096 + MAX_BLOCKS;
 constexpr int GRID_UNIT = 1024;      // smallest gridding work unit (visibility passes)
 constexpr int GRID_REC = 16;         // ints per gridding work-unit record
 constexpr int NUM_PARTIAL_BUFS = 8;
@@ -146,6 +151,13 @@ struct Plan {
     void *wt = nullptr;          // wavelet temp: nwav * N complex
     void *ws2 = nullptr;         // wavelet LL temp: nwav * N/4 complex (x2 ping-pong)
     void *vis = nullptr;         // M complex scratch (visibility-space temp)
+    // visibility blocks of the current solve (R > 1)
+    int32_t* bid = nullptr;      // M: block of each sorted visibility
+    int32_t* bperm = nullptr;    // M: sorted positions grouped by block (ascending within a block)
+    int32_t* bchunk = nullptr;   // BLK_CHUNKS x {first, end} ranges of bperm, block by block
+    int32_t* bchunk_off = nullptr;  // MAX_BLOCKS + 1: first chunk of each block
+    double* beps = nullptr;      // MAX_BLOCKS: eps_i / nu
+    double* bscale = nullptr;    // MAX_BLOCKS: ball scale of each block (this iteration)
 };
 
 // ---------------------------------------------------------------------------------------
@@ -234,6 +246,16 @@ template <typename T> void launch_modulate(const Plan& P, int s1, int s2, cpx<T>
 template <typename T> void launch_zero_edge(cpx<T>* x, int n, bool row, bool col, hipStream_t s);
 template <typename T> void launch_chat_accum(const Plan& P, const cpx<T>* H, int sig1, int sig2, bool first,
                                              hipStream_t s);
+// Visibility blocks: chunk partials of ||v3 + z3 - y~||^2 and ||y~ - v3||^2 over bperm ranges;
+// per-block finalize (scale, residual, max ratio, history); elementwise projection by block
+template <typename T> void launch_ball_part_blk(const cpx<T>* v3, const cpx<T>* z3, const cpx<T>* yt,
+                                                const int32_t* bperm, const int32_t* chunks, int nchunks,
+                                                double* part_d, double* part_res, hipStream_t s);
+void launch_ball_fin_blk(const double* part_d, const double* part_res, const int32_t* chunk_off,
+                         const double* eps, int R, double* scale, double* sc, double* hist, int hist_cap,
+                         hipStream_t s);
+template <typename T> void launch_prox_ball_blk(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const int32_t* bid,
+                                                const double* scale, int64_t n, hipStream_t s);
 // Reweighting (SARA): partials of sum Re v and sum Im v
 template <typename T> int launch_sum_part(const cpx<T>* v, int64_t n, double* part_re, double* part_im,
                                           hipStream_t s);

@@ -315,6 +315,12 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
     P.z3 = carve(M * ce);
     P.v3 = carve(M * ce);
     P.vis = carve(M * ce);
+    P.bid = (int32_t*)carve(M * 4);
+    P.bperm = (int32_t*)carve(M * 4);
+    P.bchunk = (int32_t*)carve((size_t)BLK_CHUNKS * 2 * 4);
+    P.bchunk_off = (int32_t*)carve((size_t)(MAX_BLOCKS + 1) * 4);
+    P.beps = (double*)carve((size_t)MAX_BLOCKS * sizeof(double));
+    P.bscale = (double*)carve((size_t)MAX_BLOCKS * sizeof(double));
     P.z1 = carve(D * ce);
     P.v1 = carve(D * ce);
     // FP64: every visibility's 2J tap weights, computed once (degridding and gridding read

@@ -249,8 +249,8 @@ purify_status purify_server_submit(purify_server* server, const purify_plan_desc
         return PURIFY_E_INVALID;
     }
     if (params->max_iter < 1 || params->cg_iter < 1 || !(params->epsilon >= 0) ||
-        (params->nu <= 0 && params->nu_iter < 1) || params->history || params->weights) {
-        purify::set_error("invalid SDMM parameters for a served solve (history and weights are not served)");
+        (params->nu <= 0 && params->nu_iter < 1) || params->history || params->weights || params->nblocks > 1) {
+        purify::set_error("invalid SDMM parameters for a served solve (history, weights and blocks are not served)");
         return PURIFY_E_INVALID;
     }
     auto r = std::make_shared<Request>();

@@ -328,6 +328,85 @@ k_scale_by_slot(cpx<T>* __restrict__ dst, const cpx<T>* __restrict__ src, const 
     if (i < n) dst[i] = (T)sc[slot] * src[i];
 }
 
+// Visibility blocks, pass 1: workgroup c sums over bperm[first, end) of its chunk (one block's
+// visibilities) ||v3 + z3 - y~||^2 and ||y~ - v3||^2
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_ball_part_blk(const cpx<T>* __restrict__ v3, const cpx<T>* __restrict__ z3, const cpx<T>* __restrict__ yt,
+                const int32_t* __restrict__ bperm, const int32_t* __restrict__ chunks, double* part_d,
+                double* part_res) {
+    const int a = chunks[2 * blockIdx.x], b = chunks[2 * blockIdx.x + 1];
+    double ad = 0, ar = 0;
+    for (int j = a + (int)threadIdx.x; j < b; j += VT) {
+        const int m = bperm[j];
+        const cpx<T> v = v3[m], y = yt[m];
+        const cpx<T> d = v + z3[m] - y;
+        ad += (double)d.x * d.x + (double)d.y * d.y;
+        const double rx = (double)y.x - v.x, ry = (double)y.y - v.y;
+        ar += rx * rx + ry * ry;
+    }
+    const double td = block_sum(ad);
+    const double tr = block_sum(ar);
+    if (threadIdx.x == 0) {
+        part_d[blockIdx.x] = td;
+        part_res[blockIdx.x] = tr;
+    }
+}
+
+// pass 2 (one workgroup): thread i sums block i's chunk partials in order; scale_i =
+// min(1, eps~_i / ||u_i - y~_i||); thread 0 then records, over the blocks in order, the total
+// residual ||y~ - Phi~ x||^2 (and its history row) and max_i ||y~_i - v3_i|| / eps~_i
+__global__ void __launch_bounds__(1024)
+k_ball_fin_blk(const double* __restrict__ part_d, const double* __restrict__ part_res,
+               const int32_t* __restrict__ chunk_off, const double* __restrict__ eps, int R, double* scale,
+               double* sc, double* hist, int hist_cap) {
+    __shared__ double res_b[MAX_BLOCKS];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < R; i += blockDim.x) {
+        double d2 = 0, r2 = 0;
+        for (int c = chunk_off[i]; c < chunk_off[i + 1]; ++c) {
+            d2 += part_d[c];
+            r2 += part_res[c];
+        }
+        const double nd = sqrt(d2);
+        scale[i] = (nd == 0.0 || eps[i] >= nd) ? 1.0 : eps[i] / nd;
+        res_b[i] = r2;
+        if (!(d2 == d2) || !(r2 == r2) || d2 == INFINITY || r2 == INFINITY) bad = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double tot = 0, ratio = 0;
+    for (int i = 0; i < R; ++i) {
+        tot += res_b[i];
+        const double r = sqrt(res_b[i]);
+        const double q = eps[i] > 0.0 ? r / eps[i] : (r > 0.0 ? INFINITY : 0.0);
+        ratio = fmax(ratio, q);
+    }
+    sc[SL_RES2] = tot;
+    sc[SL_BLK_RATIO] = ratio;
+    if (bad) sc[SL_NONFINITE] = 1.0;
+    if (hist) hist[2 * ((int)sc[SL_ITER] % hist_cap) + 1] = sqrt(tot);
+}
+
+// pass 3: u = v3 + z3 ; r3 = y~ + s_b (u - y~) with b the visibility's block ; z3 = u - r3 ;
+// v3 <- r3 - z3
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_prox_ball_blk(cpx<T>* __restrict__ v3, cpx<T>* __restrict__ z3, const cpx<T>* __restrict__ yt,
+                const int32_t* __restrict__ bid, const double* __restrict__ scale, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i >= n) return;
+    const T s = (T)scale[bid[i]];
+    const cpx<T> y = yt[i];
+    const cpx<T> u = v3[i] + z3[i];
+    const cpx<T> r3 = y + s * (u - y);
+    const cpx<T> z = u - r3;
+    z3[i] = z;
+    v3[i] = r3 - z;
+}
+
 // Reweighting statistics: partial sums of Re and Im (the mean of the coefficients)
 template <typename T>
 __global__ void __launch_bounds__(VT)
@@ -478,6 +557,23 @@ void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc, int 
 }
 
 template <typename T>
+void launch_ball_part_blk(const cpx<T>* v3, const cpx<T>* z3, const cpx<T>* yt, const int32_t* bperm,
+                          const int32_t* chunks, int nchunks, double* part_d, double* part_res, hipStream_t s) {
+    hipLaunchKernelGGL(k_ball_part_blk<T>, dim3(nchunks), dim3(VT), 0, s, v3, z3, yt, bperm, chunks, part_d,
+                       part_res);
+}
+void launch_ball_fin_blk(const double* part_d, const double* part_res, const int32_t* chunk_off,
+                         const double* eps, int R, double* scale, double* sc, double* hist, int hist_cap,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_ball_fin_blk, dim3(1), dim3(1024), 0, s, part_d, part_res, chunk_off, eps, R, scale, sc,
+                       hist, hist_cap);
+}
+template <typename T>
+void launch_prox_ball_blk(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const int32_t* bid, const double* scale,
+                          int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_prox_ball_blk<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, v3, z3, yt, bid, scale, n);
+}
+template <typename T>
 int launch_sum_part(const cpx<T>* v, int64_t n, double* part_re, double* part_im, hipStream_t s) {
     const int b = red_blocks(n);
     hipLaunchKernelGGL(k_sum<T>, dim3(b), dim3(VT), 0, s, v, n, part_re, part_im);
@@ -521,6 +617,10 @@ int launch_diff2_part(const cpx<T>* a, const cpx<T>* b, int64_t n, double* part_
     template void launch_permute_scale<T>(const cpx<T>*, const int32_t*, double, cpx<T>*, int64_t,       \
                                           hipStream_t);                                                  \
     template void launch_scale_by_slot<T>(cpx<T>*, const cpx<T>*, const double*, int, int64_t, hipStream_t); \
+    template void launch_ball_part_blk<T>(const cpx<T>*, const cpx<T>*, const cpx<T>*, const int32_t*,      \
+                                          const int32_t*, int, double*, double*, hipStream_t);            \
+    template void launch_prox_ball_blk<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const int32_t*, const double*,  \
+                                          int64_t, hipStream_t);                                          \
     template int launch_sum_part<T>(const cpx<T>*, int64_t, double*, double*, hipStream_t);               \
     template int launch_dev2_part<T>(const cpx<T>*, int64_t, const double*, int, int, double*, hipStream_t); \
     template void launch_reweight<T>(const cpx<T>*, int64_t, double, double*, hipStream_t);               \

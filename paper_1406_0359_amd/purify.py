@@ -53,6 +53,8 @@ class SdmmParams(ctypes.Structure):
         ("max_iter", ctypes.c_int32), ("cg_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("halting", ctypes.c_int32), ("nu_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("weights", ctypes.c_void_p), ("history", ctypes.POINTER(ctypes.c_double)),
+        ("nblocks", ctypes.c_int32), ("block_offsets", ctypes.POINTER(ctypes.c_int64)),
+        ("block_eps", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -310,8 +312,22 @@ class Plan:
         return o
 
     def _params(self, epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack,
-                check_every, weights, graph, warm, hist, toeplitz=False):
+                check_every, weights, graph, warm, hist, toeplitz=False, blocks=None):
         p = SdmmParams()
+        if blocks is not None:
+            # visibility blocks (offsets into the uv order, R + 1 of them; eps_i per block);
+            # the arrays stay referenced by the parameter object for the call
+            offs = np.ascontiguousarray(blocks[0], dtype=np.int64)
+            eps_b = np.ascontiguousarray(blocks[1], dtype=np.float64)
+            if offs.size != eps_b.size + 1:
+                raise ValueError("blocks: R + 1 offsets and R bounds")
+            if eps_b.size == 1:          # one block: the plain constraint
+                epsilon = float(eps_b[0])
+            else:
+                p._keep = (offs, eps_b)
+                p.nblocks = eps_b.size
+                p.block_offsets = offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+                p.block_eps = _dptr(eps_b)
         p.epsilon, p.gamma, p.nu, p.xi, p.slack = epsilon, gamma, nu, xi, slack
         p.max_iter, p.cg_iter, p.check_every = max_iter, cg_iter, check_every
         p.halting, p.nu_iter = int(bool(halting)), nu_iter
@@ -338,13 +354,14 @@ class Plan:
              gamma: float = 0.0, nu: float = 0.0, nu_iter: int = 100, halting: bool = False,
              xi: float = 1e-4, slack: float = 1e-3, check_every: int = 10, weights=None,
              record_history: bool = False, graph: bool = True, x0=None, toeplitz: bool = False,
-             out=None) -> SolveResult:
-        """SDMM (Algorithm 1) for eq. (3) with R = 1; returns x_hat and solver info.
-        x0: starting point x_hat(0) (default 0).  toeplitz: CG with the stored normal operator."""
+             blocks=None, out=None) -> SolveResult:
+        """SDMM (Algorithm 1) for eq. (3); returns x_hat and solver info.
+        x0: starting point x_hat(0) (default 0).  toeplitz: CG with the stored normal operator.
+        blocks: (offsets, eps_list) for R >= 2 visibility blocks (eqs. (4)-(5)); epsilon unused."""
         x = self._start(x0, out)
         hist = np.zeros(2 * max_iter) if record_history else None
         p = self._params(epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack, check_every,
-                         weights, graph, x0 is not None, hist, toeplitz)
+                         weights, graph, x0 is not None, hist, toeplitz, blocks)
         info = SdmmInfo()
         _check(self.lib.purify_sdmm_solve(self.handle, self._vec(y, self.M, "y"), ctypes.byref(p),
                                           self._vec(x, self.n * self.n, "x"), ctypes.byref(info),
@@ -359,13 +376,13 @@ class Plan:
                         max_iter: int = 300, cg_iter: int = 10, gamma: float = 0.0, nu: float = 0.0,
                         nu_iter: int = 100, halting: bool = False, xi: float = 1e-4, slack: float = 1e-3,
                         check_every: int = 10, weights=None, graph: bool = True, x0=None,
-                        toeplitz: bool = False, out=None) -> "ReweightResult":
+                        toeplitz: bool = False, blocks=None, out=None) -> "ReweightResult":
         """Reweighted l1 (SARA): solve 0 with `weights` (None: W = I), then up to `reweights`
         weighted solves (purify_sdmm_reweighted)."""
         x = self._start(x0, out)
         w = self.torch.empty(self.D, dtype=self.torch.float64, device=self.device)
         p = self._params(epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack, check_every,
-                         weights, graph, x0 is not None, None, toeplitz)
+                         weights, graph, x0 is not None, None, toeplitz, blocks)
         rw = ReweightParams()
         rw.delta0, rw.decay, rw.delta_min, rw.rel_var, rw.reweights = delta0, decay, delta_min, rel_var, reweights
         info, rinfo = SdmmInfo(), ReweightInfo()
