@@ -30,6 +30,7 @@ from typing import Callable, List, Optional
 import numpy as np
 
 from .prox import project_l2_ball, project_l2_balls, project_positive, soft_threshold
+from .tv import grad, prox_tv, tv_norm
 
 
 def operator_norm(normal: Callable[[np.ndarray], np.ndarray], shape, iters: int = 100):
@@ -78,7 +79,7 @@ class SdmmResult:
 def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
          cg_iters: int = 10, gamma: Optional[float] = None, nu: Optional[float] = None,
          weights=None, halting: bool = False, xi: float = 1e-4, slack: float = 1e-3,
-         nu_iters: int = 100, x0=None, normal=None, blocks=None) -> SdmmResult:
+         nu_iters: int = 100, x0=None, normal=None, blocks=None, tv_iters=None) -> SdmmResult:
     """Run SDMM (Algorithm 1, R = 1, S = 3) and return x_hat (complex; the image is Re).
     normal: a stored form of Phi^dagger Phi for the global update's conjugate-gradient
     operator (Section 3), e.g. the Toeplitz operator of oracle.toeplitz; None applies Phi
@@ -87,7 +88,10 @@ def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
     [offsets[i], offsets[i + 1]) with bound eps_list[i] (eqs. (4)-(5), S = R + 2 functions);
     `epsilon` is then unused.  Since Phi^dagger of the stacked vector is sum_i Phi_i^dagger,
     the R data branches together are one projection onto the product of balls followed by one
-    Phi^dagger; halting asks every block's residual to be within its bound."""
+    Phi^dagger; halting asks every block's residual to be within its bound.
+    tv_iters: f1 = the (weighted) total variation with L1 = I instead of the l1 term
+    (oracle.tv: prox by that many dual projection steps; weights per pixel; objective TV(x_hat);
+    default gamma 1e-3 max |grad Phi~^dagger y~|).  psi and psi_adj are then unused."""
     if nu is None or nu <= 0:
         nu, _ = operator_norm(lambda v: phi_adj(phi(v)), shape, nu_iters)
     yt = np.asarray(y, dtype=np.complex128) / nu
@@ -98,18 +102,22 @@ def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
     P = lambda v: phi(v) / nu
     Pt = lambda v: phi_adj(v) / nu
     if gamma is None or gamma <= 0:
-        gamma = 1e-3 * float(np.max(np.abs(psi_adj(Pt(yt)))))
+        if tv_iters is None:
+            gamma = 1e-3 * float(np.max(np.abs(psi_adj(Pt(yt)))))
+        else:
+            g1, g2 = grad(Pt(yt))
+            gamma = 1e-3 * float(np.max(np.sqrt(np.abs(g1) ** 2 + np.abs(g2) ** 2)))
     if normal is None:
         A = lambda v: Pt(P(v)) + 2.0 * v
     else:
         A = lambda v: normal(v) / (nu * nu) + 2.0 * v
 
     xh = np.zeros(shape, dtype=np.complex128) if x0 is None else np.array(x0, np.complex128)
-    v1 = psi_adj(xh)
+    v1 = psi_adj(xh) if tv_iters is None else xh.copy()
     z1 = np.zeros_like(v1, dtype=np.complex128)
     z2 = np.zeros(shape, dtype=np.complex128)
     z3 = np.zeros(yt.shape, dtype=np.complex128)
-    x1 = psi(v1).astype(np.complex128)          # L_i^dagger L_i x_hat(0)
+    x1 = (psi(v1) if tv_iters is None else v1).astype(np.complex128)   # L_1^dagger L_1 x_hat(0)
     x2 = xh.copy()
     x3 = Pt(P(xh))
     w = 1.0 if weights is None else np.asarray(weights, dtype=np.float64).reshape(v1.shape)
@@ -118,12 +126,19 @@ def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
     f_prev = None
     for t in range(1, iters + 1):
         xh = conjugate_gradient(A, x1 + x2 + x3, xh, cg_iters)
-        # i = 1: l1 term on Psi^dagger x
-        v1 = psi_adj(xh)
-        u = v1 + z1
-        r1 = soft_threshold(u, gamma * w)
-        z1 = u - r1
-        x1 = psi(r1 - z1)
+        if tv_iters is None:
+            # i = 1: l1 term on Psi^dagger x
+            v1 = psi_adj(xh)
+            u = v1 + z1
+            r1 = soft_threshold(u, gamma * w)
+            z1 = u - r1
+            x1 = psi(r1 - z1)
+        else:
+            # i = 1: total variation on x (L1 = I)
+            u = xh + z1
+            r1 = prox_tv(u, gamma, tv_iters, None if weights is None else w)
+            z1 = u - r1
+            x1 = r1 - z1
         # i = 2: positivity
         u = xh + z2
         r2 = project_positive(u)
@@ -136,7 +151,7 @@ def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
         z3 = u - r3
         x3 = Pt(r3 - z3)
 
-        f = float(np.sum(w * np.abs(v1)))
+        f = float(np.sum(w * np.abs(v1))) if tv_iters is None else tv_norm(xh, None if weights is None else w)
         resid = float(np.linalg.norm(yt - v3))
         res.objective.append(f)
         res.residual.append(resid)
