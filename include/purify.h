@@ -114,6 +114,14 @@ purify_status purify_psi_adj(const purify_plan* plan, const void* x, void* alpha
  * NUFFT's Phi^dagger Phi by the NUFFT's own error; nu, the proximity steps and the
  * data-fidelity branch still apply Phi and Phi^dagger. */
 #define PURIFY_SDMM_TOEPLITZ 4
+/* purify_sdmm_params.flags: the prior is the total variation of the image (the TV problem of
+ * Section 5: minimise sum_ij w_ij |(grad x)_ij| subject to the data constraint(s) and x >= 0)
+ * instead of ||W Psi^dagger x||_1.  f1 = TV with L1 = I, so the global update is unchanged;
+ * its proximity operator runs tv_iter steps of Chambolle's dual projection algorithm (step
+ * 1/8, from a zero dual field; forward differences, zero on the last row and column).
+ * weights, if given, are N per-pixel doubles; the default gamma is
+ * 1e-3 max_ij |(grad Phi~^dagger y~)_ij|; the objective is TV_w(x_hat). */
+#define PURIFY_SDMM_TV 8
 
 typedef struct {
     double epsilon;       /* l2 bound of eq. (2) on ||y - Phi x||, unnormalised units */
@@ -127,7 +135,8 @@ typedef struct {
     int32_t halting;      /* 0: run exactly max_iter iterations; 1: Section 3 stopping rule */
     int32_t nu_iter;      /* power-iteration count when nu <= 0 (e.g. 100) */
     int32_t flags;        /* PURIFY_SDMM_* bits; 0 = defaults */
-    const double* weights; /* device, D doubles (diagonal W of eq. (3)), or NULL for W = I */
+    const double* weights; /* device, D doubles (diagonal W of eq. (3)), or NULL for W = I;
+                              N doubles (per-pixel TV weights) with PURIFY_SDMM_TV */
     double* history;      /* host, 2 * max_iter doubles or NULL: per iteration the objective
                              ||W Psi^dag x_hat||_1 and the residual ||y~ - Phi~ x_hat|| */
     int32_t nblocks;      /* R: 0 or 1 = one data constraint with `epsilon`; 2..1024 = the data
@@ -137,6 +146,7 @@ typedef struct {
                              [off[i], off[i+1]) of the caller's uv order; off[0] = 0, off[R] = M,
                              strictly increasing */
     const double* block_eps;       /* host, R (R >= 2): eps_i >= 0, unnormalised */
+    int32_t tv_iter;      /* PURIFY_SDMM_TV: dual projection steps per proximity operator, >= 1 */
 } purify_sdmm_params;
 
 typedef struct {
@@ -206,6 +216,8 @@ typedef struct {
  * (purify_plan_dict_size), overwritten with each solve's weights (may be params->weights);
  * may be NULL when rw->reweights = 0.  x_io: device, N complex; x(0) on entry when
  * PURIFY_SDMM_WARM_START is set; receives the last solution.  info: the last solve's.
+ * With PURIFY_SDMM_TV (reweighted TV) the coefficients are the gradient magnitudes
+ * |(grad x)_ij| and weights holds N doubles.
  * Synchronous, one call per plan at a time. */
 purify_status purify_sdmm_reweighted(purify_plan* plan, const void* y, const purify_sdmm_params* params,
                                      const purify_reweight_params* rw, double* weights, void* x_io,

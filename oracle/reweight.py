@@ -18,7 +18,9 @@ these readings, shared with the GPU library:
   visibility blocks, the largest of the blocks' sigma_i = eps_i / sqrt(M_i + 2 sqrt(M_i)));
 * solve k >= 1 is SDMM warm started from x^(k-1), with the nu and gamma of solve 0;
 * stop after solve k when ||x^(k) - x^(k-1)|| / ||x^(k-1)|| < rel_var (0 when both are zero,
-  infinite when only x^(k-1) is), or when k = reweights.
+  infinite when only x^(k-1) is), or when k = reweights;
+* reweighted TV (RWTV, Section 5): the same loop with the TV prior, the coefficients being the
+  gradient magnitudes |(grad x)_ij| and the weights per pixel.
 """
 import math
 from dataclasses import dataclass, field
@@ -27,6 +29,7 @@ from typing import List, Optional
 import numpy as np
 
 from .sdmm import SdmmResult, sdmm
+from .tv import grad
 
 
 def reweight(alpha: np.ndarray, delta: float) -> np.ndarray:
@@ -77,8 +80,15 @@ def reweighted_sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, reweights: in
         floor = max(noise_floor(e, offs[i + 1] - offs[i], r0.nu) for i, e in enumerate(eps_b))
     else:
         floor = noise_floor(epsilon, np.size(y), r0.nu)
+    if sdmm_kwargs.get("tv_iters") is not None:
+        # reweighted TV: the coefficients are the gradient magnitudes |(grad x)_ij|
+        def coefficients(v):
+            g1, g2 = grad(v)
+            return np.sqrt(np.abs(g1) ** 2 + np.abs(g2) ** 2).astype(np.complex128)
+    else:
+        coefficients = psi_adj
     x = r0.x
-    alpha = psi_adj(x)
+    alpha = coefficients(x)
     delta = float(np.std(alpha)) if delta0 is None or delta0 <= 0 else delta0
     delta = max(delta, floor)
     for _ in range(reweights):
@@ -93,6 +103,6 @@ def reweighted_sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, reweights: in
         if rv < rel_var:
             break
         delta = max(decay * delta, floor)
-        alpha = psi_adj(x)
+        alpha = coefficients(x)
     out.x = x
     return out

@@ -129,6 +129,7 @@ struct Sdmm {
     double inv_nu = 1, inv_nu2 = 1, eps_t = 0, gamma = 0;
     bool toep = false;   // CG operator from the stored normal operator (PURIFY_SDMM_TOEPLITZ)
     int nblk = 0, nchunks = 0;   // visibility blocks (R >= 2) and their reduction chunks
+    bool tv = false;             // f1 = total variation with L1 = I (PURIFY_SDMM_TV)
 
     double* part(int k) const { return part_buf(P, k); }
 
@@ -179,10 +180,16 @@ struct Sdmm {
         // i = 1 (on s2): l1 prior on Psi^dag x_hat
         (void)hipEventRecord(fork, s);
         (void)hipStreamWaitEvent(s2, fork, 0);
-        launch_psi_adj<T>(P, xh, v1, s2);
-        const int nb1 = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part(3), s2);
-        launch_finalize(part(3), nb1, sc, SL_OBJ, FIN_HIST_OBJ, 0, P.hist, P.hist_cap, s2);
-        launch_psi<T>(P, v1, x1, s2);
+        if (tv) {   // TV prior: prox on u = x_hat + z1 (in v1), x1 = r1 - z1
+            int nb1 = 0;
+            launch_tv_prox<T>(P, xh, z1, x1, v1, prm->weights, gamma, prm->tv_iter, part(3), &nb1, s2);
+            launch_finalize(part(3), nb1, sc, SL_OBJ, FIN_HIST_OBJ, 0, P.hist, P.hist_cap, s2);
+        } else {
+            launch_psi_adj<T>(P, xh, v1, s2);
+            const int nb1 = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part(3), s2);
+            launch_finalize(part(3), nb1, sc, SL_OBJ, FIN_HIST_OBJ, 0, P.hist, P.hist_cap, s2);
+            launch_psi<T>(P, v1, x1, s2);
+        }
         (void)hipEventRecord(join, s2);
         // i = 2: positivity
         launch_prox_pos<T>(xh, z2, x2, N, s);
@@ -260,8 +267,9 @@ purify_status setup_blocks(const Plan& P, const purify_sdmm_params* prm, double 
     return PURIFY_OK;
 }
 
-// Check the block description of a solve (R <= 1 needs nothing).
+// Check the block description of a solve (R <= 1 needs nothing) and the TV step count.
 bool blocks_valid(const purify_sdmm_params* prm, int64_t M) {
+    if ((prm->flags & PURIFY_SDMM_TV) && prm->tv_iter < 1) return false;
     if (prm->nblocks <= 1) return true;
     if (prm->nblocks > MAX_BLOCKS || !prm->block_offsets || !prm->block_eps) return false;
     const int64_t* off = prm->block_offsets;
@@ -302,6 +310,7 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     PURIFY_HIP(hipEventRecord(R.done, s));
     PURIFY_HIP(hipStreamWaitEvent(cs, R.done, 0));
     S.toep = (prm->flags & PURIFY_SDMM_TOEPLITZ) != 0;
+    S.tv = (prm->flags & PURIFY_SDMM_TV) != 0;
     if (S.toep) {
         const purify_status st = ensure_chat<T>(P, cs);
         if (st != PURIFY_OK) return st;
@@ -343,12 +352,17 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     // y~ = y / nu in solver (tile-sorted) order
     launch_permute_scale<T>((const C*)y_user, P.perm, S.inv_nu, (C*)P.ytil, M, cs);
 
-    // gamma = 1e-3 max |Psi^dag Phi~^dag y~| unless given
+    // gamma = 1e-3 max |Psi^dag Phi~^dag y~| (TV prior: max |grad Phi~^dag y~|) unless given
     double gamma = prm->gamma;
     if (!(gamma > 0)) {
         opc.phi_adj((const C*)P.ytil, nullptr, (C*)P.p, S.inv_nu, nullptr, 0.0, nullptr);
-        launch_psi_adj<T>(P, (const C*)P.p, (C*)P.v1, cs);
-        const int nb = launch_maxabs_part<T>((const C*)P.v1, D, part_buf(P, 7), cs);
+        int nb = 0;
+        if (S.tv) {
+            nb = launch_grad_mag<T>(P, (const C*)P.p, nullptr, part_buf(P, 7), cs);
+        } else {
+            launch_psi_adj<T>(P, (const C*)P.p, (C*)P.v1, cs);
+            nb = launch_maxabs_part<T>((const C*)P.v1, D, part_buf(P, 7), cs);
+        }
         launch_finalize(part_buf(P, 7), nb, sc, SL_MAXABS, FIN_MAX, 0, nullptr, 0, cs);
         double mx = 0;
         PURIFY_HIP(hipMemcpyAsync(&mx, sc + SL_MAXABS, sizeof(double), hipMemcpyDeviceToHost, cs));
@@ -362,8 +376,12 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     // x_hat(0) = 0 every x_i is 0, else x1 = Psi Psi^dag x_hat, x2 = x_hat, x3 = Phi~^dag Phi~ x_hat.
     if (x_in) {
         PURIFY_HIP(hipMemcpyAsync(P.xh, x_in, (size_t)N * sizeof(C), hipMemcpyDeviceToDevice, cs));
-        launch_psi_adj<T>(P, (const C*)P.xh, (C*)P.v1, cs);
-        launch_psi<T>(P, (const C*)P.v1, (C*)P.x1, cs);
+        if (S.tv) {   // L1 = I
+            PURIFY_HIP(hipMemcpyAsync(P.x1, P.xh, (size_t)N * sizeof(C), hipMemcpyDeviceToDevice, cs));
+        } else {
+            launch_psi_adj<T>(P, (const C*)P.xh, (C*)P.v1, cs);
+            launch_psi<T>(P, (const C*)P.v1, (C*)P.x1, cs);
+        }
         PURIFY_HIP(hipMemcpyAsync(P.x2, P.xh, (size_t)N * sizeof(C), hipMemcpyDeviceToDevice, cs));
         launch_fft_rows_fwd<T>(P, (const C*)P.xh, (C*)P.tmp, cs);
         opc.normal_tail(nullptr, (C*)P.x3, S.inv_nu2, 0.0, nullptr);
@@ -445,7 +463,7 @@ purify_status reweighted_impl(Plan& P, const void* y, const purify_sdmm_params* 
                               const purify_reweight_params* rw, double* weights, void* x_io,
                               purify_sdmm_info* info, purify_reweight_info* rinfo, hipStream_t s) {
     using C = cpx<T>;
-    const int64_t N = P.N, D = P.D, M = P.M;
+    const int64_t N = P.N, M = P.M;
     purify_sdmm_info inf{};
     purify_reweight_info out{};
     out.solves = 1;
@@ -470,7 +488,14 @@ purify_status reweighted_impl(Plan& P, const void* y, const purify_sdmm_params* 
         }
         const double floor = rw->delta_min >= 0 ? rw->delta_min : sigma / inf.nu;
         double* sc = P.sc;
-        launch_psi_adj<T>(P, (const C*)x_io, (C*)P.v1, s);
+        // coefficients: Psi^dag x, or |grad x| for the TV prior (N of them)
+        const bool tv = (prm->flags & PURIFY_SDMM_TV) != 0;
+        const int64_t D = tv ? N : P.D;
+        auto coefficients = [&]() {
+            if (tv) launch_grad_mag<T>(P, (const C*)x_io, (C*)P.v1, nullptr, s);
+            else launch_psi_adj<T>(P, (const C*)x_io, (C*)P.v1, s);
+        };
+        coefficients();
         double delta = rw->delta0;
         if (!(delta > 0)) {   // standard deviation of the coefficients, two passes
             const int nb = launch_sum_part<T>((const C*)P.v1, D, part_buf(P, 0), part_buf(P, 1), s);
@@ -505,7 +530,7 @@ purify_status reweighted_impl(Plan& P, const void* y, const purify_sdmm_params* 
             out.rel_var = rv;
             if (rv < rw->rel_var) break;
             delta = std::max(rw->decay * delta, floor);
-            launch_psi_adj<T>(P, (const C*)x_io, (C*)P.v1, s);
+            coefficients();
         }
     }
     if (info) *info = inf;
@@ -699,7 +724,8 @@ purify_status purify_sdmm_solve(purify_plan* plan, const void* y, const purify_s
     }
     Plan& P = plan->P;
     if (!blocks_valid(params, P.M)) {
-        set_error("invalid visibility blocks (2 <= R <= 1024, offsets 0 .. M strictly increasing, eps_i >= 0)");
+        set_error("invalid visibility blocks (2 <= R <= 1024, offsets 0 .. M strictly increasing, eps_i >= 0) "
+                  "or TV step count (tv_iter >= 1)");
         return PURIFY_E_INVALID;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -730,7 +756,8 @@ purify_status purify_sdmm_reweighted(purify_plan* plan, const void* y, const pur
     }
     Plan& P = plan->P;
     if (!blocks_valid(params, P.M)) {
-        set_error("invalid visibility blocks (2 <= R <= 1024, offsets 0 .. M strictly increasing, eps_i >= 0)");
+        set_error("invalid visibility blocks (2 <= R <= 1024, offsets 0 .. M strictly increasing, eps_i >= 0) "
+                  "or TV step count (tv_iter >= 1)");
         return PURIFY_E_INVALID;
     }
     hipStream_t s = (hipStream_t)stream;

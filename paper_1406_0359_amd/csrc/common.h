@@ -151,6 +151,7 @@ struct Plan {
     void *wt = nullptr;          // wavelet temp: nwav * N complex
     void *ws2 = nullptr;         // wavelet LL temp: nwav * N/4 complex (x2 ping-pong)
     void *vis = nullptr;         // M complex scratch (visibility-space temp)
+    void *tvp = nullptr;         // TV prior: two dual fields (p1, p2) of N complex, ping-pong
     // visibility blocks of the current solve (R > 1)
     int32_t* bid = nullptr;      // M: block of each sorted visibility
     int32_t* bperm = nullptr;    // M: sorted positions grouped by block (ascending within a block)
@@ -256,6 +257,14 @@ void launch_ball_fin_blk(const double* part_d, const double* part_res, const int
                          hipStream_t s);
 template <typename T> void launch_prox_ball_blk(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const int32_t* bid,
                                                 const double* scale, int64_t n, hipStream_t s);
+// TV prior, branch i = 1: u = x_hat + z1 (into u), `iters` dual projection steps, then
+// r1 = u - gamma div p, z1 = u - r1, x1 = r1 - z1, objective partials TV_w(x_hat) (count in *nparts)
+template <typename T> void launch_tv_prox(const Plan& P, const cpx<T>* xh, cpx<T>* z1, cpx<T>* x1, cpx<T>* u,
+                                          const double* w, double gamma, int iters, double* part, int* nparts,
+                                          hipStream_t s);
+// |grad v| (into out's real parts, if out) and partial maxima (if part_max); returns the count
+template <typename T> int launch_grad_mag(const Plan& P, const cpx<T>* v, cpx<T>* out, double* part_max,
+                                          hipStream_t s);
 // Reweighting (SARA): partials of sum Re v and sum Im v
 template <typename T> int launch_sum_part(const cpx<T>* v, int64_t n, double* part_re, double* part_im,
                                           hipStream_t s);

@@ -315,6 +315,7 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
     P.z3 = carve(M * ce);
     P.v3 = carve(M * ce);
     P.vis = carve(M * ce);
+    P.tvp = carve(4 * N * ce);
     P.bid = (int32_t*)carve(M * 4);
     P.bperm = (int32_t*)carve(M * 4);
     P.bchunk = (int32_t*)carve((size_t)BLK_CHUNKS * 2 * 4);

@@ -22,6 +22,7 @@ DICT_SARA = 0x1FF
 SDMM_NO_GRAPH = 1
 SDMM_WARM_START = 2
 SDMM_TOEPLITZ = 4
+SDMM_TV = 8
 NORMAL_TOEPLITZ = 1
 
 STAGES = {
@@ -54,7 +55,7 @@ class SdmmParams(ctypes.Structure):
         ("halting", ctypes.c_int32), ("nu_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("weights", ctypes.c_void_p), ("history", ctypes.POINTER(ctypes.c_double)),
         ("nblocks", ctypes.c_int32), ("block_offsets", ctypes.POINTER(ctypes.c_int64)),
-        ("block_eps", ctypes.POINTER(ctypes.c_double)),
+        ("block_eps", ctypes.POINTER(ctypes.c_double)), ("tv_iter", ctypes.c_int32),
     ]
 
 
@@ -312,8 +313,10 @@ class Plan:
         return o
 
     def _params(self, epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack,
-                check_every, weights, graph, warm, hist, toeplitz=False, blocks=None):
+                check_every, weights, graph, warm, hist, toeplitz=False, blocks=None, tv_iter=None):
         p = SdmmParams()
+        if tv_iter is not None:
+            p.tv_iter = int(tv_iter)
         if blocks is not None:
             # visibility blocks (offsets into the uv order, R + 1 of them; eps_i per block);
             # the arrays stay referenced by the parameter object for the call
@@ -332,16 +335,16 @@ class Plan:
         p.max_iter, p.cg_iter, p.check_every = max_iter, cg_iter, check_every
         p.halting, p.nu_iter = int(bool(halting)), nu_iter
         p.flags = ((0 if graph else SDMM_NO_GRAPH) | (SDMM_WARM_START if warm else 0)
-                   | (SDMM_TOEPLITZ if toeplitz else 0))
+                   | (SDMM_TOEPLITZ if toeplitz else 0) | (SDMM_TV if tv_iter is not None else 0))
         if weights is not None:
-            p.weights = self._weights(weights)
+            p.weights = self._weights(weights, self.n * self.n if tv_iter is not None else self.D)
         p.history = _dptr(hist) if hist is not None else None
         return p
 
-    def _weights(self, w):
-        if (not isinstance(w, self.torch.Tensor) or w.dtype != self.torch.float64 or w.numel() != self.D
+    def _weights(self, w, count):
+        if (not isinstance(w, self.torch.Tensor) or w.dtype != self.torch.float64 or w.numel() != count
                 or w.device != self.device or not w.is_contiguous()):
-            raise ValueError("weights must be a contiguous float64 device tensor of size D")
+            raise ValueError(f"weights must be a contiguous float64 device tensor of {count} elements")
         return w.data_ptr()
 
     def _start(self, x0, out):
@@ -354,14 +357,16 @@ class Plan:
              gamma: float = 0.0, nu: float = 0.0, nu_iter: int = 100, halting: bool = False,
              xi: float = 1e-4, slack: float = 1e-3, check_every: int = 10, weights=None,
              record_history: bool = False, graph: bool = True, x0=None, toeplitz: bool = False,
-             blocks=None, out=None) -> SolveResult:
+             blocks=None, tv_iter=None, out=None) -> SolveResult:
         """SDMM (Algorithm 1) for eq. (3); returns x_hat and solver info.
         x0: starting point x_hat(0) (default 0).  toeplitz: CG with the stored normal operator.
-        blocks: (offsets, eps_list) for R >= 2 visibility blocks (eqs. (4)-(5)); epsilon unused."""
+        blocks: (offsets, eps_list) for R >= 2 visibility blocks (eqs. (4)-(5)); epsilon unused.
+        tv_iter: TV prior (Section 5) with that many dual projection steps per prox; weights are
+        then per pixel."""
         x = self._start(x0, out)
         hist = np.zeros(2 * max_iter) if record_history else None
         p = self._params(epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack, check_every,
-                         weights, graph, x0 is not None, hist, toeplitz, blocks)
+                         weights, graph, x0 is not None, hist, toeplitz, blocks, tv_iter)
         info = SdmmInfo()
         _check(self.lib.purify_sdmm_solve(self.handle, self._vec(y, self.M, "y"), ctypes.byref(p),
                                           self._vec(x, self.n * self.n, "x"), ctypes.byref(info),
@@ -376,13 +381,14 @@ class Plan:
                         max_iter: int = 300, cg_iter: int = 10, gamma: float = 0.0, nu: float = 0.0,
                         nu_iter: int = 100, halting: bool = False, xi: float = 1e-4, slack: float = 1e-3,
                         check_every: int = 10, weights=None, graph: bool = True, x0=None,
-                        toeplitz: bool = False, blocks=None, out=None) -> "ReweightResult":
+                        toeplitz: bool = False, blocks=None, tv_iter=None, out=None) -> "ReweightResult":
         """Reweighted l1 (SARA): solve 0 with `weights` (None: W = I), then up to `reweights`
         weighted solves (purify_sdmm_reweighted)."""
         x = self._start(x0, out)
-        w = self.torch.empty(self.D, dtype=self.torch.float64, device=self.device)
+        count = self.n * self.n if tv_iter is not None else self.D
+        w = self.torch.empty(count, dtype=self.torch.float64, device=self.device)
         p = self._params(epsilon, max_iter, cg_iter, gamma, nu, nu_iter, halting, xi, slack, check_every,
-                         weights, graph, x0 is not None, None, toeplitz, blocks)
+                         weights, graph, x0 is not None, None, toeplitz, blocks, tv_iter)
         rw = ReweightParams()
         rw.delta0, rw.decay, rw.delta_min, rw.rel_var, rw.reweights = delta0, decay, delta_min, rel_var, reweights
         info, rinfo = SdmmInfo(), ReweightInfo()

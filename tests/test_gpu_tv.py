@@ -1,0 +1,76 @@
+"""TV prior (the TV and RWTV problems of Section 5) on the GPU against the FP64 oracle,
+through the C ABI (PURIFY_SDMM_TV, purify_sdmm_reweighted).
+
+Both sides run the same fixed number of Chambolle dual projection steps per prox, so the FP64
+iterates must follow the oracle's to 1e-9 (the plain SDMM parity bound); graph replay and
+eager launches agree bit for bit; the FP32 form is held to the SNR target."""
+import numpy as np
+import pytest
+
+from gpu_cases import DEV, rel_l2, to_np
+from oracle.nufft import Nufft
+from oracle.reweight import reweighted_sdmm
+from oracle.sdmm import sdmm
+from paper_1406_0359_amd import synth
+
+torch = pytest.importorskip("torch")
+from paper_1406_0359_amd import purify  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(n=64, M=2048):
+    w = synth.WORKLOADS["small64"]
+    p = synth.make_problem(w, lambda x, uv: Nufft(x.shape[0], uv, w.J).phi(x), M=M, n=n)
+    return w, p, Nufft(n, p.uv, w.J)
+
+
+def _hist_rel(h, ref):
+    ref = np.asarray(ref, dtype=float)
+    d = np.abs(np.asarray(h) - ref)
+    return float(np.max(np.where(ref == 0, d, d / np.where(ref == 0, 1.0, np.abs(ref)))))
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_tv_sdmm_matches_oracle_fp64(weighted):
+    w, p, op = _problem()
+    wt = np.random.default_rng(3).uniform(0.5, 1.5, (64, 64)) if weighted else None
+    ref = sdmm(op.phi, op.phi_adj, None, None, p.y, p.epsilon, (64, 64), iters=40, tv_iters=30, weights=wt)
+    plan = purify.Plan(64, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels, device=DEV)
+    wd = torch.as_tensor(wt.ravel(), device=DEV) if weighted else None
+    res = plan.sdmm(plan.as_vec(p.y), p.epsilon, max_iter=40, tv_iter=30, weights=wd, record_history=True)
+    assert abs(res.gamma / ref.gamma - 1) < 1e-12
+    assert rel_l2(to_np(res.x), ref.x) < 1e-9
+    assert _hist_rel(res.history[:, 0], ref.objective) < 1e-9
+    assert _hist_rel(res.history[:, 1], ref.residual) < 1e-9
+
+
+def test_tv_graph_equals_eager_and_bad_step_count():
+    w, p, op = _problem()
+    plan = purify.Plan(64, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels, device=DEV)
+    y = plan.as_vec(p.y)
+    a = plan.sdmm(y, p.epsilon, max_iter=15, tv_iter=7)
+    b = plan.sdmm(y, p.epsilon, max_iter=15, tv_iter=7, graph=False)
+    assert torch.equal(a.x, b.x)
+    with pytest.raises(purify.PurifyError):
+        plan.sdmm(y, p.epsilon, max_iter=2, tv_iter=0)
+
+
+def test_reweighted_tv_matches_oracle_fp64():
+    w, p, op = _problem()
+    ref = reweighted_sdmm(op.phi, op.phi_adj, None, None, p.y, p.epsilon, (64, 64), reweights=2, rel_var=0.0,
+                          iters=30, tv_iters=20)
+    plan = purify.Plan(64, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels, device=DEV)
+    res = plan.sdmm_reweighted(plan.as_vec(p.y), p.epsilon, reweights=2, rel_var=0.0, max_iter=30, tv_iter=20)
+    assert res.solves == 3
+    assert abs(res.delta / ref.deltas[-1] - 1) < 1e-9
+    assert rel_l2(to_np(res.weights), np.ravel(ref.weights)) < 1e-9
+    assert rel_l2(to_np(res.x), ref.x) < 1e-9
+
+
+def test_tv_fp32_snr_within_005db_of_fp64_oracle():
+    w, p, op = _problem()
+    ref = sdmm(op.phi, op.phi_adj, None, None, p.y, p.epsilon, (64, 64), iters=150, tv_iters=30)
+    plan = purify.Plan(64, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels, precision="fp32", device=DEV)
+    res = plan.sdmm(plan.as_vec(p.y), p.epsilon, max_iter=150, tv_iter=30)
+    assert abs(synth.snr_db(p.x_true, to_np(res.x)) - synth.snr_db(p.x_true, ref.x)) < 0.05

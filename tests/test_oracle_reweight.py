@@ -100,3 +100,15 @@ def test_stops_when_relative_variation_is_small():
     floor = noise_floor(eps, y.size, full.solves[0].nu)
     d0 = max(float(np.std(sa.psi_adj(full.solves[0].x))), floor)
     assert full.deltas == [d0, max(0.5 * d0, floor), max(0.25 * d0, floor)]
+
+
+def test_reweighted_tv_huge_delta_reduces_to_warm_tv_solve():
+    op, sa, x, y, eps, _ = _tiny_problem(seed=9)
+    kw = dict(iters=30, tv_iters=20)
+    r = reweighted_sdmm(op.phi, op.phi_adj, None, None, y, eps, (8, 8), reweights=1, delta0=1e300,
+                        decay=1.0, rel_var=0.0, **kw)
+    r0 = sdmm(op.phi, op.phi_adj, None, None, y, eps, (8, 8), **kw)
+    r1 = sdmm(op.phi, op.phi_adj, None, None, y, eps, (8, 8), x0=r0.x, nu=r0.nu, gamma=r0.gamma,
+              weights=np.ones((8, 8)), **kw)
+    assert np.all(r.weights == 1.0) and r.weights.shape == (8, 8)
+    assert np.array_equal(r.x, r1.x)
