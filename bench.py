@@ -15,9 +15,10 @@ Also reported:
   Phi / Phi^dagger Gvis/s, Psi / Psi^dagger GB/s and SDMM iterations per second; the
   4096 x 4096 single solve (M = 10^7, J = 8, 5 levels, FP32); the serving form (FP32
   server on a Poisson stream of mixed-size requests against the FP64 one-at-a-time solves);
-  and, at 256^2 and 1024^2, the same solve with the stored (Toeplitz) normal operator in
-  CG (Section 3's precomputed composite operator): its iteration rate, stage times and its
-  image against the exact solve's.
+  at 256^2 and 1024^2, the same solve with the stored (Toeplitz) normal operator in CG
+  (Section 3's precomputed composite operator): its iteration rate, stage times and its
+  image against the exact solve's; and at 256^2 the paper's other methods (reweighted l1,
+  visibility blocks, TV and reweighted TV): iteration rates and SNR.
 """
 from __future__ import annotations
 
@@ -56,6 +57,8 @@ def stage_bytes(plan, stage: str) -> float:
         # stored normal operator: column stage reads n x K and the real K x K spectrum, writes
         # n x K; the whole operator adds a row pass each way
         "toep_cols": 2 * N * c + 4 * N * (c // 2) + 2 * N * c,
+        # TV prox step: read both dual fields and u, write both dual fields
+        "tv_step": 5 * N * c,
     }
     tbl["toep_normal"] = (N * c + 2 * N * c) + tbl["toep_cols"] + (2 * N * c + N * c)
     tbl["phi"] = tbl["fft_rows"] + tbl["fft_cols"] + tbl["degrid"]
@@ -180,6 +183,41 @@ def toeplitz_form(torch, plan, y, eps, nu, iters, cg, x_true, synth, x_exact) ->
     out["snr_db"] = synth.snr_db(x_true, xt)
     out["snr_db_exact"] = synth.snr_db(x_true, x_exact)
     out["rel_diff_vs_exact"] = float(np.linalg.norm(xt - x_exact) / np.linalg.norm(x_exact))
+    return out
+
+
+def method_variants(torch, plan, y, eps, nu, iters, x_true, synth, snr_plain, uv_count) -> dict:
+    """The paper's other methods on the same 256^2 FP64 plan and data: reweighted l1 (SARA,
+    three weighted solves after BPSA), four visibility blocks with per-block bounds, and the
+    TV prior (plain and reweighted).  Iterations per second and the SNR of each."""
+    def run(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+    out = {"snr_db_bpsa": snr_plain}
+    dt, r = run(lambda: plan.sdmm_reweighted(y, eps, reweights=3, rel_var=0.0, max_iter=iters, nu=nu))
+    out["sara_reweighted"] = {"solves": r.solves, "iterations": r.total_iterations,
+                              "iters_s": r.total_iterations / dt, "snr_db": synth.snr_db(x_true, r.x.cpu().numpy())}
+    R = 4
+    offs = [uv_count * i // R for i in range(R + 1)]
+    sigma = eps / math.sqrt(uv_count + 2 * math.sqrt(uv_count))
+    beps = [synth.chi2_epsilon(sigma, offs[i + 1] - offs[i]) for i in range(R)]
+    dt, r = run(lambda: plan.sdmm(y, 0.0, max_iter=iters, nu=nu, blocks=(offs, beps)))
+    out["blocks_R4"] = {"iters_s_incl_block_tables": iters / dt, "snr_db": synth.snr_db(x_true, r.x.cpu().numpy())}
+    tv_iter = 50
+    dt, r = run(lambda: plan.sdmm(y, eps, max_iter=iters, nu=nu, tv_iter=tv_iter))
+    out["tv"] = {"tv_iter": tv_iter, "iters_s": iters / dt, "snr_db": synth.snr_db(x_true, r.x.cpu().numpy())}
+    plan.time_stage("tv_step", 3)
+    ms = plan.time_stage("tv_step", 50)
+    b = stage_bytes(plan, "tv_step")
+    out["tv"]["tv_step"] = {"ms": ms, "bytes": b, "GBs": b / (ms * 1e-3) / 1e9,
+                            "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    dt, r = run(lambda: plan.sdmm_reweighted(y, eps, reweights=2, rel_var=0.0, max_iter=iters, nu=nu,
+                                             tv_iter=tv_iter))
+    out["rwtv"] = {"solves": r.solves, "iters_s": r.total_iterations / dt,
+                   "snr_db": synth.snr_db(x_true, r.x.cpu().numpy())}
     return out
 
 
@@ -324,6 +362,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=30,
                     help="requests in the serving-form stream (0: skip; 512 is the full stream)")
     ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the reweighted, visibility-block and TV solves")
     ap.add_argument("--kernel-only", default="", metavar="STAGE",
                     help="only time one stage of the 256x256 FP64 plan on real data (no solve, no "
                          "graphs; for hardware-counter runs) and print its line")
@@ -414,6 +454,12 @@ def main():
                                                  p.x_true, synth, res.x.cpu().numpy())
     except Exception as e:  # report, do not hide the main line
         also["sara256_toeplitz_error"] = repr(e)
+    if not args.no_variants:
+        try:
+            also["sara256_methods"] = method_variants(torch, plan, y, p.epsilon, res.nu, w.iters, p.x_true, synth,
+                                                      snr, w.M)
+        except Exception as e:  # report, do not hide the main line
+            also["sara256_methods_error"] = repr(e)
     if not args.no_extra:
         try:
             also["sara1024_fp32"] = precision_form(torch, purify, synth, args.extra_iters)

@@ -558,6 +558,7 @@ void run_stage(const Plan& P, int stage, hipStream_t s) {
         case PURIFY_STAGE_PSI: launch_psi<T>(P, (const C*)P.v1, (C*)P.qv, s); break;
         case PURIFY_STAGE_TOEP_COLS: launch_fft_cols_toep<T>(P, (C*)P.tmp, s); break;
         case PURIFY_STAGE_TOEP_NORMAL: op.toep_A((const C*)P.xh, (C*)P.qv, 1.0, 0.0, nullptr); break;
+        case PURIFY_STAGE_TV_STEP: launch_tv_step<T>(P, (const C*)P.xh, 1, nullptr, 1.0, s); break;
         default: break;
     }
 }
@@ -791,7 +792,7 @@ purify_status purify_phi_normal(purify_plan* plan, const void* x, void* out, int
 purify_status purify_time_stage(purify_plan* plan, int32_t stage, int32_t reps, void* stream,
                                 double* ms_per_launch) {
     CHECK_PLAN(plan);
-    if (stage < 0 || stage > PURIFY_STAGE_TOEP_NORMAL || reps < 1 || !ms_per_launch) {
+    if (stage < 0 || stage > PURIFY_STAGE_TV_STEP || reps < 1 || !ms_per_launch) {
         set_error("invalid stage or reps");
         return PURIFY_E_INVALID;
     }

@@ -142,20 +142,26 @@ int tv_blocks(int64_t N) {
 }  // namespace
 
 template <typename T>
+void launch_tv_step(const Plan& P, const cpx<T>* u, int k, const double* w, double gamma, hipStream_t s) {
+    const int64_t N = P.N;
+    cpx<T>* pa = (cpx<T>*)P.tvp;   // ping-pong dual fields: (p1, p2) of A then of B
+    cpx<T>* pb = pa + 2 * N;
+    cpx<T>* out = (k % 2 == 0) ? pa : pb;
+    const cpx<T>* in = (k % 2 == 0) ? pb : pa;
+    const int tiles = (P.n / TVT) * (P.n / TVT);
+    hipLaunchKernelGGL(k_tv_step<T>, dim3(tiles), dim3(TVT * TVT), 0, s, u, in, in + N, out, out + N, w,
+                       (T)(1.0 / gamma), P.n, k == 0 ? 1 : 0);
+}
+
+template <typename T>
 void launch_tv_prox(const Plan& P, const cpx<T>* xh, cpx<T>* z1, cpx<T>* x1, cpx<T>* u, const double* w,
                     double gamma, int iters, double* part, int* nparts, hipStream_t s) {
     const int n = P.n;
     const int64_t N = P.N;
-    cpx<T>* pa = (cpx<T>*)P.tvp;   // ping-pong dual fields: (p1, p2) of A then of B
+    cpx<T>* pa = (cpx<T>*)P.tvp;
     cpx<T>* pb = pa + 2 * N;
     hipLaunchKernelGGL(k_tv_u<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, xh, z1, u, N);
-    const int tiles = (n / TVT) * (n / TVT);
-    for (int k = 0; k < iters; ++k) {
-        cpx<T>* out = (k % 2 == 0) ? pa : pb;
-        const cpx<T>* in = (k % 2 == 0) ? pb : pa;
-        hipLaunchKernelGGL(k_tv_step<T>, dim3(tiles), dim3(TVT * TVT), 0, s, (const cpx<T>*)u, in, in + N, out,
-                           out + N, w, (T)(1.0 / gamma), n, k == 0 ? 1 : 0);
-    }
+    for (int k = 0; k < iters; ++k) launch_tv_step<T>(P, u, k, w, gamma, s);
     const cpx<T>* fin = ((iters - 1) % 2 == 0) ? pa : pb;
     const int nb = tv_blocks(N);
     hipLaunchKernelGGL(k_tv_final<T>, dim3(nb), dim3(256), 0, s, xh, (const cpx<T>*)u, fin, fin + N, (T)gamma, z1,
@@ -173,7 +179,8 @@ int launch_grad_mag(const Plan& P, const cpx<T>* v, cpx<T>* out, double* part_ma
 #define PURIFY_INST_TV(T)                                                                                   \
     template void launch_tv_prox<T>(const Plan&, const cpx<T>*, cpx<T>*, cpx<T>*, cpx<T>*, const double*,    \
                                     double, int, double*, int*, hipStream_t);                               \
-    template int launch_grad_mag<T>(const Plan&, const cpx<T>*, cpx<T>*, double*, hipStream_t);
+    template int launch_grad_mag<T>(const Plan&, const cpx<T>*, cpx<T>*, double*, hipStream_t);             \
+    template void launch_tv_step<T>(const Plan&, const cpx<T>*, int, const double*, double, hipStream_t);
 PURIFY_INST_TV(float)
 PURIFY_INST_TV(double)
 

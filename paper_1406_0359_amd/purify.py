@@ -27,7 +27,7 @@ NORMAL_TOEPLITZ = 1
 
 STAGES = {
     "fft_rows": 0, "fft_cols": 1, "degrid": 2, "grid": 3, "ifft_cols": 4, "ifft_rows": 5,
-    "phi": 6, "phi_adj": 7, "psi_adj": 8, "psi": 9, "gtg": 10, "toep_cols": 11, "toep_normal": 12,
+    "phi": 6, "phi_adj": 7, "psi_adj": 8, "psi": 9, "gtg": 10, "toep_cols": 11, "toep_normal": 12, "tv_step": 13,
 }
 
 _STATUS = {0: "ok", 1: "invalid argument", 2: "workspace", 3: "device error", 4: "non-finite"}
