@@ -147,7 +147,16 @@ def precision_form(torch, purify, synth, solve_iters: int) -> dict:
     dt = time.perf_counter() - t0
     toep = toeplitz_form(torch, plan, y, p.epsilon, res.nu, solve_iters, w.cg_iters, p.x_true, synth,
                          res.x.cpu().numpy())
+
+    def timed(k):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plan.sdmm(y, p.epsilon, max_iter=k, cg_iter=w.cg_iters, nu=res.nu)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+    steady = solve_iters / (timed(10 + solve_iters) - timed(10))
     return {
+        "sdmm_steady_iters_s": steady,
         "toeplitz": toep,
         "workload": "sara1024 FP32 (n=1024, M=2097152, SARA 9 bases, L=4, J=6)",
         "phi_gvis_s": w.M / (st["phi"]["ms"] * 1e-3) / 1e9,
