@@ -196,23 +196,25 @@ k_degrid_tiles(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const in
 // depend on the order in which lanes and waves add (bit-reproducible gridding), and LDS
 // integer atomics run at full rate.  The scale is chosen from the tile's largest |y| and
 // the plan's bound on how many visibilities cover one cell of the tile, so no sum can
-// overflow:  |cell| <= cover * max|y| * max psi^2 <= 2^(bits-2) quanta.
+// overflow:  |cell| <= cover * max|y| * max psi^2 <= 2^(bits-2) quanta, and no single
+// contribution reaches 2^(CBITS-1) quanta.  A contribution w * v is rounded to an integer
+// by one fused multiply-add onto 1.5 * 2^(mantissa bits): the sum then lies in a binade
+// whose unit is one quantum, so its low mantissa bits hold round(w v) in two's complement.
 template <typename T> struct FixedAcc;
 template <> struct FixedAcc<float> {
     using I = int;
     static constexpr int BITS = 30;   // bound on a cell sum, in quanta
-    static constexpr int CBITS = 30;  // bound on one contribution, in quanta
-    static __device__ __forceinline__ I conv(float v) { return __float2int_rn(v); }
+    static constexpr int CBITS = 22;  // bound on one contribution, in quanta
+    static __device__ __forceinline__ I conv_mul(float a, float b) {
+        return __float_as_int(fmaf(a, b, 12582912.0f)) - 0x4B400000;
+    }
 };
 template <> struct FixedAcc<double> {
     using I = long long;
     static constexpr int BITS = 62;
     static constexpr int CBITS = 51;
-    // exact round-to-nearest for |v| < 2^51: adding 1.5 * 2^52 leaves round(v) in the low
-    // mantissa bits
-    static __device__ __forceinline__ I conv(double v) {
-        const double t = v + 6755399441055744.0;
-        return __double_as_longlong(t) - 0x4338000000000000LL;
+    static __device__ __forceinline__ I conv_mul(double a, double b) {
+        return __double_as_longlong(fma(a, b, 6755399441055744.0)) - 0x4338000000000000LL;
     }
 };
 
@@ -233,12 +235,21 @@ __device__ __forceinline__ double wave_max(double v) {
 // each thread takes a contiguous chunk (so the lanes of a wave add to different cells) and
 // loads CHR items at a time -- coordinates, weights and values -- before adding any, so the
 // loads of a chunk overlap.  Contributions accumulate in LDS in fixed point (integer
-// atomics: the sum does not depend on the order of the adds).  A whole tile is written to
-// the grid; a part stores its integer partial tile and scale exponent in its own slot, and
-// k_grid_merge sums the parts of each split tile in part order.
+// atomics: the sum does not depend on the order of the adds) on the tile plus a margin of
+// J - 1 cells on every side: every item's J x J footprint lies inside that padded tile, so
+// the scatter adds all J^2 taps at fixed offsets from one base address with no bounds
+// tests (taps that fall in the margin belong to neighbouring tiles and are discarded).  A
+// whole tile is written to the grid; a part stores its integer partial tile and scale
+// exponent in its own slot, and k_grid_merge sums the parts of each split tile in part
+// order.  The real and imaginary parts accumulate in separate planes, so the lanes of one
+// add instruction spread over all LDS banks.
 //
 // GTG: the unit's visibility values are not read from y but interpolated from the grid
 // `gin` (the same J x J gather as G), so one launch applies G^T G (gin and grid distinct).
+//
+// Coordinates relative to the tile: r0 = ((k1 - t1o + J - 1) mod K) - (J - 1) lies in
+// [-(J - 1), TT) for the unit's items (own items start inside the tile, spill-ins at most
+// J - 1 cells before it); this needs K >= TT + J - 1, which the plan guarantees.
 template <typename T, int J, int TT, int NT, int CHR, bool GTG>
 __global__ void __launch_bounds__(NT)
 k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32_t* __restrict__ perm, const int32_t* __restrict__ base,
@@ -248,6 +259,8 @@ k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32
     using Acc = FixedAcc<T>;
     constexpr int JJ = J > 0 ? J : KB_MAX_J;
     constexpr int UNR = J > 0 ? J : 1;
+    constexpr int JM = JJ - 1;           // margin of the padded accumulator tile
+    constexpr int WA = TT + 2 * JM;      // padded accumulator side
     // GTG: window of gin covering every footprint of the unit's visibilities (own and
     // spill-in), rows/cols [tile origin - (J-1), tile end + J - 1)
     constexpr int WS = TT + 2 * (JJ - 1);
@@ -255,7 +268,7 @@ k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32
     // FP64: the window goes straight from global memory to LDS (global_load_lds, one 16-byte
     // element per lane at consecutive LDS slots of the wave), keeping it out of registers
     constexpr bool DMA = GTG && sizeof(T) == 8;
-    __shared__ typename Acc::I acc[2 * TT * TT];
+    __shared__ typename Acc::I acc[2 * WA * WA];
     __shared__ double red[NT / 64];
     __shared__ cpx<T> win[GTG ? WPT * NT : 1];
     const int32_t* w = work + GRID_REC * blockIdx.x;
@@ -276,7 +289,7 @@ k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32
             grid[(size_t)(t1o + i / TT) * K + t2o + i % TT] = mk<T>(0, 0);
         return;
     }
-    for (int i = threadIdx.x; i < 2 * TT * TT; i += NT) acc[i] = 0;
+    for (int i = threadIdx.x; i < 2 * WA * WA; i += NT) acc[i] = 0;
     const int ch = (total + NT - 1) / NT;
     const int j0 = (int)threadIdx.x * ch;
     auto item = [&](int j) {
@@ -316,20 +329,20 @@ k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32
         staged = true;                                         \
     } while (0)
     // the visibility value: y (gridding) or the J x J interpolation from the window (G^T G,
-    // same arithmetic order as the G kernel)
+    // same arithmetic order as the G kernel); the footprint's first window cell is
+    // ((k - wo) mod K) on each axis and the taps follow at fixed offsets
     auto value = [&](int idx, int bk, const T* wa, const T* wb) {
         if constexpr (GTG) {
-            const int k1 = bk & 0xFFFF, k2 = (bk >> 16) & 0xFFFF;
+            const cpx<T>* w0 = win + (((bk & 0xFFFF) - wo1) & mask) * WS + ((((bk >> 16) & 0xFFFF) - wo2) & mask);
             T ax = 0, ay = 0;
 #pragma unroll UNR
             for (int a = 0; a < JJ; ++a) {
                 if (a >= Jn) break;
-                const cpx<T>* row = win + ((k1 + a - wo1) & mask) * WS;
                 T rx = 0, ry = 0;
 #pragma unroll UNR
                 for (int bb = 0; bb < JJ; ++bb) {
                     if (bb >= Jn) break;
-                    const cpx<T> g = row[(k2 + bb - wo2) & mask];
+                    const cpx<T> g = w0[a * WS + bb];
                     rx += wb[bb] * g.x;
                     ry += wb[bb] * g.y;
                 }
@@ -415,22 +428,19 @@ k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32
 #pragma unroll
         for (int c = 0; c < CHR; ++c) {
             if (!ok[c]) continue;
-            const int k1 = bk[c] & 0xFFFF, k2 = (bk[c] >> 16) & 0xFFFF;
+            const int r0 = (((bk[c] & 0xFFFF) - t1o + JM) & mask) - JM;
+            const int c0 = ((((bk[c] >> 16) & 0xFFFF) - t2o + JM) & mask) - JM;
+            typename Acc::I* ap = acc + (r0 + JM) * WA + (c0 + JM);
 #pragma unroll UNR
             for (int a = 0; a < JJ; ++a) {
                 if (a >= Jn) break;
-                const int c1 = ((k1 + a) & mask) - t1o;
-                if ((unsigned)c1 >= (unsigned)TT) continue;
                 const T sc = wa[c][a] * inv_q;
                 const T vx = sc * vv[c].x, vy = sc * vv[c].y;
 #pragma unroll UNR
                 for (int bb = 0; bb < JJ; ++bb) {
                     if (bb >= Jn) break;
-                    const int c2 = ((k2 + bb) & mask) - t2o;
-                    if ((unsigned)c2 < (unsigned)TT) {
-                        lds_add<T>(&acc[2 * (c1 * TT + c2)], Acc::conv(wb[c][bb] * vx));
-                        lds_add<T>(&acc[2 * (c1 * TT + c2) + 1], Acc::conv(wb[c][bb] * vy));
-                    }
+                    lds_add<T>(ap + a * WA + bb, Acc::conv_mul(wb[c][bb], vx));
+                    lds_add<T>(ap + WA * WA + a * WA + bb, Acc::conv_mul(wb[c][bb], vy));
                 }
             }
         }
@@ -440,12 +450,16 @@ k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32
         const T q = (T)ldexp(1.0, e);
         for (int i = threadIdx.x; i < TT * TT; i += NT) {
             const int r = i / TT, c = i % TT;
-            grid[(size_t)(t1o + r) * K + t2o + c] = mk<T>(q * (T)acc[2 * i], q * (T)acc[2 * i + 1]);
+            const int pi = (r + JM) * WA + c + JM;
+            grid[(size_t)(t1o + r) * K + t2o + c] = mk<T>(q * (T)acc[pi], q * (T)acc[WA * WA + pi]);
         }
         return;
     }
     typename Acc::I* pt = partial + (size_t)slot * 2 * TT * TT;
-    for (int i = threadIdx.x; i < 2 * TT * TT; i += NT) pt[i] = acc[i];
+    for (int i = threadIdx.x; i < 2 * TT * TT; i += NT) {
+        const int cell = i >> 1, r = cell / TT, c = cell % TT;
+        pt[i] = acc[(i & 1) * WA * WA + (r + JM) * WA + c + JM];
+    }
     if (threadIdx.x == 0) pexp[slot] = e;
 }
 

@@ -248,7 +248,7 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
     P.D = (int64_t)P.q * P.N;
     // 16 x 16 tiles up to K = 1024 (more, lighter workgroups for small grids), else 32 x 32
     P.TT = P.K > 1024 ? 32 : 16;
-    P.nT = P.K / P.TT;
+    P.nT = P.K / P.TT;   // >= 2, so K >= TT + KB_MAX_J - 1: a footprint never wraps onto its own tile
     const size_t es = P.precision == PURIFY_FP64 ? sizeof(double) : sizeof(float);
     const size_t ce = 2 * es;
     P.elem = ce;
