@@ -46,11 +46,27 @@ struct Ops {
         launch_fft_rows_fwd<T>(P, v, (C*)P.tmp, s);
         normal_tail(nullptr, q, 1.0, 0.0, nullptr);
     }
-    // conjugate-gradient step: p = r + beta p (beta from the rho partials), then q = A p
-    void apply_A_cg(C* p, const C* r, const double* rho, const double* rho_new, int count, C* q,
-                    double inv_nu2, double* dot) const {
-        launch_fft_rows_fwd_cg<T>(P, p, r, rho, rho_new, count, (C*)P.tmp, s);
-        normal_tail(p, q, inv_nu2, 2.0, dot);
+    // first CG step: q = A p, keeping p's row transform in dirt for the later steps
+    void apply_A_first(const C* p, C* q, double inv_nu2, double* dot) const {
+        launch_fft_rows_fwd<T>(P, p, (C*)P.dirt, s);
+        launch_fft_cols_fwd<T>(P, (const C*)P.dirt, (C*)P.grid, s);
+        launch_gtg<T>(P, (const C*)P.grid, (C*)P.grid2, s);
+        launch_fft_cols_adj<T>(P, (const C*)P.grid2, (C*)P.tmp, s);
+        launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, inv_nu2, p, 2.0, dot, s);
+    }
+    // a later CG step: the row pass applies the previous step's update (x += alpha p,
+    // r -= alpha q, partial ||r||^2 into rho_new) and transforms r; the new direction
+    // p = r + beta p is formed by linearity in the column pass (on the row transforms, kept in
+    // dirt) and in image space by the adjoint row pass, which also gives q = A p and <p, q>.
+    // Returns the count of rho_new's partials.
+    int apply_A_step(C* x, C* r, C* p, C* q, const double* rho, int rho_count, const double* pq, int pq_count,
+                     double* rho_new, double inv_nu2, double* dot) const {
+        const int nr = launch_fft_rows_xr<T>(P, x, r, p, q, rho, rho_count, pq, pq_count, rho_new, (C*)P.tmp, s);
+        launch_fft_cols_fwd_dir<T>(P, (const C*)P.tmp, (C*)P.dirt, rho_new, nr, rho, rho_count, (C*)P.grid, s);
+        launch_gtg<T>(P, (const C*)P.grid, (C*)P.grid2, s);
+        launch_fft_cols_adj<T>(P, (const C*)P.grid2, (C*)P.tmp, s);
+        launch_fft_rows_adj_dir<T>(P, (const C*)P.tmp, q, inv_nu2, r, p, 2.0, rho_new, nr, rho, rho_count, dot, s);
+        return nr;
     }
     // q = c1 T v + c2 v with T the stored (Toeplitz) form of Phi^dag Phi (chat ready)
     void toep_A(const C* v, C* q, double c1, double c2, double* dot) const {
@@ -167,15 +183,29 @@ struct Sdmm {
         // q = A x_hat of the warm start was formed at the end of the previous iteration (or
         // by enqueue_prologue), beside branch i = 1.
         const int nb = launch_cg_init<T>(x1, x2, x3, q, r, p, N, part(0), s);
-        // step c: q = A p (for c > 0 the row pass first forms p = r + beta p), then
-        // x += alpha p, r -= alpha q; rho of step c is in buffer c & 1
-        for (int c = 0; c < prm->cg_iter; ++c) {
-            double* rho = part(c & 1);
-            double* rho_next = part((c + 1) & 1);
-            if (c == 0) A(op, p, q, part(2));
-            else if (toep) op.toep_A_cg(p, r, part((c - 1) & 1), rho, nb, q, inv_nu2, part(2));
-            else op.apply_A_cg(p, r, part((c - 1) & 1), rho, nb, q, inv_nu2, part(2));
-            launch_cg_xr<T>(xh, r, p, q, rho, nb, part(2), rows_blocks, N, rho_next, s);
+        // rho of step c (the residual norm before step c's update) is in buffer c & 1,
+        // <p, A p> in buffer 2
+        if (toep) {
+            // step c: q = T p (for c > 0 the row pass first forms p = r + beta p), then
+            // x += alpha p, r -= alpha q
+            for (int c = 0; c < prm->cg_iter; ++c) {
+                double* rho = part(c & 1);
+                double* rho_next = part((c + 1) & 1);
+                if (c == 0) A(op, p, q, part(2));
+                else op.toep_A_cg(p, r, part((c - 1) & 1), rho, nb, q, inv_nu2, part(2));
+                launch_cg_xr<T>(xh, r, p, q, rho, nb, part(2), rows_blocks, N, rho_next, s);
+            }
+        } else {
+            // step 0: q = A p; step c > 0: step c - 1's update folded into the row pass, the new
+            // direction formed in the column and adjoint row passes (Ops::apply_A_step); then
+            // the last step's update
+            op.apply_A_first(p, q, inv_nu2, part(2));
+            int rho_count = nb;
+            for (int c = 1; c < prm->cg_iter; ++c)
+                rho_count = op.apply_A_step(xh, r, p, q, part((c - 1) & 1), rho_count, part(2), rows_blocks,
+                                            part(c & 1), inv_nu2, part(2));
+            const int c = prm->cg_iter;
+            launch_cg_xr<T>(xh, r, p, q, part((c - 1) & 1), rho_count, part(2), rows_blocks, N, part(c & 1), s);
         }
         // i = 1 (on s2): l1 prior on Psi^dag x_hat
         (void)hipEventRecord(fork, s);

@@ -136,6 +136,7 @@ struct Plan {
     void* grid = nullptr;        // K x K complex, row-major G[k1][k2]
     void* grid2 = nullptr;       // K x K complex: G^T G output of the normal operator
     void* tmp = nullptr;         // n x K complex, layout [j1][k2]
+    void* dirt = nullptr;        // n x K complex: row transform of the CG direction p
     void* unit = nullptr;        // n reals, all 1 (row passes without S)
     void* chat = nullptr;        // K x K reals: spectrum of the stored normal operator, / K^2
     bool chat_ready = false;     // chat computed (on the first call that needs it)
@@ -174,6 +175,21 @@ void launch_fft_rows_fwd_cg(const Plan& P, cpx<T>* p, const cpx<T>* r, const dou
                             const void* deap = nullptr);
 template <typename T> void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s);
 template <typename T> void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s);
+// CG step from the second on, exact operator: row pass with alpha = rho / <p, q> (partials),
+// x += alpha p, r -= alpha q, partial ||r||^2 per row block (returns their count), row transform
+// of r into tmp
+template <typename T> int launch_fft_rows_xr(const Plan& P, cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q,
+                                             const double* rho_part, int rho_count, const double* pq_part, int pq_count,
+                                             double* rho_new_part, cpx<T>* tmp, hipStream_t s);
+// column pass of that step: dirt <- tmp + beta dirt (beta = rho_new / rho), transform of dirt
+template <typename T> void launch_fft_cols_fwd_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* dirt,
+                                                   const double* rho_new_part, int rho_new_count,
+                                                   const double* rho_part, int rho_count, cpx<T>* grid, hipStream_t s);
+// adjoint row pass of that step: p <- r + beta p, x = c1 (S Z^T F^dag rows)(tmp) + c2 p, partial <p, x>
+template <typename T> void launch_fft_rows_adj_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1,
+                                                   const cpx<T>* r, cpx<T>* p, double c2, const double* rho_new_part,
+                                                   int rho_new_count, const double* rho_part, int rho_count,
+                                                   double* dot_part, hipStream_t s);
 // column stage of the stored normal operator: forward transform, times chat, adjoint, in place
 template <typename T> void launch_fft_cols_toep(const Plan& P, cpx<T>* tmp, hipStream_t s);
 // x = c1 * (S Z^T F^dag rows)(tmp) + c2 * v   (v may be null); optional partial Re<v, x>

@@ -321,6 +321,21 @@ __device__ __forceinline__ double sum_parts_dyn(const double* __restrict__ part,
     return t;
 }
 
+// Block sum of one value per thread (result in thread 0), any block size.
+__device__ __forceinline__ double block_sum_dyn(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) t += red[i];
+    }
+    return t;
+}
+
 // Optional conjugate-gradient direction update folded into the row pass: the input is
 // p = r + beta p_old with beta = rho_new / rho (0 when rho == 0), summed from the partial
 // buffers; p is written back in place.
@@ -330,6 +345,32 @@ struct CgDir {
     const double* rho_part = nullptr;
     const double* rhonew_part = nullptr;
     int count = 0;
+};
+
+// Conjugate-gradient step folded into the row pass (used from the second step on):
+// alpha = rho / <p, q> from the partial sums; x += alpha p; r -= alpha q (written back); the
+// row transform is taken of the new r, and the partial ||r||^2 of the row block is written.
+// The new direction's transform F_rows(r + beta p) = F_rows(r) + beta F_rows(p) is formed by
+// the column pass (linearity), and p itself by the adjoint row pass.
+template <typename T>
+struct CgXr {
+    cpx<T>* x = nullptr;
+    cpx<T>* r = nullptr;
+    const cpx<T>* p = nullptr;
+    const cpx<T>* q = nullptr;
+    const double* rho_part = nullptr;
+    int rho_count = 0;
+    const double* pq_part = nullptr;
+    int pq_count = 0;
+    double* rho_new_part = nullptr;
+};
+
+// beta = rho_new / rho (0 when rho == 0) from two partial-sum buffers
+struct CgBeta {
+    const double* rho_new_part = nullptr;   // null: no direction update
+    int rho_new_count = 0;
+    const double* rho_part = nullptr;
+    int rho_count = 0;
 };
 
 // rows_fwd: thread (b, r, tl), line 2b + r; tmp[row][2k' + r] = (-1)^k' i^r FFT(s x tw2^r)[k']
@@ -391,15 +432,83 @@ k_fft_rows_fwd(cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __rest
     }
 }
 
+// rows pass of a CG step from the second on (see CgXr): loads x, r, p, q of the row, then
+// the partial sums; updates x and r, transforms the new r.
+template <typename T, int LOGN, int B>
+__global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN, 0>::TL))
+k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>* __restrict__ tw,
+              const cpx<T>* __restrict__ tw2, CgXr<T> cg) {
+    using PL = Plan1D<T, LOGN, 0>;
+    constexpr int N = PL::N, K = 2 * N;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[16];
+    const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
+    const int tl = threadIdx.x % PL::TL, r = (threadIdx.x / PL::TL) & 1, lr = threadIdx.x / (2 * PL::TL);
+    cpx<T>* line = base + table_elems<T, LOGN>() + (2 * lr + r) * PL::LS;
+    const int row = blockIdx.x * B + lr;
+    const T srow = deap[row];
+    const size_t ro = (size_t)row * N;
+    cpx<T>* outr = tmp + (size_t)row * K;
+    // the row's loads are issued before the partial sums are read, so both are in flight
+    cpx<T> xv[PL::RMAX], rv[PL::RMAX], pv[PL::RMAX], qv[PL::RMAX];
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int p = PL::in_pos(tl, i);
+        xv[i] = cg.x[ro + p];
+        rv[i] = cg.r[ro + p];
+        pv[i] = cg.p[ro + p];
+        qv[i] = cg.q[ro + p];
+    }
+    const double rho = sum_parts_dyn(cg.rho_part, cg.rho_count, red);
+    const double pq = sum_parts_dyn(cg.pq_part, cg.pq_count, red);
+    const T alpha = (T)(rho == 0.0 ? 0.0 : rho / pq);
+    double acc = 0;
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        xv[i] = xv[i] + alpha * pv[i];
+        rv[i] = rv[i] - alpha * qv[i];
+        acc += (double)rv[i].x * rv[i].x + (double)rv[i].y * rv[i].y;
+    }
+    // both parity groups hold the whole row; group 0 writes it back once all have read it
+    __syncthreads();
+    if (r == 0) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int p = PL::in_pos(tl, i);
+            cg.x[ro + p] = xv[i];
+            cg.r[ro + p] = rv[i];
+        }
+    }
+    const double tot = block_sum_dyn(r == 0 ? acc : 0.0, red);
+    if (threadIdx.x == 0) cg.rho_new_part[blockIdx.x] = tot;
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int p = PL::in_pos(tl, i);
+        cpx<T> a = (srow * deap[p]) * rv[i];
+        if (r) a = a * tw2[p];
+        rv[i] = a;
+    }
+    line_fft<T, LOGN, 0, false>(rv, line, tl, W);
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int kp = PL::out_pos(tl, i);
+        cpx<T> o = (kp & 1) ? neg(rv[i]) : rv[i];
+        if (r) o = mul_i(o);
+        outr[2 * kp + r] = o;
+    }
+}
+
 // cols_fwd: thread (c, r, tl) with c fastest (coalesced runs of C columns)
 template <typename T, int LOGN, int C>
 __global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN, 1>::TL))
 k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const cpx<T>* __restrict__ tw,
-               const cpx<T>* __restrict__ tw2, int sg) {
+               const cpx<T>* __restrict__ tw2, int sg, cpx<T>* __restrict__ dirt, CgBeta cb) {
     using PL = Plan1D<T, LOGN, 1>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[16];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int c = threadIdx.x % C, r = (threadIdx.x / C) & 1, tl = threadIdx.x / (2 * C);
     cpx<T>* line = base + table_elems<T, LOGN>() + (2 * c + r) * PL::LS;
@@ -407,11 +516,26 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
     __syncthreads();
     cpx<T> v[PL::RMAX];
 #pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) v[i] = tmp[(size_t)PL::in_pos(tl, i) * K + col];
+    if (cb.rho_new_part) {
+        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt for the next step
+        cpx<T> d[PL::RMAX];
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) d[i] = dirt[(size_t)PL::in_pos(tl, i) * K + col];
+        const double rn = sum_parts_dyn(cb.rho_new_part, cb.rho_new_count, red);
+        const double rho = sum_parts_dyn(cb.rho_part, cb.rho_count, red);
+        const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) v[i] = v[i] + beta * d[i];
+        __syncthreads();   // both parity groups have read dirt
+        if (r == 0) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) dirt[(size_t)PL::in_pos(tl, i) * K + col] = v[i];
+        }
+    }
+#pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
-        const int p = PL::in_pos(tl, i);
-        cpx<T> a = tmp[(size_t)p * K + col];
-        if (r) a = a * tw2[p];
-        v[i] = a;
+        if (r) v[i] = v[i] * tw2[PL::in_pos(tl, i)];
     }
     line_fft<T, LOGN, 1, false>(v, line, tl, W);
 #pragma unroll
@@ -517,19 +641,6 @@ k_fft_cols_toep(cpx<T>* __restrict__ tmp, const T* __restrict__ chat, const cpx<
     }
 }
 
-__device__ __forceinline__ double block_sum_dyn(double v, double* red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double t = 0;
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-        for (int i = 0; i < nw; ++i) t += red[i];
-    }
-    return t;
-}
 
 // rows_adj: thread (b, tl, r) with r fastest; parity lines in parallel, combined in LDS;
 // x[row][j] = c1 s_row s_j (A[j] + (-i) exp(pi i j/n) B[j]) + c2 v, partial Re<v, x>
@@ -537,7 +648,8 @@ template <typename T, int LOGN, int B>
 __global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN, 0>::TL))
 k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* __restrict__ deap,
                const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2, T c1,
-               const cpx<T>* __restrict__ vin, T c2, double* __restrict__ dot_part) {
+               cpx<T>* __restrict__ vin, T c2, double* __restrict__ dot_part, const cpx<T>* __restrict__ rin,
+               CgBeta cb) {
     using PL = Plan1D<T, LOGN, 0>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
@@ -563,6 +675,13 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
     for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
     __syncthreads();
     const T srow = c1 * deap[row];
+    // CG direction update (with rin): v = r + beta v, written back to v
+    T beta = 0;
+    if (rin) {
+        const double rn = sum_parts_dyn(cb.rho_new_part, cb.rho_new_count, red);
+        const double rho = sum_parts_dyn(cb.rho_part, cb.rho_count, red);
+        beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
+    }
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < PL::RMAX / 2; ++q) {
@@ -571,7 +690,11 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
         cpx<T> o = (srow * deap[j]) * t;
         const size_t off = (size_t)row * N + j;
         if (vin) {
-            const cpx<T> vv = vin[off];
+            cpx<T> vv = vin[off];
+            if (rin) {
+                vv = rin[off] + beta * vv;
+                vin[off] = vv;
+            }
             o = o + c2 * vv;
             acc += (double)vv.x * (double)o.x + (double)vv.y * (double)o.y;
         }
@@ -614,7 +737,17 @@ void rows_fwd_impl(const Plan& P, cpx<T>* x, cpx<T>* tmp, CgDir<T> cg, const T* 
                        (const cpx<T>*)P.tw2, cg);
 }
 template <typename T, int LOGN>
-void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
+void rows_xr_impl(const Plan& P, cpx<T>* tmp, CgXr<T> cg, const T* deap, hipStream_t s) {
+    constexpr int B = rows_per_wg<T, LOGN>();
+    constexpr int NT = 2 * B * Plan1D<T, LOGN, 0>::TL;
+    constexpr int N = 1 << LOGN;
+    const size_t lds = lds_bytes<T, LOGN, 0>(2 * B);
+    auto f = k_fft_rows_xr<T, LOGN, B>;
+    set_lds_limit(f, lds);
+    hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, tmp, deap, (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, cg);
+}
+template <typename T, int LOGN>
+void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, cpx<T>* dirt, CgBeta cb, hipStream_t s) {
     constexpr int C = cols_per_wg<T, LOGN>();
     constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
@@ -622,7 +755,7 @@ void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s
     auto f = k_fft_cols_fwd<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, tmp, grid, (const cpx<T>*)P.tw,
-                       (const cpx<T>*)P.tw2, strip_groups(P, C));
+                       (const cpx<T>*)P.tw2, strip_groups(P, C), dirt, cb);
 }
 template <typename T, int LOGN>
 void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s) {
@@ -647,8 +780,8 @@ void cols_toep_impl(const Plan& P, cpx<T>* tmp, hipStream_t s) {
                        (const cpx<T>*)P.tw2, strip_groups(P, C));
 }
 template <typename T, int LOGN>
-void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* v,
-                   double c2, double* dot_part, const T* deap, hipStream_t s) {
+void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, cpx<T>* v,
+                   double c2, double* dot_part, const T* deap, const cpx<T>* rin, CgBeta cb, hipStream_t s) {
     constexpr int B = rows_per_wg<T, LOGN>();
     constexpr int NT = 2 * B * Plan1D<T, LOGN, 0>::TL;
     constexpr int N = 1 << LOGN;
@@ -656,7 +789,7 @@ void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const
     auto f = k_fft_rows_adj<T, LOGN, B>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, tmp, x, deap, (const cpx<T>*)P.tw,
-                       (const cpx<T>*)P.tw2, (T)c1, v, (T)c2, dot_part);
+                       (const cpx<T>*)P.tw2, (T)c1, v, (T)c2, dot_part, rin, cb);
 }
 
 int ilog2(int n) {
@@ -700,7 +833,46 @@ void launch_fft_rows_fwd_cg(const Plan& P, cpx<T>* p, const cpx<T>* r, const dou
 }
 template <typename T>
 void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_fwd_impl<T, L_>(P, tmp, grid, s)));
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_fwd_impl<T, L_>(P, tmp, grid, nullptr, CgBeta{}, s)));
+}
+template <typename T>
+int launch_fft_rows_xr(const Plan& P, cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q, const double* rho_part,
+                       int rho_count, const double* pq_part, int pq_count, double* rho_new_part, cpx<T>* tmp,
+                       hipStream_t s) {
+    CgXr<T> cg;
+    cg.x = x;
+    cg.r = r;
+    cg.p = p;
+    cg.q = q;
+    cg.rho_part = rho_part;
+    cg.rho_count = rho_count;
+    cg.pq_part = pq_part;
+    cg.pq_count = pq_count;
+    cg.rho_new_part = rho_new_part;
+    int blocks = 0;
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_xr_impl<T, L_>(P, tmp, cg, (const T*)P.deap, s), blocks = (1 << L_) / rows_per_wg<T, L_>()));
+    return blocks;
+}
+template <typename T>
+void launch_fft_cols_fwd_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* dirt, const double* rho_new_part,
+                             int rho_new_count, const double* rho_part, int rho_count, cpx<T>* grid, hipStream_t s) {
+    CgBeta cb;
+    cb.rho_new_part = rho_new_part;
+    cb.rho_new_count = rho_new_count;
+    cb.rho_part = rho_part;
+    cb.rho_count = rho_count;
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_fwd_impl<T, L_>(P, tmp, grid, dirt, cb, s)));
+}
+template <typename T>
+void launch_fft_rows_adj_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* r, cpx<T>* p,
+                             double c2, const double* rho_new_part, int rho_new_count, const double* rho_part,
+                             int rho_count, double* dot_part, hipStream_t s) {
+    CgBeta cb;
+    cb.rho_new_part = rho_new_part;
+    cb.rho_new_count = rho_new_count;
+    cb.rho_part = rho_part;
+    cb.rho_count = rho_count;
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, x, c1, p, c2, dot_part, (const T*)P.deap, r, cb, s)));
 }
 template <typename T>
 void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s) {
@@ -714,7 +886,8 @@ template <typename T>
 void launch_fft_rows_adj(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* v,
                          double c2, double* dot_part, hipStream_t s, const void* deap) {
     const T* dp = (const T*)(deap ? deap : P.deap);
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, x, c1, v, c2, dot_part, dp, s)));
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, x, c1, const_cast<cpx<T>*>(v), c2, dot_part, dp,
+                                                          nullptr, CgBeta{}, s)));
 }
 template <typename T>
 int fft_rows_adj_blocks(const Plan& P) {
@@ -733,6 +906,20 @@ template void launch_fft_cols_fwd<float>(const Plan&, const cpx<float>*, cpx<flo
 template void launch_fft_cols_fwd<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
 template void launch_fft_cols_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
 template void launch_fft_cols_adj<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
+template int launch_fft_rows_xr<float>(const Plan&, cpx<float>*, cpx<float>*, const cpx<float>*, const cpx<float>*,
+                                       const double*, int, const double*, int, double*, cpx<float>*, hipStream_t);
+template int launch_fft_rows_xr<double>(const Plan&, cpx<double>*, cpx<double>*, const cpx<double>*, const cpx<double>*,
+                                        const double*, int, const double*, int, double*, cpx<double>*, hipStream_t);
+template void launch_fft_cols_fwd_dir<float>(const Plan&, const cpx<float>*, cpx<float>*, const double*, int,
+                                             const double*, int, cpx<float>*, hipStream_t);
+template void launch_fft_cols_fwd_dir<double>(const Plan&, const cpx<double>*, cpx<double>*, const double*, int,
+                                              const double*, int, cpx<double>*, hipStream_t);
+template void launch_fft_rows_adj_dir<float>(const Plan&, const cpx<float>*, cpx<float>*, double, const cpx<float>*,
+                                             cpx<float>*, double, const double*, int, const double*, int, double*,
+                                             hipStream_t);
+template void launch_fft_rows_adj_dir<double>(const Plan&, const cpx<double>*, cpx<double>*, double, const cpx<double>*,
+                                              cpx<double>*, double, const double*, int, const double*, int, double*,
+                                              hipStream_t);
 template void launch_fft_cols_toep<float>(const Plan&, cpx<float>*, hipStream_t);
 template void launch_fft_cols_toep<double>(const Plan&, cpx<double>*, hipStream_t);
 template void launch_fft_rows_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, double,
