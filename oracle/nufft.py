@@ -98,3 +98,11 @@ def nudft(x: np.ndarray, uv: np.ndarray) -> np.ndarray:
     e1 = np.exp(-1j * np.outer(uv[:, 0], p))    # M x n
     e2 = np.exp(-1j * np.outer(uv[:, 1], p))
     return np.einsum("ma,ab,mb->m", e1, np.asarray(x, dtype=np.complex128), e2)
+
+
+def nudft_adjoint_at(y: np.ndarray, uv: np.ndarray, n: int, pixels) -> np.ndarray:
+    """Direct adjoint NUDFT at selected pixels: x_p = sum_m y_m exp(+i omega_m . p), with
+    p = (j1 - n/2, j2 - n/2) for each (j1, j2) in `pixels`.  O(M) per pixel."""
+    j = np.asarray(pixels, dtype=np.float64).reshape(-1, 2) - n // 2
+    ph = np.outer(uv[:, 0], j[:, 0]) + np.outer(uv[:, 1], j[:, 1])      # M x P
+    return np.asarray(y, dtype=np.complex128) @ np.exp(1j * ph)

@@ -74,12 +74,20 @@ struct Ops {
         launch_fft_cols_toep<T>(P, (C*)P.tmp, s);
         launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, c1, v, c2, dot, s, P.unit);
     }
-    // conjugate-gradient step with T: p = r + beta p in the row pass, then q = c1 T p + 2 p
-    void toep_A_cg(C* p, const C* r, const double* rho, const double* rho_new, int count, C* q, double c1,
-                   double* dot) const {
-        launch_fft_rows_fwd_cg<T>(P, p, r, rho, rho_new, count, (C*)P.tmp, s, P.unit);
-        launch_fft_cols_toep<T>(P, (C*)P.tmp, s);
+    // CG with T, as apply_A_first / apply_A_step: first step q = c1 T p + 2 p (p's row
+    // transform kept in dirt), later steps with the previous update folded into the row pass
+    void toep_A_first(const C* p, C* q, double c1, double* dot) const {
+        launch_fft_rows_fwd<T>(P, p, (C*)P.dirt, s, P.unit);
+        launch_fft_cols_toep<T>(P, (C*)P.tmp, s, (const C*)P.dirt);
         launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, c1, p, 2.0, dot, s, P.unit);
+    }
+    int toep_A_step(C* x, C* r, C* p, C* q, const double* rho, int rho_count, const double* pq, int pq_count,
+                    double* rho_new, double c1, double* dot) const {
+        const int nr = launch_fft_rows_xr<T>(P, x, r, p, q, rho, rho_count, pq, pq_count, rho_new, (C*)P.tmp, s,
+                                             P.unit);
+        launch_fft_cols_toep_dir<T>(P, (C*)P.tmp, (C*)P.dirt, rho_new, nr, rho, rho_count, s);
+        launch_fft_rows_adj_dir<T>(P, (const C*)P.tmp, q, c1, r, p, 2.0, rho_new, nr, rho, rho_count, dot, s, P.unit);
+        return nr;
     }
     // after the row pass of v: q = c1 Phi^dag Phi v + c2 v
     void normal_tail(const C* v, C* q, double c1, double c2, double* dot) const {
@@ -185,28 +193,22 @@ struct Sdmm {
         const int nb = launch_cg_init<T>(x1, x2, x3, q, r, p, N, part(0), s);
         // rho of step c (the residual norm before step c's update) is in buffer c & 1,
         // <p, A p> in buffer 2
-        if (toep) {
-            // step c: q = T p (for c > 0 the row pass first forms p = r + beta p), then
-            // x += alpha p, r -= alpha q
-            for (int c = 0; c < prm->cg_iter; ++c) {
-                double* rho = part(c & 1);
-                double* rho_next = part((c + 1) & 1);
-                if (c == 0) A(op, p, q, part(2));
-                else op.toep_A_cg(p, r, part((c - 1) & 1), rho, nb, q, inv_nu2, part(2));
-                launch_cg_xr<T>(xh, r, p, q, rho, nb, part(2), rows_blocks, N, rho_next, s);
-            }
-        } else {
-            // step 0: q = A p; step c > 0: step c - 1's update folded into the row pass, the new
-            // direction formed in the column and adjoint row passes (Ops::apply_A_step); then
-            // the last step's update
-            op.apply_A_first(p, q, inv_nu2, part(2));
-            int rho_count = nb;
-            for (int c = 1; c < prm->cg_iter; ++c)
+        // step 0: q = A p; step c > 0: step c - 1's update folded into the row pass, the new
+        // direction formed in the column and adjoint row passes (Ops::apply_A_step); then the
+        // last step's update
+        if (toep) op.toep_A_first(p, q, inv_nu2, part(2));
+        else op.apply_A_first(p, q, inv_nu2, part(2));
+        int rho_count = nb;
+        for (int c = 1; c < prm->cg_iter; ++c) {
+            if (toep)
+                rho_count = op.toep_A_step(xh, r, p, q, part((c - 1) & 1), rho_count, part(2), rows_blocks,
+                                           part(c & 1), inv_nu2, part(2));
+            else
                 rho_count = op.apply_A_step(xh, r, p, q, part((c - 1) & 1), rho_count, part(2), rows_blocks,
                                             part(c & 1), inv_nu2, part(2));
-            const int c = prm->cg_iter;
-            launch_cg_xr<T>(xh, r, p, q, part((c - 1) & 1), rho_count, part(2), rows_blocks, N, part(c & 1), s);
         }
+        const int cl = prm->cg_iter;
+        launch_cg_xr<T>(xh, r, p, q, part((cl - 1) & 1), rho_count, part(2), rows_blocks, N, part(cl & 1), s);
         // i = 1 (on s2): l1 prior on Psi^dag x_hat
         (void)hipEventRecord(fork, s);
         (void)hipStreamWaitEvent(s2, fork, 0);

@@ -168,11 +168,6 @@ struct Plan {
 // deapodisation, the plan's `unit` table = no S (the stored normal operator)
 template <typename T> void launch_fft_rows_fwd(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s,
                                                const void* deap = nullptr);
-// Row pass on p = r + beta p (beta = rho_new / rho from partial sums), p updated in place.
-template <typename T>
-void launch_fft_rows_fwd_cg(const Plan& P, cpx<T>* p, const cpx<T>* r, const double* rho_part,
-                            const double* rhonew_part, int count, cpx<T>* tmp, hipStream_t s,
-                            const void* deap = nullptr);
 template <typename T> void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s);
 template <typename T> void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s);
 // CG step from the second on, exact operator: row pass with alpha = rho / <p, q> (partials),
@@ -180,7 +175,8 @@ template <typename T> void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid
 // of r into tmp
 template <typename T> int launch_fft_rows_xr(const Plan& P, cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q,
                                              const double* rho_part, int rho_count, const double* pq_part, int pq_count,
-                                             double* rho_new_part, cpx<T>* tmp, hipStream_t s);
+                                             double* rho_new_part, cpx<T>* tmp, hipStream_t s,
+                                             const void* deap = nullptr);
 // column pass of that step: dirt <- tmp + beta dirt (beta = rho_new / rho), transform of dirt
 template <typename T> void launch_fft_cols_fwd_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* dirt,
                                                    const double* rho_new_part, int rho_new_count,
@@ -189,9 +185,14 @@ template <typename T> void launch_fft_cols_fwd_dir(const Plan& P, const cpx<T>* 
 template <typename T> void launch_fft_rows_adj_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1,
                                                    const cpx<T>* r, cpx<T>* p, double c2, const double* rho_new_part,
                                                    int rho_new_count, const double* rho_part, int rho_count,
-                                                   double* dot_part, hipStream_t s);
-// column stage of the stored normal operator: forward transform, times chat, adjoint, in place
-template <typename T> void launch_fft_cols_toep(const Plan& P, cpx<T>* tmp, hipStream_t s);
+                                                   double* dot_part, hipStream_t s, const void* deap = nullptr);
+// column stage of the stored normal operator: forward transform, times chat, adjoint, into tmp
+// (input `in`, default tmp itself)
+template <typename T> void launch_fft_cols_toep(const Plan& P, cpx<T>* tmp, hipStream_t s, const cpx<T>* in = nullptr);
+// the same for a CG step from the second on: dirt <- tmp + beta dirt is the transformed input
+template <typename T> void launch_fft_cols_toep_dir(const Plan& P, cpx<T>* tmp, cpx<T>* dirt, const double* rho_new_part,
+                                                    int rho_new_count, const double* rho_part, int rho_count,
+                                                    hipStream_t s);
 // x = c1 * (S Z^T F^dag rows)(tmp) + c2 * v   (v may be null); optional partial Re<v, x>
 template <typename T> void launch_fft_rows_adj(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1,
                                                const cpx<T>* v, double c2, double* dot_part,

@@ -336,17 +336,6 @@ __device__ __forceinline__ double block_sum_dyn(double v, double* red) {
     return t;
 }
 
-// Optional conjugate-gradient direction update folded into the row pass: the input is
-// p = r + beta p_old with beta = rho_new / rho (0 when rho == 0), summed from the partial
-// buffers; p is written back in place.
-template <typename T>
-struct CgDir {
-    const cpx<T>* r = nullptr;        // null: plain transform of x
-    const double* rho_part = nullptr;
-    const double* rhonew_part = nullptr;
-    int count = 0;
-};
-
 // Conjugate-gradient step folded into the row pass (used from the second step on):
 // alpha = rho / <p, q> from the partial sums; x += alpha p; r -= alpha q (written back); the
 // row transform is taken of the new r, and the partial ||r||^2 of the row block is written.
@@ -376,45 +365,23 @@ struct CgBeta {
 // rows_fwd: thread (b, r, tl), line 2b + r; tmp[row][2k' + r] = (-1)^k' i^r FFT(s x tw2^r)[k']
 template <typename T, int LOGN, int B>
 __global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN, 0>::TL))
-k_fft_rows_fwd(cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __restrict__ deap,
-               const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2, CgDir<T> cg) {
+k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* __restrict__ deap,
+               const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2) {
     using PL = Plan1D<T, LOGN, 0>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[16];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int tl = threadIdx.x % PL::TL, r = (threadIdx.x / PL::TL) & 1, lr = threadIdx.x / (2 * PL::TL);
     cpx<T>* line = base + table_elems<T, LOGN>() + (2 * lr + r) * PL::LS;
     const int row = blockIdx.x * B + lr;
     const T srow = deap[row];
-    cpx<T>* xr = x + (size_t)row * N;
+    const cpx<T>* xr = x + (size_t)row * N;
     cpx<T>* outr = tmp + (size_t)row * K;
-    // the row's loads are issued before the partial sums are read, so both are in flight
-    cpx<T> v[PL::RMAX], rv[PL::RMAX];
+    cpx<T> v[PL::RMAX];
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        const int p = PL::in_pos(tl, i);
-        v[i] = xr[p];
-        if (cg.r) rv[i] = cg.r[(size_t)row * N + p];
-    }
-    T beta = 0;
-    if (cg.r) {
-        const double rho = sum_parts_dyn(cg.rho_part, cg.count, red);
-        const double rn = sum_parts_dyn(cg.rhonew_part, cg.count, red);
-        beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
-#pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) v[i] = rv[i] + beta * v[i];
-    }
-    __syncthreads();
-    if (cg.r) {
-        // both parity groups read the row; one writes the new direction once all have read
-        __syncthreads();
-        if (r == 0) {
-#pragma unroll
-            for (int i = 0; i < PL::RMAX; ++i) xr[PL::in_pos(tl, i)] = v[i];
-        }
-    }
+    for (int i = 0; i < PL::RMAX; ++i) v[i] = xr[PL::in_pos(tl, i)];
+    __syncthreads();   // the twiddle table is staged
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
         const int p = PL::in_pos(tl, i);
@@ -547,6 +514,125 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
     }
 }
 
+// Column passes for long columns, where a workgroup's LDS holds only the two parity lines
+// of one column: each thread keeps CR adjacent columns in registers, so every row access is
+// one contiguous run of CR elements, and the workgroup transforms the columns one after
+// another through the same two line buffers.
+template <typename T, int LOGN, int CR>
+__global__ void __launch_bounds__((2 * Plan1D<T, LOGN, 1>::TL))
+k_fft_cols_fwd_mc(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const cpx<T>* __restrict__ tw,
+                  const cpx<T>* __restrict__ tw2, int sg, cpx<T>* __restrict__ dirt, CgBeta cb) {
+    using PL = Plan1D<T, LOGN, 1>;
+    constexpr int N = PL::N, K = 2 * N;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[16];
+    const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
+    const int r = threadIdx.x / PL::TL, tl = threadIdx.x % PL::TL;
+    cpx<T>* line = base + table_elems<T, LOGN>() + r * PL::LS;
+    const int col0 = strip_block(sg) * CR;
+    __syncthreads();
+    cpx<T> v[CR][PL::RMAX];
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
+#pragma unroll
+        for (int cc = 0; cc < CR; ++cc) v[cc][i] = tmp[ro + cc];
+    }
+    if (cb.rho_new_part) {
+        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt
+        const double rn = sum_parts_dyn(cb.rho_new_part, cb.rho_new_count, red);
+        const double rho = sum_parts_dyn(cb.rho_part, cb.rho_count, red);
+        const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
+#pragma unroll
+            for (int cc = 0; cc < CR; ++cc) v[cc][i] = v[cc][i] + beta * dirt[ro + cc];
+        }
+        __syncthreads();   // both parity groups have read dirt
+        if (r == 0) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) {
+                const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
+#pragma unroll
+                for (int cc = 0; cc < CR; ++cc) dirt[ro + cc] = v[cc][i];
+            }
+        }
+    }
+    if (r) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const cpx<T> t = tw2[PL::in_pos(tl, i)];
+#pragma unroll
+            for (int cc = 0; cc < CR; ++cc) v[cc][i] = v[cc][i] * t;
+        }
+    }
+    // each transform's last pass reads the line before a barrier, so the next column may
+    // overwrite it
+#pragma unroll
+    for (int cc = 0; cc < CR; ++cc) line_fft<T, LOGN, 1, false>(v[cc], line, tl, W);
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int kp = PL::out_pos(tl, i);
+        const size_t ro = (size_t)(2 * kp + r) * K + col0;
+#pragma unroll
+        for (int cc = 0; cc < CR; ++cc) {
+            cpx<T> o = (kp & 1) ? neg(v[cc][i]) : v[cc][i];
+            if (r) o = mul_i(o);
+            grid[ro + cc] = o;
+        }
+    }
+}
+
+template <typename T, int LOGN, int CR>
+__global__ void __launch_bounds__((2 * Plan1D<T, LOGN, 1>::TL))
+k_fft_cols_adj_mc(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const cpx<T>* __restrict__ tw,
+                  const cpx<T>* __restrict__ tw2, int sg) {
+    using PL = Plan1D<T, LOGN, 1>;
+    constexpr int N = PL::N, K = 2 * N;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
+    const int r = threadIdx.x / PL::TL, tl = threadIdx.x % PL::TL;
+    cpx<T>* lines = base + table_elems<T, LOGN>();
+    cpx<T>* line = lines + r * PL::LS;
+    const int col0 = strip_block(sg) * CR;
+    __syncthreads();
+    cpx<T> v[CR][PL::RMAX];
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int kp = PL::in_pos(tl, i);
+        const size_t ro = (size_t)(2 * kp + r) * K + col0;
+#pragma unroll
+        for (int cc = 0; cc < CR; ++cc) {
+            const cpx<T> u = grid[ro + cc];
+            v[cc][i] = (kp & 1) ? neg(u) : u;
+        }
+    }
+    cpx<T> res[CR][PL::RMAX / 2];
+#pragma unroll
+    for (int cc = 0; cc < CR; ++cc) {
+        line_fft<T, LOGN, 1, true>(v[cc], line, tl, W);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[cc][i];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PL::RMAX / 2; ++q) {
+            const int j = r + 2 * tl + q * 2 * PL::TL;
+            res[cc][q] = lines[j] + mul_mi(mulc(lines[PL::LS + j], tw2[j]));
+        }
+        __syncthreads();   // the next column reuses the lines
+    }
+#pragma unroll
+    for (int q = 0; q < PL::RMAX / 2; ++q) {
+        const int j = r + 2 * tl + q * 2 * PL::TL;
+#pragma unroll
+        for (int cc = 0; cc < CR; ++cc) tmp[(size_t)j * K + col0 + cc] = res[cc][q];
+    }
+}
+
 // cols_adj: parity lines transformed in parallel, results meet in LDS, then
 // tmp[j][col] = A[j] + (-i) exp(pi i j / n) B[j]
 template <typename T, int LOGN, int C>
@@ -592,12 +678,13 @@ k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const 
 // adjoint pass's input order; the (-1)^k' factors of the two cancel.
 template <typename T, int LOGN, int C>
 __global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN, 1>::TL))
-k_fft_cols_toep(cpx<T>* __restrict__ tmp, const T* __restrict__ chat, const cpx<T>* __restrict__ tw,
-                const cpx<T>* __restrict__ tw2, int sg) {
+k_fft_cols_toep(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const cpx<T>* __restrict__ tw,
+                const cpx<T>* __restrict__ tw2, int sg, cpx<T>* __restrict__ dirt, CgBeta cb) {
     using PL = Plan1D<T, LOGN, 1>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[16];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int c = threadIdx.x % C, r = (threadIdx.x / C) & 1, tl = threadIdx.x / (2 * C);
     cpx<T>* lines = base + table_elems<T, LOGN>();
@@ -606,11 +693,26 @@ k_fft_cols_toep(cpx<T>* __restrict__ tmp, const T* __restrict__ chat, const cpx<
     __syncthreads();
     cpx<T> v[PL::RMAX];
 #pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) v[i] = in[(size_t)PL::in_pos(tl, i) * K + col];
+    if (cb.rho_new_part) {
+        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt
+        cpx<T> d[PL::RMAX];
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) d[i] = dirt[(size_t)PL::in_pos(tl, i) * K + col];
+        const double rn = sum_parts_dyn(cb.rho_new_part, cb.rho_new_count, red);
+        const double rho = sum_parts_dyn(cb.rho_part, cb.rho_count, red);
+        const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) v[i] = v[i] + beta * d[i];
+        __syncthreads();   // both parity groups have read dirt
+        if (r == 0) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) dirt[(size_t)PL::in_pos(tl, i) * K + col] = v[i];
+        }
+    }
+#pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
-        const int p = PL::in_pos(tl, i);
-        cpx<T> a = tmp[(size_t)p * K + col];
-        if (r) a = a * tw2[p];
-        v[i] = a;
+        if (r) v[i] = v[i] * tw2[PL::in_pos(tl, i)];
     }
     line_fft<T, LOGN, 1, false>(v, line, tl, W);
     // frequency k1 = 2k' + r holds (-1)^k' i^r v; the adjoint reads (-1)^k' times its input
@@ -637,7 +739,7 @@ k_fft_cols_toep(cpx<T>* __restrict__ tmp, const T* __restrict__ chat, const cpx<
 #pragma unroll
     for (int q = 0; q < PL::RMAX / 2; ++q) {
         const int j = r + 2 * tl + q * 2 * PL::TL;
-        tmp[(size_t)j * K + col] = la[j] + mul_mi(mulc(lb[j], tw2[j]));
+        out[(size_t)j * K + col] = la[j] + mul_mi(mulc(lb[j], tw2[j]));
     }
 }
 
@@ -726,7 +828,7 @@ size_t lds_bytes(int lines) {
 }
 
 template <typename T, int LOGN>
-void rows_fwd_impl(const Plan& P, cpx<T>* x, cpx<T>* tmp, CgDir<T> cg, const T* deap, hipStream_t s) {
+void rows_fwd_impl(const Plan& P, const cpx<T>* x, cpx<T>* tmp, const T* deap, hipStream_t s) {
     constexpr int B = rows_per_wg<T, LOGN>();
     constexpr int NT = 2 * B * Plan1D<T, LOGN, 0>::TL;
     constexpr int N = 1 << LOGN;
@@ -734,7 +836,7 @@ void rows_fwd_impl(const Plan& P, cpx<T>* x, cpx<T>* tmp, CgDir<T> cg, const T* 
     auto f = k_fft_rows_fwd<T, LOGN, B>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, x, tmp, deap, (const cpx<T>*)P.tw,
-                       (const cpx<T>*)P.tw2, cg);
+                       (const cpx<T>*)P.tw2);
 }
 template <typename T, int LOGN>
 void rows_xr_impl(const Plan& P, cpx<T>* tmp, CgXr<T> cg, const T* deap, hipStream_t s) {
@@ -752,6 +854,15 @@ void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, cpx<T>* dirt,
     constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
     const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
+    if constexpr (C == 1 && LOGN >= 11) {   // long columns: CR columns per thread in registers
+        constexpr int CR = sizeof(T) == 8 ? 2 : 4;
+        const size_t lds1 = lds_bytes<T, LOGN, 1>(2);
+        auto f = k_fft_cols_fwd_mc<T, LOGN, CR>;
+        set_lds_limit(f, lds1);
+        hipLaunchKernelGGL(f, dim3(2 * N / CR), dim3(2 * Plan1D<T, LOGN, 1>::TL), lds1, s, tmp, grid,
+                           (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, strip_groups(P, CR), dirt, cb);
+        return;
+    }
     auto f = k_fft_cols_fwd<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, tmp, grid, (const cpx<T>*)P.tw,
@@ -763,21 +874,30 @@ void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s
     constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
     const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
+    if constexpr (C == 1 && LOGN >= 11) {
+        constexpr int CR = sizeof(T) == 8 ? 2 : 4;
+        const size_t lds1 = lds_bytes<T, LOGN, 1>(2);
+        auto f = k_fft_cols_adj_mc<T, LOGN, CR>;
+        set_lds_limit(f, lds1);
+        hipLaunchKernelGGL(f, dim3(2 * N / CR), dim3(2 * Plan1D<T, LOGN, 1>::TL), lds1, s, grid, tmp,
+                           (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, strip_groups(P, CR));
+        return;
+    }
     auto f = k_fft_cols_adj<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, grid, tmp, (const cpx<T>*)P.tw,
                        (const cpx<T>*)P.tw2, strip_groups(P, C));
 }
 template <typename T, int LOGN>
-void cols_toep_impl(const Plan& P, cpx<T>* tmp, hipStream_t s) {
+void cols_toep_impl(const Plan& P, const cpx<T>* in, cpx<T>* out, cpx<T>* dirt, CgBeta cb, hipStream_t s) {
     constexpr int C = cols_per_wg<T, LOGN>();
     constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
     const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
     auto f = k_fft_cols_toep<T, LOGN, C>;
     set_lds_limit(f, lds);
-    hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, tmp, (const T*)P.chat, (const cpx<T>*)P.tw,
-                       (const cpx<T>*)P.tw2, strip_groups(P, C));
+    hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, in, out, (const T*)P.chat, (const cpx<T>*)P.tw,
+                       (const cpx<T>*)P.tw2, strip_groups(P, C), dirt, cb);
 }
 template <typename T, int LOGN>
 void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, cpx<T>* v,
@@ -817,19 +937,7 @@ int ilog2(int n) {
 template <typename T>
 void launch_fft_rows_fwd(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_t s, const void* deap) {
     const T* dp = (const T*)(deap ? deap : P.deap);
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_fwd_impl<T, L_>(P, const_cast<cpx<T>*>(x), tmp, CgDir<T>{}, dp, s)));
-}
-template <typename T>
-void launch_fft_rows_fwd_cg(const Plan& P, cpx<T>* p, const cpx<T>* r, const double* rho_part,
-                            const double* rhonew_part, int count, cpx<T>* tmp, hipStream_t s,
-                            const void* deap) {
-    CgDir<T> cg;
-    cg.r = r;
-    cg.rho_part = rho_part;
-    cg.rhonew_part = rhonew_part;
-    cg.count = count;
-    const T* dp = (const T*)(deap ? deap : P.deap);
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_fwd_impl<T, L_>(P, p, tmp, cg, dp, s)));
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_fwd_impl<T, L_>(P, x, tmp, dp, s)));
 }
 template <typename T>
 void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
@@ -838,7 +946,8 @@ void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStre
 template <typename T>
 int launch_fft_rows_xr(const Plan& P, cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q, const double* rho_part,
                        int rho_count, const double* pq_part, int pq_count, double* rho_new_part, cpx<T>* tmp,
-                       hipStream_t s) {
+                       hipStream_t s, const void* deap) {
+    const T* dp = (const T*)(deap ? deap : P.deap);
     CgXr<T> cg;
     cg.x = x;
     cg.r = r;
@@ -850,7 +959,7 @@ int launch_fft_rows_xr(const Plan& P, cpx<T>* x, cpx<T>* r, const cpx<T>* p, con
     cg.pq_count = pq_count;
     cg.rho_new_part = rho_new_part;
     int blocks = 0;
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_xr_impl<T, L_>(P, tmp, cg, (const T*)P.deap, s), blocks = (1 << L_) / rows_per_wg<T, L_>()));
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_xr_impl<T, L_>(P, tmp, cg, dp, s), blocks = (1 << L_) / rows_per_wg<T, L_>()));
     return blocks;
 }
 template <typename T>
@@ -866,21 +975,32 @@ void launch_fft_cols_fwd_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* dirt, con
 template <typename T>
 void launch_fft_rows_adj_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* r, cpx<T>* p,
                              double c2, const double* rho_new_part, int rho_new_count, const double* rho_part,
-                             int rho_count, double* dot_part, hipStream_t s) {
+                             int rho_count, double* dot_part, hipStream_t s, const void* deap) {
+    const T* dp = (const T*)(deap ? deap : P.deap);
     CgBeta cb;
     cb.rho_new_part = rho_new_part;
     cb.rho_new_count = rho_new_count;
     cb.rho_part = rho_part;
     cb.rho_count = rho_count;
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, x, c1, p, c2, dot_part, (const T*)P.deap, r, cb, s)));
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, x, c1, p, c2, dot_part, dp, r, cb, s)));
 }
 template <typename T>
 void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s) {
     PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_adj_impl<T, L_>(P, grid, tmp, s)));
 }
 template <typename T>
-void launch_fft_cols_toep(const Plan& P, cpx<T>* tmp, hipStream_t s) {
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_toep_impl<T, L_>(P, tmp, s)));
+void launch_fft_cols_toep(const Plan& P, cpx<T>* tmp, hipStream_t s, const cpx<T>* in) {
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_toep_impl<T, L_>(P, in ? in : tmp, tmp, nullptr, CgBeta{}, s)));
+}
+template <typename T>
+void launch_fft_cols_toep_dir(const Plan& P, cpx<T>* tmp, cpx<T>* dirt, const double* rho_new_part, int rho_new_count,
+                              const double* rho_part, int rho_count, hipStream_t s) {
+    CgBeta cb;
+    cb.rho_new_part = rho_new_part;
+    cb.rho_new_count = rho_new_count;
+    cb.rho_part = rho_part;
+    cb.rho_count = rho_count;
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_toep_impl<T, L_>(P, tmp, tmp, dirt, cb, s)));
 }
 template <typename T>
 void launch_fft_rows_adj(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* v,
@@ -898,30 +1018,32 @@ int fft_rows_adj_blocks(const Plan& P) {
 
 template void launch_fft_rows_fwd<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t, const void*);
 template void launch_fft_rows_fwd<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t, const void*);
-template void launch_fft_rows_fwd_cg<float>(const Plan&, cpx<float>*, const cpx<float>*, const double*,
-                                            const double*, int, cpx<float>*, hipStream_t, const void*);
-template void launch_fft_rows_fwd_cg<double>(const Plan&, cpx<double>*, const cpx<double>*, const double*,
-                                             const double*, int, cpx<double>*, hipStream_t, const void*);
 template void launch_fft_cols_fwd<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
 template void launch_fft_cols_fwd<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
 template void launch_fft_cols_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
 template void launch_fft_cols_adj<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
 template int launch_fft_rows_xr<float>(const Plan&, cpx<float>*, cpx<float>*, const cpx<float>*, const cpx<float>*,
-                                       const double*, int, const double*, int, double*, cpx<float>*, hipStream_t);
+                                       const double*, int, const double*, int, double*, cpx<float>*, hipStream_t,
+                                       const void*);
 template int launch_fft_rows_xr<double>(const Plan&, cpx<double>*, cpx<double>*, const cpx<double>*, const cpx<double>*,
-                                        const double*, int, const double*, int, double*, cpx<double>*, hipStream_t);
+                                        const double*, int, const double*, int, double*, cpx<double>*, hipStream_t,
+                                        const void*);
 template void launch_fft_cols_fwd_dir<float>(const Plan&, const cpx<float>*, cpx<float>*, const double*, int,
                                              const double*, int, cpx<float>*, hipStream_t);
 template void launch_fft_cols_fwd_dir<double>(const Plan&, const cpx<double>*, cpx<double>*, const double*, int,
                                               const double*, int, cpx<double>*, hipStream_t);
 template void launch_fft_rows_adj_dir<float>(const Plan&, const cpx<float>*, cpx<float>*, double, const cpx<float>*,
                                              cpx<float>*, double, const double*, int, const double*, int, double*,
-                                             hipStream_t);
+                                             hipStream_t, const void*);
 template void launch_fft_rows_adj_dir<double>(const Plan&, const cpx<double>*, cpx<double>*, double, const cpx<double>*,
                                               cpx<double>*, double, const double*, int, const double*, int, double*,
-                                              hipStream_t);
-template void launch_fft_cols_toep<float>(const Plan&, cpx<float>*, hipStream_t);
-template void launch_fft_cols_toep<double>(const Plan&, cpx<double>*, hipStream_t);
+                                              hipStream_t, const void*);
+template void launch_fft_cols_toep<float>(const Plan&, cpx<float>*, hipStream_t, const cpx<float>*);
+template void launch_fft_cols_toep<double>(const Plan&, cpx<double>*, hipStream_t, const cpx<double>*);
+template void launch_fft_cols_toep_dir<float>(const Plan&, cpx<float>*, cpx<float>*, const double*, int, const double*,
+                                              int, hipStream_t);
+template void launch_fft_cols_toep_dir<double>(const Plan&, cpx<double>*, cpx<double>*, const double*, int,
+                                               const double*, int, hipStream_t);
 template void launch_fft_rows_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, double,
                                          const cpx<float>*, double, double*, hipStream_t, const void*);
 template void launch_fft_rows_adj<double>(const Plan&, const cpx<double>*, cpx<double>*, double,

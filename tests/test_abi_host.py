@@ -89,3 +89,29 @@ def test_plan_create_rejects_small_workspace_without_touching_device():
     st = lib.purify_plan_create(ctypes.byref(d), None, 1 << 40, None, None)
     assert st == 1
     assert lib.purify_status_string(2) == b"workspace too small or missing"
+
+
+def test_binding_structs_match_the_c_header(tmp_path):
+    # the ctypes mirrors of the C ABI's structs: same size and field offsets as the header
+    import subprocess
+    structs = {
+        "purify_plan_desc": purify.PlanDesc, "purify_sdmm_params": purify.SdmmParams,
+        "purify_sdmm_info": purify.SdmmInfo, "purify_server_desc": purify.ServerDesc,
+        "purify_reweight_params": purify.ReweightParams, "purify_reweight_info": purify.ReweightInfo,
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "purify.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

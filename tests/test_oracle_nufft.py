@@ -114,3 +114,18 @@ def test_grid_coordinates_formula():
     uv = np.array([[np.pi / 2, -np.pi]])
     kap = grid_coordinates(uv, 128)
     assert kap.tolist() == [[32.0, -64.0]]
+
+
+def test_nudft_adjoint_at_pixels_is_the_adjoint_of_nudft():
+    # <nudft(x), y> = <x, adjoint(y)> over all pixels of a small image
+    from oracle.nufft import nudft, nudft_adjoint_at
+    rng = np.random.default_rng(31)
+    n, M = 6, 25
+    uv = rng.uniform(-np.pi, np.pi, (M, 2))
+    x = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    y = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    pix = [(a, b) for a in range(n) for b in range(n)]
+    xa = nudft_adjoint_at(y, uv, n, pix).reshape(n, n)
+    lhs = np.vdot(nudft(x, uv), y)
+    rhs = np.vdot(x, xa)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
