@@ -57,7 +57,8 @@ def stage_bytes(plan, stage: str) -> float:
         # stored normal operator: column stage reads n x K and the real K x K spectrum, writes
         # n x K; the whole operator adds a row pass each way
         "toep_cols": 2 * N * c + 4 * N * (c // 2) + 2 * N * c,
-        # TV prox step: read both dual fields and u, write both dual fields
+        # TV prox launch (four dual steps in LDS): read both dual fields and u, write both
+        # dual fields
         "tv_step": 5 * N * c,
     }
     tbl["toep_normal"] = (N * c + 2 * N * c) + tbl["toep_cols"] + (2 * N * c + N * c)

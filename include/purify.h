@@ -240,8 +240,9 @@ typedef enum {
     PURIFY_STAGE_TOEP_COLS = 11,   /* column stage of the stored normal operator (transform,
                                       spectrum, adjoint transform, in place)          (n x K -> n x K) */
     PURIFY_STAGE_TOEP_NORMAL = 12, /* whole stored normal operator T x                (n x n -> n x n) */
-    PURIFY_STAGE_TV_STEP = 13      /* one dual projection step of the TV prox (reads the dual
-                                      fields and an image, writes the dual fields)    (n x n -> n x n) */
+    PURIFY_STAGE_TV_STEP = 13      /* one launch of the TV prox's dual projection: four steps
+                                      (reads the dual fields and an image, writes the dual
+                                      fields)                                         (n x n -> n x n) */
 } purify_stage;
 
 /* Time `reps` back-to-back launches of one stage on the plan's internal buffers (their

@@ -279,7 +279,8 @@ template <typename T> void launch_prox_ball_blk(cpx<T>* v3, cpx<T>* z3, const cp
 template <typename T> void launch_tv_prox(const Plan& P, const cpx<T>* xh, cpx<T>* z1, cpx<T>* x1, cpx<T>* u,
                                           const double* w, double gamma, int iters, double* part, int* nparts,
                                           hipStream_t s);
-// one dual projection step k (k = 0 starts from p = 0) on the plan's ping-pong dual fields
+// launch k of the dual projection (four steps; k = 0 starts from p = 0) on the plan's
+// ping-pong dual fields
 template <typename T> void launch_tv_step(const Plan& P, const cpx<T>* u, int k, const double* w, double gamma,
                                           hipStream_t s);
 // |grad v| (into out's real parts, if out) and partial maxima (if part_max); returns the count

@@ -4,10 +4,11 @@
 // from p = 0 for a fixed number of steps, then r1 = u - gamma div p.  grad: forward
 // differences, zero on the last row / column; div = -grad^T; |g|^2 = |g1|^2 + |g2|^2.
 //
-// One step is one launch over 16 x 16 pixel tiles: the tile's p (with a one-pixel halo) goes
-// to LDS, div p - u / gamma is formed on the tile plus one row and one column, and its
-// gradient updates the tile's p into the other buffer of a ping-pong pair.  p stays zero on
-// the last row (p1) and column (p2), where g is zero, so div needs no boundary cases.
+// Four steps run in one launch over 16 x 16 pixel tiles: the tile's p and u with a four-pixel
+// halo go to LDS, and each step forms div p - u / gamma and its gradient there, updating p in
+// place; the tile's p is written to the other buffer of a ping-pong pair.  p stays zero on
+// the last row (p1) and column (p2), where g is zero, and outside the image, so div needs no
+// boundary cases.
 #include "common.h"
 
 namespace purify {
@@ -16,6 +17,7 @@ namespace {
 
 constexpr int TVT = 16;          // tile side (256 threads)
 constexpr double TV_TAU = 0.125;
+constexpr int TV_KS = 4;         // dual projection steps per launch (halo width)
 
 // |a|^2 + |b|^2 of two complex numbers, in T
 template <typename T>
@@ -31,48 +33,63 @@ k_tv_u(const cpx<T>* __restrict__ xh, const cpx<T>* __restrict__ z1, cpx<T>* __r
     if (i < N) u[i] = xh[i] + z1[i];
 }
 
-// One dual projection step.  first: p_in is zero (not read).
-template <typename T>
+// Several dual projection steps in one launch: a 16 x 16 output tile with a halo of KS pixels
+// (one step depends on the dual field one pixel away), so the tile's (16 + 2 KS)^2 region of
+// p and u is loaded once, KS steps run in LDS (the valid part shrinking by one pixel a step),
+// and the tile's p is written.  Pixels outside the image keep p = 0; every in-image pixel
+// runs the arithmetic of k_tv_step, so the results are the same.
+template <typename T, int KS>
 __global__ void __launch_bounds__(TVT * TVT)
-k_tv_step(const cpx<T>* __restrict__ u, const cpx<T>* __restrict__ p1i, const cpx<T>* __restrict__ p2i,
-          cpx<T>* __restrict__ p1o, cpx<T>* __restrict__ p2o, const double* __restrict__ w, T inv_gamma,
-          int n, int first) {
-    __shared__ cpx<T> s1[TVT + 2][TVT + 2];   // p1 on rows i0-1 .. i0+16, cols j0-1 .. j0+16
-    __shared__ cpx<T> s2[TVT + 2][TVT + 2];
-    __shared__ cpx<T> sw[TVT + 1][TVT + 1];   // div p - u / gamma on rows i0 .. i0+16
+k_tv_steps(const cpx<T>* __restrict__ u, const cpx<T>* __restrict__ p1i, const cpx<T>* __restrict__ p2i,
+           cpx<T>* __restrict__ p1o, cpx<T>* __restrict__ p2o, const double* __restrict__ w, T inv_gamma,
+           int n, int first, int steps) {
+    constexpr int RS = TVT + 2 * KS;
+    __shared__ cpx<T> s1[RS][RS], s2[RS][RS], su[RS][RS], sw[RS][RS];
     const int tiles = n / TVT;
-    const int i0 = (blockIdx.x / tiles) * TVT, j0 = (blockIdx.x % tiles) * TVT;
+    const int i0 = (blockIdx.x / tiles) * TVT - KS, j0 = (blockIdx.x % tiles) * TVT - KS;   // region origin
     const cpx<T> zero = mk<T>(0, 0);
-    for (int e = threadIdx.x; e < (TVT + 2) * (TVT + 2); e += TVT * TVT) {
-        const int a = e / (TVT + 2), b = e % (TVT + 2);
-        const int i = i0 - 1 + a, j = j0 - 1 + b;
-        const bool in = !first && i >= 0 && i < n && j >= 0 && j < n;
-        s1[a][b] = in ? p1i[(size_t)i * n + j] : zero;
-        s2[a][b] = in ? p2i[(size_t)i * n + j] : zero;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < (TVT + 1) * (TVT + 1); e += TVT * TVT) {
-        const int a = e / (TVT + 1), b = e % (TVT + 1);
+    for (int e = threadIdx.x; e < RS * RS; e += TVT * TVT) {
+        const int a = e / RS, b = e % RS;
         const int i = i0 + a, j = j0 + b;
-        cpx<T> v = zero;
-        if (i < n && j < n) {
-            const cpx<T> d = (s1[a + 1][b + 1] - s1[a][b + 1]) + (s2[a + 1][b + 1] - s2[a + 1][b]);
-            v = d - inv_gamma * u[(size_t)i * n + j];
-        }
-        sw[a][b] = v;
+        const bool img = i >= 0 && i < n && j >= 0 && j < n;
+        const size_t o = (size_t)(img ? i : 0) * n + (img ? j : 0);
+        s1[a][b] = img && !first ? p1i[o] : zero;
+        s2[a][b] = img && !first ? p2i[o] : zero;
+        su[a][b] = img ? u[o] : zero;
     }
     __syncthreads();
+    for (int st = 0; st < steps; ++st) {
+        // W = div p - u / gamma where its inputs (one pixel up and left) are in the region
+        for (int e = threadIdx.x; e < RS * RS; e += TVT * TVT) {
+            const int a = e / RS, b = e % RS;
+            if (a >= 1 && b >= 1) {
+                const cpx<T> d = (s1[a][b] - s1[a - 1][b]) + (s2[a][b] - s2[a][b - 1]);
+                sw[a][b] = d - inv_gamma * su[a][b];
+            }
+        }
+        __syncthreads();
+        // p <- (p + tau g) / (1 + tau |g| / w) with g the forward gradient of W (in place: a
+        // pixel's update reads only its own p)
+        for (int e = threadIdx.x; e < RS * RS; e += TVT * TVT) {
+            const int a = e / RS, b = e % RS;
+            const int i = i0 + a, j = j0 + b;
+            if (a >= 1 && b >= 1 && a < RS - 1 && b < RS - 1 && i >= 0 && i < n && j >= 0 && j < n) {
+                const cpx<T> g1 = i < n - 1 ? sw[a + 1][b] - sw[a][b] : zero;
+                const cpx<T> g2 = j < n - 1 ? sw[a][b + 1] - sw[a][b] : zero;
+                const T mag = sqrt(mag2(g1, g2));
+                const T den = (T)1 + ((T)TV_TAU * mag) / (T)(w ? w[(size_t)i * n + j] : 1.0);
+                const cpx<T> q1 = s1[a][b] + (T)TV_TAU * g1;
+                const cpx<T> q2 = s2[a][b] + (T)TV_TAU * g2;
+                s1[a][b] = mk<T>(q1.x / den, q1.y / den);
+                s2[a][b] = mk<T>(q2.x / den, q2.y / den);
+            }
+        }
+        __syncthreads();
+    }
     const int ty = threadIdx.x / TVT, tx = threadIdx.x % TVT;
-    const int i = i0 + ty, j = j0 + tx;
-    const cpx<T> g1 = i < n - 1 ? sw[ty + 1][tx] - sw[ty][tx] : zero;
-    const cpx<T> g2 = j < n - 1 ? sw[ty][tx + 1] - sw[ty][tx] : zero;
-    const T mag = sqrt(mag2(g1, g2));
-    const size_t o = (size_t)i * n + j;
-    const T den = (T)1 + ((T)TV_TAU * mag) / (T)(w ? w[o] : 1.0);
-    const cpx<T> q1 = s1[ty + 1][tx + 1] + (T)TV_TAU * g1;
-    const cpx<T> q2 = s2[ty + 1][tx + 1] + (T)TV_TAU * g2;
-    p1o[o] = mk<T>(q1.x / den, q1.y / den);
-    p2o[o] = mk<T>(q2.x / den, q2.y / den);
+    const size_t o = (size_t)(i0 + KS + ty) * n + (j0 + KS + tx);
+    p1o[o] = s1[KS + ty][KS + tx];
+    p2o[o] = s2[KS + ty][KS + tx];
 }
 
 // r1 = u - gamma div p ; z1 = u - r1 ; x1 = r1 - z1 ; partial sum_ij w_ij |(grad x_hat)_ij|
@@ -141,6 +158,8 @@ int tv_blocks(int64_t N) {
 
 }  // namespace
 
+// launch k of the dual projection (TV_KS steps from the pair written by launch k - 1; k = 0
+// starts from p = 0)
 template <typename T>
 void launch_tv_step(const Plan& P, const cpx<T>* u, int k, const double* w, double gamma, hipStream_t s) {
     const int64_t N = P.N;
@@ -149,8 +168,8 @@ void launch_tv_step(const Plan& P, const cpx<T>* u, int k, const double* w, doub
     cpx<T>* out = (k % 2 == 0) ? pa : pb;
     const cpx<T>* in = (k % 2 == 0) ? pb : pa;
     const int tiles = (P.n / TVT) * (P.n / TVT);
-    hipLaunchKernelGGL(k_tv_step<T>, dim3(tiles), dim3(TVT * TVT), 0, s, u, in, in + N, out, out + N, w,
-                       (T)(1.0 / gamma), P.n, k == 0 ? 1 : 0);
+    hipLaunchKernelGGL((k_tv_steps<T, TV_KS>), dim3(tiles), dim3(TVT * TVT), 0, s, u, in, in + N, out, out + N, w,
+                       (T)(1.0 / gamma), P.n, k == 0 ? 1 : 0, TV_KS);
 }
 
 template <typename T>
@@ -161,8 +180,18 @@ void launch_tv_prox(const Plan& P, const cpx<T>* xh, cpx<T>* z1, cpx<T>* x1, cpx
     cpx<T>* pa = (cpx<T>*)P.tvp;
     cpx<T>* pb = pa + 2 * N;
     hipLaunchKernelGGL(k_tv_u<T>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, xh, z1, u, N);
-    for (int k = 0; k < iters; ++k) launch_tv_step<T>(P, u, k, w, gamma, s);
-    const cpx<T>* fin = ((iters - 1) % 2 == 0) ? pa : pb;
+    // TV_KS steps a launch, ping-pong between the pairs A and B (the last launch's output pair
+    // holds the final field)
+    const int tiles = (n / TVT) * (n / TVT);
+    int launches = 0;
+    for (int k = 0; k < iters; k += TV_KS, ++launches) {
+        cpx<T>* out = (launches % 2 == 0) ? pa : pb;
+        const cpx<T>* in = (launches % 2 == 0) ? pb : pa;
+        const int steps = iters - k < TV_KS ? iters - k : TV_KS;
+        hipLaunchKernelGGL((k_tv_steps<T, TV_KS>), dim3(tiles), dim3(TVT * TVT), 0, s, (const cpx<T>*)u, in, in + N,
+                           out, out + N, w, (T)(1.0 / gamma), n, k == 0 ? 1 : 0, steps);
+    }
+    const cpx<T>* fin = ((launches - 1) % 2 == 0) ? pa : pb;
     const int nb = tv_blocks(N);
     hipLaunchKernelGGL(k_tv_final<T>, dim3(nb), dim3(256), 0, s, xh, (const cpx<T>*)u, fin, fin + N, (T)gamma, z1,
                        x1, w, n, part);
