@@ -139,7 +139,9 @@ __device__ __forceinline__ void reg_dft(cpx<T>* v) {
 
 // ---------------------------------------------------------------------------------------
 // Radix plans: product of the radices is n; RMAX elements live in registers per thread.
-// AX = 0: row passes, AX = 1: column passes (which reuse the row plan unless listed).
+// AX = 0: row passes, AX = 1: column passes (which reuse the row plan unless listed).  The
+// row passes of the small and mid sizes have few rows (n of them), so they are latency-bound
+// and use more, shorter threads (radix-4 passes); measured per size.
 template <typename T, int LOGN, int AX>
 struct Radices : Radices<T, LOGN, 0> {};
 #define PURIFY_RADICES_AX4(TY, LG, AX, NP_, R0, R1, R2, R3)   \
@@ -153,18 +155,22 @@ struct Radices : Radices<T, LOGN, 0> {};
 PURIFY_RADICES(float, 4, 1, 16, 1, 1)
 PURIFY_RADICES(float, 5, 1, 32, 1, 1)
 PURIFY_RADICES(float, 6, 2, 8, 8, 1)
-PURIFY_RADICES(float, 7, 3, 8, 4, 4)
-PURIFY_RADICES(float, 8, 3, 8, 8, 4)
+PURIFY_RADICES_AX4(float, 7, 0, 4, 4, 4, 4, 2)
+PURIFY_RADICES_AX(float, 7, 1, 3, 8, 4, 4)
+PURIFY_RADICES_AX4(float, 8, 0, 4, 4, 4, 4, 4)
+PURIFY_RADICES_AX(float, 8, 1, 3, 8, 8, 4)
 PURIFY_RADICES(float, 9, 3, 8, 8, 8)
 // n = 1024 FP32: rows in four passes (128 threads per line), columns in three
 PURIFY_RADICES_AX4(float, 10, 0, 4, 4, 8, 8, 4)
 PURIFY_RADICES_AX(float, 10, 1, 3, 8, 8, 16)
 PURIFY_RADICES(float, 11, 3, 32, 16, 4)
-PURIFY_RADICES(float, 12, 3, 16, 16, 16)
+PURIFY_RADICES_AX4(float, 12, 0, 4, 8, 8, 8, 8)
+PURIFY_RADICES_AX(float, 12, 1, 3, 16, 16, 16)
 PURIFY_RADICES(double, 4, 1, 16, 1, 1)
 PURIFY_RADICES(double, 5, 2, 16, 2, 1)
 PURIFY_RADICES(double, 6, 2, 8, 8, 1)
-PURIFY_RADICES(double, 7, 3, 8, 4, 4)
+PURIFY_RADICES_AX4(double, 7, 0, 4, 4, 4, 4, 2)
+PURIFY_RADICES_AX(double, 7, 1, 3, 8, 4, 4)
 // n = 256 FP64: four radix-4 passes (64 threads per line) for rows and columns; measured 3.7
 // against 5.1 us for 8 x 8 x 4 on the 256 rows of a pass
 PURIFY_RADICES_AX4(double, 8, 0, 4, 4, 4, 4, 4)
@@ -494,14 +500,11 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
     for (int i = 0; i < PL::RMAX; ++i) v[i] = tmp[(size_t)PL::in_pos(tl, i) * K + col];
     if (cb.rho_new_part) {
         // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt for the next step
-        cpx<T> d[PL::RMAX];
-#pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) d[i] = dirt[(size_t)PL::in_pos(tl, i) * K + col];
         const double rn = sum_parts_dyn(cb.rho_new_part, cb.rho_new_count, red);
         const double rho = sum_parts_dyn(cb.rho_part, cb.rho_count, red);
         const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
 #pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) v[i] = v[i] + beta * d[i];
+        for (int i = 0; i < PL::RMAX; ++i) v[i] = v[i] + beta * dirt[(size_t)PL::in_pos(tl, i) * K + col];
         __syncthreads();   // both parity groups have read dirt
         if (r == 0) {
 #pragma unroll
@@ -704,14 +707,11 @@ k_fft_cols_toep(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const
     for (int i = 0; i < PL::RMAX; ++i) v[i] = in[(size_t)PL::in_pos(tl, i) * K + col];
     if (cb.rho_new_part) {
         // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt
-        cpx<T> d[PL::RMAX];
-#pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) d[i] = dirt[(size_t)PL::in_pos(tl, i) * K + col];
         const double rn = sum_parts_dyn(cb.rho_new_part, cb.rho_new_count, red);
         const double rho = sum_parts_dyn(cb.rho_part, cb.rho_count, red);
         const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
 #pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) v[i] = v[i] + beta * d[i];
+        for (int i = 0; i < PL::RMAX; ++i) v[i] = v[i] + beta * dirt[(size_t)PL::in_pos(tl, i) * K + col];
         __syncthreads();   // both parity groups have read dirt
         if (r == 0) {
 #pragma unroll
