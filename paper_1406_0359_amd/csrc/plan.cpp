@@ -12,6 +12,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -140,7 +141,7 @@ double kb_hat(double nu, int J, double beta, long double i0b) {
 // iteration in long double, polished by Newton; each root y gives the pair z, 1/z of
 // z^2 - (2 - 4y) z + 1 = 0 and the one inside the unit circle is kept (extremal phase).
 // h = coefficients of (z + 1)^N prod (z - z_r), highest power first, scaled to sum sqrt 2.
-int daubechies(int N, double* h_out) {
+int daubechies_compute(int N, double* h_out) {
     typedef std::complex<long double> C;
     if (N < 1 || N > 8) return -1;
     std::vector<long double> pc(N);
@@ -335,6 +336,50 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
 }
 
 // ---------------------------------------------------------------------------------------
+// The Kaiser-Bessel fit (with its verification against the Bessel series) and the Daubechies
+// factorisations depend only on (J, beta, degree) and the filter order, and cost milliseconds
+// in long double; they are computed once per process and shared by later plans (the server
+// creates plans on several threads, hence the lock).
+namespace {
+struct KbFit {
+    int J, deg;
+    double beta, err;
+    std::vector<long double> coef;
+};
+std::mutex g_table_mu;
+std::vector<KbFit> g_kb_fits;
+std::vector<std::vector<double>> g_daub(9);
+}  // namespace
+
+double kb_fit_cached(int J, double beta, int deg, long double* coef) {
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    for (const KbFit& f : g_kb_fits)
+        if (f.J == J && f.deg == deg && f.beta == beta) {
+            std::copy(f.coef.begin(), f.coef.end(), coef);
+            return f.err;
+        }
+    KbFit f{J, deg, beta, 0.0, std::vector<long double>((size_t)J * (deg + 1))};
+    f.err = kb_fit(J, beta, deg, f.coef.data());
+    std::copy(f.coef.begin(), f.coef.end(), coef);
+    g_kb_fits.push_back(std::move(f));
+    return g_kb_fits.back().err;
+}
+
+int daubechies(int N, double* h_out) {
+    if (N < 1 || N > 8) return daubechies_compute(N, h_out);
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    std::vector<double>& h = g_daub[(size_t)N];
+    if (h.empty()) {
+        double tmp[2 * 8];
+        const int F = daubechies_compute(N, tmp);
+        if (F < 0) return F;
+        h.assign(tmp, tmp + F);
+    }
+    std::copy(h.begin(), h.end(), h_out);
+    return (int)h.size();
+}
+
+// ---------------------------------------------------------------------------------------
 // Host-side plan tables and visibility binning; uploads into the workspace.
 purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     const int n = P.n, K = P.K, J = P.J, TT = P.TT, nT = P.nT;
@@ -346,7 +391,7 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     P.kb_i0beta = (double)i0b;
     const int deg = f64 ? KBDeg<double>::value : KBDeg<float>::value;
     std::vector<long double> kbc((size_t)J * (deg + 1));
-    P.kb_fit_err = kb_fit(J, P.beta, deg, kbc.data());
+    P.kb_fit_err = kb_fit_cached(J, P.beta, deg, kbc.data());
     const double fit_tol = f64 ? 1e-13 : 1e-7;
     if (!(P.kb_fit_err <= fit_tol)) {
         set_error("Kaiser-Bessel polynomial fit error " + std::to_string(P.kb_fit_err) +
@@ -628,15 +673,20 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     if (f64) {
         wt.resize((size_t)M * 2 * J);
         const int nc = deg + 1;
-        for (int64_t q = 0; q < M; ++q)
-            for (int ax = 0; ax < 2; ++ax) {
-                const double x = sfr[2 * q + ax] - 0.5;
+        // Horner per weight; the 2J weights of a visibility advance together (independent
+        // chains), each with the same operations in the same order as one at a time
+        for (int64_t q = 0; q < M; ++q) {
+            double acc[2 * KB_MAX_J];
+            const double x0 = sfr[2 * q] - 0.5, x1 = sfr[2 * q + 1] - 0.5;
+            for (int a = 0; a < J; ++a) acc[a] = acc[J + a] = kbd[(size_t)a * nc + nc - 1];
+            for (int k = nc - 2; k >= 0; --k)
                 for (int a = 0; a < J; ++a) {
-                    double acc = kbd[(size_t)a * nc + nc - 1];
-                    for (int k = nc - 2; k >= 0; --k) acc = acc * x + kbd[(size_t)a * nc + k];
-                    wt[(size_t)q * 2 * J + (size_t)ax * J + a] = acc;
+                    const double c = kbd[(size_t)a * nc + k];
+                    acc[a] = acc[a] * x0 + c;
+                    acc[J + a] = acc[J + a] * x1 + c;
                 }
-            }
+            std::copy(acc, acc + 2 * J, wt.begin() + (ptrdiff_t)((size_t)q * 2 * J));
+        }
     }
 
     // Upload (pageable host memory; synchronous at the end).
