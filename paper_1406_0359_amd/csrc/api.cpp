@@ -46,17 +46,13 @@ struct Ops {
         launch_fft_rows_fwd<T>(P, v, (C*)P.tmp, s);
         normal_tail(nullptr, q, 1.0, 0.0, nullptr);
     }
-    // first CG step: the set-up r = p = x1 + x2 + x3 - q0 (partial ||r||^2 into rho, count
-    // returned) in the row pass, then q = A p, keeping p's row transform in dirt for the
-    // later steps
-    int apply_A_first(const C* x1, const C* x2, const C* x3, const C* q0, C* r, C* p, C* q, double inv_nu2,
-                      double* rho, double* dot) const {
-        const int nb = launch_fft_rows_init<T>(P, x1, x2, x3, q0, r, p, rho, (C*)P.dirt, s);
+    // first CG step: q = A p, keeping p's row transform in dirt for the later steps
+    void apply_A_first(const C* p, C* q, double inv_nu2, double* dot) const {
+        launch_fft_rows_fwd<T>(P, p, (C*)P.dirt, s);
         launch_fft_cols_fwd<T>(P, (const C*)P.dirt, (C*)P.grid, s);
         launch_gtg<T>(P, (const C*)P.grid, (C*)P.grid2, s);
         launch_fft_cols_adj<T>(P, (const C*)P.grid2, (C*)P.tmp, s);
         launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, inv_nu2, p, 2.0, dot, s);
-        return nb;
     }
     // a later CG step: the row pass applies the previous step's update (x += alpha p,
     // r -= alpha q, partial ||r||^2 into rho_new) and transforms r; the new direction
@@ -80,12 +76,10 @@ struct Ops {
     }
     // CG with T, as apply_A_first / apply_A_step: first step q = c1 T p + 2 p (p's row
     // transform kept in dirt), later steps with the previous update folded into the row pass
-    int toep_A_first(const C* x1, const C* x2, const C* x3, const C* q0, C* r, C* p, C* q, double c1,
-                     double* rho, double* dot) const {
-        const int nb = launch_fft_rows_init<T>(P, x1, x2, x3, q0, r, p, rho, (C*)P.dirt, s, P.unit);
+    void toep_A_first(const C* p, C* q, double c1, double* dot) const {
+        launch_fft_rows_fwd<T>(P, p, (C*)P.dirt, s, P.unit);
         launch_fft_cols_toep<T>(P, (C*)P.tmp, s, (const C*)P.dirt);
         launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, c1, p, 2.0, dot, s, P.unit);
-        return nb;
     }
     int toep_A_step(C* x, C* r, C* p, C* q, const double* rho, int rho_count, const double* pq, int pq_count,
                     double* rho_new, double c1, double* dot) const {
@@ -197,13 +191,15 @@ struct Sdmm {
         // at x_hat, so r = x1 + x2 + x3 - A x_hat.  With the NUFFT operator, x3 already holds
         // x3 - A x_hat (branch i = 3 below); with the stored operator, q = A x_hat was formed
         // at the end of the previous iteration (or by enqueue_prologue) beside branch i = 1.
+        const int nb = launch_cg_init<T>(x1, x2, x3, toep ? q : nullptr, r, p, N, part(0), s);
         // rho of step c (the residual norm before step c's update) is in buffer c & 1,
         // <p, A p> in buffer 2
-        // step 0: the set-up r = p = x1 + x2 + x3 (- q) folded into its row pass, then q = A p;
-        // step c > 0: step c - 1's update folded into the row pass, the new direction formed
-        // in the column and adjoint row passes (Ops::apply_A_step); then the last step's update
-        int rho_count = toep ? op.toep_A_first(x1, x2, x3, q, r, p, q, inv_nu2, part(0), part(2))
-                             : op.apply_A_first(x1, x2, x3, nullptr, r, p, q, inv_nu2, part(0), part(2));
+        // step 0: q = A p; step c > 0: step c - 1's update folded into the row pass, the new
+        // direction formed in the column and adjoint row passes (Ops::apply_A_step); then the
+        // last step's update
+        if (toep) op.toep_A_first(p, q, inv_nu2, part(2));
+        else op.apply_A_first(p, q, inv_nu2, part(2));
+        int rho_count = nb;
         for (int c = 1; c < prm->cg_iter; ++c) {
             if (toep)
                 rho_count = op.toep_A_step(xh, r, p, q, part((c - 1) & 1), rho_count, part(2), rows_blocks,

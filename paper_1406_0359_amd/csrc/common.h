@@ -173,13 +173,6 @@ template <typename T> void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid
 // CG step from the second on, exact operator: row pass with alpha = rho / <p, q> (partials),
 // x += alpha p, r -= alpha q, partial ||r||^2 per row block (returns their count), row transform
 // of r into tmp
-// first CG step's row pass with the CG set-up folded in: r = p = x1 + x2 + x3 - q0 (q0 may be
-// null), partial ||r||^2 per workgroup into rho_part (count returned), row transform of p
-// into tmp
-template <typename T> int launch_fft_rows_init(const Plan& P, const cpx<T>* x1, const cpx<T>* x2,
-                                               const cpx<T>* x3, const cpx<T>* q0, cpx<T>* r, cpx<T>* p,
-                                               double* rho_part, cpx<T>* tmp, hipStream_t s,
-                                               const void* deap = nullptr);
 template <typename T> int launch_fft_rows_xr(const Plan& P, cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q,
                                              const double* rho_part, int rho_count, const double* pq_part, int pq_count,
                                              double* rho_new_part, cpx<T>* tmp, hipStream_t s,
@@ -240,6 +233,10 @@ void launch_iter_advance(double* sc, hipStream_t s);
 void launch_finalize(const double* part, int count, double* sc, int slot, int op, double arg,
                      double* hist, int hist_index, hipStream_t s);
 
+// r = x1 + x2 + x3 - q (q may be null) ; p = r ; partial <r, r>
+template <typename T> int launch_cg_init(const cpx<T>* x1, const cpx<T>* x2, const cpx<T>* x3,
+                                         const cpx<T>* q, cpx<T>* r, cpx<T>* p, int64_t n,
+                                         double* part, hipStream_t s);
 // CG step with alpha = rho / <p, q> summed from partials inside the kernel
 template <typename T> int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q,
                                        const double* rho_part, int rho_count, const double* pq_part,

@@ -150,6 +150,24 @@ k_finalize(const double* __restrict__ part, int count, double* sc, int slot, int
     }
 }
 
+// r = x1 + x2 + x3 - q (q null: r = x1 + x2 + x3) ; p = r ; partial <r, r>
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_cg_init(const cpx<T>* __restrict__ x1, const cpx<T>* __restrict__ x2, const cpx<T>* __restrict__ x3,
+          const cpx<T>* __restrict__ q, cpx<T>* __restrict__ r, cpx<T>* __restrict__ p, int64_t n,
+          double* part) {
+    double acc = 0;
+    GRID_STRIDE(i, n) {
+        const cpx<T> b = x1[i] + x2[i] + x3[i];
+        const cpx<T> v = q ? b - q[i] : b;
+        r[i] = v;
+        p[i] = v;
+        acc += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 // CG step: alpha = rho / Re<p, q> from the partial sums of both (rho == 0: alpha = 0,
 // the early stop); x += alpha p ; r -= alpha q ; partial <r, r> of the new residual.
 template <typename T>
@@ -494,6 +512,13 @@ void launch_iter_advance(double* sc, hipStream_t s) {
     hipLaunchKernelGGL(k_iter_advance, dim3(1), dim3(64), 0, s, sc);
 }
 template <typename T>
+int launch_cg_init(const cpx<T>* x1, const cpx<T>* x2, const cpx<T>* x3, const cpx<T>* q, cpx<T>* r,
+                   cpx<T>* p, int64_t n, double* part, hipStream_t s) {
+    const int b = red_blocks(n);
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(b), dim3(VT), 0, s, x1, x2, x3, q, r, p, n, part);
+    return b;
+}
+template <typename T>
 int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q, const double* rho_part,
                  int rho_count, const double* pq_part, int pq_count, int64_t n, double* part,
                  hipStream_t s) {
@@ -595,6 +620,8 @@ int launch_diff2_part(const cpx<T>* a, const cpx<T>* b, int64_t n, double* part_
     template void launch_fill<T>(cpx<T>*, cpx<T>, int64_t, hipStream_t);                                \
     template int launch_norm2_part<T>(const cpx<T>*, int64_t, double*, hipStream_t);                     \
     template int launch_maxabs_part<T>(const cpx<T>*, int64_t, double*, hipStream_t);                    \
+    template int launch_cg_init<T>(const cpx<T>*, const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*,  \
+                                   cpx<T>*, int64_t, double*, hipStream_t);                              \
     template int launch_cg_xr<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const cpx<T>*, const double*, int,     \
                                  const double*, int, int64_t, double*, hipStream_t);                     \
     template void launch_power_normalise<T>(cpx<T>*, const cpx<T>*, const double*, int, double*, int64_t, \
