@@ -187,11 +187,10 @@ struct Sdmm {
         C *z1 = (C*)P.z1, *v1 = (C*)P.v1, *z2 = (C*)P.z2, *z3 = (C*)P.z3, *v3 = (C*)P.v3;
         const C* yt = (const C*)P.ytil;
         const int rows_blocks = fft_rows_adj_blocks<T>(P);
-        // Global update (step 5): CG on (Phi~^dag Phi~ + 2I) x = x1 + x2 + x3, warm started
-        // at x_hat, so r = x1 + x2 + x3 - A x_hat.  With the NUFFT operator, x3 already holds
-        // x3 - A x_hat (branch i = 3 below); with the stored operator, q = A x_hat was formed
-        // at the end of the previous iteration (or by enqueue_prologue) beside branch i = 1.
-        const int nb = launch_cg_init<T>(x1, x2, x3, toep ? q : nullptr, r, p, N, part(0), s);
+        // Global update (step 5): CG on (Phi~^dag Phi~ + 2I) x = x1 + x2 + x3, warm start;
+        // q = A x_hat of the warm start was formed at the end of the previous iteration (or
+        // by enqueue_prologue), beside branch i = 1.
+        const int nb = launch_cg_init<T>(x1, x2, x3, q, r, p, N, part(0), s);
         // rho of step c (the residual norm before step c's update) is in buffer c & 1,
         // <p, A p> in buffer 2
         // step 0: q = A p; step c > 0: step c - 1's update folded into the row pass, the new
@@ -226,38 +225,28 @@ struct Sdmm {
         (void)hipEventRecord(join, s2);
         // i = 2: positivity
         launch_prox_pos<T>(xh, z2, x2, N, s);
-        // i = 3: l2 ball about y~ on Phi~ x_hat.  x3 = Phi~^dag (r3 - z3); with the NUFFT
-        // operator the next CG's A x_hat = Phi~^dag (Phi~ x_hat) + 2 x_hat is folded in by
-        // linearity: the projection leaves r3 - z3 - Phi~ x_hat in v3 and the adjoint's
-        // epilogue subtracts 2 x_hat, so x3 <- x3 - A x_hat costs no operator of its own.
-        const bool fold = !toep;
+        // i = 3: l2 ball about y~ on Phi~ x_hat
         op.phi(xh, v3, inv_nu, nullptr);
         if (nblk > 1) {   // R balls: chunk sums, per-block scales, projection by block
             launch_ball_part_blk<T>(v3, z3, yt, P.bperm, P.bchunk, nchunks, part(4), part(5), s);
             launch_ball_fin_blk(part(4), part(5), P.bchunk_off, P.beps, nblk, P.bscale, sc, P.hist, P.hist_cap, s);
-            launch_prox_ball_blk<T>(v3, z3, yt, P.bid, P.bscale, M, fold, s);
+            launch_prox_ball_blk<T>(v3, z3, yt, P.bid, P.bscale, M, s);
         } else {
             const int nb3 = launch_ball_part<T>(v3, z3, yt, M, part(4), part(5), s);
-            launch_prox_ball<T>(v3, z3, yt, part(4), part(5), nb3, eps_t, sc, P.hist, P.hist_cap, M, fold, s);
+            launch_prox_ball<T>(v3, z3, yt, part(4), part(5), nb3, eps_t, sc, P.hist, P.hist_cap, M, s);
         }
-        if (fold) {
-            op.phi_adj(v3, nullptr, x3, inv_nu, xh, -2.0, nullptr);
-        } else {
-            op.phi_adj(v3, nullptr, x3, inv_nu, nullptr, 0.0, nullptr);
-            // the next iteration's warm-start product A x_hat with the stored operator needs
-            // only x_hat: it runs here, overlapping branch i = 1 on the other stream
-            A(op, xh, q, nullptr);
-        }
+        op.phi_adj(v3, nullptr, x3, inv_nu, nullptr, 0.0, nullptr);
+        // the next iteration's warm-start product A x_hat needs only x_hat: it runs here,
+        // overlapping branch i = 1 on the other stream
+        A(op, xh, q, nullptr);
         (void)hipStreamWaitEvent(s, join, 0);
         launch_iter_advance(sc, s);
     }
 
-    // The first iteration's warm start: q = A x_hat, and with the NUFFT operator
-    // x3 <- x3 - q (the form every later iteration's branch i = 3 leaves in x3).
+    // q = A x_hat for the first iteration's warm start.
     void enqueue_prologue(hipStream_t s) const {
         const Ops<T> op{P, s};
         A(op, (const C*)P.xh, (C*)P.qv, nullptr);
-        if (!toep) launch_sub<T>((C*)P.x3, (const C*)P.qv, P.N, s);
     }
 };
 

@@ -233,7 +233,6 @@ void launch_iter_advance(double* sc, hipStream_t s);
 void launch_finalize(const double* part, int count, double* sc, int slot, int op, double arg,
                      double* hist, int hist_index, hipStream_t s);
 
-// r = x1 + x2 + x3 - q (q may be null) ; p = r ; partial <r, r>
 template <typename T> int launch_cg_init(const cpx<T>* x1, const cpx<T>* x2, const cpx<T>* x3,
                                          const cpx<T>* q, cpx<T>* r, cpx<T>* p, int64_t n,
                                          double* part, hipStream_t s);
@@ -254,7 +253,7 @@ template <typename T> int launch_ball_part(const cpx<T>* v3, const cpx<T>* z3, c
                                            hipStream_t s);
 template <typename T> void launch_prox_ball(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const double* part_d,
                                             const double* part_res, int count, double eps, double* sc,
-                                            double* hist, int hist_cap, int64_t n, bool diff, hipStream_t s);
+                                            double* hist, int hist_cap, int64_t n, hipStream_t s);
 template <typename T> void launch_permute_scale(const cpx<T>* y_user, const int32_t* perm, double scale,
                                                 cpx<T>* y_sorted, int64_t n, hipStream_t s);
 template <typename T> void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc,
@@ -274,9 +273,7 @@ void launch_ball_fin_blk(const double* part_d, const double* part_res, const int
                          const double* eps, int R, double* scale, double* sc, double* hist, int hist_cap,
                          hipStream_t s);
 template <typename T> void launch_prox_ball_blk(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const int32_t* bid,
-                                                const double* scale, int64_t n, bool diff, hipStream_t s);
-// a -= b
-template <typename T> void launch_sub(cpx<T>* a, const cpx<T>* b, int64_t n, hipStream_t s);
+                                                const double* scale, int64_t n, hipStream_t s);
 // TV prior, branch i = 1: u = x_hat + z1 (into u), `iters` dual projection steps, then
 // r1 = u - gamma div p, z1 = u - r1, x1 = r1 - z1, objective partials TV_w(x_hat) (count in *nparts)
 template <typename T> void launch_tv_prox(const Plan& P, const cpx<T>* xh, cpx<T>* z1, cpx<T>* x1, cpx<T>* u,
