@@ -13,6 +13,7 @@
 #include <complex>
 #include <cstring>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -379,6 +380,32 @@ int daubechies(int N, double* h_out) {
     return (int)h.size();
 }
 
+// f(begin, end) over [0, n) split into contiguous ranges of at least `grain` items, on up to
+// eight host threads (the calling thread takes the first range); serial where a thread
+// cannot be started.  Each item must be independent of the others.
+template <typename F>
+void host_parallel(int64_t n, int64_t grain, F f) {
+    const int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+    const int64_t T = std::min<int64_t>(std::min<int64_t>(hw, 8), (n + grain - 1) / grain);
+    if (T <= 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t done = T;   // ranges [done, T) run on this thread if a thread cannot be started
+    for (int64_t t = 1; t < T; ++t) {
+        try {
+            th.emplace_back(f, n * t / T, n * (t + 1) / T);
+        } catch (...) {
+            done = t;
+            break;
+        }
+    }
+    f((int64_t)0, n / T);
+    for (int64_t t = done; t < T; ++t) f(n * t / T, n * (t + 1) / T);
+    for (auto& x : th) x.join();
+}
+
 // ---------------------------------------------------------------------------------------
 // Host-side plan tables and visibility binning; uploads into the workspace.
 purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
@@ -501,30 +528,46 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     P.grid_threads = 256;
     // Per-tile bound on the number of visibilities that add to one cell (gridding scale):
     // count first taps per cell, sum over the J x J window of first taps that reach each
-    // cell (cyclic), and take the maximum over each tile.
+    // cell (cyclic), and take the maximum over each tile.  The window sums slide along both
+    // axes (integer sums: the same values as summing each window), with the axis-1 sums of
+    // the J rows in the current axis-2 window held in a ring.
     std::vector<int32_t> cover((size_t)nT * nT, 0);
     {
-        std::vector<int32_t> cnt((size_t)K * K, 0), row((size_t)K * K, 0);
+        std::vector<int32_t> cnt((size_t)K * K, 0);
         for (int64_t m = 0; m < M; ++m) {
             const int k1 = base[m] & 0xFFFF, k2 = (base[m] >> 16) & 0xFFFF;
             ++cnt[(size_t)k2 * K + k1];
         }
-        for (int k2 = 0; k2 < K; ++k2) {
+        // r[k1] = sum_{a < J} cnt[k2][(k1 - a) mod K]
+        auto row_sums = [&](int k2, int32_t* r) {
             const int32_t* c = &cnt[(size_t)k2 * K];
-            int32_t* r = &row[(size_t)k2 * K];
-            for (int k1 = 0; k1 < K; ++k1) {
-                int32_t acc = 0;
-                for (int a = 0; a < J; ++a) acc += c[(k1 - a + K) & (K - 1)];
+            int32_t acc = 0;
+            for (int a = 0; a < J; ++a) acc += c[(K - a) & (K - 1)];
+            r[0] = acc;
+            for (int k1 = 1; k1 < K; ++k1) {
+                acc += c[k1] - c[(k1 - J + K) & (K - 1)];
                 r[k1] = acc;
             }
+        };
+        // ring slot (k2 + J) mod J holds row k2's sums; S[k1] = sum_{b < J} r[(k2 - b) mod K][k1]
+        std::vector<int32_t> ring((size_t)J * K), S((size_t)K, 0);
+        for (int b = J - 1; b >= 0; --b) {
+            int32_t* r = &ring[(size_t)((J - b) % J) * K];
+            row_sums((K - b) & (K - 1), r);
+            for (int k1 = 0; k1 < K; ++k1) S[k1] += r[k1];
         }
         for (int k2 = 0; k2 < K; ++k2) {
-            const int t2 = k2 / TT;
-            for (int k1 = 0; k1 < K; ++k1) {
-                int32_t acc = 0;
-                for (int b = 0; b < J; ++b) acc += row[(size_t)((k2 - b + K) & (K - 1)) * K + k1];
-                int32_t& cv = cover[(size_t)t2 * nT + k1 / TT];
-                if (acc > cv) cv = acc;
+            if (k2 > 0) {
+                int32_t* r = &ring[(size_t)(k2 % J) * K];   // row k2 - J, leaving the window
+                for (int k1 = 0; k1 < K; ++k1) S[k1] -= r[k1];
+                row_sums(k2, r);
+                for (int k1 = 0; k1 < K; ++k1) S[k1] += r[k1];
+            }
+            int32_t* cv = &cover[(size_t)(k2 / TT) * nT];
+            for (int t1 = 0; t1 < nT; ++t1) {
+                int32_t mx = cv[t1];
+                for (int k1 = t1 * TT; k1 < (t1 + 1) * TT; ++k1) mx = std::max(mx, S[k1]);
+                cv[t1] = mx;
             }
         }
     }
@@ -674,19 +717,22 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
         wt.resize((size_t)M * 2 * J);
         const int nc = deg + 1;
         // Horner per weight; the 2J weights of a visibility advance together (independent
-        // chains), each with the same operations in the same order as one at a time
-        for (int64_t q = 0; q < M; ++q) {
-            double acc[2 * KB_MAX_J];
-            const double x0 = sfr[2 * q] - 0.5, x1 = sfr[2 * q + 1] - 0.5;
-            for (int a = 0; a < J; ++a) acc[a] = acc[J + a] = kbd[(size_t)a * nc + nc - 1];
-            for (int k = nc - 2; k >= 0; --k)
-                for (int a = 0; a < J; ++a) {
-                    const double c = kbd[(size_t)a * nc + k];
-                    acc[a] = acc[a] * x0 + c;
-                    acc[J + a] = acc[J + a] * x1 + c;
-                }
-            std::copy(acc, acc + 2 * J, wt.begin() + (ptrdiff_t)((size_t)q * 2 * J));
-        }
+        // chains), each with the same operations in the same order as one at a time; ranges
+        // of visibilities on several host threads
+        host_parallel(M, 4096, [&](int64_t q0, int64_t q1) {
+            for (int64_t q = q0; q < q1; ++q) {
+                double acc[2 * KB_MAX_J];
+                const double x0 = sfr[2 * q] - 0.5, x1 = sfr[2 * q + 1] - 0.5;
+                for (int a = 0; a < J; ++a) acc[a] = acc[J + a] = kbd[(size_t)a * nc + nc - 1];
+                for (int k = nc - 2; k >= 0; --k)
+                    for (int a = 0; a < J; ++a) {
+                        const double c = kbd[(size_t)a * nc + k];
+                        acc[a] = acc[a] * x0 + c;
+                        acc[J + a] = acc[J + a] * x1 + c;
+                    }
+                std::copy(acc, acc + 2 * J, wt.begin() + (ptrdiff_t)((size_t)q * 2 * J));
+            }
+        });
     }
 
     // Upload (pageable host memory; synchronous at the end).
