@@ -9,6 +9,7 @@
 //  * uv wrapping, grid coordinates kappa = omega K / (2 pi), first taps and fractions, and a
 //    stable counting sort of the visibilities by (grid tile, spill class).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -451,68 +452,82 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
         }
     }
 
-    // Visibility binning.
+    // Visibility binning: first tap, fractions and bucket key of each visibility (ranges of
+    // visibilities on host threads), then a counting sort by key.
     std::vector<int32_t> base(M), key(M);
     std::vector<double> fr(2 * M);
     const double twopi = 2.0 * M_PI;
     const int nkeys = 4 * nT * nT;
-    std::vector<int64_t> cnt(nkeys + 1, 0);
     static const int rank_of_class[4] = {0, 1, 3, 2};
-    for (int64_t m = 0; m < M; ++m) {
-        int k0m[2];
-        for (int ax = 0; ax < 2; ++ax) {
-            double w = d->uv[2 * m + ax];
-            if (!std::isfinite(w)) {
-                set_error("non-finite uv coordinate");
-                return PURIFY_E_INVALID;
+    std::atomic<bool> bad_uv{false};
+    host_parallel(M, 16384, [&](int64_t m0, int64_t m1) {
+        for (int64_t m = m0; m < m1; ++m) {
+            int k0m[2];
+            for (int ax = 0; ax < 2; ++ax) {
+                double w = d->uv[2 * m + ax];
+                if (!std::isfinite(w)) {
+                    bad_uv.store(true, std::memory_order_relaxed);
+                    w = 0.0;
+                }
+                if (w < -M_PI || w >= M_PI) {
+                    w = std::fmod(w + M_PI, twopi);
+                    if (w < 0) w += twopi;
+                    w -= M_PI;
+                    if (w >= M_PI) w -= twopi;
+                }
+                const double kap = (w * K) / (2.0 * M_PI);
+                const double k0 = std::floor(kap - 0.5 * J) + 1.0;
+                fr[2 * m + ax] = kap - k0 - (0.5 * J - 1.0);
+                int km = (int)((int64_t)k0 % K);
+                if (km < 0) km += K;
+                k0m[ax] = km;
             }
-            if (w < -M_PI || w >= M_PI) {
-                w = std::fmod(w + M_PI, twopi);
-                if (w < 0) w += twopi;
-                w -= M_PI;
-                if (w >= M_PI) w -= twopi;
-            }
-            const double kap = (w * K) / (2.0 * M_PI);
-            const double k0 = std::floor(kap - 0.5 * J) + 1.0;
-            fr[2 * m + ax] = kap - k0 - (0.5 * J - 1.0);
-            int km = (int)((int64_t)k0 % K);
-            if (km < 0) km += K;
-            k0m[ax] = km;
+            base[m] = k0m[0] | (k0m[1] << 16);
+            const int t1 = k0m[0] / TT, t2 = k0m[1] / TT;
+            const int s1 = (k0m[0] % TT) + J - 1 >= TT, s2 = (k0m[1] % TT) + J - 1 >= TT;
+            key[m] = (t2 * nT + t1) * 4 + rank_of_class[s1 + 2 * s2];
         }
-        base[m] = k0m[0] | (k0m[1] << 16);
-        const int t1 = k0m[0] / TT, t2 = k0m[1] / TT;
-        const int s1 = (k0m[0] % TT) + J - 1 >= TT, s2 = (k0m[1] % TT) + J - 1 >= TT;
-        key[m] = (t2 * nT + t1) * 4 + rank_of_class[s1 + 2 * s2];
-        ++cnt[key[m] + 1];
+    });
+    if (bad_uv.load()) {
+        set_error("non-finite uv coordinate");
+        return PURIFY_E_INVALID;
     }
+    std::vector<int64_t> cnt(nkeys + 1, 0);
+    for (int64_t m = 0; m < M; ++m) ++cnt[key[m] + 1];
     for (int k = 0; k < nkeys; ++k) cnt[k + 1] += cnt[k];
     std::vector<int32_t> off(nkeys + 1);
     for (int k = 0; k <= nkeys; ++k) off[k] = (int32_t)cnt[k];
     // Order: by (tile, spill class), then by first-tap cell inside each bucket (row-major),
-    // ties in caller order.  Neighbouring visibilities then share grid cache lines.
+    // ties in caller order.  Neighbouring visibilities then share grid cache lines.  A
+    // bucket arrives in caller order, so sorting by (cell, index) is the stable order; the
+    // buckets are sorted on host threads.
     std::vector<int32_t> order(M);
     {
         std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
         for (int64_t m = 0; m < M; ++m) order[pos[key[m]]++] = (int32_t)m;
-        for (int k = 0; k < nkeys; ++k) {
-            auto b0 = order.begin() + off[k], b1 = order.begin() + off[k + 1];
-            if (b1 - b0 > 1)
-                std::stable_sort(b0, b1, [&](int32_t a, int32_t b) {
-                    const int ca = ((base[a] & 0xFFFF) << 16) | ((base[a] >> 16) & 0xFFFF);
-                    const int cb = ((base[b] & 0xFFFF) << 16) | ((base[b] >> 16) & 0xFFFF);
-                    return ca < cb;
-                });
-        }
+        host_parallel(nkeys, M < 65536 ? nkeys : 64, [&](int64_t k0, int64_t k1) {
+            for (int64_t k = k0; k < k1; ++k) {
+                auto b0 = order.begin() + off[k], b1 = order.begin() + off[k + 1];
+                if (b1 - b0 > 1)
+                    std::sort(b0, b1, [&](int32_t a, int32_t b) {
+                        const int ca = ((base[a] & 0xFFFF) << 16) | ((base[a] >> 16) & 0xFFFF);
+                        const int cb = ((base[b] & 0xFFFF) << 16) | ((base[b] >> 16) & 0xFFFF);
+                        return ca < cb || (ca == cb && a < b);
+                    });
+            }
+        });
     }
     std::vector<int32_t> perm(M), sbase(M);
     std::vector<double> sfr(2 * M);
-    for (int64_t p = 0; p < M; ++p) {
-        const int32_t m = order[p];
-        perm[p] = m;
-        sbase[p] = base[m];
-        sfr[2 * p] = fr[2 * m];
-        sfr[2 * p + 1] = fr[2 * m + 1];
-    }
+    host_parallel(M, 65536, [&](int64_t p0, int64_t p1) {
+        for (int64_t p = p0; p < p1; ++p) {
+            const int32_t m = order[p];
+            perm[p] = m;
+            sbase[p] = base[m];
+            sfr[2 * p] = fr[2 * m];
+            sfr[2 * p + 1] = fr[2 * m + 1];
+        }
+    });
 
     // Heaviest gridding workgroup: own visibilities plus the spill-ins from three neighbours.
     P.max_tile_load = 0;

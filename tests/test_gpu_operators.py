@@ -95,6 +95,16 @@ def test_uv_outside_principal_range_is_wrapped():
     assert rel_l2(to_np(b.phi(x)), to_np(a.phi(x))) < 1e-12
 
 
+@pytest.mark.parametrize("M", [200, 70000])   # serial and threaded binning
+def test_plan_rejects_non_finite_uv(M):
+    uv = uv_case(M, 64, 12)
+    uv[M - 37, 1] = np.nan
+    uv[M // 3, 0] = np.inf
+    with pytest.raises(purify.PurifyError) as e:
+        purify.Plan(64, uv, dict_mask=1, levels=1, device=DEV)
+    assert e.value.status == 1 and "non-finite uv" in str(e.value)
+
+
 PSI_CASES = [  # n, mask, levels
     (16, 0x1FF, 2),
     (16, 1 << 8, 3),     # Db8 (16 taps) wrapping a length-2 coarse axis
