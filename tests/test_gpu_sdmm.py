@@ -126,6 +126,26 @@ def test_sdmm_bitwise_repeatable_and_graph_equals_eager(prec):
     assert np.array_equal(a.history, c.history)
 
 
+@pytest.mark.parametrize("n,M,prec", [(1024, 400000, "fp32"), (2048, 600000, "fp64"),
+                                      (4096, 1000000, "fp32")])
+def test_sdmm_large_images_graph_equals_eager(n, M, prec):
+    # The solver's launch shapes for long lines (n >= 1024: four-pass row plans; from 2048
+    # on, column passes that keep several columns per thread in registers) through a few
+    # iterations: graph replay and eager launches agree bit for bit, and every history value
+    # is finite.
+    from gpu_cases import rand_complex, uv_case
+    plan = purify.Plan(n, uv_case(M, n, 21), J=6, dict_mask=0x1FF, levels=4, precision=prec,
+                       device=DEV)
+    y = plan.phi(plan.as_vec(np.abs(rand_complex((n, n), 22))))
+    eps = 1e-2 * float(torch.linalg.vector_norm(y).item())
+    a = plan.sdmm(y, eps, max_iter=3, nu_iter=5, record_history=True)
+    c = plan.sdmm(y, eps, max_iter=3, nu_iter=5, record_history=True, graph=False)
+    assert np.array_equal(to_np(a.x), to_np(c.x))
+    assert np.array_equal(a.history, c.history)
+    assert np.all(np.isfinite(a.history)) and np.all(np.isfinite(to_np(a.x)))
+    assert a.nu > 0 and np.isfinite(a.nu)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
 def test_sdmm_heavy_tiles_split_gridding_units(prec, tol):
     # 128 x 128 image, 100 000 visibilities concentrated at low spatial frequencies: the
