@@ -319,20 +319,32 @@ template <typename T, int LOGN>
 constexpr int table_elems() { return twiddles_in_lds<T, LOGN>() ? (1 << LOGN) : 0; }
 
 // ---------------------------------------------------------------------------------------
-// Sum of a partial-sum buffer by one workgroup of any size, in a fixed order (every
-// workgroup gets the identical value).
-__device__ __forceinline__ double sum_parts_dyn(const double* __restrict__ part, int count, double* red) {
-    double acc = 0;
-    for (int i = threadIdx.x; i < count; i += blockDim.x) acc += part[i];
+// Sums of two partial-sum buffers by one workgroup of any size, in one pass and in a fixed
+// order (thread-strided, then across lanes, then across waves in wave order), so every
+// workgroup gets the identical values; red holds 32 doubles.
+__device__ __forceinline__ void sum_parts2_dyn(const double* __restrict__ pa, int na, const double* __restrict__ pb,
+                                               int nb, double* red, double& ta, double& tb) {
+    double a = 0, b = 0;
+    for (int i = threadIdx.x; i < na; i += blockDim.x) a += pa[i];
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) b += pb[i];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = a;
+        red[16 + (threadIdx.x >> 6)] = b;
+    }
     __syncthreads();
-    double t = 0;
+    ta = 0;
+    tb = 0;
     const int nw = (blockDim.x + 63) >> 6;
-    for (int i = 0; i < nw; ++i) t += red[i];
+    for (int i = 0; i < nw; ++i) {
+        ta += red[i];
+        tb += red[16 + i];
+    }
     __syncthreads();
-    return t;
 }
 
 // Block sum of one value per thread (result in thread 0), any block size.
@@ -423,7 +435,7 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[16];
+    __shared__ double red[32];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int tl = threadIdx.x % PL::TL, r = (threadIdx.x / PL::TL) & 1, lr = threadIdx.x / (2 * PL::TL);
     cpx<T>* line = base + table_elems<T, LOGN>() + (2 * lr + r) * PL::LS;
@@ -441,8 +453,8 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
         pv[i] = cg.p[ro + p];
         qv[i] = cg.q[ro + p];
     }
-    const double rho = sum_parts_dyn(cg.rho_part, cg.rho_count, red);
-    const double pq = sum_parts_dyn(cg.pq_part, cg.pq_count, red);
+    double rho, pq;
+    sum_parts2_dyn(cg.rho_part, cg.rho_count, cg.pq_part, cg.pq_count, red, rho, pq);
     const T alpha = (T)(rho == 0.0 ? 0.0 : rho / pq);
     double acc = 0;
 #pragma unroll
@@ -489,7 +501,7 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[16];
+    __shared__ double red[32];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int c = threadIdx.x % C, r = (threadIdx.x / C) & 1, tl = threadIdx.x / (2 * C);
     cpx<T>* line = base + table_elems<T, LOGN>() + (2 * c + r) * PL::LS;
@@ -500,8 +512,8 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
     for (int i = 0; i < PL::RMAX; ++i) v[i] = tmp[(size_t)PL::in_pos(tl, i) * K + col];
     if (cb.rho_new_part) {
         // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt for the next step
-        const double rn = sum_parts_dyn(cb.rho_new_part, cb.rho_new_count, red);
-        const double rho = sum_parts_dyn(cb.rho_part, cb.rho_count, red);
+        double rn, rho;
+        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
         const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) v[i] = v[i] + beta * dirt[(size_t)PL::in_pos(tl, i) * K + col];
@@ -537,7 +549,7 @@ k_fft_cols_fwd_mc(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, con
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[16];
+    __shared__ double red[32];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int r = threadIdx.x / PL::TL, tl = threadIdx.x % PL::TL;
     cpx<T>* line = base + table_elems<T, LOGN>() + r * PL::LS;
@@ -552,8 +564,8 @@ k_fft_cols_fwd_mc(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, con
     }
     if (cb.rho_new_part) {
         // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt
-        const double rn = sum_parts_dyn(cb.rho_new_part, cb.rho_new_count, red);
-        const double rho = sum_parts_dyn(cb.rho_part, cb.rho_count, red);
+        double rn, rho;
+        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
         const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) {
@@ -695,7 +707,7 @@ k_fft_cols_toep(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[16];
+    __shared__ double red[32];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int c = threadIdx.x % C, r = (threadIdx.x / C) & 1, tl = threadIdx.x / (2 * C);
     cpx<T>* lines = base + table_elems<T, LOGN>();
@@ -707,8 +719,8 @@ k_fft_cols_toep(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const
     for (int i = 0; i < PL::RMAX; ++i) v[i] = in[(size_t)PL::in_pos(tl, i) * K + col];
     if (cb.rho_new_part) {
         // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt
-        const double rn = sum_parts_dyn(cb.rho_new_part, cb.rho_new_count, red);
-        const double rho = sum_parts_dyn(cb.rho_part, cb.rho_count, red);
+        double rn, rho;
+        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
         const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) v[i] = v[i] + beta * dirt[(size_t)PL::in_pos(tl, i) * K + col];
@@ -764,7 +776,7 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[16];
+    __shared__ double red[32];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int r = threadIdx.x & 1, tl = (threadIdx.x >> 1) % PL::TL, lr = threadIdx.x / (2 * PL::TL);
     cpx<T>* lines = base + table_elems<T, LOGN>() + (2 * lr) * PL::LS;
@@ -788,8 +800,8 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
     // CG direction update (with rin): v = r + beta v, written back to v
     T beta = 0;
     if (rin) {
-        const double rn = sum_parts_dyn(cb.rho_new_part, cb.rho_new_count, red);
-        const double rho = sum_parts_dyn(cb.rho_part, cb.rho_count, red);
+        double rn, rho;
+        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
         beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
     }
     double acc = 0.0;

@@ -62,6 +62,34 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
     return t;
 }
 
+// Two partial-sum buffers in one pass, each total the value sum_partials gives.
+__device__ __forceinline__ void sum_partials2(const double* __restrict__ pa, int na, const double* __restrict__ pb,
+                                              int nb, double& ta, double& tb) {
+    __shared__ double red3[2][VT / 64];
+    double a = 0, b = 0;
+    for (int i = threadIdx.x; i < na; i += VT) a += pa[i];
+    for (int i = threadIdx.x; i < nb; i += VT) b += pb[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red3[0][w] = a;
+        red3[1][w] = b;
+    }
+    __syncthreads();
+    ta = 0;
+    tb = 0;
+#pragma unroll
+    for (int i = 0; i < VT / 64; ++i) {
+        ta += red3[0][i];
+        tb += red3[1][i];
+    }
+    __syncthreads();
+}
+
 int red_blocks(int64_t n) {
     int64_t b = (n + VT - 1) / VT;
     return (int)(b < RED_BLOCKS ? (b < 1 ? 1 : b) : RED_BLOCKS);
@@ -183,8 +211,8 @@ k_cg_xr(cpx<T>* __restrict__ x, cpx<T>* __restrict__ r, const cpx<T>* __restrict
         p0 = p[i0];
         q0 = q[i0];
     }
-    const double rho = sum_partials(rho_part, rho_count);
-    const double pq = sum_partials(pq_part, pq_count);
+    double rho, pq;
+    sum_partials2(rho_part, rho_count, pq_part, pq_count, rho, pq);
     const T alpha = (T)(rho == 0.0 ? 0.0 : rho / pq);
     double acc = 0;
     GRID_STRIDE(i, n) {
