@@ -511,12 +511,23 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) v[i] = tmp[(size_t)PL::in_pos(tl, i) * K + col];
     if (cb.rho_new_part) {
-        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt for the next step
+        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt for the next step.
+        // Short lines: F_rows p is loaded before the partial sums are read (both in flight);
+        // long lines read it after (registers).
+        constexpr bool PRE = PL::RMAX <= 8;
+        cpx<T> d[PRE ? PL::RMAX : 1];
+        if constexpr (PRE) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) d[i] = dirt[(size_t)PL::in_pos(tl, i) * K + col];
+        }
         double rn, rho;
         sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
         const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
 #pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) v[i] = v[i] + beta * dirt[(size_t)PL::in_pos(tl, i) * K + col];
+        for (int i = 0; i < PL::RMAX; ++i) {
+            if constexpr (PRE) v[i] = v[i] + beta * d[i];
+            else v[i] = v[i] + beta * dirt[(size_t)PL::in_pos(tl, i) * K + col];
+        }
         __syncthreads();   // both parity groups have read dirt
         if (r == 0) {
 #pragma unroll
@@ -791,12 +802,20 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
         const cpx<T> u = inr[2 * kp + r];
         v[i] = (kp & 1) ? neg(u) : u;
     }
-    line_fft<T, LOGN, 0, true>(v, line, tl, W);
-    __syncthreads();
+    // The epilogue's operands (v, and r of the CG direction update) and beta are read before
+    // the transform, so their loads and the partial sums overlap the input's (short lines;
+    // long lines read the operands in the epilogue).
+    constexpr int NQ = PL::RMAX / 2;
+    constexpr bool PRE = PL::RMAX <= 8;
+    cpx<T> pv[PRE ? NQ : 1], pr[PRE ? NQ : 1];
+    if constexpr (PRE) {
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
-    __syncthreads();
-    const T srow = c1 * deap[row];
+        for (int q = 0; q < NQ; ++q) {
+            const size_t off = (size_t)row * N + r + 2 * tl + q * 2 * PL::TL;
+            if (vin) pv[q] = vin[off];
+            if (rin) pr[q] = rin[off];
+        }
+    }
     // CG direction update (with rin): v = r + beta v, written back to v
     T beta = 0;
     if (rin) {
@@ -804,17 +823,26 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
         sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
         beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
     }
+    line_fft<T, LOGN, 0, true>(v, line, tl, W);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
+    __syncthreads();
+    const T srow = c1 * deap[row];
     double acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < PL::RMAX / 2; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         const int j = r + 2 * tl + q * 2 * PL::TL;
         const cpx<T> t = lines[j] + mul_mi(mulc(lines[PL::LS + j], tw2[j]));
         cpx<T> o = (srow * deap[j]) * t;
         const size_t off = (size_t)row * N + j;
         if (vin) {
-            cpx<T> vv = vin[off];
+            cpx<T> vv;
+            if constexpr (PRE) vv = pv[q];
+            else vv = vin[off];
             if (rin) {
-                vv = rin[off] + beta * vv;
+                if constexpr (PRE) vv = pr[q] + beta * vv;
+                else vv = rin[off] + beta * vv;
                 vin[off] = vv;
             }
             o = o + c2 * vv;
