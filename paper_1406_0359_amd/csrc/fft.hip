@@ -453,6 +453,18 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
         pv[i] = cg.p[ro + p];
         qv[i] = cg.q[ro + p];
     }
+    // short lines: the transform's S and parity twiddles are read here too
+    constexpr bool PRE = PL::RMAX <= 8 && 2 * B * PL::TL <= 512;   // register budget
+    T dq[PRE ? PL::RMAX : 1];
+    cpx<T> t2[PRE ? PL::RMAX : 1];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int p = PL::in_pos(tl, i);
+            dq[i] = deap[p];
+            t2[i] = r ? tw2[p] : mk<T>(1, 0);
+        }
+    }
     double rho, pq;
     sum_parts2_dyn(cg.rho_part, cg.rho_count, cg.pq_part, cg.pq_count, red, rho, pq);
     const T alpha = (T)(rho == 0.0 ? 0.0 : rho / pq);
@@ -478,8 +490,14 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
         const int p = PL::in_pos(tl, i);
-        cpx<T> a = (srow * deap[p]) * rv[i];
-        if (r) a = a * tw2[p];
+        cpx<T> a;
+        if constexpr (PRE) {
+            a = (srow * dq[i]) * rv[i];
+            if (r) a = a * t2[i];
+        } else {
+            a = (srow * deap[p]) * rv[i];
+            if (r) a = a * tw2[p];
+        }
         rv[i] = a;
     }
     line_fft<T, LOGN, 0, false>(rv, line, tl, W);
@@ -510,11 +528,16 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
     cpx<T> v[PL::RMAX];
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) v[i] = tmp[(size_t)PL::in_pos(tl, i) * K + col];
+    constexpr bool PRE = PL::RMAX <= 8 && 2 * C * PL::TL <= 512;   // register budget
+    cpx<T> t2[PRE ? PL::RMAX : 1];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) t2[i] = r ? tw2[PL::in_pos(tl, i)] : mk<T>(1, 0);
+    }
     if (cb.rho_new_part) {
         // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt for the next step.
         // Short lines: F_rows p is loaded before the partial sums are read (both in flight);
         // long lines read it after (registers).
-        constexpr bool PRE = PL::RMAX <= 8;
         cpx<T> d[PRE ? PL::RMAX : 1];
         if constexpr (PRE) {
 #pragma unroll
@@ -536,7 +559,11 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
     }
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
-        if (r) v[i] = v[i] * tw2[PL::in_pos(tl, i)];
+        if constexpr (PRE) {
+            if (r) v[i] = v[i] * t2[i];
+        } else {
+            if (r) v[i] = v[i] * tw2[PL::in_pos(tl, i)];
+        }
     }
     line_fft<T, LOGN, 1, false>(v, line, tl, W);
 #pragma unroll
@@ -690,6 +717,14 @@ k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const 
         const cpx<T> u = grid[(size_t)(2 * kp + r) * K + col];
         v[i] = (kp & 1) ? neg(u) : u;
     }
+    // short lines: the combine's twiddles are read before the transform
+    constexpr int NQ = PL::RMAX / 2;
+    constexpr bool PRE = PL::RMAX <= 8 && 2 * C * PL::TL <= 512;   // register budget
+    cpx<T> tj[PRE ? NQ : 1];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tj[q] = tw2[r + 2 * tl + q * 2 * PL::TL];
+    }
     line_fft<T, LOGN, 1, true>(v, line, tl, W);
     __syncthreads();
 #pragma unroll
@@ -698,9 +733,10 @@ k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const 
     const cpx<T>* la = lines + (2 * c) * PL::LS;
     const cpx<T>* lb = la + PL::LS;
 #pragma unroll
-    for (int q = 0; q < PL::RMAX / 2; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         const int j = r + 2 * tl + q * 2 * PL::TL;
-        tmp[(size_t)j * K + col] = la[j] + mul_mi(mulc(lb[j], tw2[j]));
+        if constexpr (PRE) tmp[(size_t)j * K + col] = la[j] + mul_mi(mulc(lb[j], tj[q]));
+        else tmp[(size_t)j * K + col] = la[j] + mul_mi(mulc(lb[j], tw2[j]));
     }
 }
 
@@ -729,12 +765,22 @@ k_fft_cols_toep(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) v[i] = in[(size_t)PL::in_pos(tl, i) * K + col];
     if (cb.rho_new_part) {
-        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt
+        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt (short lines:
+        // F_rows p loaded before the partial sums are read, as in k_fft_cols_fwd)
+        constexpr bool PRE = PL::RMAX <= 8 && 2 * C * PL::TL <= 512;   // register budget
+        cpx<T> d[PRE ? PL::RMAX : 1];
+        if constexpr (PRE) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) d[i] = dirt[(size_t)PL::in_pos(tl, i) * K + col];
+        }
         double rn, rho;
         sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
         const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
 #pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) v[i] = v[i] + beta * dirt[(size_t)PL::in_pos(tl, i) * K + col];
+        for (int i = 0; i < PL::RMAX; ++i) {
+            if constexpr (PRE) v[i] = v[i] + beta * d[i];
+            else v[i] = v[i] + beta * dirt[(size_t)PL::in_pos(tl, i) * K + col];
+        }
         __syncthreads();   // both parity groups have read dirt
         if (r == 0) {
 #pragma unroll
@@ -806,14 +852,18 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
     // the transform, so their loads and the partial sums overlap the input's (short lines;
     // long lines read the operands in the epilogue).
     constexpr int NQ = PL::RMAX / 2;
-    constexpr bool PRE = PL::RMAX <= 8;
-    cpx<T> pv[PRE ? NQ : 1], pr[PRE ? NQ : 1];
+    constexpr bool PRE = PL::RMAX <= 8 && 2 * B * PL::TL <= 512;   // register budget
+    cpx<T> pv[PRE ? NQ : 1], pr[PRE ? NQ : 1], tj[PRE ? NQ : 1];
+    T dj[PRE ? NQ : 1];
     if constexpr (PRE) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const size_t off = (size_t)row * N + r + 2 * tl + q * 2 * PL::TL;
+            const int j = r + 2 * tl + q * 2 * PL::TL;
+            const size_t off = (size_t)row * N + j;
             if (vin) pv[q] = vin[off];
             if (rin) pr[q] = rin[off];
+            tj[q] = tw2[j];
+            dj[q] = deap[j];
         }
     }
     // CG direction update (with rin): v = r + beta v, written back to v
@@ -833,8 +883,14 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int j = r + 2 * tl + q * 2 * PL::TL;
-        const cpx<T> t = lines[j] + mul_mi(mulc(lines[PL::LS + j], tw2[j]));
-        cpx<T> o = (srow * deap[j]) * t;
+        cpx<T> o;
+        if constexpr (PRE) {
+            const cpx<T> t = lines[j] + mul_mi(mulc(lines[PL::LS + j], tj[q]));
+            o = (srow * dj[q]) * t;
+        } else {
+            const cpx<T> t = lines[j] + mul_mi(mulc(lines[PL::LS + j], tw2[j]));
+            o = (srow * deap[j]) * t;
+        }
         const size_t off = (size_t)row * N + j;
         if (vin) {
             cpx<T> vv;
