@@ -407,12 +407,30 @@ k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* 
     cpx<T> v[PL::RMAX];
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) v[i] = xr[PL::in_pos(tl, i)];
+    // short lines: S and the parity twiddles are read before the barrier too
+    constexpr bool PRE = PL::RMAX <= 8 && 2 * B * PL::TL <= 512;   // register budget
+    T dq[PRE ? PL::RMAX : 1];
+    cpx<T> t2[PRE ? PL::RMAX : 1];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int p = PL::in_pos(tl, i);
+            dq[i] = deap[p];
+            t2[i] = r ? tw2[p] : mk<T>(1, 0);
+        }
+    }
     __syncthreads();   // the twiddle table is staged
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
         const int p = PL::in_pos(tl, i);
-        cpx<T> a = (srow * deap[p]) * v[i];
-        if (r) a = a * tw2[p];
+        cpx<T> a;
+        if constexpr (PRE) {
+            a = (srow * dq[i]) * v[i];
+            if (r) a = a * t2[i];
+        } else {
+            a = (srow * deap[p]) * v[i];
+            if (r) a = a * tw2[p];
+        }
         v[i] = a;
     }
     line_fft<T, LOGN, 0, false>(v, line, tl, W);
