@@ -25,9 +25,23 @@ struct WavArgs {
 
 // filters layout: [basis][0..15] = h, [basis][16..31] = g.  Kernels stage a basis' taps in
 // LDS (lanes index them by output parity, which a register array cannot serve).
-template <typename T>
-__device__ __forceinline__ void load_taps(T* sh, const T* __restrict__ filt, int basis) {
-    if (threadIdx.x < 2 * MAX_TAPS) sh[threadIdx.x] = filt[basis * 2 * MAX_TAPS + threadIdx.x];
+
+// Global-to-LDS staging of `count` elements (element i read by ld(i) and stored by st(i, v),
+// count <= MAXE NTH): a thread issues the loads of all its elements before storing any, so
+// they are in flight together rather than one memory latency after another.
+template <typename V, int MAXE, int NTH, typename Ld, typename St>
+__device__ __forceinline__ void stage_batched(int count, int tid, Ld ld, St st) {
+    V v[MAXE];
+#pragma unroll
+    for (int k = 0; k < MAXE; ++k) {
+        const int i = tid + k * NTH;
+        if (i < count) v[k] = ld(i);
+    }
+#pragma unroll
+    for (int k = 0; k < MAXE; ++k) {
+        const int i = tid + k * NTH;
+        if (i < count) st(i, v[k]);
+    }
 }
 
 // Every level is one launch of 2D tiles over all bases, both axes through LDS.  Each thread
@@ -67,22 +81,29 @@ k_wav_fwd_level(const cpx<T>* __restrict__ src, size_t src_bstride, int src_ld, 
     const int z = blockIdx.z;
     if (z == A.nwav) {
         cpx<T>* d = alpha + (size_t)A.dirac_block * N;
-        for (int i = threadIdx.x; i < 4 * ap * ap; i += 256) {
-            const size_t o = (size_t)(r0 + i / (2 * ap)) * n + c0 + i % (2 * ap);
-            d[o] = scale * src[o];
-        }
+        auto at = [&](int i) { return (size_t)(r0 + i / (2 * ap)) * n + c0 + i % (2 * ap); };
+        stage_batched<cpx<T>, 4 * AP * AP / 256, 256>(
+            4 * ap * ap, threadIdx.x, [&](int i) { return src[at(i)]; },
+            [&](int i, cpx<T> v) { d[at(i)] = scale * v; });
         return;
     }
     const size_t blk = (size_t)A.block[z] * N;
     const cpx<T>* s = src + (size_t)z * src_bstride;
     const int F = A.flen[z];
     const int R = 2 * ap + F - 2, RH = R >> 1;
-    load_taps(tp, filt, z);
-    for (int i = threadIdx.x; i < R * R; i += 256) {
-        const int a = i / R, b = i - a * R;
-        in[a * IS + (b & 1) * RH + (b >> 1)] =
-            s[(size_t)((r0 + a) & (Ls - 1)) * src_ld + ((c0 + b) & (Ls - 1))];
-    }
+    // the taps and the window (R <= AR) are loaded together, then stored to LDS
+    const T tap = threadIdx.x < 2 * MAX_TAPS ? filt[z * 2 * MAX_TAPS + threadIdx.x] : (T)0;
+    stage_batched<cpx<T>, (AR * AR + 255) / 256, 256>(
+        R * R, threadIdx.x,
+        [&](int i) {
+            const int a = i / R, b = i - a * R;
+            return s[(size_t)((r0 + a) & (Ls - 1)) * src_ld + ((c0 + b) & (Ls - 1))];
+        },
+        [&](int i, cpx<T> v) {
+            const int a = i / R, b = i - a * R;
+            in[a * IS + (b & 1) * RH + (b >> 1)] = v;
+        });
+    if (threadIdx.x < 2 * MAX_TAPS) tp[threadIdx.x] = tap;
     __syncthreads();
     // axis 1: window row a, position oi -> mid[a][oi] (low), mid[a][ap + oi] (high)
     for (int i = threadIdx.x; i < R * ap; i += 256) {
@@ -145,18 +166,25 @@ k_wav_fwd_level0_all(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ alpha, c
     const int ti1 = blockIdx.x / tiles, ti2 = blockIdx.x % tiles;
     const int r0 = 2 * AP * ti1, c0 = 2 * AP * ti2;
     const int R = 2 * AP + Fmax - 2, RH = R >> 1;
-    for (int i = threadIdx.x; i < A.nwav * 2 * MAX_TAPS; i += 256)
-        tp[i / (2 * MAX_TAPS)][i % (2 * MAX_TAPS)] = filt[i];
-    for (int i = threadIdx.x; i < R * R; i += 256) {
-        const int a = i / R, b = i - a * R;
-        in[a * IS + (b & 1) * RH + (b >> 1)] = x[(size_t)((r0 + a) & (Ls - 1)) * n + ((c0 + b) & (Ls - 1))];
-    }
+    // the taps of every basis (at most 256 values) and the window are loaded together
+    const T tap = threadIdx.x < A.nwav * 2 * MAX_TAPS ? filt[threadIdx.x] : (T)0;
+    stage_batched<cpx<T>, (AR * AR + 255) / 256, 256>(
+        R * R, threadIdx.x,
+        [&](int i) {
+            const int a = i / R, b = i - a * R;
+            return x[(size_t)((r0 + a) & (Ls - 1)) * n + ((c0 + b) & (Ls - 1))];
+        },
+        [&](int i, cpx<T> v) {
+            const int a = i / R, b = i - a * R;
+            in[a * IS + (b & 1) * RH + (b >> 1)] = v;
+        });
+    if (threadIdx.x < A.nwav * 2 * MAX_TAPS) tp[threadIdx.x / (2 * MAX_TAPS)][threadIdx.x % (2 * MAX_TAPS)] = tap;
     if (A.dirac_block >= 0) {
         cpx<T>* d = alpha + (size_t)A.dirac_block * N;
-        for (int i = threadIdx.x; i < 4 * AP * AP; i += 256) {
-            const size_t o = (size_t)(r0 + i / (2 * AP)) * n + c0 + i % (2 * AP);
-            d[o] = scale * x[o];
-        }
+        auto at = [&](int i) { return (size_t)(r0 + i / (2 * AP)) * n + c0 + i % (2 * AP); };
+        stage_batched<cpx<T>, 4 * AP * AP / 256, 256>(
+            4 * AP * AP, threadIdx.x, [&](int i) { return x[at(i)]; },
+            [&](int i, cpx<T> v) { d[at(i)] = scale * v; });
     }
     __syncthreads();
     for (int z = 0; z < A.nwav; ++z) {
@@ -213,19 +241,28 @@ k_wav_fwd_level0_all(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ alpha, c
 template <typename T, int NTH, int CMAX, typename Emit>
 __device__ __forceinline__ void synth_tile(const cpx<T>* __restrict__ alpha, size_t blk, const cpx<T>* __restrict__ lls,
                                           int lld, int n, int half, int po, int m0, int m1, int F,
-                                          const T* tp, cpx<T>* in, cpx<T>* mid, int tid, Emit emit) {
+                                          const T* __restrict__ ftaps, T* tp, cpx<T>* in, cpx<T>* mid, int tid,
+                                          Emit emit) {
     constexpr int WS = 2 * CMAX + 1;   // LDS row stride of `in` and `mid`
     const int C = po / 2 + F / 2 - 1;
     const int s0 = m0 / 2 - F / 2 + 1, s1 = m1 / 2 - F / 2 + 1;   // first window index
-    for (int i = tid; i < 4 * C * C; i += NTH) {
-        const int u = i / (2 * C), v = i - u * (2 * C);
-        const bool h0 = u >= C, h1 = v >= C;
-        const int i0 = (s0 + (h0 ? u - C : u)) & (half - 1), i1 = (s1 + (h1 ? v - C : v)) & (half - 1);
-        cpx<T> val;
-        if (!h0 && !h1) val = lls[(size_t)i0 * lld + i1];
-        else val = alpha[blk + (size_t)(i0 + (h0 ? half : 0)) * n + i1 + (h1 ? half : 0)];
-        in[u * WS + v] = val;
-    }
+    // the basis' taps (ftaps, into tp) and the window (C <= CMAX) are loaded together, then
+    // stored to LDS
+    const T tap = tid < 2 * MAX_TAPS ? ftaps[tid] : (T)0;
+    stage_batched<cpx<T>, (4 * CMAX * CMAX + NTH - 1) / NTH, NTH>(
+        4 * C * C, tid,
+        [&](int i) {
+            const int u = i / (2 * C), v = i - u * (2 * C);
+            const bool h0 = u >= C, h1 = v >= C;
+            const int i0 = (s0 + (h0 ? u - C : u)) & (half - 1), i1 = (s1 + (h1 ? v - C : v)) & (half - 1);
+            return (!h0 && !h1) ? lls[(size_t)i0 * lld + i1]
+                                : alpha[blk + (size_t)(i0 + (h0 ? half : 0)) * n + i1 + (h1 ? half : 0)];
+        },
+        [&](int i, cpx<T> val) {
+            const int u = i / (2 * C), v = i - u * (2 * C);
+            in[u * WS + v] = val;
+        });
+    if (tid < 2 * MAX_TAPS) tp[tid] = tap;
     __syncthreads();
     // undo axis 0: output rows 2j, 2j+1 (j = m0/2 + jr) for every window column v
     const int hp = po / 2;
@@ -295,9 +332,9 @@ k_wav_inv_level(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ lli
     const size_t blk = (size_t)A.block[z] * N;
     const cpx<T>* lls = ll_from_alpha ? alpha + blk : llin + (size_t)z * (N / 4);
     const int lld = ll_from_alpha ? n : half;
-    load_taps(tp, filt, z);
     cpx<T>* o = out + (size_t)z * (N / 4);
-    synth_tile<T, 256, SC>(alpha, blk, lls, lld, n, half, po, m0, m1, A.flen[z], tp, in, mid, (int)threadIdx.x,
+    synth_tile<T, 256, SC>(alpha, blk, lls, lld, n, half, po, m0, m1, A.flen[z], filt + z * 2 * MAX_TAPS, tp, in,
+                           mid, (int)threadIdx.x,
                        [&](int, int r, int c, cpx<T> e, cpx<T> od) {
                            o[(size_t)(m0 + r) * Ls + m1 + c] = e;
                            o[(size_t)(m0 + r) * Ls + m1 + c + 1] = od;
@@ -337,10 +374,9 @@ k_wav_inv_final(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ lli
         const cpx<T>* lls = ll_from_alpha ? alpha + blk : llin + (size_t)zz * (N / 4);
         const int lld = ll_from_alpha ? n : half;
         if (rd > 0) __syncthreads();
-        if (tid < 2 * MAX_TAPS) tp[slot][tid] = filt[zz * 2 * MAX_TAPS + tid];
         // inactive slots run on basis 0 and discard the result (keeps the barriers uniform)
-        synth_tile<T, 256, CF>(alpha, blk, lls, lld, n, half, FP, m0, m1, A.flen[zz], tp[slot], in[slot], mid[slot],
-                               tid, [&](int k, int, int, cpx<T> e, cpx<T> od) {
+        synth_tile<T, 256, CF>(alpha, blk, lls, lld, n, half, FP, m0, m1, A.flen[zz], filt + zz * 2 * MAX_TAPS,
+                               tp[slot], in[slot], mid[slot], tid, [&](int k, int, int, cpx<T> e, cpx<T> od) {
                                    if (active) {
                                        acc0[k].x += e.x;
                                        acc0[k].y += e.y;
