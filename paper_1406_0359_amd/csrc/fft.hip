@@ -324,9 +324,24 @@ constexpr int table_elems() { return twiddles_in_lds<T, LOGN>() ? (1 << LOGN) : 
 // workgroup gets the identical values; red holds 32 doubles.
 __device__ __forceinline__ void sum_parts2_dyn(const double* __restrict__ pa, int na, const double* __restrict__ pb,
                                                int nb, double* red, double& ta, double& tb) {
+    // four loads of each buffer in flight at a time, added in the thread-strided order
     double a = 0, b = 0;
-    for (int i = threadIdx.x; i < na; i += blockDim.x) a += pa[i];
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) b += pb[i];
+    const int st = blockDim.x;
+    for (int i0 = threadIdx.x; i0 < na || i0 < nb; i0 += 4 * st) {
+        double va[4], vb[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = i0 + k * st;
+            va[k] = i < na ? pa[i] : 0.0;
+            vb[k] = i < nb ? pb[i] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = i0 + k * st;
+            if (i < na) a += va[k];
+            if (i < nb) b += vb[k];
+        }
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         a += __shfl_xor(a, o);

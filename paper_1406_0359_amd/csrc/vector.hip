@@ -46,10 +46,24 @@ __device__ __forceinline__ double block_max(double v) {
 
 // Every workgroup of a consumer kernel re-sums a partial-sum buffer in the same fixed
 // order, so all of them see the identical scalar (no finalize launch, still deterministic).
+// acc <- acc + part[i] (or fmax) over i = threadIdx.x + k VT, k = 0, 1, ... in that order,
+// four loads in flight at a time (the loop otherwise waits on each load in turn)
+template <bool MAX>
+__device__ __forceinline__ double strided_fold(const double* __restrict__ part, int count, double acc) {
+    for (int i0 = threadIdx.x; i0 < count; i0 += 4 * VT) {
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = i0 + k * VT < count ? part[i0 + k * VT] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i0 + k * VT < count) acc = MAX ? fmax(acc, v[k]) : acc + v[k];
+    }
+    return acc;
+}
+
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int count) {
     __shared__ double red2[VT / 64];
-    double acc = 0;
-    for (int i = threadIdx.x; i < count; i += VT) acc += part[i];
+    double acc = strided_fold<false>(part, count, 0.0);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -66,9 +80,8 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 __device__ __forceinline__ void sum_partials2(const double* __restrict__ pa, int na, const double* __restrict__ pb,
                                               int nb, double& ta, double& tb) {
     __shared__ double red3[2][VT / 64];
-    double a = 0, b = 0;
-    for (int i = threadIdx.x; i < na; i += VT) a += pa[i];
-    for (int i = threadIdx.x; i < nb; i += VT) b += pb[i];
+    double a = strided_fold<false>(pa, na, 0.0);
+    double b = strided_fold<false>(pb, nb, 0.0);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         a += __shfl_xor(a, o);
@@ -132,11 +145,9 @@ k_finalize(const double* __restrict__ part, int count, double* sc, int slot, int
            double* hist, int hist_index) {
     double acc = 0;
     if (op == FIN_MAX) {
-        for (int i = threadIdx.x; i < count; i += VT) acc = fmax(acc, part[i]);
-        acc = block_max(acc);
+        acc = block_max(strided_fold<true>(part, count, acc));
     } else {
-        for (int i = threadIdx.x; i < count; i += VT) acc += part[i];
-        acc = block_sum(acc);
+        acc = block_sum(strided_fold<false>(part, count, acc));
     }
     if (threadIdx.x != 0) return;
     const bool bad = !(acc == acc) || acc == INFINITY;
