@@ -24,6 +24,9 @@
 // registers (unrolled, compile-time roots of unity), and passes exchange data through one
 // LDS line buffer.  n = 1024 is two radix-32 passes: a single LDS round trip.  Inter-pass
 // twiddles come from an FP64-accurate table staged in LDS.
+#include <map>
+#include <mutex>
+
 #include "common.h"
 
 namespace purify {
@@ -951,11 +954,21 @@ int strip_groups(const Plan& P, int C) {
     return (P.strip_xcd && P.TT % C == 0) ? P.TT / C : 0;
 }
 
+// Raises a kernel's dynamic LDS limit above 64 KB once per process (per kernel), under a
+// lock: solves on several host threads (the server) then never change a kernel's attribute
+// while another thread launches or captures it.
+std::mutex g_lds_mu;
+std::map<const void*, size_t> g_lds_set;
+
 template <typename F>
 void set_lds_limit(F* f, size_t bytes) {
-    if (bytes > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(f),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (bytes <= 65536) return;
+    const void* k = reinterpret_cast<const void*>(f);
+    std::lock_guard<std::mutex> lk(g_lds_mu);
+    auto it = g_lds_set.find(k);
+    if (it != g_lds_set.end() && it->second >= bytes) return;
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        g_lds_set[k] = bytes;
 }
 
 template <typename T, int LOGN, int AX>
