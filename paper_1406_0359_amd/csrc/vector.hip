@@ -44,8 +44,6 @@ __device__ __forceinline__ double block_max(double v) {
     return t;
 }
 
-// Every workgroup of a consumer kernel re-sums a partial-sum buffer in the same fixed
-// order, so all of them see the identical scalar (no finalize launch, still deterministic).
 // acc <- acc + part[i] (or fmax) over i = threadIdx.x + k VT, k = 0, 1, ... in that order,
 // four loads in flight at a time (the loop otherwise waits on each load in turn)
 template <bool MAX>
@@ -61,6 +59,8 @@ __device__ __forceinline__ double strided_fold(const double* __restrict__ part, 
     return acc;
 }
 
+// Every workgroup of a consumer kernel re-sums a partial-sum buffer in the same fixed
+// order, so all of them see the identical scalar (no finalize launch, still deterministic).
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int count) {
     __shared__ double red2[VT / 64];
     double acc = strided_fold<false>(part, count, 0.0);
