@@ -69,8 +69,9 @@ def stage_bytes(plan, stage: str) -> float:
 
 # launches of each kernel stage per SDMM iteration with cg CG steps
 def launches_per_iter(cg: int) -> dict:
-    a = cg + 1            # A-applications in CG (warm-start residual + cg steps), each with
-                          # G^T G fused; Phi and Phi^dagger once more for the l2-ball branch
+    a = cg                # A-applications in CG (one per step; the warm-start residual's
+                          # A x_hat rides on the l2-ball branch's Phi^dagger), each with G^T G
+                          # fused; Phi and Phi^dagger once more for the l2-ball branch
     return {"fft_rows": a + 1, "fft_cols": a + 1, "degrid": 1, "grid": 1, "gtg": a,
             "ifft_cols": a + 1, "ifft_rows": a + 1, "psi_adj": 1, "psi": 1}
 

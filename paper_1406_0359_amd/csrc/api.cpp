@@ -46,13 +46,17 @@ struct Ops {
         launch_fft_rows_fwd<T>(P, v, (C*)P.tmp, s);
         normal_tail(nullptr, q, 1.0, 0.0, nullptr);
     }
-    // first CG step: q = A p, keeping p's row transform in dirt for the later steps
-    void apply_A_first(const C* p, C* q, double inv_nu2, double* dot) const {
-        launch_fft_rows_fwd<T>(P, p, (C*)P.dirt, s);
+    // first CG step: the set-up r = p = x1 + x2 + x3 - q0 (partial ||r||^2 into rho, count
+    // returned) in the row pass, then q = A p, keeping p's row transform in dirt for the
+    // later steps
+    int apply_A_first(const C* x1, const C* x2, const C* x3, const C* q0, C* r, C* p, C* q, double inv_nu2,
+                      double* rho, double* dot) const {
+        const int nb = launch_fft_rows_init<T>(P, x1, x2, x3, q0, r, p, rho, (C*)P.dirt, s);
         launch_fft_cols_fwd<T>(P, (const C*)P.dirt, (C*)P.grid, s);
         launch_gtg<T>(P, (const C*)P.grid, (C*)P.grid2, s);
         launch_fft_cols_adj<T>(P, (const C*)P.grid2, (C*)P.tmp, s);
         launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, inv_nu2, p, 2.0, dot, s);
+        return nb;
     }
     // a later CG step: the row pass applies the previous step's update (x += alpha p,
     // r -= alpha q, partial ||r||^2 into rho_new) and transforms r; the new direction
@@ -76,10 +80,12 @@ struct Ops {
     }
     // CG with T, as apply_A_first / apply_A_step: first step q = c1 T p + 2 p (p's row
     // transform kept in dirt), later steps with the previous update folded into the row pass
-    void toep_A_first(const C* p, C* q, double c1, double* dot) const {
-        launch_fft_rows_fwd<T>(P, p, (C*)P.dirt, s, P.unit);
+    int toep_A_first(const C* x1, const C* x2, const C* x3, const C* q0, C* r, C* p, C* q, double c1,
+                     double* rho, double* dot) const {
+        const int nb = launch_fft_rows_init<T>(P, x1, x2, x3, q0, r, p, rho, (C*)P.dirt, s, P.unit);
         launch_fft_cols_toep<T>(P, (C*)P.tmp, s, (const C*)P.dirt);
         launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, c1, p, 2.0, dot, s, P.unit);
+        return nb;
     }
     int toep_A_step(C* x, C* r, C* p, C* q, const double* rho, int rho_count, const double* pq, int pq_count,
                     double* rho_new, double c1, double* dot) const {
@@ -187,18 +193,17 @@ struct Sdmm {
         C *z1 = (C*)P.z1, *v1 = (C*)P.v1, *z2 = (C*)P.z2, *z3 = (C*)P.z3, *v3 = (C*)P.v3;
         const C* yt = (const C*)P.ytil;
         const int rows_blocks = fft_rows_adj_blocks<T>(P);
-        // Global update (step 5): CG on (Phi~^dag Phi~ + 2I) x = x1 + x2 + x3, warm start;
-        // q = A x_hat of the warm start was formed at the end of the previous iteration (or
-        // by enqueue_prologue), beside branch i = 1.
-        const int nb = launch_cg_init<T>(x1, x2, x3, q, r, p, N, part(0), s);
+        // Global update (step 5): CG on (Phi~^dag Phi~ + 2I) x = x1 + x2 + x3, warm started
+        // at x_hat, so r = x1 + x2 + x3 - A x_hat.  With the NUFFT operator, x3 already holds
+        // x3 - A x_hat (branch i = 3 below); with the stored operator, q = A x_hat was formed
+        // at the end of the previous iteration (or by enqueue_prologue) beside branch i = 1.
         // rho of step c (the residual norm before step c's update) is in buffer c & 1,
         // <p, A p> in buffer 2
-        // step 0: q = A p; step c > 0: step c - 1's update folded into the row pass, the new
-        // direction formed in the column and adjoint row passes (Ops::apply_A_step); then the
-        // last step's update
-        if (toep) op.toep_A_first(p, q, inv_nu2, part(2));
-        else op.apply_A_first(p, q, inv_nu2, part(2));
-        int rho_count = nb;
+        // step 0: the set-up r = p = x1 + x2 + x3 (- q) folded into its row pass, then q = A p;
+        // step c > 0: step c - 1's update folded into the row pass, the new direction formed
+        // in the column and adjoint row passes (Ops::apply_A_step); then the last step's update
+        int rho_count = toep ? op.toep_A_first(x1, x2, x3, q, r, p, q, inv_nu2, part(0), part(2))
+                             : op.apply_A_first(x1, x2, x3, nullptr, r, p, q, inv_nu2, part(0), part(2));
         for (int c = 1; c < prm->cg_iter; ++c) {
             if (toep)
                 rho_count = op.toep_A_step(xh, r, p, q, part((c - 1) & 1), rho_count, part(2), rows_blocks,
@@ -225,28 +230,38 @@ struct Sdmm {
         (void)hipEventRecord(join, s2);
         // i = 2: positivity
         launch_prox_pos<T>(xh, z2, x2, N, s);
-        // i = 3: l2 ball about y~ on Phi~ x_hat
+        // i = 3: l2 ball about y~ on Phi~ x_hat.  x3 = Phi~^dag (r3 - z3); with the NUFFT
+        // operator the next CG's A x_hat = Phi~^dag (Phi~ x_hat) + 2 x_hat is folded in by
+        // linearity: the projection leaves r3 - z3 - Phi~ x_hat in v3 and the adjoint's
+        // epilogue subtracts 2 x_hat, so x3 <- x3 - A x_hat costs no operator of its own.
+        const bool fold = !toep;
         op.phi(xh, v3, inv_nu, nullptr);
         if (nblk > 1) {   // R balls: chunk sums, per-block scales, projection by block
             launch_ball_part_blk<T>(v3, z3, yt, P.bperm, P.bchunk, nchunks, part(4), part(5), s);
             launch_ball_fin_blk(part(4), part(5), P.bchunk_off, P.beps, nblk, P.bscale, sc, P.hist, P.hist_cap, s);
-            launch_prox_ball_blk<T>(v3, z3, yt, P.bid, P.bscale, M, s);
+            launch_prox_ball_blk<T>(v3, z3, yt, P.bid, P.bscale, M, fold, s);
         } else {
             const int nb3 = launch_ball_part<T>(v3, z3, yt, M, part(4), part(5), s);
-            launch_prox_ball<T>(v3, z3, yt, part(4), part(5), nb3, eps_t, sc, P.hist, P.hist_cap, M, s);
+            launch_prox_ball<T>(v3, z3, yt, part(4), part(5), nb3, eps_t, sc, P.hist, P.hist_cap, M, fold, s);
         }
-        op.phi_adj(v3, nullptr, x3, inv_nu, nullptr, 0.0, nullptr);
-        // the next iteration's warm-start product A x_hat needs only x_hat: it runs here,
-        // overlapping branch i = 1 on the other stream
-        A(op, xh, q, nullptr);
+        if (fold) {
+            op.phi_adj(v3, nullptr, x3, inv_nu, xh, -2.0, nullptr);
+        } else {
+            op.phi_adj(v3, nullptr, x3, inv_nu, nullptr, 0.0, nullptr);
+            // the next iteration's warm-start product A x_hat with the stored operator needs
+            // only x_hat: it runs here, overlapping branch i = 1 on the other stream
+            A(op, xh, q, nullptr);
+        }
         (void)hipStreamWaitEvent(s, join, 0);
         launch_iter_advance(sc, s);
     }
 
-    // q = A x_hat for the first iteration's warm start.
+    // The first iteration's warm start: q = A x_hat, and with the NUFFT operator
+    // x3 <- x3 - q (the form every later iteration's branch i = 3 leaves in x3).
     void enqueue_prologue(hipStream_t s) const {
         const Ops<T> op{P, s};
         A(op, (const C*)P.xh, (C*)P.qv, nullptr);
+        if (!toep) launch_sub<T>((C*)P.x3, (const C*)P.qv, P.N, s);
     }
 };
 

@@ -170,6 +170,13 @@ template <typename T> void launch_fft_rows_fwd(const Plan& P, const cpx<T>* x, c
                                                const void* deap = nullptr);
 template <typename T> void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s);
 template <typename T> void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s);
+// first CG step's row pass with the CG set-up folded in: r = p = x1 + x2 + x3 - q0 (q0 may be
+// null), partial ||r||^2 per workgroup into rho_part (count returned), row transform of p
+// into tmp
+template <typename T> int launch_fft_rows_init(const Plan& P, const cpx<T>* x1, const cpx<T>* x2,
+                                               const cpx<T>* x3, const cpx<T>* q0, cpx<T>* r, cpx<T>* p,
+                                               double* rho_part, cpx<T>* tmp, hipStream_t s,
+                                               const void* deap = nullptr);
 // CG step from the second on, exact operator: row pass with alpha = rho / <p, q> (partials),
 // x += alpha p, r -= alpha q, partial ||r||^2 per row block (returns their count), row transform
 // of r into tmp
@@ -233,9 +240,6 @@ void launch_iter_advance(double* sc, hipStream_t s);
 void launch_finalize(const double* part, int count, double* sc, int slot, int op, double arg,
                      double* hist, int hist_index, hipStream_t s);
 
-template <typename T> int launch_cg_init(const cpx<T>* x1, const cpx<T>* x2, const cpx<T>* x3,
-                                         const cpx<T>* q, cpx<T>* r, cpx<T>* p, int64_t n,
-                                         double* part, hipStream_t s);
 // CG step with alpha = rho / <p, q> summed from partials inside the kernel
 template <typename T> int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q,
                                        const double* rho_part, int rho_count, const double* pq_part,
@@ -253,7 +257,7 @@ template <typename T> int launch_ball_part(const cpx<T>* v3, const cpx<T>* z3, c
                                            hipStream_t s);
 template <typename T> void launch_prox_ball(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const double* part_d,
                                             const double* part_res, int count, double eps, double* sc,
-                                            double* hist, int hist_cap, int64_t n, hipStream_t s);
+                                            double* hist, int hist_cap, int64_t n, bool diff, hipStream_t s);
 template <typename T> void launch_permute_scale(const cpx<T>* y_user, const int32_t* perm, double scale,
                                                 cpx<T>* y_sorted, int64_t n, hipStream_t s);
 template <typename T> void launch_scale_by_slot(cpx<T>* dst, const cpx<T>* src, const double* sc,
@@ -273,7 +277,9 @@ void launch_ball_fin_blk(const double* part_d, const double* part_res, const int
                          const double* eps, int R, double* scale, double* sc, double* hist, int hist_cap,
                          hipStream_t s);
 template <typename T> void launch_prox_ball_blk(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const int32_t* bid,
-                                                const double* scale, int64_t n, hipStream_t s);
+                                                const double* scale, int64_t n, bool diff, hipStream_t s);
+// a -= b
+template <typename T> void launch_sub(cpx<T>* a, const cpx<T>* b, int64_t n, hipStream_t s);
 // TV prior, branch i = 1: u = x_hat + z1 (into u), `iters` dual projection steps, then
 // r1 = u - gamma div p, z1 = u - r1, x1 = r1 - z1, objective partials TV_w(x_hat) (count in *nparts)
 template <typename T> void launch_tv_prox(const Plan& P, const cpx<T>* xh, cpx<T>* z1, cpx<T>* x1, cpx<T>* u,

@@ -461,6 +461,73 @@ k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* 
     }
 }
 
+// CG set-up folded into the first step's row pass: r = p = x1 + x2 + x3 - q0 (q0 may be
+// null), partial ||r||^2 per workgroup, and p's row transform.
+template <typename T>
+struct CgInit {
+    const cpx<T>* x1 = nullptr;
+    const cpx<T>* x2 = nullptr;
+    const cpx<T>* x3 = nullptr;
+    const cpx<T>* q0 = nullptr;
+    cpx<T>* r = nullptr;
+    cpx<T>* p = nullptr;
+    double* rho_part = nullptr;
+};
+
+template <typename T, int LOGN, int B>
+__global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN, 0>::TL))
+k_fft_rows_init(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>* __restrict__ tw,
+                const cpx<T>* __restrict__ tw2, CgInit<T> ci) {
+    using PL = Plan1D<T, LOGN, 0>;
+    constexpr int N = PL::N, K = 2 * N;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[16];
+    const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
+    const int tl = threadIdx.x % PL::TL, r = (threadIdx.x / PL::TL) & 1, lr = threadIdx.x / (2 * PL::TL);
+    cpx<T>* line = base + table_elems<T, LOGN>() + (2 * lr + r) * PL::LS;
+    const int row = blockIdx.x * B + lr;
+    const T srow = deap[row];
+    const size_t ro = (size_t)row * N;
+    cpx<T>* outr = tmp + (size_t)row * K;
+    cpx<T> v[PL::RMAX];
+    double acc = 0;
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int p = PL::in_pos(tl, i);
+        cpx<T> b = ci.x1[ro + p] + ci.x2[ro + p] + ci.x3[ro + p];
+        if (ci.q0) b = b - ci.q0[ro + p];
+        v[i] = b;
+        acc += (double)b.x * b.x + (double)b.y * b.y;
+    }
+    // both parity groups hold the whole row: group 0 writes r and p and counts ||r||^2
+    if (r == 0) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int p = PL::in_pos(tl, i);
+            ci.r[ro + p] = v[i];
+            ci.p[ro + p] = v[i];
+        }
+    }
+    const double tot = block_sum_dyn(r == 0 ? acc : 0.0, red);   // also orders the twiddle staging
+    if (threadIdx.x == 0) ci.rho_part[blockIdx.x] = tot;
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int p = PL::in_pos(tl, i);
+        cpx<T> a = (srow * deap[p]) * v[i];
+        if (r) a = a * tw2[p];
+        v[i] = a;
+    }
+    line_fft<T, LOGN, 0, false>(v, line, tl, W);
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const int kp = PL::out_pos(tl, i);
+        cpx<T> o = (kp & 1) ? neg(v[i]) : v[i];
+        if (r) o = mul_i(o);
+        outr[2 * kp + r] = o;
+    }
+}
+
 // rows pass of a CG step from the second on (see CgXr): loads x, r, p, q of the row, then
 // the partial sums; updates x and r, transforms the new r.
 template <typename T, int LOGN, int B>
@@ -999,6 +1066,16 @@ void rows_xr_impl(const Plan& P, cpx<T>* tmp, CgXr<T> cg, const T* deap, hipStre
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, tmp, deap, (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, cg);
 }
 template <typename T, int LOGN>
+void rows_init_impl(const Plan& P, cpx<T>* tmp, CgInit<T> ci, const T* deap, hipStream_t s) {
+    constexpr int B = rows_per_wg<T, LOGN>();
+    constexpr int NT = 2 * B * Plan1D<T, LOGN, 0>::TL;
+    constexpr int N = 1 << LOGN;
+    const size_t lds = lds_bytes<T, LOGN, 0>(2 * B);
+    auto f = k_fft_rows_init<T, LOGN, B>;
+    set_lds_limit(f, lds);
+    hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, tmp, deap, (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, ci);
+}
+template <typename T, int LOGN>
 void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, cpx<T>* dirt, CgBeta cb, hipStream_t s) {
     constexpr int C = cols_per_wg<T, LOGN>();
     constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
@@ -1090,6 +1167,22 @@ void launch_fft_rows_fwd(const Plan& P, const cpx<T>* x, cpx<T>* tmp, hipStream_
     PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_fwd_impl<T, L_>(P, x, tmp, dp, s)));
 }
 template <typename T>
+int launch_fft_rows_init(const Plan& P, const cpx<T>* x1, const cpx<T>* x2, const cpx<T>* x3, const cpx<T>* q0,
+                         cpx<T>* r, cpx<T>* p, double* rho_part, cpx<T>* tmp, hipStream_t s, const void* deap) {
+    CgInit<T> ci;
+    ci.x1 = x1;
+    ci.x2 = x2;
+    ci.x3 = x3;
+    ci.q0 = q0;
+    ci.r = r;
+    ci.p = p;
+    ci.rho_part = rho_part;
+    const T* dp = (const T*)(deap ? deap : P.deap);
+    int blocks = 0;
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_init_impl<T, L_>(P, tmp, ci, dp, s), blocks = (1 << L_) / rows_per_wg<T, L_>()));
+    return blocks;
+}
+template <typename T>
 void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
     PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_fwd_impl<T, L_>(P, tmp, grid, nullptr, CgBeta{}, s)));
 }
@@ -1168,6 +1261,12 @@ int fft_rows_adj_blocks(const Plan& P) {
 
 template void launch_fft_rows_fwd<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t, const void*);
 template void launch_fft_rows_fwd<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t, const void*);
+template int launch_fft_rows_init<float>(const Plan&, const cpx<float>*, const cpx<float>*, const cpx<float>*,
+                                         const cpx<float>*, cpx<float>*, cpx<float>*, double*, cpx<float>*,
+                                         hipStream_t, const void*);
+template int launch_fft_rows_init<double>(const Plan&, const cpx<double>*, const cpx<double>*, const cpx<double>*,
+                                          const cpx<double>*, cpx<double>*, cpx<double>*, double*, cpx<double>*,
+                                          hipStream_t, const void*);
 template void launch_fft_cols_fwd<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
 template void launch_fft_cols_fwd<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
 template void launch_fft_cols_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);

@@ -189,23 +189,6 @@ k_finalize(const double* __restrict__ part, int count, double* sc, int slot, int
     }
 }
 
-// r = x1 + x2 + x3 - q ; p = r ; partial <r, r>
-template <typename T>
-__global__ void __launch_bounds__(VT)
-k_cg_init(const cpx<T>* __restrict__ x1, const cpx<T>* __restrict__ x2, const cpx<T>* __restrict__ x3,
-          const cpx<T>* __restrict__ q, cpx<T>* __restrict__ r, cpx<T>* __restrict__ p, int64_t n,
-          double* part) {
-    double acc = 0;
-    GRID_STRIDE(i, n) {
-        const cpx<T> v = x1[i] + x2[i] + x3[i] - q[i];
-        r[i] = v;
-        p[i] = v;
-        acc += (double)v.x * v.x + (double)v.y * v.y;
-    }
-    const double t = block_sum(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
 // CG step: alpha = rho / Re<p, q> from the partial sums of both (rho == 0: alpha = 0,
 // the early stop); x += alpha p ; r -= alpha q ; partial <r, r> of the new residual.
 template <typename T>
@@ -296,19 +279,21 @@ k_ball_part(const cpx<T>* __restrict__ v3, const cpx<T>* __restrict__ z3, const 
 }
 
 // i = 3, pass 2: s = min(1, eps~ / ||v3 + z3 - y~||) from the partial sums;
-// u = v3 + z3 ; r3 = y~ + (u - y~) s ; z3 = u - r3 ; v3 <- r3 - z3.  Workgroup 0 also
-// records ||u - y~||^2, the residual ||y~ - v3||^2 and its history row.
+// u = v3 + z3 ; r3 = y~ + (u - y~) s ; z3 = u - r3 ; v3 <- r3 - z3 (diff: v3 <- r3 - z3 - v3,
+// the change from the incoming Phi~ x_hat).  Workgroup 0 also records ||u - y~||^2, the
+// residual ||y~ - v3||^2 and its history row.
 template <typename T>
 __global__ void __launch_bounds__(VT)
 k_prox_ball(cpx<T>* __restrict__ v3, cpx<T>* __restrict__ z3, const cpx<T>* __restrict__ yt,
             const double* __restrict__ part_d, const double* __restrict__ part_res, int count,
-            double eps, double* sc, double* hist, int hist_cap, int64_t n) {
+            double eps, double* sc, double* hist, int hist_cap, int64_t n, int diff) {
     // first element's operands are loaded before the partial sums are read (both in flight)
     const int64_t i0 = (int64_t)blockIdx.x * VT + threadIdx.x;
-    cpx<T> y0, u0;
+    cpx<T> y0, v0, z0;
     if (i0 < n) {
         y0 = yt[i0];
-        u0 = v3[i0] + z3[i0];
+        v0 = v3[i0];
+        z0 = z3[i0];
     }
     const double d2 = sum_partials(part_d, count);
     const double nd = sqrt(d2);
@@ -324,11 +309,12 @@ k_prox_ball(cpx<T>* __restrict__ v3, cpx<T>* __restrict__ z3, const cpx<T>* __re
     }
     GRID_STRIDE(i, n) {
         const cpx<T> y = i == i0 ? y0 : yt[i];
-        const cpx<T> u = i == i0 ? u0 : v3[i] + z3[i];
+        const cpx<T> v = i == i0 ? v0 : v3[i];
+        const cpx<T> u = v + (i == i0 ? z0 : z3[i]);
         const cpx<T> r3 = y + s * (u - y);
         const cpx<T> z = u - r3;
         z3[i] = z;
-        v3[i] = r3 - z;
+        v3[i] = diff ? (r3 - z) - v : r3 - z;
     }
 }
 
@@ -434,16 +420,25 @@ k_ball_fin_blk(const double* __restrict__ part_d, const double* __restrict__ par
 template <typename T>
 __global__ void __launch_bounds__(VT)
 k_prox_ball_blk(cpx<T>* __restrict__ v3, cpx<T>* __restrict__ z3, const cpx<T>* __restrict__ yt,
-                const int32_t* __restrict__ bid, const double* __restrict__ scale, int64_t n) {
+                const int32_t* __restrict__ bid, const double* __restrict__ scale, int64_t n, int diff) {
     const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
     if (i >= n) return;
     const T s = (T)scale[bid[i]];
     const cpx<T> y = yt[i];
-    const cpx<T> u = v3[i] + z3[i];
+    const cpx<T> v = v3[i];
+    const cpx<T> u = v + z3[i];
     const cpx<T> r3 = y + s * (u - y);
     const cpx<T> z = u - r3;
     z3[i] = z;
-    v3[i] = r3 - z;
+    v3[i] = diff ? (r3 - z) - v : r3 - z;
+}
+
+// a -= b
+template <typename T>
+__global__ void __launch_bounds__(VT)
+k_sub(cpx<T>* __restrict__ a, const cpx<T>* __restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i < n) a[i] = a[i] - b[i];
 }
 
 // Reweighting statistics: partial sums of Re and Im (the mean of the coefficients)
@@ -538,13 +533,6 @@ void launch_iter_advance(double* sc, hipStream_t s) {
     hipLaunchKernelGGL(k_iter_advance, dim3(1), dim3(64), 0, s, sc);
 }
 template <typename T>
-int launch_cg_init(const cpx<T>* x1, const cpx<T>* x2, const cpx<T>* x3, const cpx<T>* q, cpx<T>* r,
-                   cpx<T>* p, int64_t n, double* part, hipStream_t s) {
-    const int b = red_blocks(n);
-    hipLaunchKernelGGL(k_cg_init<T>, dim3(b), dim3(VT), 0, s, x1, x2, x3, q, r, p, n, part);
-    return b;
-}
-template <typename T>
 int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q, const double* rho_part,
                  int rho_count, const double* pq_part, int pq_count, int64_t n, double* part,
                  hipStream_t s) {
@@ -574,9 +562,9 @@ int launch_ball_part(const cpx<T>* v3, const cpx<T>* z3, const cpx<T>* yt, int64
 template <typename T>
 void launch_prox_ball(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const double* part_d,
                       const double* part_res, int count, double eps, double* sc, double* hist,
-                      int hist_cap, int64_t n, hipStream_t s) {
+                      int hist_cap, int64_t n, bool diff, hipStream_t s) {
     hipLaunchKernelGGL(k_prox_ball<T>, dim3(red_blocks(n)), dim3(VT), 0, s, v3, z3, yt, part_d, part_res,
-                       count, eps, sc, hist, hist_cap, n);
+                       count, eps, sc, hist, hist_cap, n, diff ? 1 : 0);
 }
 template <typename T>
 void launch_power_normalise(cpx<T>* v, const cpx<T>* w, const double* part, int count, double* sc,
@@ -609,8 +597,13 @@ void launch_ball_fin_blk(const double* part_d, const double* part_res, const int
 }
 template <typename T>
 void launch_prox_ball_blk(cpx<T>* v3, cpx<T>* z3, const cpx<T>* yt, const int32_t* bid, const double* scale,
-                          int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_prox_ball_blk<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, v3, z3, yt, bid, scale, n);
+                          int64_t n, bool diff, hipStream_t s) {
+    hipLaunchKernelGGL(k_prox_ball_blk<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, v3, z3, yt, bid, scale, n,
+                       diff ? 1 : 0);
+}
+template <typename T>
+void launch_sub(cpx<T>* a, const cpx<T>* b, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub<T>, dim3(ew_blocks(n)), dim3(VT), 0, s, a, b, n);
 }
 template <typename T>
 int launch_sum_part(const cpx<T>* v, int64_t n, double* part_re, double* part_im, hipStream_t s) {
@@ -641,8 +634,6 @@ int launch_diff2_part(const cpx<T>* a, const cpx<T>* b, int64_t n, double* part_
     template void launch_fill<T>(cpx<T>*, cpx<T>, int64_t, hipStream_t);                                \
     template int launch_norm2_part<T>(const cpx<T>*, int64_t, double*, hipStream_t);                     \
     template int launch_maxabs_part<T>(const cpx<T>*, int64_t, double*, hipStream_t);                    \
-    template int launch_cg_init<T>(const cpx<T>*, const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*,  \
-                                   cpx<T>*, int64_t, double*, hipStream_t);                              \
     template int launch_cg_xr<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const cpx<T>*, const double*, int,     \
                                  const double*, int, int64_t, double*, hipStream_t);                     \
     template void launch_power_normalise<T>(cpx<T>*, const cpx<T>*, const double*, int, double*, int64_t, \
@@ -652,14 +643,15 @@ int launch_diff2_part(const cpx<T>* a, const cpx<T>* b, int64_t n, double* part_
     template int launch_ball_part<T>(const cpx<T>*, const cpx<T>*, const cpx<T>*, int64_t, double*,      \
                                      double*, hipStream_t);                                              \
     template void launch_prox_ball<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const double*, const double*, int,  \
-                                      double, double*, double*, int, int64_t, hipStream_t);             \
+                                      double, double*, double*, int, int64_t, bool, hipStream_t);       \
     template void launch_permute_scale<T>(const cpx<T>*, const int32_t*, double, cpx<T>*, int64_t,       \
                                           hipStream_t);                                                  \
     template void launch_scale_by_slot<T>(cpx<T>*, const cpx<T>*, const double*, int, int64_t, hipStream_t); \
     template void launch_ball_part_blk<T>(const cpx<T>*, const cpx<T>*, const cpx<T>*, const int32_t*,      \
                                           const int32_t*, int, double*, double*, hipStream_t);            \
     template void launch_prox_ball_blk<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const int32_t*, const double*,  \
-                                          int64_t, hipStream_t);                                          \
+                                          int64_t, bool, hipStream_t);                                    \
+    template void launch_sub<T>(cpx<T>*, const cpx<T>*, int64_t, hipStream_t);                           \
     template int launch_sum_part<T>(const cpx<T>*, int64_t, double*, double*, hipStream_t);               \
     template int launch_dev2_part<T>(const cpx<T>*, int64_t, const double*, int, int, double*, hipStream_t); \
     template void launch_reweight<T>(const cpx<T>*, int64_t, double, double*, hipStream_t);               \
