@@ -287,7 +287,9 @@ int32_t purify_server_poll(purify_server* server, int64_t ticket);
 /* Block until the request is done, then release it.  x: host, N complex of the request's
  * precision (or NULL); info as for purify_sdmm_solve (or NULL); timings: host, 3 doubles or
  * NULL: milliseconds waiting for admission, running (plan creation, solve, result
- * download), and from submission to the result on the host.  Returns the solve's status. */
+ * download), and from submission to the result on the host.  Returns the solve's status.
+ * A ticket is collected once: an unknown or already collected ticket, or a second thread
+ * waiting on the same ticket, gets PURIFY_E_INVALID. */
 purify_status purify_server_wait(purify_server* server, int64_t ticket, void* x, purify_sdmm_info* info,
                                  double* timings);
 

@@ -307,7 +307,11 @@ purify_status purify_server_wait(purify_server* server, int64_t ticket, void* x,
         }
         r = it->second;
         server->cv_done.wait(lk, [&] { return r->state == 2; });
-        server->requests.erase(it);
+        // by key: another thread waiting on the same ticket may have collected it meanwhile
+        if (server->requests.erase(ticket) == 0) {
+            purify::set_error("ticket collected by another waiter");
+            return PURIFY_E_INVALID;
+        }
     }
     if (x && r->x.size() == r->x_bytes) std::memcpy(x, r->x.data(), r->x_bytes);
     if (info) *info = r->info;

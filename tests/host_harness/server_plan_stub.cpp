@@ -160,7 +160,29 @@ int main(int argc, char** argv) {
         if (i % 5 == 0) std::this_thread::sleep_for(std::chrono::microseconds(300));
     }
     int bad = 0;
-    for (size_t i = 0; i < tickets.size(); ++i) {
+    // Two threads wait on the first ticket at once: exactly one collects it, intact.
+    purify_status st2[2];
+    std::vector<unsigned char> x2[2];
+    purify_sdmm_info info2[2];
+    {
+        const size_t es = precs[0] == PURIFY_FP64 ? 16 : 8;
+        std::vector<std::thread> waiters;
+        for (int k = 0; k < 2; ++k) {
+            x2[k].assign((size_t)ns[0] * ns[0] * es, 0);
+            info2[k] = purify_sdmm_info{};
+            waiters.emplace_back([&, k] { st2[k] = purify_server_wait(S, tickets[0], x2[k].data(), &info2[k], nullptr); });
+        }
+        for (auto& w : waiters) w.join();
+        const int got = st2[0] == PURIFY_OK ? 0 : 1;
+        double v0 = 0;
+        std::memcpy(&v0, x2[got].data(), sizeof v0);
+        if (st2[got] != PURIFY_OK || st2[1 - got] != PURIFY_E_INVALID || info2[got].nu != (double)Ms[0] ||
+            v0 != (double)Ms[0]) {
+            printf("request 0: double wait gave %d and %d\n", (int)st2[0], (int)st2[1]);
+            ++bad;
+        }
+    }
+    for (size_t i = 1; i < tickets.size(); ++i) {
         const size_t es = precs[i] == PURIFY_FP64 ? 16 : 8;
         std::vector<unsigned char> x((size_t)ns[i] * ns[i] * es);
         purify_sdmm_info info{};
