@@ -217,14 +217,14 @@ struct Sdmm {
         // i = 1 (on s2): l1 prior on Psi^dag x_hat
         (void)hipEventRecord(fork, s);
         (void)hipStreamWaitEvent(s2, fork, 0);
+        // the objective's partial sums (part 3, nb1 of them) are summed on the main stream after
+        // the join, by the kernel that ends the iteration, off this branch's chain
+        int nb1 = 0;
         if (tv) {   // TV prior: prox on u = x_hat + z1 (in v1), x1 = r1 - z1
-            int nb1 = 0;
             launch_tv_prox<T>(P, xh, z1, x1, v1, prm->weights, gamma, prm->tv_iter, part(3), &nb1, s2);
-            launch_finalize(part(3), nb1, sc, SL_OBJ, FIN_HIST_OBJ, 0, P.hist, P.hist_cap, s2);
         } else {
             launch_psi_adj<T>(P, xh, v1, s2);
-            const int nb1 = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part(3), s2);
-            launch_finalize(part(3), nb1, sc, SL_OBJ, FIN_HIST_OBJ, 0, P.hist, P.hist_cap, s2);
+            nb1 = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part(3), s2);
             launch_psi<T>(P, v1, x1, s2);
         }
         (void)hipEventRecord(join, s2);
@@ -253,7 +253,7 @@ struct Sdmm {
             A(op, xh, q, nullptr);
         }
         (void)hipStreamWaitEvent(s, join, 0);
-        launch_iter_advance(sc, s);
+        launch_finalize(part(3), nb1, sc, SL_OBJ, FIN_HIST_OBJ_END, 0, P.hist, P.hist_cap, s);
     }
 
     // The first iteration's warm start: q = A x_hat, and with the NUFFT operator

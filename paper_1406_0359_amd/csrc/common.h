@@ -232,10 +232,9 @@ enum FinalOp : int {
     FIN_MAX = 4,          // sc[slot] = max
     FIN_BALL = 5,         // sc[D2] = sum; sc[BALL] = min(1, eps / sqrt(sum)) (1 if 0)
     FIN_HIST_OBJ = 6,     // sc[OBJ] = sum; hist[2*it] = sum, it = sc[ITER] mod hist_index
-    FIN_HIST_RES = 7      // sc[RES2] = sum; hist[2*it+1] = sqrt(sum)
+    FIN_HIST_RES = 7,     // sc[RES2] = sum; hist[2*it+1] = sqrt(sum)
+    FIN_HIST_OBJ_END = 8  // as FIN_HIST_OBJ, then sc[ITER] += 1 (the end of an SDMM iteration)
 };
-// sc[ITER] += 1 (end of an SDMM iteration)
-void launch_iter_advance(double* sc, hipStream_t s);
 // For FIN_HIST_*, hist_index is the history capacity and the row is sc[SL_ITER] mod it.
 void launch_finalize(const double* part, int count, double* sc, int slot, int op, double arg,
                      double* hist, int hist_index, hipStream_t s);

@@ -175,10 +175,12 @@ k_finalize(const double* __restrict__ part, int count, double* sc, int slot, int
             const double nd = sqrt(acc);
             sc[SL_BALL] = (nd == 0.0 || arg >= nd) ? 1.0 : arg / nd;
         } break;
-        case FIN_HIST_OBJ: {
+        case FIN_HIST_OBJ:
+        case FIN_HIST_OBJ_END: {
             sc[SL_OBJ] = acc;
             const int row = (int)sc[SL_ITER] % hist_index;
             if (hist) hist[2 * row] = acc;
+            if (op == FIN_HIST_OBJ_END) sc[SL_ITER] += 1.0;
         } break;
         case FIN_HIST_RES: {
             sc[SL_RES2] = acc;
@@ -331,10 +333,6 @@ k_power_normalise(cpx<T>* __restrict__ v, const cpx<T>* __restrict__ w, const do
     }
     const T inv = (T)(l > 0.0 ? 1.0 / l : 0.0);
     GRID_STRIDE(i, n) v[i] = inv * w[i];
-}
-
-__global__ void k_iter_advance(double* sc) {
-    if (threadIdx.x == 0) sc[SL_ITER] += 1.0;
 }
 
 template <typename T>
@@ -528,9 +526,6 @@ void launch_finalize(const double* part, int count, double* sc, int slot, int op
                      double* hist, int hist_index, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(VT), 0, s, part, count, sc, slot, op, arg, hist,
                        hist_index);
-}
-void launch_iter_advance(double* sc, hipStream_t s) {
-    hipLaunchKernelGGL(k_iter_advance, dim3(1), dim3(64), 0, s, sc);
 }
 template <typename T>
 int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q, const double* rho_part,
