@@ -135,7 +135,7 @@ purify_status ensure_chat(Plan& P, hipStream_t s) {
 // RAII holder for the solver's internal streams, events and graphs.
 struct SolveResources {
     hipStream_t cs = nullptr, cs2 = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr, done = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, done = nullptr, hat = nullptr;
     hipGraph_t g_iter = nullptr, g_pow = nullptr;
     hipGraphExec_t x_iter = nullptr, x_pow = nullptr;
     ~SolveResources() {
@@ -146,6 +146,7 @@ struct SolveResources {
         if (fork) (void)hipEventDestroy(fork);
         if (join) (void)hipEventDestroy(join);
         if (done) (void)hipEventDestroy(done);
+        if (hat) (void)hipEventDestroy(hat);
         if (cs) (void)hipStreamDestroy(cs);
         if (cs2) (void)hipStreamDestroy(cs2);
     }
@@ -183,7 +184,7 @@ struct Sdmm {
     // fork and join events; CG and branches i = 2, 3 run on s.  Scalars (CG alpha and beta,
     // the l2-ball scale) are summed from partial-sum buffers inside the kernels that use
     // them; rho alternates between buffers 0 and 1, <p, Ap> uses buffer 2.
-    void enqueue_iteration(hipStream_t s, hipStream_t s2, hipEvent_t fork, hipEvent_t join) const {
+    void enqueue_iteration(hipStream_t s, hipStream_t s2, hipEvent_t fork, hipEvent_t join, hipEvent_t hat) const {
         const Ops<T> op{P, s};
         const int64_t N = P.N, M = P.M, D = P.D;
         double* sc = P.sc;
@@ -213,19 +214,33 @@ struct Sdmm {
                                             part(c & 1), inv_nu2, part(2));
         }
         const int cl = prm->cg_iter;
-        launch_cg_xr<T>(xh, r, p, q, part((cl - 1) & 1), rho_count, part(2), rows_blocks, N, part(cl & 1), s);
-        // i = 1 (on s2): l1 prior on Psi^dag x_hat
-        (void)hipEventRecord(fork, s);
-        (void)hipStreamWaitEvent(s2, fork, 0);
-        // the objective's partial sums (part 3, nb1 of them) are summed on the main stream after
-        // the join, by the kernel that ends the iteration, off this branch's chain
+        // i = 1 (on s2): l1 prior on Psi^dag x_hat.  Branch i = 1 is the longer one, so where
+        // the analysis can form x_hat = x + alpha p itself it forks before the CG's last
+        // update, and the update (which writes x_hat over x) waits only for the finest
+        // analysis level, the one launch that reads x and p.
+        // The objective's partial sums (part 3, nb1 of them) are summed on the main stream
+        // after the join, by the kernel that ends the iteration, off this branch's chain.
         int nb1 = 0;
-        if (tv) {   // TV prior: prox on u = x_hat + z1 (in v1), x1 = r1 - z1
-            launch_tv_prox<T>(P, xh, z1, x1, v1, prm->weights, gamma, prm->tv_iter, part(3), &nb1, s2);
-        } else {
-            launch_psi_adj<T>(P, xh, v1, s2);
+        if (!tv && psi_adj_takes_xhat(P)) {
+            (void)hipEventRecord(fork, s);
+            (void)hipStreamWaitEvent(s2, fork, 0);
+            const XhatArgs<T> xa{p, part((cl - 1) & 1), rho_count, part(2), rows_blocks};
+            launch_psi_adj<T>(P, xh, v1, s2, &xa, hat);
+            (void)hipStreamWaitEvent(s, hat, 0);
+            launch_cg_xr<T>(xh, r, p, q, part((cl - 1) & 1), rho_count, part(2), rows_blocks, N, part(cl & 1), s);
             nb1 = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part(3), s2);
             launch_psi<T>(P, v1, x1, s2);
+        } else {
+            launch_cg_xr<T>(xh, r, p, q, part((cl - 1) & 1), rho_count, part(2), rows_blocks, N, part(cl & 1), s);
+            (void)hipEventRecord(fork, s);
+            (void)hipStreamWaitEvent(s2, fork, 0);
+            if (tv) {   // TV prior: prox on u = x_hat + z1 (in v1), x1 = r1 - z1
+                launch_tv_prox<T>(P, xh, z1, x1, v1, prm->weights, gamma, prm->tv_iter, part(3), &nb1, s2);
+            } else {
+                launch_psi_adj<T>(P, xh, v1, s2);
+                nb1 = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part(3), s2);
+                launch_psi<T>(P, v1, x1, s2);
+            }
         }
         (void)hipEventRecord(join, s2);
         // i = 2: positivity
@@ -351,6 +366,7 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     PURIFY_HIP(hipEventCreateWithFlags(&R.fork, hipEventDisableTiming));
     PURIFY_HIP(hipEventCreateWithFlags(&R.join, hipEventDisableTiming));
     PURIFY_HIP(hipEventCreateWithFlags(&R.done, hipEventDisableTiming));
+    PURIFY_HIP(hipEventCreateWithFlags(&R.hat, hipEventDisableTiming));
     hipStream_t cs = R.cs;
 
     // the solver's streams start after the caller's prior work on s
@@ -443,7 +459,7 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
 
     if (use_graph) {
         PURIFY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-        S.enqueue_iteration(cs, R.cs2, R.fork, R.join);
+        S.enqueue_iteration(cs, R.cs2, R.fork, R.join, R.hat);
         purify_status st = capture(cs, &R.g_iter, &R.x_iter);
         if (st != PURIFY_OK) return st;
     }
@@ -453,7 +469,7 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     bool converged = false;
     for (int t = 0; t < T_max; ++t) {
         if (use_graph) PURIFY_HIP(hipGraphLaunch(R.x_iter, cs));
-        else S.enqueue_iteration(cs, R.cs2, R.fork, R.join);
+        else S.enqueue_iteration(cs, R.cs2, R.fork, R.join, R.hat);
         it_done = t + 1;
         if (prm->halting && t >= 1 && ((t + 1) % check == 0 || t + 1 == T_max)) {
             double h[5] = {0, 0, 0, 0, 0};

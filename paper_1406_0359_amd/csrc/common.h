@@ -215,7 +215,21 @@ template <typename T> void launch_grid(const Plan& P, const cpx<T>* y, const int
 // gout = G^T G gin (visibility values interpolated from gin and gridded in one launch)
 template <typename T> void launch_gtg(const Plan& P, const cpx<T>* gin, cpx<T>* gout, hipStream_t s);
 
-template <typename T> void launch_psi_adj(const Plan& P, const cpx<T>* x, cpx<T>* alpha, hipStream_t s);
+// The CG's last update folded into the analysis: with XhatArgs, Psi^dag is taken of
+// x + alpha p, alpha = rho / <p, q> from the partial sums (the value the CG update kernel
+// derives from them), and `first_done` (if given) is recorded after the finest level, the
+// only one that reads x and p.  Only plans for which psi_adj_takes_xhat holds accept it.
+template <typename T>
+struct XhatArgs {
+    const cpx<T>* p = nullptr;
+    const double* rho_part = nullptr;
+    int rho_count = 0;
+    const double* pq_part = nullptr;
+    int pq_count = 0;
+};
+bool psi_adj_takes_xhat(const Plan& P);
+template <typename T> void launch_psi_adj(const Plan& P, const cpx<T>* x, cpx<T>* alpha, hipStream_t s,
+                                          const XhatArgs<T>* xa = nullptr, hipEvent_t first_done = nullptr);
 template <typename T> void launch_psi(const Plan& P, const cpx<T>* alpha, cpx<T>* x, hipStream_t s);
 
 // Vector kernels (vector.hip)

@@ -8,6 +8,7 @@
 // (CG alpha / beta, the l2-ball scale, ...) on the device.  No float atomics, so the FP64
 // path is bitwise reproducible.
 #include "common.h"
+#include "partials.h"
 
 namespace purify {
 
@@ -15,6 +16,7 @@ namespace {
 
 constexpr int RED_BLOCKS = 1024;   // grid size of every reducing vector kernel
 constexpr int VT = 256;
+static_assert(VT == PART_THREADS, "partial sums assume the vector kernels' block size");
 
 __device__ __forceinline__ double block_sum(double v) {
     __shared__ double red[VT / 64];
@@ -44,21 +46,6 @@ __device__ __forceinline__ double block_max(double v) {
     return t;
 }
 
-// acc <- acc + part[i] (or fmax) over i = threadIdx.x + k VT, k = 0, 1, ... in that order,
-// four loads in flight at a time (the loop otherwise waits on each load in turn)
-template <bool MAX>
-__device__ __forceinline__ double strided_fold(const double* __restrict__ part, int count, double acc) {
-    for (int i0 = threadIdx.x; i0 < count; i0 += 4 * VT) {
-        double v[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = i0 + k * VT < count ? part[i0 + k * VT] : 0.0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (i0 + k * VT < count) acc = MAX ? fmax(acc, v[k]) : acc + v[k];
-    }
-    return acc;
-}
-
 // Every workgroup of a consumer kernel re-sums a partial-sum buffer in the same fixed
 // order, so all of them see the identical scalar (no finalize launch, still deterministic).
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int count) {
@@ -74,33 +61,6 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
     for (int i = 0; i < VT / 64; ++i) t += red2[i];
     __syncthreads();
     return t;
-}
-
-// Two partial-sum buffers in one pass, each total the value sum_partials gives.
-__device__ __forceinline__ void sum_partials2(const double* __restrict__ pa, int na, const double* __restrict__ pb,
-                                              int nb, double& ta, double& tb) {
-    __shared__ double red3[2][VT / 64];
-    double a = strided_fold<false>(pa, na, 0.0);
-    double b = strided_fold<false>(pb, nb, 0.0);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o);
-        b += __shfl_xor(b, o);
-    }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) {
-        red3[0][w] = a;
-        red3[1][w] = b;
-    }
-    __syncthreads();
-    ta = 0;
-    tb = 0;
-#pragma unroll
-    for (int i = 0; i < VT / 64; ++i) {
-        ta += red3[0][i];
-        tb += red3[1][i];
-    }
-    __syncthreads();
 }
 
 int red_blocks(int64_t n) {
@@ -207,9 +167,7 @@ k_cg_xr(cpx<T>* __restrict__ x, cpx<T>* __restrict__ r, const cpx<T>* __restrict
         p0 = p[i0];
         q0 = q[i0];
     }
-    double rho, pq;
-    sum_partials2(rho_part, rho_count, pq_part, pq_count, rho, pq);
-    const T alpha = (T)(rho == 0.0 ? 0.0 : rho / pq);
+    const T alpha = cg_alpha<T>(rho_part, rho_count, pq_part, pq_count);
     double acc = 0;
     GRID_STRIDE(i, n) {
         const bool first = i == i0;

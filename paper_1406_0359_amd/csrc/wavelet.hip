@@ -11,6 +11,7 @@
 // through LDS).  The finest synthesis level sums every basis (and the Dirac block) per
 // output tile and writes the image once.
 #include "common.h"
+#include "partials.h"
 
 namespace purify {
 
@@ -63,10 +64,13 @@ constexpr int SC = SP / 2 + MAX_TAPS / 2 - 1;   // synthesis window per axis per
 // (compact slots of (n/2)^2 per basis, row stride Ls/2), or into the alpha block at the
 // coarsest level (llout == null), so no launch reads what it writes.  blockIdx.z == nwav
 // copies the image into the Dirac block instead.
-template <typename T>
+// XHAT (finest level only): the image is x + a p with a the CG step length from xa's partial
+// sums, formed as the window is read.
+template <typename T, bool XHAT>
 __global__ void __launch_bounds__(256)
 k_wav_fwd_level(const cpx<T>* __restrict__ src, size_t src_bstride, int src_ld, cpx<T>* __restrict__ alpha,
-                cpx<T>* __restrict__ llout, const T* __restrict__ filt, WavArgs A, int Ls, T scale) {
+                cpx<T>* __restrict__ llout, const T* __restrict__ filt, WavArgs A, int Ls, T scale,
+                XhatArgs<T> xa) {
     constexpr int IS = AR + 1, MS = 2 * AP + 1;
     __shared__ cpx<T> in[AR * IS];
     __shared__ cpx<T> mid[AR * MS];
@@ -79,11 +83,18 @@ k_wav_fwd_level(const cpx<T>* __restrict__ src, size_t src_bstride, int src_ld, 
     const int ti1 = blockIdx.x / tiles, ti2 = blockIdx.x % tiles;
     const int r0 = 2 * ap * ti1, c0 = 2 * ap * ti2;
     const int z = blockIdx.z;
+    T xs = 0;
+    if constexpr (XHAT) xs = cg_alpha<T>(xa.rho_part, xa.rho_count, xa.pq_part, xa.pq_count);
+    // image element at offset o (x + a p with XHAT)
+    auto img = [&](size_t o) {
+        if constexpr (XHAT) return src[o] + xs * xa.p[o];
+        else return src[o];
+    };
     if (z == A.nwav) {
         cpx<T>* d = alpha + (size_t)A.dirac_block * N;
         auto at = [&](int i) { return (size_t)(r0 + i / (2 * ap)) * n + c0 + i % (2 * ap); };
         stage_batched<cpx<T>, 4 * AP * AP / 256, 256>(
-            4 * ap * ap, threadIdx.x, [&](int i) { return src[at(i)]; },
+            4 * ap * ap, threadIdx.x, [&](int i) { return img(at(i)); },
             [&](int i, cpx<T> v) { d[at(i)] = scale * v; });
         return;
     }
@@ -97,7 +108,9 @@ k_wav_fwd_level(const cpx<T>* __restrict__ src, size_t src_bstride, int src_ld, 
         R * R, threadIdx.x,
         [&](int i) {
             const int a = i / R, b = i - a * R;
-            return s[(size_t)((r0 + a) & (Ls - 1)) * src_ld + ((c0 + b) & (Ls - 1))];
+            const size_t o = (size_t)((r0 + a) & (Ls - 1)) * src_ld + ((c0 + b) & (Ls - 1));
+            if constexpr (XHAT) return img(o);
+            else return s[o];
         },
         [&](int i, cpx<T> v) {
             const int a = i / R, b = i - a * R;
@@ -435,8 +448,18 @@ WavArgs wav_args(const Plan& P) {
 
 }  // namespace
 
+// The finest level goes through k_wav_fwd_level (which can form x + alpha p) unless the
+// image is large enough for the one-pass kernel of all bases.
+bool psi_adj_takes_xhat(const Plan& P) {
+    if (P.nwav == 0) return false;
+    const int ap = std::min(AP, P.n / 2), tiles = (P.n / 2) / ap;
+    return !(ap == AP && tiles * tiles >= 1024);
+}
+
 template <typename T>
-void launch_psi_adj(const Plan& P, const cpx<T>* x, cpx<T>* alpha, hipStream_t s) {
+void launch_psi_adj(const Plan& P, const cpx<T>* x, cpx<T>* alpha, hipStream_t s, const XhatArgs<T>* xa,
+                    hipEvent_t first_done) {
+    if (xa && !psi_adj_takes_xhat(P)) return;   // callers check psi_adj_takes_xhat first
     const WavArgs A = wav_args(P);
     const T scale = (T)(1.0 / std::sqrt((double)P.q));
     const int64_t N = P.N;
@@ -462,12 +485,17 @@ void launch_psi_adj(const Plan& P, const cpx<T>* x, cpx<T>* alpha, hipStream_t s
             for (int i = 0; i < P.nwav; ++i) Fmax = std::max(Fmax, A.flen[i]);
             hipLaunchKernelGGL(k_wav_fwd_level0_all<T>, dim3(tiles * tiles), dim3(256), 0, s, x, alpha, llout,
                                filt, A, scale, Fmax);
-        } else if (lev == 0)
-            hipLaunchKernelGGL(k_wav_fwd_level<T>, g, dim3(256), 0, s, x, (size_t)0, P.n, alpha, llout, filt, A,
-                               Ls, scale);
-        else
-            hipLaunchKernelGGL(k_wav_fwd_level<T>, g, dim3(256), 0, s, (const cpx<T>*)llb[(lev - 1) & 1],
-                               (size_t)(N / 4), Ls, alpha, llout, filt, A, Ls, (T)1);
+        } else if (lev == 0 && xa) {
+            hipLaunchKernelGGL((k_wav_fwd_level<T, true>), g, dim3(256), 0, s, x, (size_t)0, P.n, alpha, llout,
+                               filt, A, Ls, scale, *xa);
+        } else if (lev == 0) {
+            hipLaunchKernelGGL((k_wav_fwd_level<T, false>), g, dim3(256), 0, s, x, (size_t)0, P.n, alpha, llout,
+                               filt, A, Ls, scale, XhatArgs<T>{});
+        } else {
+            hipLaunchKernelGGL((k_wav_fwd_level<T, false>), g, dim3(256), 0, s, (const cpx<T>*)llb[(lev - 1) & 1],
+                               (size_t)(N / 4), Ls, alpha, llout, filt, A, Ls, (T)1, XhatArgs<T>{});
+        }
+        if (lev == 0 && first_done) (void)hipEventRecord(first_done, s);
     }
 }
 
@@ -511,8 +539,10 @@ void launch_psi(const Plan& P, const cpx<T>* alpha, cpx<T>* x, hipStream_t s) {
                        cur < 0 ? 1 : 0, x, filt, A, scale);
 }
 
-template void launch_psi_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
-template void launch_psi_adj<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
+template void launch_psi_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t,
+                                    const XhatArgs<float>*, hipEvent_t);
+template void launch_psi_adj<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t,
+                                     const XhatArgs<double>*, hipEvent_t);
 template void launch_psi<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
 template void launch_psi<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
 
