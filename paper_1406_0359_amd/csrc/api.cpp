@@ -214,14 +214,16 @@ struct Sdmm {
                                             part(c & 1), inv_nu2, part(2));
         }
         const int cl = prm->cg_iter;
-        // i = 1 (on s2): l1 prior on Psi^dag x_hat.  Branch i = 1 is the longer one, so where
-        // the analysis can form x_hat = x + alpha p itself it forks before the CG's last
-        // update, and the update (which writes x_hat over x) waits only for the finest
-        // analysis level, the one launch that reads x and p.
+        // i = 1 (on s2): l1 prior on Psi^dag x_hat.  With the NUFFT operator branch i = 1 is
+        // the longer one, so where the analysis can form x_hat = x + alpha p itself it forks
+        // before the CG's last update, and the update (which writes x_hat over x) waits only
+        // for the finest analysis level, the one launch that reads x and p.  With the stored
+        // operator the main stream also forms the next A x_hat and is the longer branch, so
+        // it does not wait.
         // The objective's partial sums (part 3, nb1 of them) are summed on the main stream
         // after the join, by the kernel that ends the iteration, off this branch's chain.
         int nb1 = 0;
-        if (!tv && psi_adj_takes_xhat(P)) {
+        if (!tv && !toep && psi_adj_takes_xhat(P)) {
             (void)hipEventRecord(fork, s);
             (void)hipStreamWaitEvent(s2, fork, 0);
             const XhatArgs<T> xa{p, part((cl - 1) & 1), rho_count, part(2), rows_blocks};
