@@ -229,11 +229,11 @@ struct Sdmm {
             const XhatArgs<T> xa{p, part((cl - 1) & 1), rho_count, part(2), rows_blocks};
             launch_psi_adj<T>(P, xh, v1, s2, &xa, hat);
             (void)hipStreamWaitEvent(s, hat, 0);
-            launch_cg_xr<T>(xh, r, p, q, part((cl - 1) & 1), rho_count, part(2), rows_blocks, N, part(cl & 1), s);
+            launch_cg_x<T>(xh, p, part((cl - 1) & 1), rho_count, part(2), rows_blocks, N, s);
             nb1 = launch_prox_l1<T>(v1, z1, prm->weights, gamma, D, part(3), s2);
             launch_psi<T>(P, v1, x1, s2);
         } else {
-            launch_cg_xr<T>(xh, r, p, q, part((cl - 1) & 1), rho_count, part(2), rows_blocks, N, part(cl & 1), s);
+            launch_cg_x<T>(xh, p, part((cl - 1) & 1), rho_count, part(2), rows_blocks, N, s);
             (void)hipEventRecord(fork, s);
             (void)hipStreamWaitEvent(s2, fork, 0);
             if (tv) {   // TV prior: prox on u = x_hat + z1 (in v1), x1 = r1 - z1

@@ -253,10 +253,9 @@ enum FinalOp : int {
 void launch_finalize(const double* part, int count, double* sc, int slot, int op, double arg,
                      double* hist, int hist_index, hipStream_t s);
 
-// CG step with alpha = rho / <p, q> summed from partials inside the kernel
-template <typename T> int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q,
-                                       const double* rho_part, int rho_count, const double* pq_part,
-                                       int pq_count, int64_t n, double* part, hipStream_t s);
+// the CG's last update x += alpha p, alpha = rho / <p, q> summed from partials in the kernel
+template <typename T> void launch_cg_x(cpx<T>* x, const cpx<T>* p, const double* rho_part, int rho_count,
+                                       const double* pq_part, int pq_count, int64_t n, hipStream_t s);
 // p = r + (rho_new / rho) p, both from partials
 // power-iteration normalisation v = w / ||w|| (||w||^2 from partials), sc[LAMBDA] = ||w||
 template <typename T> void launch_power_normalise(cpx<T>* v, const cpx<T>* w, const double* part,

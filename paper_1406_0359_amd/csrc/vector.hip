@@ -151,33 +151,25 @@ k_finalize(const double* __restrict__ part, int count, double* sc, int slot, int
     }
 }
 
-// CG step: alpha = rho / Re<p, q> from the partial sums of both (rho == 0: alpha = 0,
-// the early stop); x += alpha p ; r -= alpha q ; partial <r, r> of the new residual.
+// The CG's last update: alpha = rho / Re<p, q> from the partial sums of both (rho == 0:
+// alpha = 0, the early stop); x += alpha p.  The residual is not updated: the next global
+// update starts again from r = b - A x.
 template <typename T>
 __global__ void __launch_bounds__(VT)
-k_cg_xr(cpx<T>* __restrict__ x, cpx<T>* __restrict__ r, const cpx<T>* __restrict__ p,
-        const cpx<T>* __restrict__ q, const double* __restrict__ rho_part, int rho_count,
-        const double* __restrict__ pq_part, int pq_count, int64_t n, double* part) {
+k_cg_x(cpx<T>* __restrict__ x, const cpx<T>* __restrict__ p, const double* __restrict__ rho_part, int rho_count,
+       const double* __restrict__ pq_part, int pq_count, int64_t n) {
     // first element's operands are loaded before the partial sums are read (both in flight)
     const int64_t i0 = (int64_t)blockIdx.x * VT + threadIdx.x;
-    cpx<T> x0, r0, p0, q0;
+    cpx<T> x0, p0;
     if (i0 < n) {
         x0 = x[i0];
-        r0 = r[i0];
         p0 = p[i0];
-        q0 = q[i0];
     }
     const T alpha = cg_alpha<T>(rho_part, rho_count, pq_part, pq_count);
-    double acc = 0;
     GRID_STRIDE(i, n) {
         const bool first = i == i0;
         x[i] = (first ? x0 : x[i]) + alpha * (first ? p0 : p[i]);
-        const cpx<T> v = (first ? r0 : r[i]) - alpha * (first ? q0 : q[i]);
-        r[i] = v;
-        acc += (double)v.x * v.x + (double)v.y * v.y;
     }
-    const double t = block_sum(acc);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // i = 1 of Algorithm 1: u = v1 + z1 ; r1 = soft(u, gamma w) ; z1 = u - r1 ; v1 <- r1 - z1 ;
@@ -486,13 +478,10 @@ void launch_finalize(const double* part, int count, double* sc, int slot, int op
                        hist_index);
 }
 template <typename T>
-int launch_cg_xr(cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q, const double* rho_part,
-                 int rho_count, const double* pq_part, int pq_count, int64_t n, double* part,
-                 hipStream_t s) {
-    const int b = red_blocks(n);
-    hipLaunchKernelGGL(k_cg_xr<T>, dim3(b), dim3(VT), 0, s, x, r, p, q, rho_part, rho_count, pq_part,
-                       pq_count, n, part);
-    return b;
+void launch_cg_x(cpx<T>* x, const cpx<T>* p, const double* rho_part, int rho_count, const double* pq_part,
+                 int pq_count, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_x<T>, dim3(red_blocks(n)), dim3(VT), 0, s, x, p, rho_part, rho_count, pq_part,
+                       pq_count, n);
 }
 template <typename T>
 int launch_prox_l1(cpx<T>* v1, cpx<T>* z1, const double* w, double gamma, int64_t n, double* part,
@@ -587,8 +576,8 @@ int launch_diff2_part(const cpx<T>* a, const cpx<T>* b, int64_t n, double* part_
     template void launch_fill<T>(cpx<T>*, cpx<T>, int64_t, hipStream_t);                                \
     template int launch_norm2_part<T>(const cpx<T>*, int64_t, double*, hipStream_t);                     \
     template int launch_maxabs_part<T>(const cpx<T>*, int64_t, double*, hipStream_t);                    \
-    template int launch_cg_xr<T>(cpx<T>*, cpx<T>*, const cpx<T>*, const cpx<T>*, const double*, int,     \
-                                 const double*, int, int64_t, double*, hipStream_t);                     \
+    template void launch_cg_x<T>(cpx<T>*, const cpx<T>*, const double*, int, const double*, int, int64_t, \
+                                 hipStream_t);                                                           \
     template void launch_power_normalise<T>(cpx<T>*, const cpx<T>*, const double*, int, double*, int64_t, \
                                             hipStream_t);                                                \
     template int launch_prox_l1<T>(cpx<T>*, cpx<T>*, const double*, double, int64_t, double*, hipStream_t); \
