@@ -17,12 +17,17 @@ conventions taken (the paper defers them to its companion paper):
   F (not its inverse) and G^T is the transpose of the real matrix G.
 """
 import math
+import os
 
 import numpy as np
 import scipy.fft
 import scipy.sparse as sp
 
 from .kaiser_bessel import default_beta, deapodisation, kb_kernel
+
+# scipy.fft splits a 2D transform into independent 1D transforms over its threads, so the
+# thread count changes the run time, not the result.
+FFT_WORKERS = os.cpu_count() or 1
 
 
 def grid_coordinates(uv: np.ndarray, K: int) -> np.ndarray:
@@ -76,14 +81,14 @@ class Nufft:
         """y = G F Z S x."""
         x = np.asarray(x, dtype=np.complex128).reshape(self.n, self.n)
         g = self.zero_pad(self.s2 * x)
-        ghat = scipy.fft.fft2(g)
+        ghat = scipy.fft.fft2(g, workers=FFT_WORKERS)
         return self.G @ ghat.ravel()
 
     def phi_adj(self, y: np.ndarray) -> np.ndarray:
         """x = S Z^T F^dagger G^T y."""
         y = np.asarray(y, dtype=np.complex128)
         ghat = (self.GT @ y).reshape(self.K, self.K)
-        g = scipy.fft.ifft2(ghat) * (self.K * self.K)
+        g = scipy.fft.ifft2(ghat, workers=FFT_WORKERS) * (self.K * self.K)
         return self.s2 * self.crop(g)
 
     def normal(self, x: np.ndarray) -> np.ndarray:

@@ -65,6 +65,30 @@ def conjugate_gradient(apply_A, b, x0, iters: int):
     return x
 
 
+def halting_due(t: int, check_every: int, iters: int) -> bool:
+    """Whether the stopping test runs after iteration t (1-based) when it is checked every
+    ``check_every`` iterations: from the second iteration on (the first has no predecessor
+    to compare with), at multiples of ``check_every`` and after the last iteration."""
+    k = max(1, int(check_every))
+    return t >= 2 and (t % k == 0 or t == iters)
+
+
+def constraints_met(residuals, bounds, slack: float) -> bool:
+    """Data-fidelity half of the stopping rule (Section 3): every block's residual
+    ||y_i - Phi_i x_hat|| is within its bound eps_i, relaxed by the factor (1 + slack)."""
+    return all(r <= e * (1.0 + slack) for r, e in zip(residuals, bounds))
+
+
+def halting_test(f_prev: float, f: float, feasible: bool, xi: float) -> bool:
+    """Stopping rule of Section 3 (Algorithm 1's halting criteria): stop when the relative
+    variation of the objective between successive solutions, |f_t - f_{t-1}| / f_t, is
+    below xi AND the data constraints hold (``feasible``).  Both conditions are required;
+    a zero (or non-positive, or non-finite) current objective never stops."""
+    if f_prev is None or not (f > 0) or not np.isfinite(f) or not np.isfinite(f_prev):
+        return False
+    return bool(abs(f - f_prev) / f < xi) and bool(feasible)
+
+
 @dataclass
 class SdmmResult:
     x: np.ndarray
@@ -79,7 +103,8 @@ class SdmmResult:
 def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
          cg_iters: int = 10, gamma: Optional[float] = None, nu: Optional[float] = None,
          weights=None, halting: bool = False, xi: float = 1e-4, slack: float = 1e-3,
-         nu_iters: int = 100, x0=None, normal=None, blocks=None, tv_iters=None) -> SdmmResult:
+         nu_iters: int = 100, x0=None, normal=None, blocks=None, tv_iters=None,
+         check_every: int = 1) -> SdmmResult:
     """Run SDMM (Algorithm 1, R = 1, S = 3) and return x_hat (complex; the image is Re).
     normal: a stored form of Phi^dagger Phi for the global update's conjugate-gradient
     operator (Section 3), e.g. the Toeplitz operator of oracle.toeplitz; None applies Phi
@@ -91,7 +116,10 @@ def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
     Phi^dagger; halting asks every block's residual to be within its bound.
     tv_iters: f1 = the (weighted) total variation with L1 = I instead of the l1 term
     (oracle.tv: prox by that many dual projection steps; weights per pixel; objective TV(x_hat);
-    default gamma 1e-3 max |grad Phi~^dagger y~|).  psi and psi_adj are then unused."""
+    default gamma 1e-3 max |grad Phi~^dagger y~|).  psi and psi_adj are then unused.
+    halting: stop after iteration t when halting_due(t, check_every, iters) and
+    halting_test(f_{t-1}, f_t, constraints_met(...), xi); f_{t-1} is always the previous
+    iteration's objective (successive solutions), whatever the test period."""
     if nu is None or nu <= 0:
         nu, _ = operator_norm(lambda v: phi_adj(phi(v)), shape, nu_iters)
     yt = np.asarray(y, dtype=np.complex128) / nu
@@ -156,13 +184,13 @@ def sdmm(phi, phi_adj, psi, psi_adj, y, epsilon, shape, iters: int = 300,
         res.objective.append(f)
         res.residual.append(resid)
         res.iterations = t
-        if blocks is None:
-            feasible = resid <= et * (1.0 + slack)
-        else:
-            feasible = all(np.linalg.norm(yt[a:b] - v3[a:b]) <= e * (1.0 + slack)
-                           for a, b, e in zip(offsets[:-1], offsets[1:], ets))
-        if halting and f_prev is not None and f > 0:
-            if abs(f - f_prev) / f < xi and feasible:
+        if halting and halting_due(t, check_every, iters):
+            if blocks is None:
+                feasible = constraints_met([resid], [et], slack)
+            else:
+                feasible = constraints_met(
+                    [np.linalg.norm(yt[a:b] - v3[a:b]) for a, b in zip(offsets[:-1], offsets[1:])], ets, slack)
+            if halting_test(f_prev, f, feasible, xi):
                 res.converged = True
                 break
         f_prev = f

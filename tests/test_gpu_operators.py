@@ -113,6 +113,9 @@ PSI_CASES = [  # n, mask, levels
     (64, 0x006, 1),
     (128, 0x101, 5),
     (256, 0x1FF, 4),
+    (512, 0x1FF, 4),     # FP32 synthesis: 32 x 32 finest-level tiles from n = 512 on
+    (1024, 0x1FF, 4),    # analysis: every basis' finest level in one pass from n = 1024 on
+    (1024, 0x0FE, 5),    # wavelets only, five levels
 ]
 
 
@@ -135,8 +138,11 @@ def test_psi_and_adjoint_match_oracle(n, mask, L, prec):
         assert max_rel(got_a, ref_a) < 1e-11 and max_rel(got_x, ref_x) < 1e-11
 
 
-def test_gpu_tight_frame():
-    n = 256
-    plan = purify.Plan(n, uv_case(10, n, 1), dict_mask=0x1FF, levels=4, device=DEV)
+@pytest.mark.parametrize("n,L,prec,tol", [(256, 4, "fp64", 1e-13), (1024, 4, "fp64", 1e-13),
+                                          (1024, 4, "fp32", 1e-6), (4096, 5, "fp32", 1e-6)])
+def test_gpu_tight_frame(n, L, prec, tol):
+    # Psi Psi^dagger = I (Section 3) holds at any size: at 4096^2 (five levels, the large
+    # single solve's dictionary) where the oracle's own transform would take minutes
+    plan = purify.Plan(n, uv_case(10, n, 1), dict_mask=0x1FF, levels=L, precision=prec, device=DEV)
     x = plan.as_vec(rand_complex((n, n), 12))
-    assert rel_l2(to_np(plan.psi(plan.psi_adj(x))), to_np(x)) < 1e-13
+    assert rel_l2(to_np(plan.psi(plan.psi_adj(x))), to_np(x)) < tol

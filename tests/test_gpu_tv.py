@@ -31,14 +31,16 @@ def _hist_rel(h, ref):
     return float(np.max(np.where(ref == 0, d, d / np.where(ref == 0, 1.0, np.abs(ref)))))
 
 
-@pytest.mark.parametrize("weighted", [False, True])
-def test_tv_sdmm_matches_oracle_fp64(weighted):
+@pytest.mark.parametrize("weighted,cg", [(False, 10), (True, 10), (False, 1), (False, 2), (False, 3)])
+def test_tv_sdmm_matches_oracle_fp64(weighted, cg):
     w, p, op = _problem()
     wt = np.random.default_rng(3).uniform(0.5, 1.5, (64, 64)) if weighted else None
-    ref = sdmm(op.phi, op.phi_adj, None, None, p.y, p.epsilon, (64, 64), iters=40, tv_iters=30, weights=wt)
+    ref = sdmm(op.phi, op.phi_adj, None, None, p.y, p.epsilon, (64, 64), iters=40, tv_iters=30, weights=wt,
+               cg_iters=cg)
     plan = purify.Plan(64, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels, device=DEV)
     wd = torch.as_tensor(wt.ravel(), device=DEV) if weighted else None
-    res = plan.sdmm(plan.as_vec(p.y), p.epsilon, max_iter=40, tv_iter=30, weights=wd, record_history=True)
+    res = plan.sdmm(plan.as_vec(p.y), p.epsilon, max_iter=40, tv_iter=30, weights=wd, record_history=True,
+                    cg_iter=cg)
     assert abs(res.gamma / ref.gamma - 1) < 1e-12
     assert rel_l2(to_np(res.x), ref.x) < 1e-9
     assert _hist_rel(res.history[:, 0], ref.objective) < 1e-9

@@ -7,7 +7,10 @@
 * special case eps >= ||y||: x_hat -> 0;
 * constraint satisfaction at convergence;
 * brute force: SLSQP on a tiny real problem reaches the same objective as SDMM;
-* the chi-square noise bound covers ~97.7% of noise draws (Monte Carlo).
+* the chi-square noise bound covers ~97.7% of noise draws (Monte Carlo);
+* the stopping rule (Section 3: relative objective variation below xi AND every data
+  constraint met) on a hand-written table of cases, its test schedule, and the iteration a
+  halting run stops at against a fixed-length run of the same problem.
 """
 import math
 
@@ -18,7 +21,8 @@ from scipy import optimize
 from oracle.nufft import Nufft
 from oracle.prox import project_l2_ball, project_positive, soft_threshold
 from oracle.sara import Sara
-from oracle.sdmm import conjugate_gradient, operator_norm, sdmm
+from oracle.sdmm import (conjugate_gradient, constraints_met, halting_due, halting_test, operator_norm,
+                         sdmm)
 from paper_1406_0359_amd import synth
 
 
@@ -163,3 +167,66 @@ def test_chi2_epsilon_coverage():
         n = sigma * synth.unit_complex_noise(M, rng)
         hits += np.linalg.norm(n) <= eps
     assert abs(hits / trials - 0.977) < 0.012
+
+
+# (f_prev, f, residuals, bounds, xi, slack, stop?) -- outcomes worked out by hand from the
+# rule's two conditions: |f - f_prev| / f < xi, and residual_i <= eps_i (1 + slack) for all i.
+HALTING_TABLE = [
+    (1.0, 1.0, [0.5], [1.0], 1e-4, 0.0, True),          # no change, well inside the ball
+    (1.0, 1.00005, [0.5], [1.0], 1e-4, 0.0, True),      # variation 5.0e-5 < 1e-4
+    (1.00005, 1.0, [0.5], [1.0], 1e-4, 0.0, True),      # decreasing objective, same size
+    (1.0, 1.0002, [0.5], [1.0], 1e-4, 0.0, False),      # variation 2.0e-4: too large
+    (1.0, 1.0, [1.0005], [1.0], 1e-4, 1e-3, True),      # outside eps, inside eps (1 + slack)
+    (1.0, 1.0, [1.002], [1.0], 1e-4, 1e-3, False),      # outside eps (1 + slack): infeasible
+    (1.0, 1.0, [1.0], [1.0], 1e-4, 0.0, True),          # on the sphere counts as inside
+    (1.0, 1.5, [2.0], [1.0], 1e-4, 0.0, False),         # both conditions fail
+    (2.0, 1.0, [0.1], [1.0], 0.6, 0.0, False),          # |1 - 2| / 1 = 1.0 >= 0.6 (relative to f_t,
+                                                        # not f_{t-1}: 0.5 would stop)
+    (1.0, 2.0, [0.1], [1.0], 0.6, 0.0, True),           # |2 - 1| / 2 = 0.5 < 0.6
+    (1.0, 1.0, [0.5, 0.9, 1.3], [1.0, 1.0, 1.0], 1e-4, 0.0, False),   # one block of three outside
+    (1.0, 1.0, [0.5, 0.9, 1.0], [1.0, 1.0, 1.0], 1e-4, 0.0, True),    # every block inside
+    (1.0, 1.0, [0.2, 3.0], [0.1, 5.0], 1e-4, 0.0, False),  # per-block bounds, not a shared one
+    (0.0, 0.0, [0.0], [1.0], 1e-4, 0.0, False),         # zero objective never stops
+    (None, 1.0, [0.0], [1.0], 1e-4, 0.0, False),        # first iteration: no predecessor
+    (1.0, float("nan"), [0.0], [1.0], 1e-4, 0.0, False),
+]
+
+
+@pytest.mark.parametrize("f_prev,f,res,bnd,xi,slack,stop", HALTING_TABLE)
+def test_halting_rule_table(f_prev, f, res, bnd, xi, slack, stop):
+    assert halting_test(f_prev, f, constraints_met(res, bnd, slack), xi) is stop
+
+
+def test_halting_schedule():
+    due = lambda k, T: [t for t in range(1, T + 1) if halting_due(t, k, T)]
+    assert due(1, 6) == [2, 3, 4, 5, 6]
+    assert due(10, 35) == [10, 20, 30, 35]
+    assert due(3, 7) == [3, 6, 7]
+    assert due(10, 1) == []
+    assert due(0, 4) == [2, 3, 4]          # a non-positive period means every iteration
+
+
+@pytest.mark.parametrize("check_every", [1, 3])
+def test_sdmm_halting_stops_at_first_due_iteration_meeting_both_conditions(check_every):
+    # Halting does not change the iterates, so a fixed-length run's history says where the
+    # halting run must stop: the first scheduled iteration t >= 2 at which the objective moved
+    # by less than xi relative to f_t since iteration t - 1 and the residual is within the
+    # relaxed bound.  The stopping point's constraint is then checked on the image directly.
+    op, sa, x, y, eps = _tiny_problem(n=16, M=160, mask=0x1FF, L=2, seed=4)
+    xi, slack, T = 2e-3, 1e-3, 400
+    full = sdmm(op.phi, op.phi_adj, sa.psi, sa.psi_adj, y, eps, (16, 16), iters=T)
+    f, res, et = full.objective, full.residual, eps / full.nu
+    expect = None
+    for t in range(2, T + 1):
+        if t % check_every and t != T:
+            continue
+        if abs(f[t - 1] - f[t - 2]) < xi * f[t - 1] and res[t - 1] <= et * (1 + slack):
+            expect = t
+            break
+    assert expect is not None and expect < T
+    r = sdmm(op.phi, op.phi_adj, sa.psi, sa.psi_adj, y, eps, (16, 16), iters=T, halting=True, xi=xi,
+             slack=slack, check_every=check_every)
+    assert r.converged and r.iterations == expect
+    short = sdmm(op.phi, op.phi_adj, sa.psi, sa.psi_adj, y, eps, (16, 16), iters=expect)
+    assert np.array_equal(r.x, short.x)
+    assert np.linalg.norm(y - op.phi(r.x)) <= eps * (1 + slack)
