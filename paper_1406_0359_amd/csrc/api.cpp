@@ -132,26 +132,6 @@ purify_status ensure_chat(Plan& P, hipStream_t s) {
     return PURIFY_OK;
 }
 
-// RAII holder for the solver's internal streams, events and graphs.
-struct SolveResources {
-    hipStream_t cs = nullptr, cs2 = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr, done = nullptr, hat = nullptr;
-    hipGraph_t g_iter = nullptr, g_pow = nullptr;
-    hipGraphExec_t x_iter = nullptr, x_pow = nullptr;
-    ~SolveResources() {
-        if (x_iter) (void)hipGraphExecDestroy(x_iter);
-        if (x_pow) (void)hipGraphExecDestroy(x_pow);
-        if (g_iter) (void)hipGraphDestroy(g_iter);
-        if (g_pow) (void)hipGraphDestroy(g_pow);
-        if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
-        if (done) (void)hipEventDestroy(done);
-        if (hat) (void)hipEventDestroy(hat);
-        if (cs) (void)hipStreamDestroy(cs);
-        if (cs2) (void)hipStreamDestroy(cs2);
-    }
-};
-
 template <typename T>
 struct Sdmm {
     using C = cpx<T>;
@@ -345,12 +325,6 @@ bool blocks_valid(const purify_sdmm_params* prm, int64_t M) {
     return true;
 }
 
-purify_status capture(hipStream_t cs, hipGraph_t* g, hipGraphExec_t* x) {
-    PURIFY_HIP(hipStreamEndCapture(cs, g));
-    PURIFY_HIP(hipGraphInstantiate(x, *g, nullptr, nullptr, 0));
-    return PURIFY_OK;
-}
-
 // x_in: x_hat(0) (device, N complex) or null for x_hat(0) = 0; x_out: receives x_hat, or null
 // to leave it in the plan's x_hat buffer only (x_in and x_out may be the same vector).
 template <typename T>
@@ -362,18 +336,21 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     double* sc = P.sc;
     const bool use_graph = (prm->flags & PURIFY_SDMM_NO_GRAPH) == 0;
     Sdmm<T> S{P, prm};
-    SolveResources R;
-    PURIFY_HIP(hipStreamCreateWithFlags(&R.cs, hipStreamNonBlocking));
-    PURIFY_HIP(hipStreamCreateWithFlags(&R.cs2, hipStreamNonBlocking));
-    PURIFY_HIP(hipEventCreateWithFlags(&R.fork, hipEventDisableTiming));
-    PURIFY_HIP(hipEventCreateWithFlags(&R.join, hipEventDisableTiming));
-    PURIFY_HIP(hipEventCreateWithFlags(&R.done, hipEventDisableTiming));
-    PURIFY_HIP(hipEventCreateWithFlags(&R.hat, hipEventDisableTiming));
+    if (!P.ss) {
+        set_error("plan has no solver streams");
+        return PURIFY_E_INVALID;
+    }
+    {
+        const purify_status st = solver_streams_init(*P.ss);
+        if (st != PURIFY_OK) return st;
+    }
+    SolverStreams& R = *P.ss;
+    SolveGraphs G(&R);   // drains R's streams before its graphs go, also on error returns
     hipStream_t cs = R.cs;
 
     // the solver's streams start after the caller's prior work on s
-    PURIFY_HIP(hipEventRecord(R.done, s));
-    PURIFY_HIP(hipStreamWaitEvent(cs, R.done, 0));
+    PURIFY_HIP(hipEventRecord(R.entry, s));
+    PURIFY_HIP(hipStreamWaitEvent(cs, R.entry, 0));
     S.toep = (prm->flags & PURIFY_SDMM_TOEPLITZ) != 0;
     S.tv = (prm->flags & PURIFY_SDMM_TV) != 0;
     if (S.toep) {
@@ -388,11 +365,14 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     if (!(nu > 0)) {
         launch_fill<T>((C*)P.p, mk<T>((T)(1.0 / std::sqrt((double)N)), 0), N, cs);
         if (use_graph && prm->nu_iter > 1) {
-            PURIFY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-            S.enqueue_power_step(cs);
-            purify_status st = capture(cs, &R.g_pow, &R.x_pow);
-            if (st != PURIFY_OK) return st;
-            for (int it = 0; it < prm->nu_iter; ++it) PURIFY_HIP(hipGraphLaunch(R.x_pow, cs));
+            {
+                std::lock_guard<std::mutex> lk(graph_mutex());
+                PURIFY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+                S.enqueue_power_step(cs);
+                const purify_status st = end_capture(G, 0, cs);
+                if (st != PURIFY_OK) return st;
+            }
+            for (int it = 0; it < prm->nu_iter; ++it) PURIFY_HIP(hipGraphLaunch(G.x[0], cs));
         } else {
             for (int it = 0; it < prm->nu_iter; ++it) S.enqueue_power_step(cs);
         }
@@ -460,9 +440,10 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     S.enqueue_prologue(cs);
 
     if (use_graph) {
+        std::lock_guard<std::mutex> lk(graph_mutex());
         PURIFY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
         S.enqueue_iteration(cs, R.cs2, R.fork, R.join, R.hat);
-        purify_status st = capture(cs, &R.g_iter, &R.x_iter);
+        const purify_status st = end_capture(G, 1, cs);
         if (st != PURIFY_OK) return st;
     }
     const int T_max = prm->max_iter;
@@ -470,7 +451,7 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
     int it_done = 0;
     bool converged = false;
     for (int t = 0; t < T_max; ++t) {
-        if (use_graph) PURIFY_HIP(hipGraphLaunch(R.x_iter, cs));
+        if (use_graph) PURIFY_HIP(hipGraphLaunch(G.x[1], cs));
         else S.enqueue_iteration(cs, R.cs2, R.fork, R.join, R.hat);
         it_done = t + 1;
         if (prm->halting && t >= 1 && ((t + 1) % check == 0 || t + 1 == T_max)) {
@@ -499,9 +480,9 @@ purify_status sdmm_impl(Plan& P, const void* y_user, const purify_sdmm_params* p
         PURIFY_HIP(hipMemcpyAsync(prm->history, P.hist, (size_t)2 * cnt * sizeof(double),
                                   hipMemcpyDeviceToHost, cs));
     }
+    // cs has drained (branch i = 1 joins it inside every iteration), so the caller's later
+    // work on s, enqueued after this call returns, is ordered after the solve
     PURIFY_HIP(hipStreamSynchronize(cs));
-    PURIFY_HIP(hipEventRecord(R.done, cs));
-    PURIFY_HIP(hipStreamWaitEvent(s, R.done, 0));
     if (info) {
         info->iterations = it_done;
         info->converged = converged ? 1 : 0;
@@ -707,6 +688,7 @@ purify_status purify_plan_create(const purify_plan_desc* desc, void* workspace, 
         return PURIFY_E_WORKSPACE;
     }
     layout(P, desc, (char*)workspace);
+    P.ss = &h->own;
     P.ws = (char*)workspace;
     P.ws_bytes = bytes;
     const purify_status st = build_plan(P, desc, (hipStream_t)stream);
@@ -718,7 +700,11 @@ purify_status purify_plan_create(const purify_plan_desc* desc, void* workspace, 
     return PURIFY_OK;
 }
 
-void purify_plan_destroy(purify_plan* plan) { delete plan; }
+void purify_plan_destroy(purify_plan* plan) {
+    if (!plan) return;
+    solver_streams_release(plan->own);
+    delete plan;
+}
 
 purify_status purify_phi(const purify_plan* plan, const void* x, void* y, void* stream) {
     CHECK_PLAN(plan);

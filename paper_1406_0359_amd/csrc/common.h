@@ -11,6 +11,8 @@
 
 namespace purify {
 
+struct SolverStreams;   // solver_rt.h
+
 // ---------------------------------------------------------------------------------------
 // Complex numbers: interleaved (re, im), 8- or 16-byte aligned so loads are single vector
 // instructions.
@@ -160,6 +162,8 @@ struct Plan {
     int32_t* bchunk_off = nullptr;  // MAX_BLOCKS + 1: first chunk of each block
     double* beps = nullptr;      // MAX_BLOCKS: eps_i / nu
     double* bscale = nullptr;    // MAX_BLOCKS: ball scale of each block (this iteration)
+    // streams and events the solver runs on (the plan's own, or a server slot's)
+    SolverStreams* ss = nullptr;
 };
 
 // ---------------------------------------------------------------------------------------
@@ -345,7 +349,11 @@ int daubechies(int N, double* h_out);
         }                                                                                  \
     } while (0)
 
-// The plan struct handle type of the C ABI
+#include "solver_rt.h"
+
+// The plan struct handle type of the C ABI.  `own` holds the plan's solver streams, created
+// on its first solve unless P.ss points elsewhere (a server slot's).
 struct purify_plan {
     purify::Plan P;
+    purify::SolverStreams own;
 };

@@ -1021,9 +1021,9 @@ int strip_groups(const Plan& P, int C) {
     return (P.strip_xcd && P.TT % C == 0) ? P.TT / C : 0;
 }
 
-// Raises a kernel's dynamic LDS limit above 64 KB once per process (per kernel), under a
-// lock: solves on several host threads (the server) then never change a kernel's attribute
-// while another thread launches or captures it.
+// Raises a kernel's dynamic LDS limit above 64 KB once per process (per kernel and size),
+// under a lock: solves on several host threads (the server) then never change a kernel's
+// attribute while another thread launches or captures it at a size it already allows.
 std::mutex g_lds_mu;
 std::map<const void*, size_t> g_lds_set;
 

@@ -6,8 +6,9 @@
 // image) from a first-fit allocator; the block returns to the arena when the result has
 // reached the host.  Each of `max_active` worker slots owns a stream and runs one solve at a
 // time -- plan creation (host binning, upload), then the same graph-replayed SDMM iteration
-// as purify_sdmm_solve -- so the device executes the kernels of up to `max_active` solves at
-// once while new requests wait for a free slot and enough arena memory.  A waiting request
+// as purify_sdmm_solve, on solver streams and events the slot creates once for all its
+// solves -- so the device executes the kernels of up to `max_active` solves at once while
+// new requests wait for a free slot and enough arena memory.  A waiting request
 // may be overtaken by a later one that fits, at most 2 * max_active times, after which it
 // is admitted first.  Results are identical to solving the request alone: the kernels are
 // deterministic and no state is shared between solves.
@@ -127,7 +128,7 @@ std::shared_ptr<Request> admit(purify_server* S) {
     return nullptr;
 }
 
-void run_request(purify_server* S, Request& r, size_t off, hipStream_t st) {
+void run_request(purify_server* S, Request& r, size_t off, hipStream_t st, purify::SolverStreams& slot) {
     char* blk = S->arena_base + off;
     void* ws = blk;
     void* ydev = blk + round_up(r.ws_bytes);
@@ -135,6 +136,9 @@ void run_request(purify_server* S, Request& r, size_t off, hipStream_t st) {
     r.x.assign(r.x_bytes, 0);
     purify_plan* plan = nullptr;
     hipError_t e = hipMemcpyAsync(ydev, r.y.data(), r.y_bytes, hipMemcpyHostToDevice, st);
+    // the image starts at zero: a solve that stops before writing it (a zero or non-finite
+    // operator norm) then returns zeros, not a previous request's memory
+    if (e == hipSuccess) e = hipMemsetAsync(xdev, 0, r.x_bytes, st);
     if (e != hipSuccess) {
         r.status = PURIFY_E_DEVICE;
         r.error = std::string("visibility upload: ") + hipGetErrorString(e);
@@ -143,7 +147,10 @@ void run_request(purify_server* S, Request& r, size_t off, hipStream_t st) {
     purify_plan_desc d = r.desc;
     d.uv = r.uv.data();
     r.status = purify_plan_create(&d, ws, r.ws_bytes, st, &plan);
-    if (r.status == PURIFY_OK) r.status = purify_sdmm_solve(plan, ydev, &r.prm, xdev, &r.info, st);
+    if (r.status == PURIFY_OK) {
+        plan->P.ss = &slot;   // the slot's streams and events, created once for all its solves
+        r.status = purify_sdmm_solve(plan, ydev, &r.prm, xdev, &r.info, st);
+    }
     if (r.status != PURIFY_OK) r.error = purify_last_error();
     if (r.status == PURIFY_OK || r.status == PURIFY_E_NONFINITE) {
         e = hipMemcpyAsync(r.x.data(), xdev, r.x_bytes, hipMemcpyDeviceToHost, st);
@@ -162,6 +169,11 @@ void worker_main(purify_server* S) {
     (void)hipSetDevice(S->device);
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    purify::SolverStreams slot;
+    if (st && purify::solver_streams_init(slot) != PURIFY_OK) {
+        (void)hipStreamDestroy(st);
+        st = nullptr;
+    }
     for (;;) {
         std::shared_ptr<Request> r;
         {
@@ -174,7 +186,7 @@ void worker_main(purify_server* S) {
         }
         if (!r) break;
         const size_t off = r->off;
-        if (st) run_request(S, *r, off, st);
+        if (st) run_request(S, *r, off, st, slot);
         else {
             r->status = PURIFY_E_DEVICE;
             r->error = "worker stream creation failed";
@@ -188,7 +200,11 @@ void worker_main(purify_server* S) {
         S->cv_done.notify_all();
         S->cv_work.notify_all();
     }
-    if (st) (void)hipStreamDestroy(st);
+    purify::solver_streams_release(slot);
+    if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
 }
 
 }  // namespace

@@ -42,6 +42,25 @@ hipError_t hipStreamDestroy(hipStream_t s) {
     return hipSuccess;
 }
 const char* hipGetErrorString(hipError_t) { return "host stand-in"; }
+// the solver streams of a worker slot (solver_rt.cpp): events and graphs are dummies here
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) {
+    *e = (hipEvent_t) new int(0);
+    return hipSuccess;
+}
+hipError_t hipEventDestroy(hipEvent_t e) {
+    delete (int*)e;
+    return hipSuccess;
+}
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) {
+    *g = nullptr;
+    return hipSuccess;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t* x, hipGraph_t, hipGraphNode_t*, char*, size_t) {
+    *x = nullptr;
+    return hipSuccess;
+}
+hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
+hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
 
 namespace purify {
 thread_local std::string g_err;

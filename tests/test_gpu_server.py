@@ -17,12 +17,6 @@ from paper_1406_0359_amd import purify  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-# Concurrent worker slots (max_active >= 2) ran the solve's HIP work from several host threads
-# at once, and a benchmark stream on that path ended in host segmentation faults whose cause
-# was not shown; the tests that run it stay skipped until a fix with a shown cause is in.
-CONCURRENT_SKIP = pytest.mark.skip(reason="concurrent server workers: host segmentation fault under "
-                                          "investigation, cause not yet shown")
-
 PARAMS = dict(max_iter=40, cg_iter=10, halting=True, xi=1e-4, slack=1e-3, check_every=10, nu_iter=50)
 
 
@@ -46,7 +40,6 @@ def _submit(srv, p, n, precision):
                       **PARAMS)
 
 
-@CONCURRENT_SKIP
 def test_served_results_equal_solo_results_in_a_mix():
     reqs = [(64, 1200, 0, "fp32"), (128, 3000, 1, "fp32"), (64, 2500, 2, "fp64"), (128, 6000, 3, "fp32"),
             (32, 400, 4, "fp32"), (64, 800, 5, "fp64")]
@@ -62,7 +55,6 @@ def test_served_results_equal_solo_results_in_a_mix():
         assert s.latency_ms >= s.run_ms > 0
 
 
-@CONCURRENT_SKIP
 def test_small_arena_serialises_admission_with_the_same_results():
     reqs = [(64, 1500, 10), (64, 1800, 11), (64, 1200, 12)]
     probs = [_request(n, M, s) for n, M, s in reqs]
@@ -86,7 +78,6 @@ def test_oversized_request_is_rejected():
     srv.close()
 
 
-@CONCURRENT_SKIP
 def test_served_fp32_snr_within_005db_of_fp64_solve():
     p = _request(128, 5000, 30)
     srv = purify.Server(256 << 20, max_active=2, device=DEV)

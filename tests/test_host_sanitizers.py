@@ -26,7 +26,8 @@ def test_server_and_plan_host_code_under_sanitizers(san, tmp_path):
     flags = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=" + san,
              "-D__HIP_PLATFORM_AMD__", "-I" + HIP_INCLUDE, "-w"]
     exe = str(tmp_path / "harness")
-    srcs = [os.path.join(CSRC, "plan.cpp"), os.path.join(CSRC, "server.cpp"), HARNESS]
+    srcs = [os.path.join(CSRC, "plan.cpp"), os.path.join(CSRC, "server.cpp"), os.path.join(CSRC, "solver_rt.cpp"),
+            HARNESS]
     r = subprocess.run([gxx, *flags, *srcs, "-o", exe, "-lpthread"], capture_output=True, text=True,
                        timeout=600)
     if r.returncode != 0 and any(lib in r.stderr for lib in ("libtsan", "libasan", "libubsan")):
