@@ -15,7 +15,8 @@
  *   omega_1, axis 1 with omega_2; pixel coordinate p = j - n/2.
  * - Vectors passed to compute calls are DEVICE pointers owned by the caller.  The library
  *   never allocates device memory: every plan-owned buffer is carved out of the caller's
- *   workspace.  Host pointers are marked "host".
+ *   workspace (the one exception, purify_phi_noalloc's fixed array, is part of the library's
+ *   code object).  Host pointers are marked "host".
  * - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Compute calls
  *   enqueue on it and return without synchronising, except purify_plan_create and
  *   purify_sdmm_solve, which return once their work is complete.
@@ -89,6 +90,18 @@ void purify_plan_destroy(purify_plan* plan);
 /* y = Phi x = G F Z S x (Section 4; Phi of eq. (2)).  x: device, N = n*n complex.
  * y: device, M complex in the caller's uv order. */
 purify_status purify_phi(const purify_plan* plan, const void* x, void* y, void* stream);
+
+/* y = Phi x as purify_phi, for callers that cannot allocate device memory or touch the plan's
+ * workspace (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the row-transformed image and the oversampled grid live in a fixed 48 MiB array
+ * of library device memory, one per device, held until the process ends, instead of the
+ * plan's workspace.  The call allocates nothing and calls no allocating routine; the array's
+ * device address is looked up once per device (the first call with that device current).
+ * Same kernels and same result as purify_phi.  n x K + K x K complex values must fit in the
+ * array (n <= 1024 in FP32, n <= 512 in FP64); larger plans get PURIFY_E_INVALID.  Every call
+ * on a device shares its array: calls that overlap on one device (other streams, other host
+ * threads) race and must be serialised by the caller. */
+purify_status purify_phi_noalloc(const purify_plan* plan, const void* x, void* y, void* stream);
 
 /* x = Phi^dagger y = S Z^T F^dagger G^T y (the exact adjoint of purify_phi). */
 purify_status purify_phi_adj(const purify_plan* plan, const void* y, void* x, void* stream);

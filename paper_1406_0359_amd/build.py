@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libpurify.so")
-SOURCES = ["fft.hip", "nufft.hip", "wavelet.hip", "vector.hip", "toeplitz.hip", "tv.hip", "plan.cpp", "api.cpp", "solver_rt.cpp", "server.cpp"]
+SOURCES = ["fft.hip", "nufft.hip", "wavelet.hip", "vector.hip", "toeplitz.hip", "tv.hip", "noalloc.hip", "plan.cpp", "api.cpp", "solver_rt.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

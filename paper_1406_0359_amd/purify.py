@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "purify_plan_create": (i32, [pdesc, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
         "purify_plan_destroy": (None, [vp]),
         "purify_phi": (i32, [vp, vp, vp, vp]),
+        "purify_phi_noalloc": (i32, [vp, vp, vp, vp]),
         "purify_phi_adj": (i32, [vp, vp, vp, vp]),
         "purify_psi": (i32, [vp, vp, vp, vp]),
         "purify_psi_adj": (i32, [vp, vp, vp, vp]),
@@ -280,6 +281,14 @@ class Plan:
         y = self.empty(self.M) if out is None else out
         _check(self.lib.purify_phi(self.handle, self._vec(x, self.n * self.n, "x"),
                                    self._vec(y, self.M, "y"), self._stream()), "purify_phi")
+        return y
+
+    def phi_noalloc(self, x, out=None):
+        """y = Phi x through purify_phi_noalloc (intermediates in the library's fixed device
+        array instead of the plan workspace; n <= 1024 FP32, n <= 512 FP64)."""
+        y = self.empty(self.M) if out is None else out
+        _check(self.lib.purify_phi_noalloc(self.handle, self._vec(x, self.n * self.n, "x"),
+                                           self._vec(y, self.M, "y"), self._stream()), "purify_phi_noalloc")
         return y
 
     def phi_adj(self, y, out=None):
