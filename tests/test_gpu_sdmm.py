@@ -135,7 +135,10 @@ def test_sdmm_sara1024_fp32_against_stored_oracle():
     # FP32 rounding (~6e-8 a value) perturbs each iteration; the iteration is a composition of
     # nonexpansive maps, so the drift stays near the per-iteration perturbation times the
     # iteration count, well inside 1e-3 relative for the history and the sampled image.
-    g = np.load(os.path.join(GOLDEN, "sara1024_t300.npz"))
+    path = os.path.join(GOLDEN, "sara1024_t300.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored 1024^2 oracle solve not written yet (make_oracle_fixtures.py sara1024)")
+    g = np.load(path)
     w = synth.WORKLOADS["sara1024"]
     p = synth.make_inputs(w)
     synth.add_noise(p, Nufft(w.n, p.uv, w.J).phi(p.x_true))
