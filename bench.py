@@ -7,18 +7,23 @@ off.  ``value`` is SDMM iterations per second over the timed steps (inputs resid
 
 Also reported:
 * ``roofline``: the dominant kernel's algorithmic bytes per launch divided by its average
-  launch time (HIP events on the stream it runs on), against 8 TB/s HBM;
+  launch time (HIP events on the stream it runs on), against 8 TB/s HBM; ``traffic`` is the
+  copy-calibrated counter figure committed under profiles/ for that kernel and workload (null
+  when the kernel source changed since); ``roofline_large`` is the same for the 4096^2 solve;
 * ``cpu_baseline``: the FP64 NumPy/SciPy oracle on the same workload, timed on a bounded
-  sample (setup + a few SDMM iterations, extrapolated to the 300-iteration solve);
+  sample (setup + a few SDMM iterations, extrapolated to the 300-iteration solve), and one
+  whole 64^2 solve;
 * ``steady_state``: the marginal SDMM iterations per second on an existing plan;
-* ``also``: per-stage timings; the 1024 x 1024 FP32 precision-form workload (M = 2N):
-  Phi / Phi^dagger Gvis/s, Psi / Psi^dagger GB/s and SDMM iterations per second; the
-  4096 x 4096 single solve (M = 10^7, J = 8, 5 levels, FP32); the serving form (FP32
-  server on a Poisson stream of mixed-size requests against the FP64 one-at-a-time solves);
-  at 256^2 and 1024^2, the same solve with the stored (Toeplitz) normal operator in CG
-  (Section 3's precomputed composite operator): its iteration rate, stage times and its
-  image against the exact solve's; and at 256^2 the paper's other methods (reweighted l1,
-  visibility blocks, TV and reweighted TV): iteration rates and SNR.
+* ``also``: per-stage timings; rocFFT (torch.fft.fft2) on each workload's oversampled grid
+  beside the library's row + column passes; the 1024 x 1024 FP32 precision-form workload
+  (M = 2N): Phi / Phi^dagger Gvis/s, Psi / Psi^dagger GB/s and SDMM iterations per second;
+  the 4096 x 4096 single solve (M = 10^7, J = 8, 5 levels, FP32, 100 iterations: SNR and
+  residual at the end), alone and beside a Poisson stream of 256^2 requests on the server;
+  the serving form (FP32 server on a Poisson stream of mixed-size requests against the FP64
+  one-at-a-time solves); at 256^2 and 1024^2, the same solve with the stored (Toeplitz) normal
+  operator in CG (Section 3's precomputed composite operator): its iteration rate, stage times
+  and its image against the exact solve's; and at 256^2 the paper's other methods (reweighted
+  l1, visibility blocks, TV and reweighted TV): iteration rates and SNR.
 """
 from __future__ import annotations
 
@@ -36,6 +41,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+T_START = time.perf_counter()
+
+
+def progress(msg: str) -> None:
+    """One line per finished section on stderr (the JSON result line goes to stdout)."""
+    print(f"[bench {time.perf_counter() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def stage_bytes(plan, stage: str) -> float:
@@ -110,10 +121,14 @@ def make_gpu_problem(w, torch, purify, synth, precision: str):
 
 def cpu_baseline(w, p, sample_iters: int) -> dict:
     """Oracle timed on this host: NUFFT set-up, 100 power iterations, gamma, and
-    ``sample_iters`` SDMM iterations; extrapolated to the full solve."""
+    ``sample_iters`` SDMM iterations of the workload, extrapolated to the full solve; plus one
+    whole 64^2 Db8 solve (200 iterations).  scipy.fft runs on every host core (the oracle's
+    setting); the sparse products and the wavelet transforms are single-threaded."""
+    from oracle import nufft as onufft
     from oracle.nufft import Nufft
     from oracle.sara import Sara
     from oracle import sdmm as osd
+    from paper_1406_0359_amd import synth
 
     t0 = time.perf_counter()
     op = Nufft(w.n, p.uv, w.J)
@@ -126,13 +141,24 @@ def cpu_baseline(w, p, sample_iters: int) -> dict:
     setup = t1 - t0
     per_iter = (t2 - t1) / sample_iters
     solve_s = setup + w.iters * per_iter
-    return {"value": w.iters / solve_s, "unit": "iters/s", "cores": 1, "kind": "oracle",
+    w1 = synth.WORKLOADS["small64"]
+    p1 = synth.make_problem(w1, lambda x, uv: Nufft(x.shape[0], uv, w1.J).phi(x))
+    t3 = time.perf_counter()
+    op1 = Nufft(w1.n, p1.uv, w1.J)
+    sa1 = Sara(w1.n, w1.dict_mask, w1.levels)
+    r1 = osd.sdmm(op1.phi, op1.phi_adj, sa1.psi, sa1.psi_adj, p1.y, p1.epsilon, (w1.n, w1.n), iters=w1.iters,
+                  cg_iters=w1.cg_iters)
+    t4 = time.perf_counter()
+    cores = onufft.FFT_WORKERS
+    return {"value": w.iters / solve_s, "unit": "iters/s", "cores": cores, "kind": "oracle",
             "sample": f"{w.name}: set-up + 100 power iterations ({setup:.1f} s) and "
                       f"{sample_iters} SDMM iterations ({per_iter:.2f} s each), "
-                      f"extrapolated to the {w.iters}-iteration solve; "
-                      f"single-threaded NumPy/SciPy FP64 on {platform.processor() or platform.machine()}, "
-                      f"{os.cpu_count()} host cores visible",
-            "seconds": t2 - t0}
+                      f"extrapolated to the {w.iters}-iteration solve; NumPy/SciPy FP64, scipy.fft on "
+                      f"{cores} threads, sparse products and wavelets single-threaded, on "
+                      f"{platform.processor() or platform.machine()} ({os.cpu_count()} host cores visible)",
+            "small64_full_solve": {"iterations": w1.iters, "seconds": t4 - t3, "iters_s": w1.iters / (t4 - t3),
+                                   "snr_db": synth.snr_db(p1.x_true, r1.x)},
+            "seconds": t4 - t0}
 
 
 def precision_form(torch, purify, synth, solve_iters: int) -> dict:
@@ -159,6 +185,9 @@ def precision_form(torch, purify, synth, solve_iters: int) -> dict:
     steady = solve_iters / (timed(10 + solve_iters) - timed(10))
     return {
         "sdmm_steady_iters_s": steady,
+        "roofline": dominant_roofline(st, w.cg_iters, "sara1024"),
+        "fft_vs_rocfft": fft_vs_rocfft(torch, 2 * w.n, torch.complex64, st["fft_rows"]["ms"] + st["fft_cols"]["ms"],
+                                       st["fft_rows"]["bytes"] + st["fft_cols"]["bytes"]),
         "toeplitz": toep,
         "workload": "sara1024 FP32 (n=1024, M=2097152, SARA 9 bases, L=4, J=6)",
         "phi_gvis_s": w.M / (st["phi"]["ms"] * 1e-3) / 1e9,
@@ -232,32 +261,91 @@ def method_variants(torch, plan, y, eps, nu, iters, x_true, synth, snr_plain, uv
     return out
 
 
-COUNTER_FILE = os.path.join(ROOT, "profiles", "k_grid_gtg_sara256_counters.md")
-COUNTER_SOURCE = os.path.join(ROOT, "paper_1406_0359_amd", "csrc", "nufft.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_1406_0359_amd", "csrc")
+STAGE_SOURCE = {"gtg": "nufft.hip", "grid": "nufft.hip", "degrid": "nufft.hip", "fft_rows": "fft.hip",
+                "fft_cols": "fft.hip", "ifft_cols": "fft.hip", "ifft_rows": "fft.hip", "psi": "wavelet.hip",
+                "psi_adj": "wavelet.hip"}
 
 
-def measured_traffic(stage: str):
-    """HBM bytes per launch of the G^T G kernel from the committed counter summary (two
-    rocprofv3 --pmc runs, FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy kernel of
-    known size).  None unless the summary covers `stage` and the kernel source it was taken
-    on is the current one."""
-    if stage != "gtg" or not os.path.exists(COUNTER_FILE):
-        return None
-    fields = {}
-    for ln in open(COUNTER_FILE):
-        if ":" in ln and ln.split(":", 1)[0].strip() in ("traffic_bytes_per_launch", "kernel_source_sha256"):
-            k, v = ln.split(":", 1)
-            fields[k.strip()] = v.strip().strip("`")
+def measured_traffic(stage: str, workload: str):
+    """HBM bytes per launch of a stage's kernel from a committed counter summary under
+    profiles/ (two rocprofv3 --pmc runs, FETCH_SIZE and WRITE_SIZE, each scaled by a plain
+    copy kernel of known size).  None unless a summary covers (stage, workload) and the kernel
+    source it was taken on is the current one."""
+    import glob
     import hashlib
-    sha = hashlib.sha256(open(COUNTER_SOURCE, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+    src = STAGE_SOURCE.get(stage)
+    if src is None:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    sha = hashlib.sha256(open(os.path.join(CSRC, src), "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*_counters.md"))):
+        fields = {}
+        for ln in open(path):
+            if ":" in ln:
+                k, v = ln.split(":", 1)
+                if k.strip() in ("stage", "workload", "traffic_bytes_per_launch", "kernel_source_sha256"):
+                    fields[k.strip()] = v.strip().strip("`")
+        if fields.get("stage") == stage and fields.get("workload") == workload:
+            if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+                return None
+            return float(fields["traffic_bytes_per_launch"])
+    return None
 
 
-def large_solve(torch, purify, synth, iters: int) -> dict:
+def dominant_roofline(st: dict, cg: int, workload: str) -> dict:
+    """Roofline entry for the kernel stage with the largest time share of an SDMM iteration
+    (launches per iteration x average launch time from the stage table)."""
+    per_iter = launches_per_iter(cg)
+    share = {k: st[k]["ms"] * per_iter[k] for k in per_iter if k in KERNEL_NAME}
+    dom = max(share, key=lambda k: share[k])
+    d = st[dom]
+    return {"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["frac"],
+            "traffic": measured_traffic(dom, workload), "kernel": KERNEL_NAME[dom], "stage": dom,
+            "bytes_per_launch": d["bytes"], "ms_per_launch": d["ms"],
+            "share_of_iteration_kernels": share[dom] / sum(share.values())}
+
+
+def fft_vs_rocfft(torch, K: int, dtype, ours_ms: float, ours_bytes: float) -> dict:
+    """torch.fft.fft2 (rocFFT on this build) of a K x K grid, timed with events on the current
+    stream, beside the library's row + column passes of the same oversampled transform (which
+    read the n x n image and never touch the zero half of the padded grid)."""
+    a = torch.randn(K, K, dtype=dtype, device="cuda:0")
+    for _ in range(3):
+        torch.fft.fft2(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        torch.fft.fft2(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    b = 2.0 * K * K * a.element_size()
+    del a
+    return {"grid": f"{K}x{K} {str(dtype).replace('torch.', '')}", "rocfft_ms": ms, "rocfft_GBs": b / (ms * 1e-3) / 1e9,
+            "ours_rows_plus_cols_ms": ours_ms, "ours_GBs": ours_bytes / (ours_ms * 1e-3) / 1e9}
+
+
+def gpu_requests(purify, reqs):
+    """Noiseless visibilities of each request from the FP64 operator, then its noise."""
+    from paper_1406_0359_amd import synth
+    for p in reqs:
+        n = p.x_true.shape[0]
+        pl = purify.Plan(n, p.uv, precision="fp64", device="cuda:0")
+        y0 = pl.phi(pl.as_vec(p.x_true)).cpu().numpy()
+        synth.add_noise(p, y0, p.extra["isnr_db"])
+        del pl
+    return reqs
+
+
+def large_solve(torch, purify, synth, iters: int, background: int) -> dict:
     """The 4096^2 single solve (M = 10^7, J = 8, SARA, 5 levels, FP32 with FP64 reductions):
-    per-operator rates and SDMM iterations per second (nu, gamma and the plan excluded)."""
+    per-operator rates, the dominant kernel's roofline, the oversampled FFT against rocFFT, and
+    the full solve (nu by 100 power iterations, `iters` SDMM iterations) with its SNR and
+    residual; then the same solve beside a Poisson stream of 256^2 requests served at half
+    their standalone capacity."""
     w = synth.WORKLOADS["sara4096"]
     t0 = time.perf_counter()
     p = synth.make_inputs(w)
@@ -270,22 +358,87 @@ def large_solve(torch, purify, synth, iters: int) -> dict:
     y0 = plan.phi(plan.as_vec(p.x_true)).cpu().numpy().astype(np.complex128)
     synth.add_noise(p, y0)
     y = plan.as_vec(p.y)
-    r0 = plan.sdmm(y, p.epsilon, max_iter=2, nu_iter=100)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r0 = plan.sdmm(y, p.epsilon, max_iter=1, nu_iter=100)
+    torch.cuda.synchronize()
+    t_nu = time.perf_counter() - t0
     st = stage_table(plan, reps=5)
     t0 = time.perf_counter()
-    r = plan.sdmm(y, p.epsilon, max_iter=iters, nu=r0.nu)
+    r = plan.sdmm(y, p.epsilon, max_iter=iters, nu=r0.nu, gamma=r0.gamma, record_history=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {
+    x_solo = r.x.clone()
+    out = {
         "workload": "sara4096 FP32 (n=4096, M=10^7, J=8, SARA 9 bases, L=5; 512 blobs + 1/f^2 field)",
-        "sdmm_iters_s": iters / dt, "solve_iters": iters, "snr_db": synth.snr_db(p.x_true, r.x.cpu().numpy()),
+        "sdmm_iters_s": iters / dt, "solve_iters": iters, "solve_s": dt,
+        "snr_db": synth.snr_db(p.x_true, x_solo.cpu().numpy()),
         "residual_over_eps": r.residual / p.epsilon,
+        "objective_rel_change_last": abs(r.history[-1, 0] - r.history[-2, 0]) / r.history[-1, 0],
         "phi_gvis_s": w.M / (st["phi"]["ms"] * 1e-3) / 1e9,
         "phi_adj_gvis_s": w.M / (st["phi_adj"]["ms"] * 1e-3) / 1e9,
         "psi_adj_GBs": st["psi_adj"]["GBs"], "psi_GBs": st["psi"]["GBs"],
-        "host_inputs_s": t_inputs, "plan_s": t_plan, "stages": st,
+        "host_inputs_s": t_inputs, "plan_s": t_plan, "nu_s": t_nu, "stages": st,
+        "roofline": dominant_roofline(st, w.cg_iters, "sara4096"),
+        "fft_vs_rocfft": fft_vs_rocfft(torch, 2 * w.n, torch.complex64,
+                                       st["fft_rows"]["ms"] + st["fft_cols"]["ms"],
+                                       st["fft_rows"]["bytes"] + st["fft_cols"]["bytes"]),
     }
+    if background > 0:
+        out["with_background"] = large_with_background(torch, purify, synth, plan, y, p.epsilon, r0.nu, r0.gamma,
+                                                       iters, x_solo, iters / dt, background)
+    return out
+
+
+def large_with_background(torch, purify, synth, plan, y, eps, nu, gamma, iters, x_solo, solo_rate, count):
+    """The large solve again while a server runs 256^2 FP32 requests (halting on, T_max 300)
+    arriving as a Poisson stream at half the rate the server sustains for them alone."""
+    import threading
+    probe = 8
+    reqs = gpu_requests(purify, synth.background_requests(count + probe))
+    kw = dict(max_iter=300, cg_iter=10, halting=True, xi=1e-4, slack=1e-3, check_every=10)
+    srv = purify.Server(16 << 30, max_active=4, device="cuda:0")
+
+    def submit(p):
+        return srv.submit(p.x_true.shape[0], p.uv, p.y.astype(np.complex64), p.epsilon, precision="fp32", **kw)
+    t0 = time.perf_counter()
+    done = [srv.wait(t) for t in [submit(p) for p in reqs[:probe]]]
+    capacity = probe / (time.perf_counter() - t0)
+    rate = 0.5 * capacity
+    arrivals = synth.poisson_arrivals(count, rate, index=synth.BACKGROUND_INDEX)
+    tickets, stop = [], threading.Event()
+
+    def feeder():
+        t_start = time.perf_counter()
+        for p, at in zip(reqs[probe:], arrivals):
+            if stop.is_set():
+                break
+            now = time.perf_counter() - t_start
+            if at > now and stop.wait(at - now):
+                break
+            tickets.append(submit(p))
+    th = threading.Thread(target=feeder)
+    torch.cuda.synchronize()
+    th.start()
+    # While the server's workers may be capturing graphs, this thread makes no device-wide
+    # synchronisation (the runtime refuses one while any stream captures): the solve returns
+    # once its own streams have drained.
+    t0 = time.perf_counter()
+    r = plan.sdmm(y, eps, max_iter=iters, nu=nu, gamma=gamma)
+    dt = time.perf_counter() - t0
+    stop.set()
+    th.join()
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    lat = np.array([q.latency_ms for q in res]) if res else np.zeros(1)
+    same = bool(torch.equal(r.x, x_solo))
+    return {"large_sdmm_iters_s": iters / dt, "large_sdmm_iters_s_alone": solo_rate,
+            "large_image_bitwise_equal_to_alone": same,
+            "background": "256^2 SARA FP32, M/N ~ U[0.2, 2], ISNR ~ U[20, 40] dB, halting (xi 1e-4, every 10), 4 slots",
+            "background_capacity_solves_s": capacity, "arrival_rate_per_s": rate,
+            "background_served": len(res), "background_solves_s_during_large": len(res) / dt,
+            "background_p50_ms": float(np.percentile(lat, 50)), "background_p99_ms": float(np.percentile(lat, 99)),
+            "probe_mean_iterations": float(np.mean([q.iterations for q in done]))}
 
 
 def serving(torch, purify, synth, count: int, max_active: int) -> dict:
@@ -294,13 +447,7 @@ def serving(torch, purify, synth, count: int, max_active: int) -> dict:
     one-at-a-time GPU baseline (plan + solve per request, in order, on one stream), then the
     FP32 server fed by Poisson arrivals at twice the baseline's solves/s.  Latency is arrival
     to result on the host."""
-    reqs = synth.serving_requests(count)
-    for p in reqs:       # noiseless visibilities from the FP64 operator, then the request's noise
-        n = p.x_true.shape[0]
-        pl = purify.Plan(n, p.uv, precision="fp64", device="cuda:0")
-        y0 = pl.phi(pl.as_vec(p.x_true)).cpu().numpy()
-        synth.add_noise(p, y0, p.extra["isnr_db"])
-        del pl
+    reqs = gpu_requests(purify, synth.serving_requests(count))
     kw = dict(max_iter=300, cg_iter=10, halting=True, xi=1e-4, slack=1e-3, check_every=10)
     torch.cuda.synchronize()
     base_ms, base_snr = [], []
@@ -316,6 +463,7 @@ def serving(torch, purify, synth, count: int, max_active: int) -> dict:
         del pl, r
     base_s = time.perf_counter() - t0
     base_rate = count / base_s
+    progress(f"serving: FP64 one-at-a-time baseline {base_rate:.2f} solves/s")
 
     free, _ = torch.cuda.mem_get_info()
     arena = int(min(200e9, free - 16e9))
@@ -366,20 +514,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-extra", action="store_true", help="skip the 1024^2 FP32 workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--extra-iters", type=int, default=30)
-    ap.add_argument("--large-iters", type=int, default=20,
-                    help="SDMM iterations timed on the 4096^2 solve (0: skip it)")
-    ap.add_argument("--serving-requests", type=int, default=0,
-                    help="requests in the serving-form stream (0, the default: skip; 512 is the full "
-                         "stream).  Off by default: a 30-request run ended in a segmentation fault "
-                         "in a server worker thread whose cause is not yet known")
+    ap.add_argument("--large-iters", type=int, default=100,
+                    help="SDMM iterations of the 4096^2 solve (0: skip it)")
+    ap.add_argument("--background-requests", type=int, default=160,
+                    help="256^2 requests available to the background stream beside the 4096^2 solve "
+                         "(0: no background run)")
+    ap.add_argument("--serving-requests", type=int, default=512,
+                    help="requests in the serving-form stream (0: skip; 512 is the full stream)")
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the reweighted, visibility-block and TV solves")
-    ap.add_argument("--kernel-only", default="", metavar="STAGE",
-                    help="only time one stage of the 256x256 FP64 plan on real data (no solve, no "
-                         "graphs; for hardware-counter runs) and print its line")
+    ap.add_argument("--kernel-only", default="", metavar="STAGE[,STAGE...]",
+                    help="only time stages (20 launches each) of one workload's plan on real data (no "
+                         "solve, no graphs; for hardware-counter runs) and print one line per stage")
+    ap.add_argument("--kernel-workload", default="sara256", choices=["sara256", "sara1024", "sara4096"],
+                    help="workload of --kernel-only (sara256 in FP64, the others in FP32)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, negate a float32 tensor of MIB MiB into another 10 times "
                          "(a plain read-once/write-once kernel of known size that calibrates the "
@@ -396,21 +547,23 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.kernel_only:
+        wk = synth.WORKLOADS[args.kernel_workload]
+        pk, plank = make_gpu_problem(wk, torch, purify, synth, "fp64" if args.kernel_workload == "sara256" else "fp32")
+        # stage inputs from one Phi and one Phi^dagger of the problem's data
+        plank.phi_adj(plank.as_vec(pk.y), out=None)
+        plank.phi(plank.as_vec(pk.x_true))
+        plank.time_stage("degrid", 1)
+        for stage in args.kernel_only.split(","):
+            ms = plank.time_stage(stage, 20)
+            print(json.dumps({"workload": args.kernel_workload, "stage": stage, "ms_per_launch": ms,
+                              "bytes_per_launch": stage_bytes(plank, stage), "launches": 20}), flush=True)
+        if args.copy_calibration > 0:
+            print(json.dumps({"copy_calibration_bytes": copy_calibration(torch, args.copy_calibration)}))
+        return
     w = synth.WORKLOADS["sara256"]
     p, plan0 = make_gpu_problem(w, torch, purify, synth, "fp64")
     y = plan0.as_vec(p.y)
-    if args.kernel_only:
-        # stage inputs from one Phi and one Phi^dagger of the problem's data
-        plan0.phi_adj(y, out=None)
-        plan0.phi(plan0.as_vec(p.x_true))
-        plan0.time_stage("degrid", 1)
-        ms = plan0.time_stage(args.kernel_only, 20)
-        line = {"stage": args.kernel_only, "ms_per_launch": ms,
-                "bytes_per_launch": stage_bytes(plan0, args.kernel_only), "launches": 20}
-        if args.copy_calibration > 0:
-            line["copy_calibration_bytes"] = copy_calibration(torch, args.copy_calibration)
-        print(json.dumps(line))
-        return
 
     def step():
         plan = purify.Plan(w.n, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels,
@@ -437,16 +590,11 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t
     steady = w.iters / (timed_solve(10 + w.iters) - timed_solve(10))
+    progress(f"sara256 FP64: {value:.0f} SDMM iterations/s over {args.steps} timed solves")
 
     # per-stage timing (HIP events on the plan's stream) and the dominant kernel
     st = stage_table(plan)
-    per_iter = launches_per_iter(w.cg_iters)
-    share = {k: st[k]["ms"] * per_iter[k] for k in per_iter}
-    dom = max((k for k in share if k in KERNEL_NAME), key=lambda k: share[k])
-    d = st[dom]
-    roofline = {"bound": "hbm", "achieved": d["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["frac"], "traffic": measured_traffic(dom), "kernel": KERNEL_NAME[dom],
-                "bytes_per_launch": d["bytes"], "ms_per_launch": d["ms"]}
+    roofline = dominant_roofline(st, w.cg_iters, "sara256")
 
     line = {
         "metric": "SDMM iters/s", "value": value, "unit": "iters/s", "n_gpus": 1,
@@ -461,36 +609,46 @@ def main():
                          "what": "marginal SDMM iterations/s on the plan (no plan, nu or gamma)"},
         "roofline": roofline,
     }
-    also = {"sara256_stages": st}
+    also = {"sara256_stages": st,
+            "sara256_fft_vs_rocfft": fft_vs_rocfft(torch, 2 * w.n, torch.complex128,
+                                                   st["fft_rows"]["ms"] + st["fft_cols"]["ms"],
+                                                   st["fft_rows"]["bytes"] + st["fft_cols"]["bytes"])}
     try:
         also["sara256_toeplitz"] = toeplitz_form(torch, plan, y, p.epsilon, res.nu, w.iters, w.cg_iters,
                                                  p.x_true, synth, res.x.cpu().numpy())
     except Exception as e:  # report, do not hide the main line
         also["sara256_toeplitz_error"] = repr(e)
+    progress("sara256 stages, rocFFT comparison, stored-operator solves")
     if not args.no_variants:
         try:
             also["sara256_methods"] = method_variants(torch, plan, y, p.epsilon, res.nu, w.iters, p.x_true, synth,
                                                       snr, w.M)
         except Exception as e:  # report, do not hide the main line
             also["sara256_methods_error"] = repr(e)
+    progress("sara256 method variants")
     if not args.no_extra:
         try:
             also["sara1024_fp32"] = precision_form(torch, purify, synth, args.extra_iters)
         except Exception as e:  # report, do not hide the main line
             also["sara1024_fp32_error"] = repr(e)
+    progress("sara1024 precision form")
     if args.large_iters > 0:
         try:
-            also["sara4096_fp32"] = large_solve(torch, purify, synth, args.large_iters)
+            also["sara4096_fp32"] = large_solve(torch, purify, synth, args.large_iters, args.background_requests)
+            line["roofline_large"] = also["sara4096_fp32"]["roofline"]
         except Exception as e:  # report, do not hide the main line
             also["sara4096_fp32_error"] = repr(e)
+    progress("sara4096 large solve")
     if args.serving_requests > 0:
         try:
             also["serving"] = serving(torch, purify, synth, args.serving_requests, args.serving_slots)
         except Exception as e:  # report, do not hide the main line
             also["serving_error"] = repr(e)
+    progress("serving stream")
     line["also"] = also
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, p, args.cpu_iters)
+        progress("CPU oracle baseline")
     if args.copy_calibration > 0:
         line["copy_calibration_bytes"] = copy_calibration(torch, args.copy_calibration)
     print(json.dumps(line))

@@ -222,8 +222,28 @@ def serving_requests(count: int) -> list:
     return out
 
 
-def poisson_arrivals(count: int, rate: float) -> np.ndarray:
+BACKGROUND_INDEX = 5
+
+
+def background_requests(count: int, n: int = 256) -> list:
+    """``count`` requests of one size (the background stream beside the large single solve):
+    M/N ~ U[0.2, 2], ISNR ~ U[20, 40] dB, SARA, as the serving stream; noise not yet added."""
+    out = []
+    for i in range(count):
+        r = np.random.default_rng(SEED_BASE + 100 * BACKGROUND_INDEX + 10 + i)
+        M = int(round(r.uniform(0.2, 2.0) * n * n))
+        isnr = float(r.uniform(20.0, 40.0))
+        w = Workload(f"bg{i}", n=n, M=M, J=6, dict_mask=0x1FF, levels=4, iters=300, blobs=40,
+                     isnr_db=isnr, index=BACKGROUND_INDEX, precision="fp32")
+        img = blob_image(n, w.blobs, r)
+        uv = uv_coverage(M, 2 * n, r, 0.0)
+        nz = unit_complex_noise(M, r)
+        out.append(Problem(w, img, uv, nz, extra={"isnr_db": isnr}))
+    return out
+
+
+def poisson_arrivals(count: int, rate: float, index: int = SERVING_INDEX) -> np.ndarray:
     """Arrival times (seconds from the first) of a Poisson stream of ``rate`` per second."""
-    gaps = rng_for(SERVING_INDEX, 1).exponential(1.0 / rate, size=count)
+    gaps = rng_for(index, 1).exponential(1.0 / rate, size=count)
     gaps[0] = 0.0
     return np.cumsum(gaps)
