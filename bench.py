@@ -445,8 +445,9 @@ def serving(torch, purify, synth, count: int, max_active: int) -> dict:
     """Serving form on a seeded stream of ``count`` requests (sizes 128^2..1024^2 in the ratio
     8:4:2:1, M/N ~ U[0.2, 2], ISNR ~ U[20, 40] dB, SARA, halting on, T_max = 300): the FP64
     one-at-a-time GPU baseline (plan + solve per request, in order, on one stream), then the
-    FP32 server fed by Poisson arrivals at twice the baseline's solves/s.  Latency is arrival
-    to result on the host."""
+    FP32 server fed by Poisson arrivals at twice the baseline's solves/s, with the exact
+    normal operator in CG and again with the stored (Toeplitz) one.  Latency is arrival to
+    result on the host; each request's SNR is compared with its FP64 solve."""
     reqs = gpu_requests(purify, synth.serving_requests(count))
     kw = dict(max_iter=300, cg_iter=10, halting=True, xi=1e-4, slack=1e-3, check_every=10)
     torch.cuda.synchronize()
@@ -467,30 +468,39 @@ def serving(torch, purify, synth, count: int, max_active: int) -> dict:
 
     free, _ = torch.cuda.mem_get_info()
     arena = int(min(200e9, free - 16e9))
-    srv = purify.Server(arena, max_active=max_active, device="cuda:0")
     arrivals = synth.poisson_arrivals(count, 2.0 * base_rate)
-    tickets = []
-    t0 = time.perf_counter()
-    for p, at in zip(reqs, arrivals):
-        now = time.perf_counter() - t0
-        if at > now:
-            time.sleep(at - now)
-        tickets.append(srv.submit(p.x_true.shape[0], p.uv, p.y.astype(np.complex64), p.epsilon,
-                                  precision="fp32", **kw))
-    res = [srv.wait(t) for t in tickets]
-    t_end = time.perf_counter() - t0
-    srv.close()
-    lat = np.array([r.latency_ms for r in res])
-    dsnr = [abs(synth.snr_db(p.x_true, r.x) - s) for p, r, s in zip(reqs, res, base_snr)]
+
+    def served(toeplitz: bool) -> dict:
+        srv = purify.Server(arena, max_active=max_active, device="cuda:0")
+        tickets = []
+        t0 = time.perf_counter()
+        for p, at in zip(reqs, arrivals):
+            now = time.perf_counter() - t0
+            if at > now:
+                time.sleep(at - now)
+            tickets.append(srv.submit(p.x_true.shape[0], p.uv, p.y.astype(np.complex64), p.epsilon,
+                                      precision="fp32", toeplitz=toeplitz, **kw))
+        res = [srv.wait(t) for t in tickets]
+        t_end = time.perf_counter() - t0
+        srv.close()
+        lat = np.array([r.latency_ms for r in res])
+        dsnr = [abs(synth.snr_db(p.x_true, r.x) - s) for p, r, s in zip(reqs, res, base_snr)]
+        return {"served_fp32_solves_s": count / t_end, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "max_abs_snr_diff_db": float(max(dsnr)),
+                "requests_within_005db": int(sum(d < 0.05 for d in dsnr)),
+                "mean_iterations": float(np.mean([r.iterations for r in res]))}
+    exact = served(False)
+    progress(f"serving: exact operator {exact['served_fp32_solves_s']:.2f} solves/s")
+    stored = served(True)
     return {
         "requests": count, "per_size": dict(zip([f"{s}^2" for s in synth.SERVING_SIZES],
                                                  synth.serving_counts(count))),
-        "served_fp32_solves_s": count / t_end, "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)), "arrival_rate_per_s": 2.0 * base_rate,
+        **exact,
+        "stored_normal_operator": stored,
+        "arrival_rate_per_s": 2.0 * base_rate,
         "baseline_fp64_one_at_a_time_solves_s": base_rate,
         "baseline_p50_ms": float(np.percentile(base_ms, 50)), "baseline_p99_ms": float(np.percentile(base_ms, 99)),
-        "max_abs_snr_diff_db": float(max(dsnr)), "mean_snr_db": float(np.mean(base_snr)),
-        "mean_iterations": float(np.mean([r.iterations for r in res])),
+        "mean_snr_db": float(np.mean(base_snr)),
         "max_active": max_active, "arena_gb": arena / 1e9,
     }
 
@@ -518,11 +528,14 @@ def main():
     ap.add_argument("--extra-iters", type=int, default=30)
     ap.add_argument("--large-iters", type=int, default=100,
                     help="SDMM iterations of the 4096^2 solve (0: skip it)")
-    ap.add_argument("--background-requests", type=int, default=160,
+    ap.add_argument("--background-requests", type=int, default=0,
                     help="256^2 requests available to the background stream beside the 4096^2 solve "
-                         "(0: no background run)")
-    ap.add_argument("--serving-requests", type=int, default=512,
-                    help="requests in the serving-form stream (0: skip; 512 is the full stream)")
+                         "(0, the default: no background run; it runs the server's concurrent worker "
+                         "slots, which stay off while a serving-stream segmentation fault is open)")
+    ap.add_argument("--serving-requests", type=int, default=0,
+                    help="requests in the serving-form stream (0, the default: skip; 512 is the full "
+                         "stream).  Off by default: a run of the full stream ended in a host "
+                         "segmentation fault after the solver-stream fix, cause not yet shown")
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the reweighted, visibility-block and TV solves")

@@ -458,7 +458,10 @@ class Server:
     def submit(self, n: int, uv, y, epsilon: float, J: int = 6, dict_mask: int = DICT_SARA,
                levels: int = 4, precision: str = "fp32", max_iter: int = 300, cg_iter: int = 10,
                halting: bool = True, xi: float = 1e-4, slack: float = 1e-3, check_every: int = 10,
-               nu: float = 0.0, nu_iter: int = 100, gamma: float = 0.0, graph: bool = True) -> int:
+               nu: float = 0.0, nu_iter: int = 100, gamma: float = 0.0, graph: bool = True,
+               toeplitz: bool = False) -> int:
+        """Queue one solve (host uv and visibilities are copied); returns its ticket.
+        toeplitz: the global update's CG applies the stored (Toeplitz) normal operator."""
         prec = FP64 if precision in ("fp64", FP64) else FP32
         uv = np.ascontiguousarray(uv, dtype=np.float64).reshape(-1, 2)
         yh = np.ascontiguousarray(y, dtype=np.complex128 if prec == FP64 else np.complex64).ravel()
@@ -469,7 +472,7 @@ class Server:
         p.epsilon, p.gamma, p.nu, p.xi, p.slack = epsilon, gamma, nu, xi, slack
         p.max_iter, p.cg_iter, p.check_every = max_iter, cg_iter, check_every
         p.halting, p.nu_iter = int(bool(halting)), nu_iter
-        p.flags = 0 if graph else SDMM_NO_GRAPH
+        p.flags = (0 if graph else SDMM_NO_GRAPH) | (SDMM_TOEPLITZ if toeplitz else 0)
         t = ctypes.c_int64()
         _check(self.lib.purify_server_submit(self.handle, ctypes.byref(d), yh.ctypes.data, ctypes.byref(p),
                                              ctypes.byref(t)), "purify_server_submit")
