@@ -276,7 +276,7 @@ def measured_traffic(stage: str, workload: str):
     import glob
     import hashlib
     src = STAGE_SOURCE.get(stage)
-    if src is None:
+    if src is None or not os.path.exists(os.path.join(CSRC, src)):
         return None
     sha = hashlib.sha256(open(os.path.join(CSRC, src), "rb").read()).hexdigest()
     for path in sorted(glob.glob(os.path.join(PROFILES, "*_counters.md"))):
