@@ -262,3 +262,20 @@ def test_sdmm_heavy_tiles_split_gridding_units(prec, tol):
     assert _hist_rel(h[:, 0], ref.objective) < tol
     assert _hist_rel(h[:, 1], ref.residual) < tol
     assert rel_l2(to_np(res.x), ref.x) < tol
+
+
+@pytest.mark.parametrize("halting", [False, True])
+def test_sdmm_non_finite_visibilities_are_reported(halting):
+    # a NaN visibility makes the residual non-finite: the solve reports PURIFY_E_NONFINITE (with
+    # halting on, the stopping test sees the non-finite residual and stops early) instead of
+    # returning a result
+    w, p = _problem("small64")
+    y = p.y.copy()
+    y[17] = np.nan
+    plan = purify.Plan(w.n, p.uv, J=w.J, dict_mask=w.dict_mask, levels=w.levels, device=DEV)
+    with pytest.raises(purify.PurifyError) as e:
+        plan.sdmm(plan.as_vec(y), p.epsilon, max_iter=20, nu=700.0, halting=halting, check_every=1)
+    assert e.value.status == 4
+    # the plan stays usable
+    res = plan.sdmm(plan.as_vec(p.y), p.epsilon, max_iter=5, nu=700.0)
+    assert np.all(np.isfinite(to_np(res.x)))
