@@ -122,7 +122,11 @@ struct Plan {
     bool strip_xcd = false;      // work unit w handles a tile of strip t2 with t2 % 8 == w % 8
     int32_t* dchunk = nullptr;   // degridding: {first visibility, count} per workgroup (strip order)
     int ndchunk = 0, dchunk_cap = 0;   // 0 workgroups listed: plain 256-visibility blocks
-    bool degrid_tiles = false;   // G by gridding work units with an LDS window of the grid
+    bool degrid_tiles = false;   // G by tiles with an LDS window of the grid (else per visibility)
+    int TD = 32, nTD = 0;        // degridding tile side (TT or 2 TT) and tiles per axis
+    int32_t* dwork = nullptr;    // TD > TT: degridding records {tile, -, -, -, s0, e0, s1, e1, ...}
+    int ndwork = 0, dwork_cap = 0;
+    int dunit = 0;               // visibilities per degridding record before a tile is split
     int grid_unit = 0;           // visibility passes per gridding work unit before a split
     int32_t* gmerge = nullptr;   // split tiles {tile, parts, first partial slot}
     int nmerge = 0, gmerge_cap = 0;

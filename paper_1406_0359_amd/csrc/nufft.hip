@@ -223,6 +223,18 @@ __device__ __forceinline__ void lds_add(typename FixedAcc<T>::I* p, typename Fix
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// FP32 path: the real and imaginary int32 sums of a cell share one 64-bit word, real part
+// in the high half, so one 64-bit LDS atomic adds both.  Addition mod 2^64 gives
+// word = R 2^32 + I exactly; as |I| < 2^31 (the scale bound above), the low half read as
+// int32 is I, and (word - I) / 2^32 read as int32 is R.
+__device__ __forceinline__ unsigned long long pack_pair(int re, int im) {
+    return ((unsigned long long)(unsigned)re << 32) + (unsigned long long)(long long)im;
+}
+__device__ __forceinline__ void unpack_pair(unsigned long long w, int& re, int& im) {
+    im = (int)(unsigned)w;
+    re = (int)(unsigned)((w - (unsigned long long)(long long)im) >> 32);
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -268,7 +280,10 @@ k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32
     // FP64: the window goes straight from global memory to LDS (global_load_lds, one 16-byte
     // element per lane at consecutive LDS slots of the wave), keeping it out of registers
     constexpr bool DMA = GTG && sizeof(T) == 8;
-    __shared__ typename Acc::I acc[2 * WA * WA];
+    // FP32: one 64-bit word per cell holding both parts; FP64: a real and an imaginary plane
+    constexpr bool PACK = sizeof(T) == 4;
+    __shared__ __attribute__((aligned(8))) typename Acc::I acc[2 * WA * WA];
+    unsigned long long* accp = reinterpret_cast<unsigned long long*>(acc);
     __shared__ double red[NT / 64];
     __shared__ cpx<T> win[GTG ? WPT * NT : 1];
     const int32_t* w = work + GRID_REC * blockIdx.x;
@@ -439,26 +454,49 @@ k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32
 #pragma unroll UNR
                 for (int bb = 0; bb < JJ; ++bb) {
                     if (bb >= Jn) break;
-                    lds_add<T>(ap + a * WA + bb, Acc::conv_mul(wb[c][bb], vx));
-                    lds_add<T>(ap + WA * WA + a * WA + bb, Acc::conv_mul(wb[c][bb], vy));
+                    if constexpr (PACK) {
+                        __hip_atomic_fetch_add(accp + (ap - acc) + a * WA + bb,
+                                               pack_pair((int)Acc::conv_mul(wb[c][bb], vx),
+                                                         (int)Acc::conv_mul(wb[c][bb], vy)),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    } else {
+                        lds_add<T>(ap + a * WA + bb, Acc::conv_mul(wb[c][bb], vx));
+                        lds_add<T>(ap + WA * WA + a * WA + bb, Acc::conv_mul(wb[c][bb], vy));
+                    }
                 }
             }
         }
     }
     __syncthreads();
+    // the cell sums (real, imaginary) of padded-tile cell pi
+    auto cell = [&](int pi, typename Acc::I& re, typename Acc::I& im) {
+        if constexpr (PACK) {
+            int a, b;
+            unpack_pair(accp[pi], a, b);
+            re = a;
+            im = b;
+        } else {
+            re = acc[pi];
+            im = acc[WA * WA + pi];
+        }
+    };
     if (slot < 0) {
         const T q = (T)ldexp(1.0, e);
         for (int i = threadIdx.x; i < TT * TT; i += NT) {
             const int r = i / TT, c = i % TT;
-            const int pi = (r + JM) * WA + c + JM;
-            grid[(size_t)(t1o + r) * K + t2o + c] = mk<T>(q * (T)acc[pi], q * (T)acc[WA * WA + pi]);
+            typename Acc::I re, im;
+            cell((r + JM) * WA + c + JM, re, im);
+            grid[(size_t)(t1o + r) * K + t2o + c] = mk<T>(q * (T)re, q * (T)im);
         }
         return;
     }
     typename Acc::I* pt = partial + (size_t)slot * 2 * TT * TT;
-    for (int i = threadIdx.x; i < 2 * TT * TT; i += NT) {
-        const int cell = i >> 1, r = cell / TT, c = cell % TT;
-        pt[i] = acc[(i & 1) * WA * WA + (r + JM) * WA + c + JM];
+    for (int i = threadIdx.x; i < TT * TT; i += NT) {
+        const int r = i / TT, c = i % TT;
+        typename Acc::I re, im;
+        cell((r + JM) * WA + c + JM, re, im);
+        pt[2 * i] = re;
+        pt[2 * i + 1] = im;
     }
     if (threadIdx.x == 0) pexp[slot] = e;
 }
@@ -511,15 +549,19 @@ void grid_tt(const Plan& P, const cpx<T>* y, const cpx<T>* gin, const int32_t* p
 template <typename T, int TT>
 void degrid_tiles_tt(const Plan& P, const cpx<T>* grid, cpx<T>* y, const int32_t* perm, double scale,
                      hipStream_t s) {
-    const dim3 g(P.nwork), b(256);
+    // tiles of side TD: the gridding work units (TD = TT) or the plan's degridding records
+    const bool own = P.TD > P.TT;
+    const int32_t* work = own ? P.dwork : P.gwork;
+    const int nT = own ? P.nTD : P.nT;
+    const dim3 g(own ? P.ndwork : P.nwork), b(256);
     const T* fr = (const T*)P.frac;
     const T* kbc = (const T*)P.kbpoly;
     const T* wt = (const T*)P.wtab;
     switch (P.J) {
-        case 4: hipLaunchKernelGGL((k_degrid_tiles<T, 4, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, P.gwork, P.K, P.nT, (T)scale, 4); break;
-        case 6: hipLaunchKernelGGL((k_degrid_tiles<T, 6, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, P.gwork, P.K, P.nT, (T)scale, 6); break;
-        case 8: hipLaunchKernelGGL((k_degrid_tiles<T, 8, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, P.gwork, P.K, P.nT, (T)scale, 8); break;
-        default: hipLaunchKernelGGL((k_degrid_tiles<T, 0, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, P.gwork, P.K, P.nT, (T)scale, P.J); break;
+        case 4: hipLaunchKernelGGL((k_degrid_tiles<T, 4, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, work, P.K, nT, (T)scale, 4); break;
+        case 6: hipLaunchKernelGGL((k_degrid_tiles<T, 6, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, work, P.K, nT, (T)scale, 6); break;
+        case 8: hipLaunchKernelGGL((k_degrid_tiles<T, 8, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, work, P.K, nT, (T)scale, 8); break;
+        default: hipLaunchKernelGGL((k_degrid_tiles<T, 0, TT, 256>), g, b, 0, s, grid, y, perm, P.base, fr, kbc, wt, work, P.K, nT, (T)scale, P.J); break;
     }
 }
 
@@ -527,8 +569,11 @@ template <typename T>
 void launch_degrid(const Plan& P, const cpx<T>* grid, cpx<T>* y, const int32_t* perm, double scale,
                    hipStream_t s) {
     if (P.degrid_tiles) {
-        if (P.TT == 16) degrid_tiles_tt<T, 16>(P, grid, y, perm, scale, s);
-        else degrid_tiles_tt<T, 32>(P, grid, y, perm, scale, s);
+        if (P.TD == 16) degrid_tiles_tt<T, 16>(P, grid, y, perm, scale, s);
+        else if constexpr (sizeof(T) == 4) {   // 64 x 64 windows: FP32 only (LDS)
+            if (P.TD == 64) degrid_tiles_tt<T, 64>(P, grid, y, perm, scale, s);
+            else degrid_tiles_tt<T, 32>(P, grid, y, perm, scale, s);
+        } else degrid_tiles_tt<T, 32>(P, grid, y, perm, scale, s);
         return;
     }
     const int M = (int)P.M;

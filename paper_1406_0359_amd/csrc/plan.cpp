@@ -252,6 +252,11 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
     // 16 x 16 tiles up to K = 1024 (more, lighter workgroups for small grids), else 32 x 32
     P.TT = P.K > 1024 ? 32 : 16;
     P.nT = P.K / P.TT;   // >= 2, so K >= TT + KB_MAX_J - 1: a footprint never wraps onto its own tile
+    // Degridding reads no neighbour's visibilities and adds nothing, so it takes larger tiles
+    // where its LDS window fits: FP32 plans from K = 2048 degrid by 64 x 64 tiles, each the
+    // union of 2 x 2 gridding tiles (smaller halo per visibility)
+    P.TD = (P.precision == PURIFY_FP32 && P.K >= 2048) ? 2 * P.TT : P.TT;
+    P.nTD = P.K / P.TD;
     const size_t es = P.precision == PURIFY_FP64 ? sizeof(double) : sizeof(float);
     const size_t ce = 2 * es;
     P.elem = ce;
@@ -287,6 +292,12 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
         const size_t ib = P.precision == PURIFY_FP64 ? 8 : 4;
         P.gscratch = carve(parts_max * 2 * (size_t)P.TT * P.TT * ib);
         P.gexp = (int32_t*)carve(parts_max * sizeof(int32_t));
+        // degridding records: sum over tiles of ceil(load / dunit) <= tiles + M / dunit <= 1.5
+        // tiles parts, room for strip padding up to twice the tiles
+        const size_t dtiles = (size_t)P.nTD * P.nTD;
+        P.dunit = (int)std::max<int64_t>(GRID_UNIT, (2 * (int64_t)M + (int64_t)dtiles - 1) / (int64_t)dtiles);
+        P.dwork_cap = (int)(2 * dtiles + (size_t)(M / P.dunit) + 8);
+        P.dwork = P.TD > P.TT ? (int32_t*)carve((size_t)P.dwork_cap * GRID_REC * sizeof(int32_t)) : nullptr;
         // degridding chunk table: at most twice the blocks of a plain launch plus one partial
         // chunk per strip and padding (larger strip-ordered tables fall back to plain blocks)
         P.dchunk_cap = (int)std::min<int64_t>((int64_t)2 * ((M + 255) / 256) + P.nT + 64, INT32_MAX / 2);
@@ -682,16 +693,95 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
         P.nwork = (int)(work.size() / GRID_REC);
         P.nmerge = (int)(merge.size() / 3);
     }
-    // G by work units (k_degrid_tiles) when the units' grid windows, (TT + J - 1)^2 cells each,
+    // Degridding tiles of side TD = 2 TT: tile (d1, d2) is gridding tiles (2 d1 + i, 2 d2 + j),
+    // i, j in {0, 1}; the two with j = 0 are adjacent in the sorted order (keys ascend with
+    // t = t2 nT + t1), and so are the two with j = 1, so its visibilities are two contiguous
+    // ranges.  A tile with more than dunit visibilities is split into parts (each part a
+    // slice of the two ranges); heavy tiles come first, then the list is strip-ordered like
+    // the gridding work list (record w holds a tile of strip d2 = w (mod 8)) when the padding
+    // fits.
+    std::vector<int32_t> dwork;
+    if (P.TD > TT) {
+        const int nTD = P.nTD;
+        std::vector<std::pair<int, int>> load_tile;   // (load, tile)
+        auto dranges = [&](int t, int* s, int* e) {
+            const int d1 = t % nTD, d2 = t / nTD;
+            for (int j = 0; j < 2; ++j) {
+                const int g = (2 * d2 + j) * nT + 2 * d1;
+                s[j] = off[4 * g];
+                e[j] = off[4 * (g + 2)];
+            }
+        };
+        for (int t = 0; t < nTD * nTD; ++t) {
+            int s[2], e[2];
+            dranges(t, s, e);
+            load_tile.push_back({(e[0] - s[0]) + (e[1] - s[1]), t});
+        }
+        std::stable_sort(load_tile.begin(), load_tile.end(),
+                         [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first > b.first; });
+        std::vector<int32_t> list;
+        for (const auto& lt : load_tile) {
+            const int t = lt.second, L = lt.first;
+            const int parts = std::max(1, (L + P.dunit - 1) / P.dunit);
+            int s[2], e[2];
+            dranges(t, s, e);
+            const int n0 = e[0] - s[0];
+            for (int q = 0; q < parts; ++q) {
+                // slice [a, b) of the two ranges laid end to end
+                const int a = (int)((int64_t)L * q / parts), b = (int)((int64_t)L * (q + 1) / parts);
+                int32_t rec[GRID_REC] = {};
+                rec[0] = t;
+                rec[4] = s[0] + std::min(a, n0);
+                rec[5] = s[0] + std::min(b, n0);
+                rec[6] = s[1] + std::max(a, n0) - n0;
+                rec[7] = s[1] + std::max(b, n0) - n0;
+                list.insert(list.end(), rec, rec + GRID_REC);
+            }
+        }
+        const size_t nrec = list.size() / GRID_REC;
+        if (nrec > (size_t)P.dwork_cap) {
+            set_error("internal: degridding work list exceeds its bound");
+            return PURIFY_E_INVALID;
+        }
+        dwork.swap(list);
+        if (nTD % 8 == 0) {
+            std::vector<std::vector<int32_t>> q(8);
+            for (size_t u = 0; u < nrec; ++u) {
+                const int32_t* rec = &dwork[u * GRID_REC];
+                const int e = (rec[0] / nTD) % 8;
+                q[e].insert(q[e].end(), rec, rec + GRID_REC);
+            }
+            size_t longest = 0;
+            for (const auto& v : q) longest = std::max(longest, v.size() / GRID_REC);
+            if (8 * longest <= (size_t)P.dwork_cap) {
+                std::vector<int32_t> ord;
+                ord.reserve(8 * longest * GRID_REC);
+                for (size_t k = 0; k < longest; ++k)
+                    for (int e = 0; e < 8; ++e) {
+                        if (k < q[e].size() / GRID_REC) {
+                            ord.insert(ord.end(), q[e].begin() + k * GRID_REC, q[e].begin() + (k + 1) * GRID_REC);
+                        } else {
+                            int32_t empty[GRID_REC] = {};
+                            empty[0] = -1;   // no tile: the workgroup exits at once
+                            ord.insert(ord.end(), empty, empty + GRID_REC);
+                        }
+                    }
+                dwork.swap(ord);
+            }
+        }
+        P.ndwork = (int)(dwork.size() / GRID_REC);
+    }
+    // G by tiles (k_degrid_tiles) when the tiles' grid windows, (TD + J - 1)^2 cells each,
     // add up to at most half the J^2 taps the visibilities gather (dense coverage); sparse
     // coverage keeps one thread per visibility gathering straight from the grid.
     {
+        const std::vector<int32_t>& dl = P.TD > TT ? dwork : work;
         int64_t busy = 0;
-        for (size_t u = 0; u < work.size() / GRID_REC; ++u) {
-            const int32_t* rec = &work[u * GRID_REC];
+        for (size_t u = 0; u < dl.size() / GRID_REC; ++u) {
+            const int32_t* rec = &dl[u * GRID_REC];
             if (rec[0] >= 0 && (rec[5] - rec[4]) + (rec[7] - rec[6]) > 0) ++busy;
         }
-        const int64_t ws = TT + J - 1;
+        const int64_t ws = P.TD + J - 1;
         P.degrid_tiles = busy * ws * ws * 2 <= (int64_t)M * J * J;
     }
     // Degridding in the same strip order: workgroup b (XCD b % 8) takes up to 256 visibilities
@@ -767,6 +857,7 @@ purify_status build_plan(Plan& P, const purify_plan_desc* d, hipStream_t s) {
     PURIFY_HIP(up(P.tileoff, off.data(), off.size() * 4));
     PURIFY_HIP(up(P.tilecover, cover.data(), cover.size() * 4));
     PURIFY_HIP(up(P.gwork, work.data(), work.size() * sizeof(int32_t)));
+    if (!dwork.empty()) PURIFY_HIP(up(P.dwork, dwork.data(), dwork.size() * sizeof(int32_t)));
     if (!dch.empty()) PURIFY_HIP(up(P.dchunk, dch.data(), dch.size() * sizeof(int32_t)));
     if (!merge.empty()) PURIFY_HIP(up(P.gmerge, merge.data(), merge.size() * sizeof(int32_t)));
     PURIFY_HIP(up_real(P.frac, sfr));
