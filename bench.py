@@ -540,8 +540,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the reweighted, visibility-block and TV solves")
     ap.add_argument("--kernel-only", default="", metavar="STAGE[,STAGE...]",
-                    help="only time stages (20 launches each) of one workload's plan on real data (no "
-                         "solve, no graphs; for hardware-counter runs) and print one line per stage")
+                    help="only time stages (20 launches each, plain launches) of one workload's plan, "
+                         "on the buffers a two-iteration solve of its data leaves (for hardware-counter "
+                         "runs), and print one line per stage")
     ap.add_argument("--kernel-workload", default="sara256", choices=["sara256", "sara1024", "sara4096"],
                     help="workload of --kernel-only (sara256 in FP64, the others in FP32)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -563,10 +564,11 @@ def main():
     if args.kernel_only:
         wk = synth.WORKLOADS[args.kernel_workload]
         pk, plank = make_gpu_problem(wk, torch, purify, synth, "fp64" if args.kernel_workload == "sara256" else "fp32")
-        # stage inputs from one Phi and one Phi^dagger of the problem's data
-        plank.phi_adj(plank.as_vec(pk.y), out=None)
-        plank.phi(plank.as_vec(pk.x_true))
-        plank.time_stage("degrid", 1)
+        # stage inputs from a two-iteration solve of the problem's data, so that every buffer a
+        # stage reads (x_hat, the grids, the visibilities) holds the solve's values: a fresh
+        # plan's x_hat is zero, every stage chained from it would then see zeros, and the
+        # gridding kernels skip the adds of a tile whose values are all zero
+        plank.sdmm(plank.as_vec(pk.y), pk.epsilon, max_iter=2, nu_iter=20)
         for stage in args.kernel_only.split(","):
             ms = plank.time_stage(stage, 20)
             print(json.dumps({"workload": args.kernel_workload, "stage": stage, "ms_per_launch": ms,
