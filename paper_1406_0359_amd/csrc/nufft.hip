@@ -529,7 +529,10 @@ template <typename T, int TT, int NT, bool GTG>
 void grid_tt(const Plan& P, const cpx<T>* y, const cpx<T>* gin, const int32_t* perm, cpx<T>* grid, hipStream_t s) {
     const dim3 g(P.nwork), b(NT);
     using I = typename FixedAcc<T>::I;
-    constexpr int C = sizeof(T) == 8 ? 2 : 4;   // items per batch (register budget)
+    // items per batch (register budget).  FP32 gridding of y: one, for occupancy (a unit whose
+    // threads hold more items reads y once more for the scale); FP32 G^T G: four, since
+    // there the scale's extra pass would interpolate every value twice
+    constexpr int C = sizeof(T) == 8 ? 2 : (GTG ? 4 : 1);
     I* scr = (I*)P.gscratch;
     const T* fr = (const T*)P.frac;
     const T* kbc = (const T*)P.kbpoly;
