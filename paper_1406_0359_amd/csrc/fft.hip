@@ -167,8 +167,11 @@ PURIFY_RADICES(float, 9, 3, 8, 8, 8)
 PURIFY_RADICES_AX4(float, 10, 0, 4, 4, 8, 8, 4)
 PURIFY_RADICES_AX(float, 10, 1, 3, 8, 8, 16)
 PURIFY_RADICES(float, 11, 3, 32, 16, 4)
+// n = 4096 FP32: rows and columns in four radix-8 passes (512 threads per line); the long
+// column passes then hold half as many values a thread (126 instead of 256 VGPRs), so a CU
+// runs 16 waves of them instead of 8 (forward 556 -> 460 us, adjoint 480 -> 451 us against
+// three radix-16 passes)
 PURIFY_RADICES_AX4(float, 12, 0, 4, 8, 8, 8, 8)
-PURIFY_RADICES_AX(float, 12, 1, 3, 16, 16, 16)
 PURIFY_RADICES(double, 4, 1, 16, 1, 1)
 PURIFY_RADICES(double, 5, 2, 16, 2, 1)
 PURIFY_RADICES(double, 6, 2, 8, 8, 1)
@@ -204,6 +207,25 @@ struct Plan1D {
     }
 };
 
+// FP32 lines of 4096 and more take their inter-pass twiddles from two short tables,
+// W[m] = W[(m >> LB) 2^LB] W[m mod 2^LB] (2^LB + n / 2^LB entries instead of n; one more
+// rounding, well inside FP32 accuracy), so a workgroup's LDS is little more than its line
+// buffers and two workgroups fit on a CU.
+template <typename T, int LOGN>
+constexpr bool twiddles_split() { return sizeof(T) == 4 && LOGN >= 12; }
+template <typename T, int LOGN>
+constexpr int split_lb() { return (LOGN + 1) / 2; }
+// twiddle W[m] = exp(-2 pi i m / n) from the staged table
+template <typename T, int LOGN>
+__device__ __forceinline__ cpx<T> tw_get(const cpx<T>* W, int m) {
+    if constexpr (twiddles_split<T, LOGN>()) {
+        constexpr int LB = split_lb<T, LOGN>(), L = 1 << LB;
+        return W[L + (m >> LB)] * W[m & (L - 1)];
+    } else {
+        return W[m];
+    }
+}
+
 template <typename T, int LOGN, int AX, int P, bool INV>
 __device__ __forceinline__ void fft_pass(cpx<T>* v, cpx<T>* line, int tl, const cpx<T>* W) {
     using PL = Plan1D<T, LOGN, AX>;
@@ -226,7 +248,7 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, cpx<T>* line, int tl, const 
             const int k = j % NS;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                cpx<T> w = W[r * k * (N / (NS * R))];
+                cpx<T> w = tw_get<T, LOGN>(W, r * k * (N / (NS * R)));
                 if (INV) w.y = -w.y;
                 v[b * R + r] = v[b * R + r] * w;
             }
@@ -294,7 +316,12 @@ constexpr int rows_per_wg() {
 template <typename T, int LOGN>
 constexpr bool twiddles_in_lds() {
     constexpr int N = 1 << LOGN;
-    return (size_t)(N + 2 * (N + 1)) * 2 * sizeof(T) <= 160 * 1024;
+    return twiddles_split<T, LOGN>() || (size_t)(N + 2 * (N + 1)) * 2 * sizeof(T) <= 160 * 1024;
+}
+template <typename T, int LOGN>
+constexpr int table_elems() {
+    if constexpr (twiddles_split<T, LOGN>()) return (1 << split_lb<T, LOGN>()) + (1 << (LOGN - split_lb<T, LOGN>()));
+    else return twiddles_in_lds<T, LOGN>() ? (1 << LOGN) : 0;
 }
 template <typename T, int LOGN>
 constexpr int cols_per_wg() {
@@ -304,22 +331,32 @@ constexpr int cols_per_wg() {
     if (c > (4 * N) / 256) c = (4 * N) / 256;
     if (c > 8) c = 8;
     if (c < 1) c = 1;
-    const int tab = twiddles_in_lds<T, LOGN>() ? N : 0;
+    const int tab = table_elems<T, LOGN>();
     while (c > 1 && (size_t)(tab + 2 * c * (N + 1)) * 2 * sizeof(T) > 160 * 1024) c >>= 1;
     return c;
 }
 
+// Long columns (a workgroup's LDS holds only one column's two parity lines, or FP32 lines of
+// 4096 and more) run the kernels that keep CR adjacent columns per thread in registers.
+template <typename T, int LOGN>
+constexpr bool long_cols() { return LOGN >= 11 && (cols_per_wg<T, LOGN>() == 1 || twiddles_split<T, LOGN>()); }
+template <typename T>
+constexpr int long_cols_cr() { return sizeof(T) == 8 ? 2 : 4; }
+
 template <typename T, int LOGN>
 __device__ __forceinline__ const cpx<T>* stage_twiddles(cpx<T>* Wl, const cpx<T>* __restrict__ tw) {
-    if constexpr (twiddles_in_lds<T, LOGN>()) {
+    if constexpr (twiddles_split<T, LOGN>()) {
+        constexpr int LB = split_lb<T, LOGN>(), L = 1 << LB;
+        for (int i = threadIdx.x; i < table_elems<T, LOGN>(); i += blockDim.x)
+            Wl[i] = i < L ? tw[i] : tw[(size_t)(i - L) << LB];
+        return Wl;
+    } else if constexpr (twiddles_in_lds<T, LOGN>()) {
         for (int i = threadIdx.x; i < (1 << LOGN); i += blockDim.x) Wl[i] = tw[i];
         return Wl;
     } else {
         return tw;
     }
 }
-template <typename T, int LOGN>
-constexpr int table_elems() { return twiddles_in_lds<T, LOGN>() ? (1 << LOGN) : 0; }
 
 // ---------------------------------------------------------------------------------------
 // Sums of two partial-sum buffers by one workgroup of any size, in one pass and in a fixed
@@ -1081,8 +1118,8 @@ void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, cpx<T>* dirt,
     constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
     const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
-    if constexpr (C == 1 && LOGN >= 11) {   // long columns: CR columns per thread in registers
-        constexpr int CR = sizeof(T) == 8 ? 2 : 4;
+    if constexpr (long_cols<T, LOGN>()) {   // long columns: CR columns per thread in registers
+        constexpr int CR = long_cols_cr<T>();
         const size_t lds1 = lds_bytes<T, LOGN, 1>(2);
         // each XCD takes one contiguous range of column groups (sg = 0), so the groups that
         // share 128-byte lines run on one L2 at about the same time (the adjoint 559 -> 506 us
@@ -1104,8 +1141,8 @@ void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s
     constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
     const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
-    if constexpr (C == 1 && LOGN >= 11) {
-        constexpr int CR = sizeof(T) == 8 ? 2 : 4;
+    if constexpr (long_cols<T, LOGN>()) {
+        constexpr int CR = long_cols_cr<T>();
         const size_t lds1 = lds_bytes<T, LOGN, 1>(2);
         auto f = k_fft_cols_adj_mc<T, LOGN, CR>;
         set_lds_limit(f, lds1);

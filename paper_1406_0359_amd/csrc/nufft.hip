@@ -600,6 +600,14 @@ void launch_grid(const Plan& P, const cpx<T>* y, const int32_t* perm, cpx<T>* gr
 
 template <typename T>
 void launch_gtg(const Plan& P, const cpx<T>* gin, cpx<T>* gout, hipStream_t s) {
+    if (sizeof(T) == 4 && P.K >= 8192) {
+        // very large FP32 grids: G into the plan's visibility buffer, then G^T from it (its
+        // wide 64 x 64 degridding windows and one-item gridding batches beat the fused
+        // launch's 46 x 46 windows there)
+        launch_degrid<T>(P, gin, (cpx<T>*)P.vis, nullptr, 1.0, s);
+        launch_grid<T>(P, (const cpx<T>*)P.vis, nullptr, gout, s);
+        return;
+    }
     if (P.TT == 16) grid_tt<T, 16, 256, true>(P, nullptr, gin, nullptr, gout, s);
     else grid_tt<T, 32, 256, true>(P, nullptr, gin, nullptr, gout, s);
 }

@@ -72,6 +72,25 @@ unsigned ew_blocks(int64_t n) { return (unsigned)((n + VT - 1) / VT); }
 #define GRID_STRIDE(i, n) \
     for (int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x; i < (n); i += (int64_t)gridDim.x * VT)
 
+// Grid-stride loop over [0, n) that takes U of a thread's elements at a time: ld(i) for all
+// of them first, so their loads are in flight together, then op(i, loaded) in index order --
+// the order of GRID_STRIDE, so sums come out bit for bit the same.  (A reducing kernel's grid
+// is RED_BLOCKS workgroups, four per CU: one element at a time keeps too few loads in flight
+// to stream at HBM rate.)
+template <int U, typename Ld, typename Op>
+__device__ __forceinline__ void grid_stride_batched(int64_t n, Ld ld, Op op) {
+    const int64_t S = (int64_t)gridDim.x * VT;
+    for (int64_t i0 = (int64_t)blockIdx.x * VT + threadIdx.x; i0 < n; i0 += U * S) {
+        decltype(ld(i0)) v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u * S < n) v[u] = ld(i0 + u * S);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u * S < n) op(i0 + u * S, v[u]);
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(VT) k_fill(cpx<T>* v, cpx<T> val, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
@@ -81,10 +100,9 @@ __global__ void __launch_bounds__(VT) k_fill(cpx<T>* v, cpx<T> val, int64_t n) {
 template <typename T>
 __global__ void __launch_bounds__(VT) k_norm2(const cpx<T>* __restrict__ v, int64_t n, double* part) {
     double acc = 0;
-    GRID_STRIDE(i, n) {
-        const cpx<T> a = v[i];
+    grid_stride_batched<4>(n, [&](int64_t i) { return v[i]; }, [&](int64_t, cpx<T> a) {
         acc += (double)a.x * a.x + (double)a.y * a.y;
-    }
+    });
     const double t = block_sum(acc);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -92,10 +110,9 @@ __global__ void __launch_bounds__(VT) k_norm2(const cpx<T>* __restrict__ v, int6
 template <typename T>
 __global__ void __launch_bounds__(VT) k_maxabs(const cpx<T>* __restrict__ v, int64_t n, double* part) {
     double acc = 0;
-    GRID_STRIDE(i, n) {
-        const cpx<T> a = v[i];
+    grid_stride_batched<4>(n, [&](int64_t i) { return v[i]; }, [&](int64_t, cpx<T> a) {
         acc = fmax(acc, sqrt((double)a.x * a.x + (double)a.y * a.y));
-    }
+    });
     const double t = block_max(acc);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -179,19 +196,25 @@ __global__ void __launch_bounds__(VT)
 k_prox_l1(cpx<T>* __restrict__ v1, cpx<T>* __restrict__ z1, const double* __restrict__ w, double gamma,
           int64_t n, double* part) {
     double acc = 0;
-    GRID_STRIDE(i, n) {
-        const cpx<T> v = v1[i];
-        const double wi = w ? w[i] : 1.0;
-        acc += wi * sqrt((double)v.x * v.x + (double)v.y * v.y);
-        const cpx<T> u = v + z1[i];
-        const T mag = sqrt(u.x * u.x + u.y * u.y);
-        const T thr = (T)(gamma * wi);
-        const T s = mag > thr ? (T)1 - thr / mag : (T)0;
-        const cpx<T> r1 = s * u;
-        const cpx<T> z = u - r1;
-        z1[i] = z;
-        v1[i] = r1 - z;
-    }
+    struct In {
+        cpx<T> v, z;
+        double w;
+    };
+    grid_stride_batched<4>(
+        n, [&](int64_t i) { return In{v1[i], z1[i], w ? w[i] : 1.0}; },
+        [&](int64_t i, const In& a) {
+            const cpx<T> v = a.v;
+            const double wi = a.w;
+            acc += wi * sqrt((double)v.x * v.x + (double)v.y * v.y);
+            const cpx<T> u = v + a.z;
+            const T mag = sqrt(u.x * u.x + u.y * u.y);
+            const T thr = (T)(gamma * wi);
+            const T s = mag > thr ? (T)1 - thr / mag : (T)0;
+            const cpx<T> r1 = s * u;
+            const cpx<T> z = u - r1;
+            z1[i] = z;
+            v1[i] = r1 - z;
+        });
     const double t = block_sum(acc);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -215,13 +238,17 @@ __global__ void __launch_bounds__(VT)
 k_ball_part(const cpx<T>* __restrict__ v3, const cpx<T>* __restrict__ z3, const cpx<T>* __restrict__ yt,
             int64_t n, double* part_d, double* part_res) {
     double ad = 0, ar = 0;
-    GRID_STRIDE(i, n) {
-        const cpx<T> v = v3[i], y = yt[i];
-        const cpx<T> d = v + z3[i] - y;
-        ad += (double)d.x * d.x + (double)d.y * d.y;
-        const double rx = (double)y.x - v.x, ry = (double)y.y - v.y;
-        ar += rx * rx + ry * ry;
-    }
+    struct In {
+        cpx<T> v, y, z;
+    };
+    grid_stride_batched<4>(
+        n, [&](int64_t i) { return In{v3[i], yt[i], z3[i]}; },
+        [&](int64_t, const In& a) {
+            const cpx<T> d = a.v + a.z - a.y;
+            ad += (double)d.x * d.x + (double)d.y * d.y;
+            const double rx = (double)a.y.x - a.v.x, ry = (double)a.y.y - a.v.y;
+            ar += rx * rx + ry * ry;
+        });
     const double td = block_sum(ad);
     const double tr = block_sum(ar);
     if (threadIdx.x == 0) {

@@ -367,7 +367,7 @@ k_wav_inv_final(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ lli
     __shared__ cpx<T> in[NSLOT][2 * CF * WS];
     __shared__ cpx<T> mid[NSLOT][FP * WS];
     __shared__ T tp[NSLOT][2 * MAX_TAPS];
-    __shared__ cpx<T> part[NSLOT][FP * FP];
+    __shared__ cpx<T> part[NSLOT][NSLOT > 1 ? FP * FP : 1];   // one slot writes directly
     const int n = A.n;
     const size_t N = (size_t)n * n;
     const int half = n >> 1;
@@ -397,6 +397,26 @@ k_wav_inv_final(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ lli
                                        acc1[k].y += od.y;
                                    }
                                });
+    }
+    if constexpr (NSLOT == 1) {
+        // one slot: each thread adds the Dirac block to its own output pairs and writes them
+#pragma unroll
+        for (int k = 0; k < PAIRS; ++k) {
+            const int i = tid + 256 * k;
+            if (i < FP * FP / 2) {
+                const int r = i / (FP / 2), c = 2 * (i % (FP / 2));
+                const size_t o = (size_t)(m0 + r) * n + m1 + c;
+                cpx<T> e = acc0[k], od = acc1[k];
+                if (A.dirac_block >= 0) {
+                    const cpx<T>* d = alpha + (size_t)A.dirac_block * N + o;
+                    e = e + d[0];
+                    od = od + d[1];
+                }
+                x[o] = scale * e;
+                x[o + 1] = scale * od;
+            }
+        }
+        return;
     }
 #pragma unroll
     for (int k = 0; k < PAIRS; ++k) {
@@ -524,12 +544,14 @@ void launch_psi(const Plan& P, const cpx<T>* alpha, cpx<T>* x, hipStream_t s) {
         cur = dst;
     }
     const cpx<T>* in = cur < 0 ? alpha : llb[cur];
-    // FP32 on large images: 32 x 32 tiles (half the window overhead of 16 x 16); the FP64
-    // windows of a 32 x 32 tile would not fit in LDS four bases at a time
+    // FP32 on large images: 32 x 32 tiles (half the window overhead of 16 x 16), one basis
+    // at a time per workgroup, so four workgroups share a CU's LDS and one's window loads
+    // overlap another's filtering (4096^2: 1321 -> 1078 us for the whole synthesis against
+    // four bases at a time in one workgroup)
     if constexpr (sizeof(T) == 4) {
         if (P.n >= 512) {
             const int tiles = P.n / 32;
-            hipLaunchKernelGGL((k_wav_inv_final<T, 32, 4>), dim3(tiles * tiles), dim3(1024), 0, s, alpha, in,
+            hipLaunchKernelGGL((k_wav_inv_final<T, 32, 1>), dim3(tiles * tiles), dim3(256), 0, s, alpha, in,
                                cur < 0 ? 1 : 0, x, filt, A, scale);
             return;
         }

@@ -11,7 +11,7 @@ largest sampled magnitude.  The adjoint identity holds to rounding: 1e-5 (FP32),
 The whole outputs are also compared with the oracle's NUFFT, element by element, where its
 sparse interpolation matrix fits in host memory: the 1024 x 1024 precision-form shape with its
 full coverage (M = 2N = 2 097 152, 10% uniform) in FP32, n = 2048 in FP64 and n = 4096 with
-J = 8 (10^6 visibilities) in FP32.  Bounds: FP64 relative l2 <= 1e-12 and element-wise
+J = 8 (10^6 visibilities) in FP32, each with the normal operator Phi^dagger Phi as well.  Bounds: FP64 relative l2 <= 1e-12 and element-wise
 <= 1e-11 of the largest value; FP32 relative l2 and element-wise <= 1e-5."""
 import numpy as np
 import pytest
@@ -66,9 +66,15 @@ def test_large_phi_and_adjoint_elementwise_against_oracle(n, M, J, uf, prec):
     got_y = to_np(plan.phi(plan.as_vec(x)))
     ref_x = op.phi_adj(v)
     got_x = to_np(plan.phi_adj(plan.as_vec(v)))
+    # the normal operator as the CG update applies it (G^T G fused in one launch, or G then
+    # G^T on the 8192^2 FP32 grid) against the oracle's Phi^dagger (Phi x)
+    ref_n = op.phi_adj(ref_y)
+    got_n = to_np(plan.normal(plan.as_vec(x)))
     if prec == "fp64":
         assert rel_l2(got_y, ref_y) < 1e-12 and max_rel(got_y, ref_y) < 1e-11
         assert rel_l2(got_x, ref_x) < 1e-12 and max_rel(got_x, ref_x) < 1e-11
+        assert rel_l2(got_n, ref_n) < 1e-12 and max_rel(got_n, ref_n) < 1e-11
     else:
         assert rel_l2(got_y, ref_y) < 1e-5 and max_rel(got_y, ref_y) < 1e-5
         assert rel_l2(got_x, ref_x) < 1e-5 and max_rel(got_x, ref_x) < 1e-5
+        assert rel_l2(got_n, ref_n) < 1e-5 and max_rel(got_n, ref_n) < 1e-5
