@@ -246,38 +246,63 @@ k_wav_fwd_level0_all(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ alpha, c
     }
 }
 
-// Synthesis of one level on a po x po output tile (po = min(SP, Ls)) of one basis: loads
-// the window of the four subbands the tile reaches (po/2 + F/2 - 1 positions per axis per
-// subband, periodic) into `in`, undoes axis 0 into `mid`, then axis 1; returns the thread's
-// outputs (pairs of adjacent samples along axis 1) through `emit`.
+// Synthesis of one level on a po x po output tile (po = min(SP, Ls)) of one basis: the
+// window of the four subbands the tile reaches (po/2 + F/2 - 1 positions per axis per
+// subband, periodic) goes into `in`, axis 0 is undone into `mid`, then axis 1; the thread's
+// outputs (pairs of adjacent samples along axis 1) are returned through `emit`.
 // Window layout: rows [0, C) lowpass and [C, 2C) highpass along axis 0, columns likewise.
-template <typename T, int NTH, int CMAX, typename Emit>
-__device__ __forceinline__ void synth_tile(const cpx<T>* __restrict__ alpha, size_t blk, const cpx<T>* __restrict__ lls,
-                                          int lld, int n, int half, int po, int m0, int m1, int F,
-                                          const T* __restrict__ ftaps, T* tp, cpx<T>* in, cpx<T>* mid, int tid,
-                                          Emit emit) {
-    constexpr int WS = 2 * CMAX + 1;   // LDS row stride of `in` and `mid`
+// synth_tile loads the window and runs synth_axis0 and synth_axis1; the finest-level kernel
+// that prefetches the next basis uses synth_load (the window into registers) and
+// synth_store (registers into `in`) instead.
+template <typename T, int NTH, int CMAX>
+struct SynthWin {
+    static constexpr int WS = 2 * CMAX + 1;   // LDS row stride of `in` and `mid`
+    static constexpr int E = (4 * CMAX * CMAX + NTH - 1) / NTH;   // window elements a thread
+    cpx<T> v[E];
+    T tap;
+};
+
+template <typename T, int NTH, int CMAX>
+__device__ __forceinline__ void synth_load(SynthWin<T, NTH, CMAX>& w, const cpx<T>* __restrict__ alpha, size_t blk,
+                                           const cpx<T>* __restrict__ lls, int lld, int n, int half, int po,
+                                           int m0, int m1, int F, const T* __restrict__ ftaps, int tid) {
     const int C = po / 2 + F / 2 - 1;
     const int s0 = m0 / 2 - F / 2 + 1, s1 = m1 / 2 - F / 2 + 1;   // first window index
-    // the basis' taps (ftaps, into tp) and the window (C <= CMAX) are loaded together, then
-    // stored to LDS
-    const T tap = tid < 2 * MAX_TAPS ? ftaps[tid] : (T)0;
-    stage_batched<cpx<T>, (4 * CMAX * CMAX + NTH - 1) / NTH, NTH>(
-        4 * C * C, tid,
-        [&](int i) {
+    w.tap = tid < 2 * MAX_TAPS ? ftaps[tid] : (T)0;
+#pragma unroll
+    for (int k = 0; k < SynthWin<T, NTH, CMAX>::E; ++k) {
+        const int i = tid + k * NTH;
+        if (i < 4 * C * C) {
             const int u = i / (2 * C), v = i - u * (2 * C);
             const bool h0 = u >= C, h1 = v >= C;
             const int i0 = (s0 + (h0 ? u - C : u)) & (half - 1), i1 = (s1 + (h1 ? v - C : v)) & (half - 1);
-            return (!h0 && !h1) ? lls[(size_t)i0 * lld + i1]
-                                : alpha[blk + (size_t)(i0 + (h0 ? half : 0)) * n + i1 + (h1 ? half : 0)];
-        },
-        [&](int i, cpx<T> val) {
+            w.v[k] = (!h0 && !h1) ? lls[(size_t)i0 * lld + i1]
+                                  : alpha[blk + (size_t)(i0 + (h0 ? half : 0)) * n + i1 + (h1 ? half : 0)];
+        }
+    }
+}
+
+template <typename T, int NTH, int CMAX>
+__device__ __forceinline__ void synth_store(const SynthWin<T, NTH, CMAX>& w, int po, int F, T* tp, cpx<T>* in,
+                                            int tid) {
+    constexpr int WS = SynthWin<T, NTH, CMAX>::WS;
+    const int C = po / 2 + F / 2 - 1;
+#pragma unroll
+    for (int k = 0; k < SynthWin<T, NTH, CMAX>::E; ++k) {
+        const int i = tid + k * NTH;
+        if (i < 4 * C * C) {
             const int u = i / (2 * C), v = i - u * (2 * C);
-            in[u * WS + v] = val;
-        });
-    if (tid < 2 * MAX_TAPS) tp[tid] = tap;
-    __syncthreads();
-    // undo axis 0: output rows 2j, 2j+1 (j = m0/2 + jr) for every window column v
+            in[u * WS + v] = w.v[k];
+        }
+    }
+    if (tid < 2 * MAX_TAPS) tp[tid] = w.tap;
+}
+
+// undo axis 0: output rows 2j, 2j+1 (j = m0/2 + jr) for every window column v
+template <typename T, int NTH, int CMAX>
+__device__ __forceinline__ void synth_axis0(int po, int F, const T* tp, const cpx<T>* in, cpx<T>* mid, int tid) {
+    constexpr int WS = SynthWin<T, NTH, CMAX>::WS;
+    const int C = po / 2 + F / 2 - 1;
     const int hp = po / 2;
     for (int i = tid; i < hp * 2 * C; i += NTH) {
         const int jr = i / (2 * C), v = i - jr * (2 * C);
@@ -297,9 +322,15 @@ __device__ __forceinline__ void synth_tile(const cpx<T>* __restrict__ alpha, siz
         mid[(2 * jr) * WS + v] = mk<T>(ex, ey);
         mid[(2 * jr + 1) * WS + v] = mk<T>(ox, oy);
     }
-    __syncthreads();
-    // undo axis 1: row r, output columns 2j, 2j+1 (a thread's k-th pair is i = tid + k NTH;
-    // the unrolled k is a compile-time index for the caller's accumulators)
+}
+
+// undo axis 1: row r, output columns 2j, 2j+1 (a thread's k-th pair is i = tid + k NTH;
+// the unrolled k is a compile-time index for the caller's accumulators)
+template <typename T, int NTH, int CMAX, typename Emit>
+__device__ __forceinline__ void synth_axis1(int po, int F, const T* tp, const cpx<T>* mid, int tid, Emit emit) {
+    constexpr int WS = SynthWin<T, NTH, CMAX>::WS;
+    const int C = po / 2 + F / 2 - 1;
+    const int hp = po / 2;
     constexpr int PMAX = CMAX - MAX_TAPS / 2 + 1;          // largest po / 2
     constexpr int KMAX = (2 * PMAX * PMAX + NTH - 1) / NTH;
 #pragma unroll
@@ -322,6 +353,37 @@ __device__ __forceinline__ void synth_tile(const cpx<T>* __restrict__ alpha, siz
         }
         emit(k, r, 2 * jc, mk<T>(ex, ey), mk<T>(ox, oy));
     }
+}
+
+template <typename T, int NTH, int CMAX, typename Emit>
+__device__ __forceinline__ void synth_tile(const cpx<T>* __restrict__ alpha, size_t blk, const cpx<T>* __restrict__ lls,
+                                          int lld, int n, int half, int po, int m0, int m1, int F,
+                                          const T* __restrict__ ftaps, T* tp, cpx<T>* in, cpx<T>* mid, int tid,
+                                          Emit emit) {
+    constexpr int WS = SynthWin<T, NTH, CMAX>::WS;
+    const int C = po / 2 + F / 2 - 1;
+    const int s0 = m0 / 2 - F / 2 + 1, s1 = m1 / 2 - F / 2 + 1;   // first window index
+    // the basis' taps (ftaps, into tp) and the window (C <= CMAX) are loaded together, then
+    // stored to LDS
+    const T tap = tid < 2 * MAX_TAPS ? ftaps[tid] : (T)0;
+    stage_batched<cpx<T>, (4 * CMAX * CMAX + NTH - 1) / NTH, NTH>(
+        4 * C * C, tid,
+        [&](int i) {
+            const int u = i / (2 * C), v = i - u * (2 * C);
+            const bool h0 = u >= C, h1 = v >= C;
+            const int i0 = (s0 + (h0 ? u - C : u)) & (half - 1), i1 = (s1 + (h1 ? v - C : v)) & (half - 1);
+            return (!h0 && !h1) ? lls[(size_t)i0 * lld + i1]
+                                : alpha[blk + (size_t)(i0 + (h0 ? half : 0)) * n + i1 + (h1 ? half : 0)];
+        },
+        [&](int i, cpx<T> val) {
+            const int u = i / (2 * C), v = i - u * (2 * C);
+            in[u * WS + v] = val;
+        });
+    if (tid < 2 * MAX_TAPS) tp[tid] = tap;
+    __syncthreads();
+    synth_axis0<T, NTH, CMAX>(po, F, tp, in, mid, tid);
+    __syncthreads();
+    synth_axis1<T, NTH, CMAX>(po, F, tp, mid, tid, emit);
 }
 
 // One synthesis level (output side Ls, level >= 1) for every basis (blockIdx.z): the
@@ -367,7 +429,7 @@ k_wav_inv_final(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ lli
     __shared__ cpx<T> in[NSLOT][2 * CF * WS];
     __shared__ cpx<T> mid[NSLOT][FP * WS];
     __shared__ T tp[NSLOT][2 * MAX_TAPS];
-    __shared__ cpx<T> part[NSLOT][NSLOT > 1 ? FP * FP : 1];   // one slot writes directly
+    __shared__ cpx<T> part[NSLOT][FP * FP];
     const int n = A.n;
     const size_t N = (size_t)n * n;
     const int half = n >> 1;
@@ -398,26 +460,6 @@ k_wav_inv_final(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ lli
                                    }
                                });
     }
-    if constexpr (NSLOT == 1) {
-        // one slot: each thread adds the Dirac block to its own output pairs and writes them
-#pragma unroll
-        for (int k = 0; k < PAIRS; ++k) {
-            const int i = tid + 256 * k;
-            if (i < FP * FP / 2) {
-                const int r = i / (FP / 2), c = 2 * (i % (FP / 2));
-                const size_t o = (size_t)(m0 + r) * n + m1 + c;
-                cpx<T> e = acc0[k], od = acc1[k];
-                if (A.dirac_block >= 0) {
-                    const cpx<T>* d = alpha + (size_t)A.dirac_block * N + o;
-                    e = e + d[0];
-                    od = od + d[1];
-                }
-                x[o] = scale * e;
-                x[o + 1] = scale * od;
-            }
-        }
-        return;
-    }
 #pragma unroll
     for (int k = 0; k < PAIRS; ++k) {
         const int i = tid + 256 * k;
@@ -443,6 +485,73 @@ k_wav_inv_final(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ lli
             sy += part[sl][i].y;
         }
         x[o] = mk<T>(scale * sx, scale * sy);
+    }
+}
+
+// Finest synthesis level, one basis at a time per 256-thread workgroup, with the next basis'
+// window loaded into registers while the current one is filtered: it is stored to `in` as
+// soon as axis 0 of the current basis has read `in` (the taps are double-buffered), so its
+// load latency hides behind the filtering.  Same arithmetic, in the same basis order, as
+// k_wav_inv_final with one slot.
+template <typename T, int FP>
+__global__ void __launch_bounds__(256)
+k_wav_inv_final_pipe(const cpx<T>* __restrict__ alpha, const cpx<T>* __restrict__ llin, int ll_from_alpha,
+                     cpx<T>* __restrict__ x, const T* __restrict__ filt, WavArgs A, T scale) {
+    constexpr int CF = FP / 2 + MAX_TAPS / 2 - 1;
+    constexpr int WS = 2 * CF + 1;
+    constexpr int PAIRS = (FP * FP / 2 + 255) / 256;   // output pairs per thread
+    __shared__ cpx<T> in[2 * CF * WS];
+    __shared__ cpx<T> mid[FP * WS];
+    __shared__ T tp[2][2 * MAX_TAPS];
+    const int n = A.n;
+    const size_t N = (size_t)n * n;
+    const int half = n >> 1;
+    const int tiles = n / FP;
+    const int m0 = FP * (blockIdx.x / tiles), m1 = FP * (blockIdx.x % tiles);
+    const int tid = threadIdx.x;
+    const int lld = ll_from_alpha ? n : half;
+    auto blk_of = [&](int z) { return (size_t)A.block[z] * N; };
+    auto lls_of = [&](int z) { return ll_from_alpha ? alpha + blk_of(z) : llin + (size_t)z * (N / 4); };
+    cpx<T> acc0[PAIRS], acc1[PAIRS];
+#pragma unroll
+    for (int k = 0; k < PAIRS; ++k) acc0[k] = acc1[k] = mk<T>(0, 0);
+    SynthWin<T, 256, CF> w;
+    synth_load<T, 256, CF>(w, alpha, blk_of(0), lls_of(0), lld, n, half, FP, m0, m1, A.flen[0], filt, tid);
+    synth_store<T, 256, CF>(w, FP, A.flen[0], tp[0], in, tid);
+    __syncthreads();
+    for (int z = 0; z < A.nwav; ++z) {
+        const int F = A.flen[z];
+        const bool more = z + 1 < A.nwav;
+        if (more)
+            synth_load<T, 256, CF>(w, alpha, blk_of(z + 1), lls_of(z + 1), lld, n, half, FP, m0, m1, A.flen[z + 1],
+                                   filt + (z + 1) * 2 * MAX_TAPS, tid);
+        synth_axis0<T, 256, CF>(FP, F, tp[z & 1], in, mid, tid);
+        __syncthreads();
+        if (more) synth_store<T, 256, CF>(w, FP, A.flen[z + 1], tp[(z + 1) & 1], in, tid);
+        synth_axis1<T, 256, CF>(FP, F, tp[z & 1], mid, tid, [&](int k, int, int, cpx<T> e, cpx<T> od) {
+            acc0[k].x += e.x;
+            acc0[k].y += e.y;
+            acc1[k].x += od.x;
+            acc1[k].y += od.y;
+        });
+        __syncthreads();
+    }
+    // each thread adds the Dirac block to its own output pairs and writes them
+#pragma unroll
+    for (int k = 0; k < PAIRS; ++k) {
+        const int i = tid + 256 * k;
+        if (i < FP * FP / 2) {
+            const int r = i / (FP / 2), c = 2 * (i % (FP / 2));
+            const size_t o = (size_t)(m0 + r) * n + m1 + c;
+            cpx<T> e = acc0[k], od = acc1[k];
+            if (A.dirac_block >= 0) {
+                const cpx<T>* d = alpha + (size_t)A.dirac_block * N + o;
+                e = e + d[0];
+                od = od + d[1];
+            }
+            x[o] = scale * e;
+            x[o + 1] = scale * od;
+        }
     }
 }
 
@@ -545,13 +654,13 @@ void launch_psi(const Plan& P, const cpx<T>* alpha, cpx<T>* x, hipStream_t s) {
     }
     const cpx<T>* in = cur < 0 ? alpha : llb[cur];
     // FP32 on large images: 32 x 32 tiles (half the window overhead of 16 x 16), one basis
-    // at a time per workgroup, so four workgroups share a CU's LDS and one's window loads
-    // overlap another's filtering (4096^2: 1321 -> 1078 us for the whole synthesis against
-    // four bases at a time in one workgroup)
+    // at a time per 256-thread workgroup with the next basis' window prefetched, so five
+    // workgroups share a CU's LDS and loads overlap filtering (4096^2: 1321 -> 950 us for the
+    // whole synthesis against four bases at a time in one 1024-thread workgroup)
     if constexpr (sizeof(T) == 4) {
         if (P.n >= 512) {
             const int tiles = P.n / 32;
-            hipLaunchKernelGGL((k_wav_inv_final<T, 32, 1>), dim3(tiles * tiles), dim3(256), 0, s, alpha, in,
+            hipLaunchKernelGGL((k_wav_inv_final_pipe<T, 32>), dim3(tiles * tiles), dim3(256), 0, s, alpha, in,
                                cur < 0 ? 1 : 0, x, filt, A, scale);
             return;
         }
