@@ -91,9 +91,10 @@ KERNEL_NAME = {
     "fft_rows": "k_fft_rows_fwd", "fft_cols": "k_fft_cols_fwd", "degrid": "k_degrid",
     "grid": "k_grid", "gtg": "k_grid (G^T G)", "ifft_cols": "k_fft_cols_adj", "ifft_rows": "k_fft_rows_adj",
 }
-# where a workload's stage runs other kernels: the 8192^2 FP32 grid applies G^T G as G then
+# where a workload's stage runs other kernels: FP32 grids from 2048^2 apply G^T G as G then
 # G^T (two launches; the stage's algorithmic bytes stay those of G^T G)
-KERNEL_NAME_BY_WORKLOAD = {("sara4096", "gtg"): "k_degrid_tiles + k_grid (G^T G as G then G^T)"}
+KERNEL_NAME_BY_WORKLOAD = {(w, "gtg"): "k_degrid_tiles + k_grid (G^T G as G then G^T)"
+                           for w in ("sara1024", "sara4096")}
 
 
 def kernel_name(stage: str, workload: str) -> str:

@@ -190,7 +190,7 @@ purify_status purify_sdmm_solve(purify_plan* plan, const void* y, const purify_s
 
 /* out = Phi^dagger Phi x (x, out: device, N complex; both n x n).  mode 0: through the
  * NUFFT, exactly the operator of the CG update (the interpolation and gridding of G^T G fused
- * in one launch; on FP32 grids of 8192 x 8192 and more, G then G^T as two launches).  mode PURIFY_NORMAL_TOEPLITZ: the stored form
+ * in one launch; on FP32 grids of 2048 x 2048 and more, G then G^T as two launches).  mode PURIFY_NORMAL_TOEPLITZ: the stored form
  * T = Z^T F^dagger diag(c_hat) F Z, a convolution with the point-spread function
  * h(d) = sum_m exp(i omega_m . d) on the 2n x 2n circulant embedding, with c_hat the real
  * part of its spectrum / K^2 (so T is Hermitian).  h comes from the plan's Phi^dagger applied

@@ -35,7 +35,7 @@ def test_dominant_roofline_picks_the_largest_share():
     assert r["stage"] == "fft_cols" and r["kernel"] == "k_fft_cols_fwd"
     assert r["traffic"] is None
     assert r["bound"] == "hbm" and r["peak"] == 8000.0 and r["unit"] == "GB/s"
-    # on the 8192^2 FP32 grid the G^T G stage is two launches, named as such
+    # on FP32 grids from 2048^2 the G^T G stage is two launches, named as such
     st["gtg"]["ms"] = 0.7
     r = bench.dominant_roofline(st, 10, "sara4096")
     assert r["stage"] == "gtg" and r["kernel"].startswith("k_degrid_tiles + k_grid")

@@ -67,7 +67,7 @@ def test_large_phi_and_adjoint_elementwise_against_oracle(n, M, J, uf, prec):
     ref_x = op.phi_adj(v)
     got_x = to_np(plan.phi_adj(plan.as_vec(v)))
     # the normal operator as the CG update applies it (G^T G fused in one launch, or G then
-    # G^T on the 8192^2 FP32 grid) against the oracle's Phi^dagger (Phi x)
+    # G^T on FP32 grids from 2048^2) against the oracle's Phi^dagger (Phi x)
     ref_n = op.phi_adj(ref_y)
     got_n = to_np(plan.normal(plan.as_vec(x)))
     if prec == "fp64":
