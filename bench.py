@@ -352,8 +352,9 @@ def large_solve(torch, purify, synth, iters: int, background: int) -> dict:
     """The 4096^2 single solve (M = 10^7, J = 8, SARA, 5 levels, FP32 with FP64 reductions):
     per-operator rates, the dominant kernel's roofline, the oversampled FFT against rocFFT, and
     the full solve (nu by 100 power iterations, `iters` SDMM iterations) with its SNR and
-    residual; then the same solve beside a Poisson stream of 256^2 requests served at half
-    their standalone capacity."""
+    residual, the same solve with the stored (Toeplitz) normal operator in CG; then the exact
+    solve beside a Poisson stream of 256^2 requests served at half their standalone
+    capacity."""
     w = synth.WORKLOADS["sara4096"]
     t0 = time.perf_counter()
     p = synth.make_inputs(w)
@@ -394,6 +395,11 @@ def large_solve(torch, purify, synth, iters: int, background: int) -> dict:
                                        st["fft_rows"]["ms"] + st["fft_cols"]["ms"],
                                        st["fft_rows"]["bytes"] + st["fft_cols"]["bytes"]),
     }
+    try:
+        out["toeplitz"] = toeplitz_form(torch, plan, y, p.epsilon, r0.nu, iters, w.cg_iters, p.x_true, synth,
+                                        x_solo.cpu().numpy())
+    except Exception as e:  # report, do not hide the rest
+        out["toeplitz_error"] = repr(e)
     if background > 0:
         out["with_background"] = large_with_background(torch, purify, synth, plan, y, p.epsilon, r0.nu, r0.gamma,
                                                        iters, x_solo, iters / dt, background)

@@ -961,6 +961,99 @@ k_fft_cols_toep(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const
 }
 
 
+// The stored normal operator's column stage for long columns: each thread keeps CR adjacent
+// columns in registers (32-byte runs of a row, as in k_fft_cols_fwd_mc) and the workgroup
+// takes them one after another through the same two line buffers, each column with the same
+// arithmetic as k_fft_cols_toep; a column's adjoint output replaces its input in registers and
+// all CR columns are written at the end (in place is safe: every read precedes every write).
+template <typename T, int LOGN, int CR>
+__global__ void __launch_bounds__((2 * Plan1D<T, LOGN, 1>::TL))
+k_fft_cols_toep_mc(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const cpx<T>* __restrict__ tw,
+                   const cpx<T>* __restrict__ tw2, int sg, cpx<T>* __restrict__ dirt, CgBeta cb) {
+    using PL = Plan1D<T, LOGN, 1>;
+    constexpr int N = PL::N, K = 2 * N;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
+    __shared__ double red[32];
+    const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
+    const int r = threadIdx.x / PL::TL, tl = threadIdx.x % PL::TL;
+    cpx<T>* lines = base + table_elems<T, LOGN>();
+    cpx<T>* line = lines + r * PL::LS;
+    const int col0 = strip_block(sg) * CR;
+    __syncthreads();
+    cpx<T> v[CR][PL::RMAX];
+#pragma unroll
+    for (int i = 0; i < PL::RMAX; ++i) {
+        const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
+#pragma unroll
+        for (int cc = 0; cc < CR; ++cc) v[cc][i] = in[ro + cc];
+    }
+    if (cb.rho_new_part) {
+        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt
+        double rn, rho;
+        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
+        const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
+#pragma unroll
+            for (int cc = 0; cc < CR; ++cc) v[cc][i] = v[cc][i] + beta * dirt[ro + cc];
+        }
+        __syncthreads();   // both parity groups have read dirt
+        if (r == 0) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) {
+                const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
+#pragma unroll
+                for (int cc = 0; cc < CR; ++cc) dirt[ro + cc] = v[cc][i];
+            }
+        }
+    }
+    if (r) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const cpx<T> t = tw2[PL::in_pos(tl, i)];
+#pragma unroll
+            for (int cc = 0; cc < CR; ++cc) v[cc][i] = v[cc][i] * t;
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < CR; ++cc) {
+        line_fft<T, LOGN, 1, false>(v[cc], line, tl, W);
+        // frequency k1 = 2k' + r holds (-1)^k' i^r v; the adjoint reads (-1)^k' times its input
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int kp = PL::out_pos(tl, i);
+            cpx<T> o = chat[(size_t)(2 * kp + r) * K + col0 + cc] * v[cc][i];
+            v[cc][i] = r ? mul_i(o) : o;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[cc][i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) v[cc][i] = line[PL::in_pos(tl, i)];
+        __syncthreads();
+        line_fft<T, LOGN, 1, true>(v[cc], line, tl, W);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[cc][i];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PL::RMAX / 2; ++q) {
+            const int j = r + 2 * tl + q * 2 * PL::TL;
+            v[cc][q] = lines[j] + mul_mi(mulc(lines[PL::LS + j], tw2[j]));
+        }
+        __syncthreads();   // the next column reuses the lines
+    }
+#pragma unroll
+    for (int q = 0; q < PL::RMAX / 2; ++q) {
+        const int j = r + 2 * tl + q * 2 * PL::TL;
+#pragma unroll
+        for (int cc = 0; cc < CR; ++cc) out[(size_t)j * K + col0 + cc] = v[cc][q];
+    }
+}
+
 // rows_adj: thread (b, tl, r) with r fastest; parity lines in parallel, combined in LDS;
 // x[row][j] = c1 s_row s_j (A[j] + (-i) exp(pi i j/n) B[j]) + c2 v, partial Re<v, x>
 template <typename T, int LOGN, int B>
@@ -1161,6 +1254,17 @@ void cols_toep_impl(const Plan& P, const cpx<T>* in, cpx<T>* out, cpx<T>* dirt, 
     constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
     const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
+    if constexpr (sizeof(T) == 4 && long_cols<T, LOGN>()) {
+        // long FP32 columns: two columns per thread in registers (four, with the spectrum's
+        // loads, spilled at the 128-register limit of the 1024-thread workgroup)
+        constexpr int CR = 2;
+        const size_t lds1 = lds_bytes<T, LOGN, 1>(2);
+        auto f = k_fft_cols_toep_mc<T, LOGN, CR>;
+        set_lds_limit(f, lds1);
+        hipLaunchKernelGGL(f, dim3(2 * N / CR), dim3(2 * Plan1D<T, LOGN, 1>::TL), lds1, s, in, out,
+                           (const T*)P.chat, (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, 0, dirt, cb);
+        return;
+    }
     auto f = k_fft_cols_toep<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, in, out, (const T*)P.chat, (const cpx<T>*)P.tw,

@@ -61,12 +61,14 @@ def test_toeplitz_normal_sara256():
     assert rel_l2(got, ref) < 1e-4
 
 
-def test_toeplitz_normal_large_fp32_agrees_with_nufft_normal():
-    # 1024 x 1024 FP32 plan (the large-image shape; fewer visibilities to keep the plan quick):
-    # a property that holds at any size, the stored operator agrees with the NUFFT normal
-    n, M = 1024, 300000
+@pytest.mark.parametrize("n,M,J", [(1024, 300000, 6), (4096, 1000000, 8)])
+def test_toeplitz_normal_large_fp32_agrees_with_nufft_normal(n, M, J):
+    # FP32 plans at the large-image shapes (fewer visibilities to keep the plans quick; 4096
+    # reaches the register-held-column stage of the stored operator): a property that holds
+    # at any size, the stored operator agrees with the NUFFT normal operator, which is itself
+    # compared with the oracle at these shapes
     uv = synth.uv_coverage(M, 2 * n, np.random.default_rng(7), 0.1)
-    plan = purify.Plan(n, uv, J=6, dict_mask=0x1FF, levels=4, precision="fp32", device=DEV)
+    plan = purify.Plan(n, uv, J=J, dict_mask=0x1FF, levels=4, precision="fp32", device=DEV)
     x = plan.as_vec(np.abs(rand_complex((n, n), 8)))
     a = to_np(plan.normal(x, toeplitz=True))
     b = to_np(plan.normal(x))
