@@ -186,6 +186,15 @@ PURIFY_RADICES(double, 10, 3, 16, 16, 4)
 PURIFY_RADICES(double, 11, 3, 16, 16, 8)
 PURIFY_RADICES(double, 12, 3, 16, 16, 16)
 
+// Long FP32 columns (n >= 4096) keep one pad element after every 8 of a line buffer.  A
+// Stockham pass writes its first outputs 8 elements apart (64 bytes: every lane of a wave on
+// the same two of LDS's banks) and its second in runs of 8 that repeat every 512 bytes; with
+// the pad the strides become 9 elements and runs 72 apart, which spread over all banks.
+// Every stride of these plans is a multiple of 8, so a padded address is still a per-thread
+// base plus a compile-time offset.
+template <typename T, int LOGN, int AX>
+constexpr bool pad_lines() { return AX == 1 && sizeof(T) == 4 && LOGN >= 12; }
+
 template <typename T, int LOGN, int AX>
 struct Plan1D {
     using Rd = Radices<T, LOGN, AX>;
@@ -197,13 +206,28 @@ struct Plan1D {
     static constexpr int RMAX23 = Rd::r[2] > Rd::r[3] ? Rd::r[2] : Rd::r[3];
     static constexpr int RMAX = RMAX01 > RMAX23 ? RMAX01 : RMAX23;
     static constexpr int TL = N / RMAX;          // threads per line
-    static constexpr int LS = N + 1;             // LDS line stride (padding)
+    static constexpr bool PAD = pad_lines<T, LOGN, AX>();
+    static constexpr int LS = PAD ? N + N / 8 : N + 1;   // LDS line stride (padding)
+    static_assert(!PAD || TL % 8 == 0, "padded lines need thread counts in multiples of 8");
+    // LDS offset of line position p, and the LDS distance of a position distance d (a
+    // multiple of 8 in padded lines)
+    __device__ static __forceinline__ int at(int p) { return PAD ? p + (p >> 3) : p; }
+    static constexpr int span(int d) { return PAD ? d + d / 8 : d; }
     // register slot i on entry holds position in_pos(tl, i); on exit out_pos(tl, i)
     __device__ static __forceinline__ int in_pos(int tl, int i) {
         return tl + (i / R0) * TL + (i % R0) * (N / R0);
     }
     __device__ static __forceinline__ int out_pos(int tl, int i) {
         return tl + (i / RL) * TL + (i % RL) * (N / RL);
+    }
+    // LDS offsets of in_pos and out_pos
+    __device__ static __forceinline__ int in_at(int tl, int i) {
+        static_assert(!PAD || (N / R0) % 8 == 0, "padded lines");
+        return at(tl) + span((i / R0) * TL + (i % R0) * (N / R0));
+    }
+    __device__ static __forceinline__ int out_at(int tl, int i) {
+        static_assert(!PAD || (N / RL) % 8 == 0, "padded lines");
+        return at(tl) + span((i / RL) * TL + (i % RL) * (N / RL));
     }
 };
 
@@ -234,12 +258,13 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, cpx<T>* line, int tl, const 
     constexpr int R = Rd::r[P];
     constexpr int NB = PL::RMAX / R;   // butterflies per thread in this pass
     constexpr int NS = P == 0 ? 1 : (P == 1 ? Rd::r[0] : (P == 2 ? Rd::r[0] * Rd::r[1] : Rd::r[0] * Rd::r[1] * Rd::r[2]));
+    static_assert(!PL::PAD || ((N / R) % 8 == 0 && (NS % 8 == 0 || (NS == 1 && R == 8))), "padded lines");
     if constexpr (P > 0) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int j = tl + b * PL::TL;
+            const int j = PL::at(tl) + PL::span(b * PL::TL);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b * R + r] = line[j + r * (N / R)];
+            for (int r = 0; r < R; ++r) v[b * R + r] = line[j + r * PL::span(N / R)];
         }
         __syncthreads();
 #pragma unroll
@@ -261,9 +286,9 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, cpx<T>* line, int tl, const 
         for (int b = 0; b < NB; ++b) {
             const int j = tl + b * PL::TL;
             const int k = j % NS;
-            const int o = (j - k) * R + k;
+            const int o = PL::at((j - k) * R + k);
 #pragma unroll
-            for (int t = 0; t < R; ++t) line[o + t * NS] = v[b * R + t];
+            for (int t = 0; t < R; ++t) line[o + t * PL::span(NS)] = v[b * R + t];
         }
         __syncthreads();
     }
@@ -817,12 +842,12 @@ k_fft_cols_adj_mc(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, con
         line_fft<T, LOGN, 1, true>(v[cc], line, tl, W);
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[cc][i];
+        for (int i = 0; i < PL::RMAX; ++i) line[PL::out_at(tl, i)] = v[cc][i];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PL::RMAX / 2; ++q) {
-            const int j = r + 2 * tl + q * 2 * PL::TL;
-            res[cc][q] = lines[j] + mul_mi(mulc(lines[PL::LS + j], tw2[j]));
+            const int j = r + 2 * tl + q * 2 * PL::TL, a = PL::at(r + 2 * tl) + PL::span(q * 2 * PL::TL);
+            res[cc][q] = lines[a] + mul_mi(mulc(lines[PL::LS + a], tw2[j]));
         }
         __syncthreads();   // the next column reuses the lines
     }
@@ -868,15 +893,15 @@ k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const 
     line_fft<T, LOGN, 1, true>(v, line, tl, W);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
+    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_at(tl, i)] = v[i];
     __syncthreads();
     const cpx<T>* la = lines + (2 * c) * PL::LS;
     const cpx<T>* lb = la + PL::LS;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int j = r + 2 * tl + q * 2 * PL::TL;
-        if constexpr (PRE) tmp[(size_t)j * K + col] = la[j] + mul_mi(mulc(lb[j], tj[q]));
-        else tmp[(size_t)j * K + col] = la[j] + mul_mi(mulc(lb[j], tw2[j]));
+        const int j = r + 2 * tl + q * 2 * PL::TL, a = PL::at(r + 2 * tl) + PL::span(q * 2 * PL::TL);
+        if constexpr (PRE) tmp[(size_t)j * K + col] = la[a] + mul_mi(mulc(lb[a], tj[q]));
+        else tmp[(size_t)j * K + col] = la[a] + mul_mi(mulc(lb[a], tw2[j]));
     }
 }
 
@@ -941,22 +966,22 @@ k_fft_cols_toep(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
+    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_at(tl, i)] = v[i];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) v[i] = line[PL::in_pos(tl, i)];
+    for (int i = 0; i < PL::RMAX; ++i) v[i] = line[PL::in_at(tl, i)];
     __syncthreads();
     line_fft<T, LOGN, 1, true>(v, line, tl, W);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
+    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_at(tl, i)] = v[i];
     __syncthreads();
     const cpx<T>* la = lines + (2 * c) * PL::LS;
     const cpx<T>* lb = la + PL::LS;
 #pragma unroll
     for (int q = 0; q < PL::RMAX / 2; ++q) {
-        const int j = r + 2 * tl + q * 2 * PL::TL;
-        out[(size_t)j * K + col] = la[j] + mul_mi(mulc(lb[j], tw2[j]));
+        const int j = r + 2 * tl + q * 2 * PL::TL, a = PL::at(r + 2 * tl) + PL::span(q * 2 * PL::TL);
+        out[(size_t)j * K + col] = la[a] + mul_mi(mulc(lb[a], tw2[j]));
     }
 }
 
@@ -1029,20 +1054,20 @@ k_fft_cols_toep_mc(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, co
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[cc][i];
+        for (int i = 0; i < PL::RMAX; ++i) line[PL::out_at(tl, i)] = v[cc][i];
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) v[cc][i] = line[PL::in_pos(tl, i)];
+        for (int i = 0; i < PL::RMAX; ++i) v[cc][i] = line[PL::in_at(tl, i)];
         __syncthreads();
         line_fft<T, LOGN, 1, true>(v[cc], line, tl, W);
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[cc][i];
+        for (int i = 0; i < PL::RMAX; ++i) line[PL::out_at(tl, i)] = v[cc][i];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PL::RMAX / 2; ++q) {
-            const int j = r + 2 * tl + q * 2 * PL::TL;
-            v[cc][q] = lines[j] + mul_mi(mulc(lines[PL::LS + j], tw2[j]));
+            const int j = r + 2 * tl + q * 2 * PL::TL, a = PL::at(r + 2 * tl) + PL::span(q * 2 * PL::TL);
+            v[cc][q] = lines[a] + mul_mi(mulc(lines[PL::LS + a], tw2[j]));
         }
         __syncthreads();   // the next column reuses the lines
     }
@@ -1109,19 +1134,19 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
     line_fft<T, LOGN, 0, true>(v, line, tl, W);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_pos(tl, i)] = v[i];
+    for (int i = 0; i < PL::RMAX; ++i) line[PL::out_at(tl, i)] = v[i];
     __syncthreads();
     const T srow = c1 * deap[row];
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int j = r + 2 * tl + q * 2 * PL::TL;
+        const int j = r + 2 * tl + q * 2 * PL::TL, a = PL::at(r + 2 * tl) + PL::span(q * 2 * PL::TL);
         cpx<T> o;
         if constexpr (PRE) {
-            const cpx<T> t = lines[j] + mul_mi(mulc(lines[PL::LS + j], tj[q]));
+            const cpx<T> t = lines[a] + mul_mi(mulc(lines[PL::LS + a], tj[q]));
             o = (srow * dj[q]) * t;
         } else {
-            const cpx<T> t = lines[j] + mul_mi(mulc(lines[PL::LS + j], tw2[j]));
+            const cpx<T> t = lines[a] + mul_mi(mulc(lines[PL::LS + a], tw2[j]));
             o = (srow * deap[j]) * t;
         }
         const size_t off = (size_t)row * N + j;

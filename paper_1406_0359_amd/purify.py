@@ -221,12 +221,14 @@ class Plan:
     """A measurement operator / dictionary / solver plan on one GPU.
 
     ``uv`` is an (M, 2) float64 host array of frequencies in radians per pixel.  The plan's
-    workspace is a torch uint8 tensor on ``device``; vectors are torch complex tensors of
-    the plan's precision (complex128 for fp64, complex64 for fp32) on the same device.
+    workspace is a torch uint8 tensor on ``device`` (allocated here, or the caller's
+    ``workspace`` of at least ``purify_plan_workspace_bytes``); vectors are torch complex
+    tensors of the plan's precision (complex128 for fp64, complex64 for fp32) on the same
+    device.
     """
 
     def __init__(self, n: int, uv, J: int = 6, beta: float = 0.0, dict_mask: int = DICT_SARA,
-                 levels: int = 4, precision: str = "fp64", device="cuda:0"):
+                 levels: int = 4, precision: str = "fp64", device="cuda:0", workspace=None):
         import torch
         self.lib = load_library()
         self.torch = torch
@@ -242,7 +244,14 @@ class Plan:
             raise PurifyError(1, "purify_plan_workspace_bytes")
         self.D = int(self.lib.purify_plan_dict_size(ctypes.byref(d)))
         self.q = self.D // (n * n)
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        if workspace is None:
+            workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        elif (not isinstance(workspace, torch.Tensor) or workspace.device != self.device
+              or workspace.dtype != torch.uint8 or not workspace.is_contiguous()
+              or workspace.numel() < self.ws_bytes or workspace.data_ptr() % 256):
+            raise ValueError(f"workspace must be a contiguous, 256-byte aligned uint8 tensor on "
+                             f"{self.device} of at least {self.ws_bytes} bytes")
+        self.workspace = workspace
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(self.lib.purify_plan_create(ctypes.byref(d), self.workspace.data_ptr(),
