@@ -468,6 +468,47 @@ struct CgBeta {
     int rho_count = 0;
 };
 
+// A row's K outputs after its two parity transforms: position 2k' + r holds (-1)^k' i^r
+// times parity r's value k'.  FP32 rows of 4096 and more pass through the line buffers first
+// (both parity groups have read their last pass's inputs before that pass's barrier), so each
+// thread stores both parities of a position as one 16-byte store and a wave's stores are one
+// contiguous run; written straight from registers, the two parity groups' 8-byte stores
+// interleave at a 16-byte stride.
+template <typename T, int LOGN>
+constexpr bool rows_pair_store() { return sizeof(T) == 4 && LOGN >= 12; }
+
+template <typename T, int LOGN>
+__device__ __forceinline__ void store_row_fwd(const cpx<T>* v, cpx<T>* lines, cpx<T>* outr, int tl, int r) {
+    using PL = Plan1D<T, LOGN, 0>;
+    if constexpr (rows_pair_store<T, LOGN>()) {
+        static_assert(PL::NP > 1, "the last pass's barrier orders these writes after its reads");
+        cpx<T>* line = lines + r * PL::LS;
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int kp = PL::out_pos(tl, i);
+            cpx<T> o = (kp & 1) ? neg(v[i]) : v[i];
+            if (r) o = mul_i(o);
+            line[PL::out_at(tl, i)] = o;
+        }
+        __syncthreads();
+        const int t = r * PL::TL + tl;
+#pragma unroll
+        for (int m = 0; m < PL::RMAX / 2; ++m) {
+            const int a = PL::at(t) + PL::span(m * 2 * PL::TL);
+            const cpx<T> e = lines[a], o = lines[PL::LS + a];
+            *reinterpret_cast<float4*>(outr + 2 * (t + m * 2 * PL::TL)) = make_float4(e.x, e.y, o.x, o.y);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int kp = PL::out_pos(tl, i);
+            cpx<T> o = (kp & 1) ? neg(v[i]) : v[i];
+            if (r) o = mul_i(o);
+            outr[2 * kp + r] = o;
+        }
+    }
+}
+
 // rows_fwd: thread (b, r, tl), line 2b + r; tmp[row][2k' + r] = (-1)^k' i^r FFT(s x tw2^r)[k']
 template <typename T, int LOGN, int B>
 __global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN, 0>::TL))
@@ -514,13 +555,7 @@ k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* 
         v[i] = a;
     }
     line_fft<T, LOGN, 0, false>(v, line, tl, W);
-#pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        const int kp = PL::out_pos(tl, i);
-        cpx<T> o = (kp & 1) ? neg(v[i]) : v[i];
-        if (r) o = mul_i(o);
-        outr[2 * kp + r] = o;
-    }
+    store_row_fwd<T, LOGN>(v, line - r * PL::LS, outr, tl, r);
 }
 
 // CG set-up folded into the first step's row pass: r = p = x1 + x2 + x3 - q0 (q0 may be
@@ -581,13 +616,7 @@ k_fft_rows_init(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<
         v[i] = a;
     }
     line_fft<T, LOGN, 0, false>(v, line, tl, W);
-#pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        const int kp = PL::out_pos(tl, i);
-        cpx<T> o = (kp & 1) ? neg(v[i]) : v[i];
-        if (r) o = mul_i(o);
-        outr[2 * kp + r] = o;
-    }
+    store_row_fwd<T, LOGN>(v, line - r * PL::LS, outr, tl, r);
 }
 
 // rows pass of a CG step from the second on (see CgXr): loads x, r, p, q of the row, then
@@ -666,13 +695,7 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
         rv[i] = a;
     }
     line_fft<T, LOGN, 0, false>(rv, line, tl, W);
-#pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        const int kp = PL::out_pos(tl, i);
-        cpx<T> o = (kp & 1) ? neg(rv[i]) : rv[i];
-        if (r) o = mul_i(o);
-        outr[2 * kp + r] = o;
-    }
+    store_row_fwd<T, LOGN>(rv, line - r * PL::LS, outr, tl, r);
 }
 
 // cols_fwd: thread (c, r, tl) with c fastest (coalesced runs of C columns)
