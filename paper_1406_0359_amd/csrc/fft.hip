@@ -367,6 +367,35 @@ template <typename T, int LOGN>
 constexpr bool long_cols() { return LOGN >= 11 && (cols_per_wg<T, LOGN>() == 1 || twiddles_split<T, LOGN>()); }
 template <typename T>
 constexpr int long_cols_cr() { return sizeof(T) == 8 ? 2 : 4; }
+// The long-column kernels keep the n parity twiddles exp(-pi i j / n) in LDS beside their two
+// line buffers where they fit: staged at the start (all loads in flight at once), then read
+// for every column from LDS instead of from global memory once each column's data is in.
+template <typename T, int LOGN>
+constexpr bool mc_tw2_in_lds() {
+    return (size_t)(table_elems<T, LOGN>() + 2 * Plan1D<T, LOGN, 1>::LS + (1 << LOGN)) * sizeof(cpx<T>) <= 160 * 1024;
+}
+template <typename T, int LOGN>
+constexpr size_t mc_lds_bytes() {
+    return (size_t)(table_elems<T, LOGN>() + 2 * Plan1D<T, LOGN, 1>::LS + (mc_tw2_in_lds<T, LOGN>() ? (1 << LOGN) : 0)) *
+           sizeof(cpx<T>);
+}
+// stage tw2 after the two line buffers (a workgroup of 2 TL threads); returns where to read it
+template <typename T, int LOGN>
+__device__ __forceinline__ const cpx<T>* mc_stage_tw2(cpx<T>* lines, const cpx<T>* __restrict__ tw2) {
+    using PL = Plan1D<T, LOGN, 1>;
+    if constexpr (mc_tw2_in_lds<T, LOGN>()) {
+        constexpr int NQ = PL::RMAX / 2;
+        cpx<T>* t2l = lines + 2 * PL::LS;
+        cpx<T> t[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) t[k] = tw2[threadIdx.x + k * 2 * PL::TL];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) t2l[threadIdx.x + k * 2 * PL::TL] = t[k];
+        return t2l;
+    } else {
+        return tw2;
+    }
+}
 
 template <typename T, int LOGN>
 __device__ __forceinline__ const cpx<T>* stage_twiddles(cpx<T>* Wl, const cpx<T>* __restrict__ tw) {
@@ -780,6 +809,15 @@ k_fft_cols_fwd_mc(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, con
     const int r = threadIdx.x / PL::TL, tl = threadIdx.x % PL::TL;
     cpx<T>* line = base + table_elems<T, LOGN>() + r * PL::LS;
     const int col0 = strip_block(sg) * CR;
+    const cpx<T>* T2 = mc_stage_tw2<T, LOGN>(base + table_elems<T, LOGN>(), tw2);
+    // CG direction (steps from the second on): beta from the partial sums first, so that the
+    // column loads below are not held behind their round trip
+    T beta = 0;
+    if (cb.rho_new_part) {
+        double rn, rho;
+        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
+        beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
+    }
     __syncthreads();
     cpx<T> v[CR][PL::RMAX];
 #pragma unroll
@@ -789,10 +827,7 @@ k_fft_cols_fwd_mc(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, con
         for (int cc = 0; cc < CR; ++cc) v[cc][i] = tmp[ro + cc];
     }
     if (cb.rho_new_part) {
-        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt
-        double rn, rho;
-        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
-        const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
+        // F_rows p_new = F_rows r + beta F_rows p, kept in dirt
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) {
             const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
@@ -812,7 +847,7 @@ k_fft_cols_fwd_mc(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, con
     if (r) {
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) {
-            const cpx<T> t = tw2[PL::in_pos(tl, i)];
+            const cpx<T> t = T2[PL::in_pos(tl, i)];
 #pragma unroll
             for (int cc = 0; cc < CR; ++cc) v[cc][i] = v[cc][i] * t;
         }
@@ -847,19 +882,21 @@ k_fft_cols_adj_mc(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, con
     cpx<T>* lines = base + table_elems<T, LOGN>();
     cpx<T>* line = lines + r * PL::LS;
     const int col0 = strip_block(sg) * CR;
+    constexpr int NQ = PL::RMAX / 2;
+    const cpx<T>* T2 = mc_stage_tw2<T, LOGN>(lines, tw2);
     __syncthreads();
+    // The (-1)^k' factor of the input is left out: it shifts each transform by n/2, so the
+    // combine reads position j + n/2 (mod n) of the lines instead.  The loads then have no
+    // use before the transforms and are all in flight together.
+    static_assert(PL::RMAX % 4 == 0, "the n/2 shift is a whole number of combine slots");
     cpx<T> v[CR][PL::RMAX];
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
-        const int kp = PL::in_pos(tl, i);
-        const size_t ro = (size_t)(2 * kp + r) * K + col0;
+        const size_t ro = (size_t)(2 * PL::in_pos(tl, i) + r) * K + col0;
 #pragma unroll
-        for (int cc = 0; cc < CR; ++cc) {
-            const cpx<T> u = grid[ro + cc];
-            v[cc][i] = (kp & 1) ? neg(u) : u;
-        }
+        for (int cc = 0; cc < CR; ++cc) v[cc][i] = grid[ro + cc];
     }
-    cpx<T> res[CR][PL::RMAX / 2];
+    cpx<T> res[CR][NQ];
 #pragma unroll
     for (int cc = 0; cc < CR; ++cc) {
         line_fft<T, LOGN, 1, true>(v[cc], line, tl, W);
@@ -868,14 +905,14 @@ k_fft_cols_adj_mc(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, con
         for (int i = 0; i < PL::RMAX; ++i) line[PL::out_at(tl, i)] = v[cc][i];
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < PL::RMAX / 2; ++q) {
-            const int j = r + 2 * tl + q * 2 * PL::TL, a = PL::at(r + 2 * tl) + PL::span(q * 2 * PL::TL);
-            res[cc][q] = lines[a] + mul_mi(mulc(lines[PL::LS + a], tw2[j]));
+        for (int q = 0; q < NQ; ++q) {
+            const int a = PL::at(r + 2 * tl) + PL::span(((q + NQ / 2) % NQ) * 2 * PL::TL);
+            res[cc][q] = lines[a] + mul_mi(mulc(lines[PL::LS + a], T2[r + 2 * tl + q * 2 * PL::TL]));
         }
         __syncthreads();   // the next column reuses the lines
     }
 #pragma unroll
-    for (int q = 0; q < PL::RMAX / 2; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         const int j = r + 2 * tl + q * 2 * PL::TL;
 #pragma unroll
         for (int cc = 0; cc < CR; ++cc) tmp[(size_t)j * K + col0 + cc] = res[cc][q];
@@ -1028,6 +1065,7 @@ k_fft_cols_toep_mc(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, co
     cpx<T>* lines = base + table_elems<T, LOGN>();
     cpx<T>* line = lines + r * PL::LS;
     const int col0 = strip_block(sg) * CR;
+    const cpx<T>* T2 = mc_stage_tw2<T, LOGN>(lines, tw2);
     __syncthreads();
     cpx<T> v[CR][PL::RMAX];
 #pragma unroll
@@ -1060,7 +1098,7 @@ k_fft_cols_toep_mc(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, co
     if (r) {
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) {
-            const cpx<T> t = tw2[PL::in_pos(tl, i)];
+            const cpx<T> t = T2[PL::in_pos(tl, i)];
 #pragma unroll
             for (int cc = 0; cc < CR; ++cc) v[cc][i] = v[cc][i] * t;
         }
@@ -1090,7 +1128,7 @@ k_fft_cols_toep_mc(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, co
 #pragma unroll
         for (int q = 0; q < PL::RMAX / 2; ++q) {
             const int j = r + 2 * tl + q * 2 * PL::TL, a = PL::at(r + 2 * tl) + PL::span(q * 2 * PL::TL);
-            v[cc][q] = lines[a] + mul_mi(mulc(lines[PL::LS + a], tw2[j]));
+            v[cc][q] = lines[a] + mul_mi(mulc(lines[PL::LS + a], T2[j]));
         }
         __syncthreads();   // the next column reuses the lines
     }
@@ -1217,7 +1255,7 @@ void set_lds_limit(F* f, size_t bytes) {
 }
 
 template <typename T, int LOGN, int AX>
-size_t lds_bytes(int lines) {
+constexpr size_t lds_bytes(int lines) {
     using PL = Plan1D<T, LOGN, AX>;
     return (size_t)(table_elems<T, LOGN>() + lines * PL::LS) * sizeof(cpx<T>);
 }
@@ -1261,7 +1299,7 @@ void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, cpx<T>* dirt,
     const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
     if constexpr (long_cols<T, LOGN>()) {   // long columns: CR columns per thread in registers
         constexpr int CR = long_cols_cr<T>();
-        const size_t lds1 = lds_bytes<T, LOGN, 1>(2);
+        const size_t lds1 = mc_lds_bytes<T, LOGN>();
         // each XCD takes one contiguous range of column groups (sg = 0), so the groups that
         // share 128-byte lines run on one L2 at about the same time (the adjoint 559 -> 506 us
         // at n = 4096 against the gridding-strip order)
@@ -1284,7 +1322,7 @@ void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s
     const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
     if constexpr (long_cols<T, LOGN>()) {
         constexpr int CR = long_cols_cr<T>();
-        const size_t lds1 = lds_bytes<T, LOGN, 1>(2);
+        const size_t lds1 = mc_lds_bytes<T, LOGN>();
         auto f = k_fft_cols_adj_mc<T, LOGN, CR>;
         set_lds_limit(f, lds1);
         hipLaunchKernelGGL(f, dim3(2 * N / CR), dim3(2 * Plan1D<T, LOGN, 1>::TL), lds1, s, grid, tmp,
@@ -1306,7 +1344,7 @@ void cols_toep_impl(const Plan& P, const cpx<T>* in, cpx<T>* out, cpx<T>* dirt, 
         // long FP32 columns: two columns per thread in registers (four, with the spectrum's
         // loads, spilled at the 128-register limit of the 1024-thread workgroup)
         constexpr int CR = 2;
-        const size_t lds1 = lds_bytes<T, LOGN, 1>(2);
+        const size_t lds1 = mc_lds_bytes<T, LOGN>();
         auto f = k_fft_cols_toep_mc<T, LOGN, CR>;
         set_lds_limit(f, lds1);
         hipLaunchKernelGGL(f, dim3(2 * N / CR), dim3(2 * Plan1D<T, LOGN, 1>::TL), lds1, s, in, out,
