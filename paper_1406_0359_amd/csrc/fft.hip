@@ -213,6 +213,7 @@ struct Plan1D {
     // multiple of 8 in padded lines)
     __device__ static __forceinline__ int at(int p) { return PAD ? p + (p >> 3) : p; }
     static constexpr int span(int d) { return PAD ? d + d / 8 : d; }
+    static constexpr int at_c(int p) { return PAD ? p + p / 8 : p; }
     // register slot i on entry holds position in_pos(tl, i); on exit out_pos(tl, i)
     __device__ static __forceinline__ int in_pos(int tl, int i) {
         return tl + (i / R0) * TL + (i % R0) * (N / R0);
@@ -258,7 +259,7 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, cpx<T>* line, int tl, const 
     constexpr int R = Rd::r[P];
     constexpr int NB = PL::RMAX / R;   // butterflies per thread in this pass
     constexpr int NS = P == 0 ? 1 : (P == 1 ? Rd::r[0] : (P == 2 ? Rd::r[0] * Rd::r[1] : Rd::r[0] * Rd::r[1] * Rd::r[2]));
-    static_assert(!PL::PAD || ((N / R) % 8 == 0 && (NS % 8 == 0 || (NS == 1 && R == 8))), "padded lines");
+    static_assert(!PL::PAD || ((N / R) % 8 == 0 && (NS % 8 == 0 || (NS == 1 && R % 8 == 0))), "padded lines");
     if constexpr (P > 0) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -288,7 +289,7 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, cpx<T>* line, int tl, const 
             const int k = j % NS;
             const int o = PL::at((j - k) * R + k);
 #pragma unroll
-            for (int t = 0; t < R; ++t) line[o + t * PL::span(NS)] = v[b * R + t];
+            for (int t = 0; t < R; ++t) line[o + (NS == 1 ? PL::at_c(t) : PL::span(t * NS))] = v[b * R + t];
         }
         __syncthreads();
     }
@@ -365,14 +366,28 @@ constexpr int cols_per_wg() {
 // 4096 and more) run the kernels that keep CR adjacent columns per thread in registers.
 template <typename T, int LOGN>
 constexpr bool long_cols() { return LOGN >= 11 && (cols_per_wg<T, LOGN>() == 1 || twiddles_split<T, LOGN>()); }
-template <typename T>
-constexpr int long_cols_cr() { return sizeof(T) == 8 ? 2 : 4; }
+template <typename T, int LOGN>
+constexpr int long_cols_cr() { return sizeof(T) == 8 || Plan1D<T, LOGN, 1>::RMAX >= 16 ? 2 : 4; }
+// workgroups of a long-column kernel that can share a CU: two of 512 threads or fewer (16
+// waves at up to 128 VGPRs) if their twiddle table and two line buffers fit twice in LDS
+template <typename T, int LOGN>
+constexpr int mc_wgs_per_cu() {
+    constexpr size_t lines = (size_t)(table_elems<T, LOGN>() + 2 * Plan1D<T, LOGN, 1>::LS) * sizeof(cpx<T>);
+    return 2 * Plan1D<T, LOGN, 1>::TL <= 512 && 2 * lines <= 160 * 1024 ? 2 : 1;
+}
 // The long-column kernels keep the n parity twiddles exp(-pi i j / n) in LDS beside their two
 // line buffers where they fit: staged at the start (all loads in flight at once), then read
 // for every column from LDS instead of from global memory once each column's data is in.
 template <typename T, int LOGN>
 constexpr bool mc_tw2_in_lds() {
-    return (size_t)(table_elems<T, LOGN>() + 2 * Plan1D<T, LOGN, 1>::LS + (1 << LOGN)) * sizeof(cpx<T>) <= 160 * 1024;
+    return (size_t)(table_elems<T, LOGN>() + 2 * Plan1D<T, LOGN, 1>::LS + (1 << LOGN)) * sizeof(cpx<T>) <=
+           160 * 1024 / mc_wgs_per_cu<T, LOGN>();
+}
+// waves per SIMD the register allocation of a long-column kernel must allow
+template <typename T, int LOGN>
+constexpr int mc_waves_per_eu() {
+    constexpr int w = mc_wgs_per_cu<T, LOGN>() * 2 * Plan1D<T, LOGN, 1>::TL / 256;
+    return w < 1 ? 1 : w;
 }
 template <typename T, int LOGN>
 constexpr size_t mc_lds_bytes() {
@@ -797,7 +812,7 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
 // one contiguous run of CR elements, and the workgroup transforms the columns one after
 // another through the same two line buffers.
 template <typename T, int LOGN, int CR>
-__global__ void __launch_bounds__((2 * Plan1D<T, LOGN, 1>::TL))
+__global__ void __launch_bounds__((2 * Plan1D<T, LOGN, 1>::TL)) __attribute__((amdgpu_waves_per_eu(mc_waves_per_eu<T, LOGN>())))
 k_fft_cols_fwd_mc(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const cpx<T>* __restrict__ tw,
                   const cpx<T>* __restrict__ tw2, int sg, cpx<T>* __restrict__ dirt, CgBeta cb) {
     using PL = Plan1D<T, LOGN, 1>;
@@ -870,7 +885,7 @@ k_fft_cols_fwd_mc(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, con
 }
 
 template <typename T, int LOGN, int CR>
-__global__ void __launch_bounds__((2 * Plan1D<T, LOGN, 1>::TL))
+__global__ void __launch_bounds__((2 * Plan1D<T, LOGN, 1>::TL)) __attribute__((amdgpu_waves_per_eu(mc_waves_per_eu<T, LOGN>())))
 k_fft_cols_adj_mc(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const cpx<T>* __restrict__ tw,
                   const cpx<T>* __restrict__ tw2, int sg) {
     using PL = Plan1D<T, LOGN, 1>;
@@ -1052,7 +1067,7 @@ k_fft_cols_toep(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const
 // arithmetic as k_fft_cols_toep; a column's adjoint output replaces its input in registers and
 // all CR columns are written at the end (in place is safe: every read precedes every write).
 template <typename T, int LOGN, int CR>
-__global__ void __launch_bounds__((2 * Plan1D<T, LOGN, 1>::TL))
+__global__ void __launch_bounds__((2 * Plan1D<T, LOGN, 1>::TL)) __attribute__((amdgpu_waves_per_eu(mc_waves_per_eu<T, LOGN>())))
 k_fft_cols_toep_mc(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const cpx<T>* __restrict__ tw,
                    const cpx<T>* __restrict__ tw2, int sg, cpx<T>* __restrict__ dirt, CgBeta cb) {
     using PL = Plan1D<T, LOGN, 1>;
@@ -1298,7 +1313,7 @@ void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, cpx<T>* dirt,
     constexpr int N = 1 << LOGN;
     const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
     if constexpr (long_cols<T, LOGN>()) {   // long columns: CR columns per thread in registers
-        constexpr int CR = long_cols_cr<T>();
+        constexpr int CR = long_cols_cr<T, LOGN>();
         const size_t lds1 = mc_lds_bytes<T, LOGN>();
         // each XCD takes one contiguous range of column groups (sg = 0), so the groups that
         // share 128-byte lines run on one L2 at about the same time (the adjoint 559 -> 506 us
@@ -1321,7 +1336,7 @@ void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s
     constexpr int N = 1 << LOGN;
     const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
     if constexpr (long_cols<T, LOGN>()) {
-        constexpr int CR = long_cols_cr<T>();
+        constexpr int CR = long_cols_cr<T, LOGN>();
         const size_t lds1 = mc_lds_bytes<T, LOGN>();
         auto f = k_fft_cols_adj_mc<T, LOGN, CR>;
         set_lds_limit(f, lds1);
