@@ -47,29 +47,29 @@ struct Ops {
         normal_tail(nullptr, q, 1.0, 0.0, nullptr);
     }
     // first CG step: the set-up r = p = x1 + x2 + x3 - q0 (partial ||r||^2 into rho, count
-    // returned) in the row pass, then q = A p, keeping p's row transform in dirt for the
-    // later steps
+    // returned) in the row pass, then q = A p with the partial sums of <p, q>, <r, q> and
+    // ||q||^2 (dots[0..2]) for the next step
     int apply_A_first(const C* x1, const C* x2, const C* x3, const C* q0, C* r, C* p, C* q, double inv_nu2,
-                      double* rho, double* dot) const {
-        const int nb = launch_fft_rows_init<T>(P, x1, x2, x3, q0, r, p, rho, (C*)P.dirt, s);
-        launch_fft_cols_fwd<T>(P, (const C*)P.dirt, (C*)P.grid, s);
+                      double* rho, double* const* dots) const {
+        const int nb = launch_fft_rows_init<T>(P, x1, x2, x3, q0, r, p, rho, (C*)P.tmp, s);
+        launch_fft_cols_fwd<T>(P, (const C*)P.tmp, (C*)P.grid, s);
         launch_gtg<T>(P, (const C*)P.grid, (C*)P.grid2, s);
         launch_fft_cols_adj<T>(P, (const C*)P.grid2, (C*)P.tmp, s);
-        launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, inv_nu2, p, 2.0, dot, s);
+        launch_fft_rows_adj_cg<T>(P, (const C*)P.tmp, q, inv_nu2, p, 2.0, dots[0], r, dots[1], dots[2], s);
         return nb;
     }
     // a later CG step: the row pass applies the previous step's update (x += alpha p,
-    // r -= alpha q, partial ||r||^2 into rho_new) and transforms r; the new direction
-    // p = r + beta p is formed by linearity in the column pass (on the row transforms, kept in
-    // dirt) and in image space by the adjoint row pass, which also gives q = A p and <p, q>.
-    // Returns the count of rho_new's partials.
-    int apply_A_step(C* x, C* r, C* p, C* q, const double* rho, int rho_count, const double* pq, int pq_count,
-                     double* rho_new, double inv_nu2, double* dot) const {
-        const int nr = launch_fft_rows_xr<T>(P, x, r, p, q, rho, rho_count, pq, pq_count, rho_new, (C*)P.tmp, s);
-        launch_fft_cols_fwd_dir<T>(P, (const C*)P.tmp, (C*)P.dirt, rho_new, nr, rho, rho_count, (C*)P.grid, s);
+    // r -= alpha q, p = r + beta p, partial ||r||^2 into rho_new) and transforms the new p;
+    // then q = A p with its dot products, as in the first step.  Returns the count of rho_new's
+    // partials.
+    int apply_A_step(C* x, C* r, C* p, C* q, const double* rho, int rho_count, double* const* dots, int dot_count,
+                     double* rho_new, double inv_nu2) const {
+        const int nr = launch_fft_rows_xr<T>(P, x, r, p, q, rho, rho_count, dots[0], dots[1], dots[2], dot_count,
+                                             rho_new, (C*)P.tmp, s);
+        launch_fft_cols_fwd<T>(P, (const C*)P.tmp, (C*)P.grid, s);
         launch_gtg<T>(P, (const C*)P.grid, (C*)P.grid2, s);
         launch_fft_cols_adj<T>(P, (const C*)P.grid2, (C*)P.tmp, s);
-        launch_fft_rows_adj_dir<T>(P, (const C*)P.tmp, q, inv_nu2, r, p, 2.0, rho_new, nr, rho, rho_count, dot, s);
+        launch_fft_rows_adj_cg<T>(P, (const C*)P.tmp, q, inv_nu2, p, 2.0, dots[0], r, dots[1], dots[2], s);
         return nr;
     }
     // q = c1 T v + c2 v with T the stored (Toeplitz) form of Phi^dag Phi (chat ready)
@@ -78,21 +78,20 @@ struct Ops {
         launch_fft_cols_toep<T>(P, (C*)P.tmp, s);
         launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, c1, v, c2, dot, s, P.unit);
     }
-    // CG with T, as apply_A_first / apply_A_step: first step q = c1 T p + 2 p (p's row
-    // transform kept in dirt), later steps with the previous update folded into the row pass
+    // CG with T, as apply_A_first / apply_A_step: q = c1 T p + 2 p
     int toep_A_first(const C* x1, const C* x2, const C* x3, const C* q0, C* r, C* p, C* q, double c1,
-                     double* rho, double* dot) const {
-        const int nb = launch_fft_rows_init<T>(P, x1, x2, x3, q0, r, p, rho, (C*)P.dirt, s, P.unit);
-        launch_fft_cols_toep<T>(P, (C*)P.tmp, s, (const C*)P.dirt);
-        launch_fft_rows_adj<T>(P, (const C*)P.tmp, q, c1, p, 2.0, dot, s, P.unit);
+                     double* rho, double* const* dots) const {
+        const int nb = launch_fft_rows_init<T>(P, x1, x2, x3, q0, r, p, rho, (C*)P.tmp, s, P.unit);
+        launch_fft_cols_toep<T>(P, (C*)P.tmp, s);
+        launch_fft_rows_adj_cg<T>(P, (const C*)P.tmp, q, c1, p, 2.0, dots[0], r, dots[1], dots[2], s, P.unit);
         return nb;
     }
-    int toep_A_step(C* x, C* r, C* p, C* q, const double* rho, int rho_count, const double* pq, int pq_count,
-                    double* rho_new, double c1, double* dot) const {
-        const int nr = launch_fft_rows_xr<T>(P, x, r, p, q, rho, rho_count, pq, pq_count, rho_new, (C*)P.tmp, s,
-                                             P.unit);
-        launch_fft_cols_toep_dir<T>(P, (C*)P.tmp, (C*)P.dirt, rho_new, nr, rho, rho_count, s);
-        launch_fft_rows_adj_dir<T>(P, (const C*)P.tmp, q, c1, r, p, 2.0, rho_new, nr, rho, rho_count, dot, s, P.unit);
+    int toep_A_step(C* x, C* r, C* p, C* q, const double* rho, int rho_count, double* const* dots, int dot_count,
+                    double* rho_new, double c1) const {
+        const int nr = launch_fft_rows_xr<T>(P, x, r, p, q, rho, rho_count, dots[0], dots[1], dots[2], dot_count,
+                                             rho_new, (C*)P.tmp, s, P.unit);
+        launch_fft_cols_toep<T>(P, (C*)P.tmp, s);
+        launch_fft_rows_adj_cg<T>(P, (const C*)P.tmp, q, c1, p, 2.0, dots[0], r, dots[1], dots[2], s, P.unit);
         return nr;
     }
     // after the row pass of v: q = c1 Phi^dag Phi v + c2 v
@@ -179,19 +178,22 @@ struct Sdmm {
         // x3 - A x_hat (branch i = 3 below); with the stored operator, q = A x_hat was formed
         // at the end of the previous iteration (or by enqueue_prologue) beside branch i = 1.
         // rho of step c (the residual norm before step c's update) is in buffer c & 1,
-        // <p, A p> in buffer 2
+        // <p, A p> in buffer 2, <r, A p> and ||A p||^2 in buffers 8 and 9
         // step 0: the set-up r = p = x1 + x2 + x3 (- q) folded into its row pass, then q = A p;
-        // step c > 0: step c - 1's update folded into the row pass, the new direction formed
-        // in the column and adjoint row passes (Ops::apply_A_step); then the last step's update
-        int rho_count = toep ? op.toep_A_first(x1, x2, x3, q, r, p, q, inv_nu2, part(0), part(2))
-                             : op.apply_A_first(x1, x2, x3, nullptr, r, p, q, inv_nu2, part(0), part(2));
+        // step c > 0: step c - 1's update and the new direction p = r + beta p folded into the
+        // row pass (beta from ||r - alpha q||^2 expanded in those dot products, so it is known
+        // before the new residual is summed), then q = A p (Ops::apply_A_step); then the last
+        // step's update
+        double* const dots[3] = {part(2), part(8), part(9)};   // <p, q>, <r, q>, ||q||^2
+        int rho_count = toep ? op.toep_A_first(x1, x2, x3, q, r, p, q, inv_nu2, part(0), dots)
+                             : op.apply_A_first(x1, x2, x3, nullptr, r, p, q, inv_nu2, part(0), dots);
         for (int c = 1; c < prm->cg_iter; ++c) {
             if (toep)
-                rho_count = op.toep_A_step(xh, r, p, q, part((c - 1) & 1), rho_count, part(2), rows_blocks,
-                                           part(c & 1), inv_nu2, part(2));
+                rho_count = op.toep_A_step(xh, r, p, q, part((c - 1) & 1), rho_count, dots, rows_blocks, part(c & 1),
+                                           inv_nu2);
             else
-                rho_count = op.apply_A_step(xh, r, p, q, part((c - 1) & 1), rho_count, part(2), rows_blocks,
-                                            part(c & 1), inv_nu2, part(2));
+                rho_count = op.apply_A_step(xh, r, p, q, part((c - 1) & 1), rho_count, dots, rows_blocks, part(c & 1),
+                                            inv_nu2);
         }
         const int cl = prm->cg_iter;
         // i = 1 (on s2): l1 prior on Psi^dag x_hat.  With the NUFFT operator branch i = 1 is

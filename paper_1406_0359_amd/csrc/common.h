@@ -85,7 +85,7 @@ constexpr int MAX_BLOCKS = 1024;
 constexpr int BLK_CHUNKS = 4096 + MAX_BLOCKS;
 constexpr int GRID_UNIT = 1024;      // smallest gridding work unit (visibility passes)
 constexpr int GRID_REC = 16;         // ints per gridding work-unit record
-constexpr int NUM_PARTIAL_BUFS = 8;
+constexpr int NUM_PARTIAL_BUFS = 10;
 
 // ---------------------------------------------------------------------------------------
 // Plan: host handle with device pointers into the caller's workspace.
@@ -142,7 +142,6 @@ struct Plan {
     void* grid = nullptr;        // K x K complex, row-major G[k1][k2]
     void* grid2 = nullptr;       // K x K complex: G^T G output of the normal operator
     void* tmp = nullptr;         // n x K complex, layout [j1][k2]
-    void* dirt = nullptr;        // n x K complex: row transform of the CG direction p
     void* unit = nullptr;        // n reals, all 1 (row passes without S)
     void* chat = nullptr;        // K x K reals: spectrum of the stored normal operator, / K^2
     bool chat_ready = false;     // chat computed (on the first call that needs it)
@@ -185,29 +184,24 @@ template <typename T> int launch_fft_rows_init(const Plan& P, const cpx<T>* x1, 
                                                const cpx<T>* x3, const cpx<T>* q0, cpx<T>* r, cpx<T>* p,
                                                double* rho_part, cpx<T>* tmp, hipStream_t s,
                                                const void* deap = nullptr);
-// CG step from the second on, exact operator: row pass with alpha = rho / <p, q> (partials),
-// x += alpha p, r -= alpha q, partial ||r||^2 per row block (returns their count), row transform
-// of r into tmp
-template <typename T> int launch_fft_rows_xr(const Plan& P, cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q,
-                                             const double* rho_part, int rho_count, const double* pq_part, int pq_count,
+// CG step from the second on (exact or stored operator): row pass with alpha = rho / <p, q>,
+// x += alpha p, r -= alpha q, beta = (rho - 2 alpha <r, q> + alpha^2 ||q||^2) / rho,
+// p = r + beta p (partial sums of rho, <p, q>, <r, q>, ||q||^2 given; the last three dot_count
+// of them), partial ||r||^2 per row block (returns their count), row transform of p into tmp
+template <typename T> int launch_fft_rows_xr(const Plan& P, cpx<T>* x, cpx<T>* r, cpx<T>* p, const cpx<T>* q,
+                                             const double* rho_part, int rho_count, const double* pq_part,
+                                             const double* rq_part, const double* qq_part, int dot_count,
                                              double* rho_new_part, cpx<T>* tmp, hipStream_t s,
                                              const void* deap = nullptr);
-// column pass of that step: dirt <- tmp + beta dirt (beta = rho_new / rho), transform of dirt
-template <typename T> void launch_fft_cols_fwd_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* dirt,
-                                                   const double* rho_new_part, int rho_new_count,
-                                                   const double* rho_part, int rho_count, cpx<T>* grid, hipStream_t s);
-// adjoint row pass of that step: p <- r + beta p, x = c1 (S Z^T F^dag rows)(tmp) + c2 p, partial <p, x>
-template <typename T> void launch_fft_rows_adj_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1,
-                                                   const cpx<T>* r, cpx<T>* p, double c2, const double* rho_new_part,
-                                                   int rho_new_count, const double* rho_part, int rho_count,
-                                                   double* dot_part, hipStream_t s, const void* deap = nullptr);
+// adjoint row pass of a CG step: q = c1 (S Z^T F^dag rows)(tmp) + c2 p, partials <p, q>, <r, q>
+// and ||q||^2 per row block
+template <typename T> void launch_fft_rows_adj_cg(const Plan& P, const cpx<T>* tmp, cpx<T>* q, double c1,
+                                                  const cpx<T>* p, double c2, double* pq_part, const cpx<T>* r,
+                                                  double* rq_part, double* qq_part, hipStream_t s,
+                                                  const void* deap = nullptr);
 // column stage of the stored normal operator: forward transform, times chat, adjoint, into tmp
 // (input `in`, default tmp itself)
 template <typename T> void launch_fft_cols_toep(const Plan& P, cpx<T>* tmp, hipStream_t s, const cpx<T>* in = nullptr);
-// the same for a CG step from the second on: dirt <- tmp + beta dirt is the transformed input
-template <typename T> void launch_fft_cols_toep_dir(const Plan& P, cpx<T>* tmp, cpx<T>* dirt, const double* rho_new_part,
-                                                    int rho_new_count, const double* rho_part, int rho_count,
-                                                    hipStream_t s);
 // x = c1 * (S Z^T F^dag rows)(tmp) + c2 * v   (v may be null); optional partial Re<v, x>
 template <typename T> void launch_fft_rows_adj(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1,
                                                const cpx<T>* v, double c2, double* dot_part,

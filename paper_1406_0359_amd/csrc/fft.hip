@@ -486,30 +486,63 @@ __device__ __forceinline__ double block_sum_dyn(double v, double* red) {
     return t;
 }
 
-// Conjugate-gradient step folded into the row pass (used from the second step on):
-// alpha = rho / <p, q> from the partial sums; x += alpha p; r -= alpha q (written back); the
-// row transform is taken of the new r, and the partial ||r||^2 of the row block is written.
-// The new direction's transform F_rows(r + beta p) = F_rows(r) + beta F_rows(p) is formed by
-// the column pass (linearity), and p itself by the adjoint row pass.
+// Block sums of three values per thread (results in thread 0), any block size up to 1024;
+// red holds 48 doubles.
+__device__ __forceinline__ void block_sum3_dyn(double a, double b, double c, double* red, double& ta, double& tb,
+                                               double& tc) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+        c += __shfl_xor(c, o);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[w] = a;
+        red[16 + w] = b;
+        red[32 + w] = c;
+    }
+    __syncthreads();
+    ta = tb = tc = 0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) {
+            ta += red[i];
+            tb += red[16 + i];
+            tc += red[32 + i];
+        }
+    }
+}
+
+// Conjugate-gradient step folded into the row pass (used from the second step on), with the
+// previous step's q = A p and the partial sums of rho = ||r||^2, <p, q>, <r, q> and ||q||^2:
+// alpha = rho / <p, q>; x += alpha p; r -= alpha q; the new rho, ||r - alpha q||^2 =
+// rho - 2 alpha <r, q> + alpha^2 ||q||^2, gives beta = rho_new / rho before any new residual is
+// summed, so the new direction p = r + beta p is formed here too.  x, r and p are written back,
+// the row transform is taken of the new p, and the partial ||r||^2 of the row block is written
+// (the next step's rho, summed exactly).
 template <typename T>
 struct CgXr {
     cpx<T>* x = nullptr;
     cpx<T>* r = nullptr;
-    const cpx<T>* p = nullptr;
+    cpx<T>* p = nullptr;
     const cpx<T>* q = nullptr;
     const double* rho_part = nullptr;
     int rho_count = 0;
     const double* pq_part = nullptr;
-    int pq_count = 0;
+    int pq_count = 0;               // also the count of rq_part and qq_part
+    const double* rq_part = nullptr;
+    const double* qq_part = nullptr;
     double* rho_new_part = nullptr;
 };
 
-// beta = rho_new / rho (0 when rho == 0) from two partial-sum buffers
-struct CgBeta {
-    const double* rho_new_part = nullptr;   // null: no direction update
-    int rho_new_count = 0;
-    const double* rho_part = nullptr;
-    int rho_count = 0;
+// Dot products of the adjoint row pass of a CG step besides <p, q>: <r, q> and ||q||^2 (the
+// next row pass's beta)
+template <typename T>
+struct CgDots {
+    const cpx<T>* r = nullptr;      // null: none
+    double* rq_part = nullptr;
+    double* qq_part = nullptr;
 };
 
 // A row's K outputs after its two parity transforms: position 2k' + r holds (-1)^k' i^r
@@ -664,7 +697,7 @@ k_fft_rows_init(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<
 }
 
 // rows pass of a CG step from the second on (see CgXr): loads x, r, p, q of the row, then
-// the partial sums; updates x and r, transforms the new r.
+// the partial sums; updates x, r and p, transforms the new p.
 template <typename T, int LOGN, int B>
 __global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN, 0>::TL))
 k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>* __restrict__ tw,
@@ -703,15 +736,19 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
             t2[i] = r ? tw2[p] : mk<T>(1, 0);
         }
     }
-    double rho, pq;
+    double rho, pq, rq, qq;
     sum_parts2_dyn(cg.rho_part, cg.rho_count, cg.pq_part, cg.pq_count, red, rho, pq);
-    const T alpha = (T)(rho == 0.0 ? 0.0 : rho / pq);
+    sum_parts2_dyn(cg.rq_part, cg.pq_count, cg.qq_part, cg.pq_count, red, rq, qq);
+    const double al = rho == 0.0 ? 0.0 : rho / pq;
+    const double rn = rho - 2.0 * al * rq + al * al * qq;
+    const T alpha = (T)al, beta = (T)(rho == 0.0 || !(rn > 0.0) ? 0.0 : rn / rho);
     double acc = 0;
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
         xv[i] = xv[i] + alpha * pv[i];
         rv[i] = rv[i] - alpha * qv[i];
         acc += (double)rv[i].x * rv[i].x + (double)rv[i].y * rv[i].y;
+        pv[i] = rv[i] + beta * pv[i];
     }
     // both parity groups hold the whole row; group 0 writes it back once all have read it
     __syncthreads();
@@ -721,6 +758,7 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
             const int p = PL::in_pos(tl, i);
             cg.x[ro + p] = xv[i];
             cg.r[ro + p] = rv[i];
+            cg.p[ro + p] = pv[i];
         }
     }
     const double tot = block_sum_dyn(r == 0 ? acc : 0.0, red);
@@ -730,28 +768,27 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
         const int p = PL::in_pos(tl, i);
         cpx<T> a;
         if constexpr (PRE) {
-            a = (srow * dq[i]) * rv[i];
+            a = (srow * dq[i]) * pv[i];
             if (r) a = a * t2[i];
         } else {
-            a = (srow * deap[p]) * rv[i];
+            a = (srow * deap[p]) * pv[i];
             if (r) a = a * tw2[p];
         }
-        rv[i] = a;
+        pv[i] = a;
     }
-    line_fft<T, LOGN, 0, false>(rv, line, tl, W);
-    store_row_fwd<T, LOGN>(rv, line - r * PL::LS, outr, tl, r);
+    line_fft<T, LOGN, 0, false>(pv, line, tl, W);
+    store_row_fwd<T, LOGN>(pv, line - r * PL::LS, outr, tl, r);
 }
 
 // cols_fwd: thread (c, r, tl) with c fastest (coalesced runs of C columns)
 template <typename T, int LOGN, int C>
 __global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN, 1>::TL))
 k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const cpx<T>* __restrict__ tw,
-               const cpx<T>* __restrict__ tw2, int sg, cpx<T>* __restrict__ dirt, CgBeta cb) {
+               const cpx<T>* __restrict__ tw2, int sg) {
     using PL = Plan1D<T, LOGN, 1>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[32];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int c = threadIdx.x % C, r = (threadIdx.x / C) & 1, tl = threadIdx.x / (2 * C);
     cpx<T>* line = base + table_elems<T, LOGN>() + (2 * c + r) * PL::LS;
@@ -765,29 +802,6 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
     if constexpr (PRE) {
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) t2[i] = r ? tw2[PL::in_pos(tl, i)] : mk<T>(1, 0);
-    }
-    if (cb.rho_new_part) {
-        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt for the next step.
-        // Short lines: F_rows p is loaded before the partial sums are read (both in flight);
-        // long lines read it after (registers).
-        cpx<T> d[PRE ? PL::RMAX : 1];
-        if constexpr (PRE) {
-#pragma unroll
-            for (int i = 0; i < PL::RMAX; ++i) d[i] = dirt[(size_t)PL::in_pos(tl, i) * K + col];
-        }
-        double rn, rho;
-        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
-        const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
-#pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) {
-            if constexpr (PRE) v[i] = v[i] + beta * d[i];
-            else v[i] = v[i] + beta * dirt[(size_t)PL::in_pos(tl, i) * K + col];
-        }
-        __syncthreads();   // both parity groups have read dirt
-        if (r == 0) {
-#pragma unroll
-            for (int i = 0; i < PL::RMAX; ++i) dirt[(size_t)PL::in_pos(tl, i) * K + col] = v[i];
-        }
     }
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
@@ -814,25 +828,16 @@ k_fft_cols_fwd(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const 
 template <typename T, int LOGN, int CR>
 __global__ void __launch_bounds__((2 * Plan1D<T, LOGN, 1>::TL)) __attribute__((amdgpu_waves_per_eu(mc_waves_per_eu<T, LOGN>())))
 k_fft_cols_fwd_mc(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, const cpx<T>* __restrict__ tw,
-                  const cpx<T>* __restrict__ tw2, int sg, cpx<T>* __restrict__ dirt, CgBeta cb) {
+                  const cpx<T>* __restrict__ tw2, int sg) {
     using PL = Plan1D<T, LOGN, 1>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[32];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int r = threadIdx.x / PL::TL, tl = threadIdx.x % PL::TL;
     cpx<T>* line = base + table_elems<T, LOGN>() + r * PL::LS;
     const int col0 = strip_block(sg) * CR;
     const cpx<T>* T2 = mc_stage_tw2<T, LOGN>(base + table_elems<T, LOGN>(), tw2);
-    // CG direction (steps from the second on): beta from the partial sums first, so that the
-    // column loads below are not held behind their round trip
-    T beta = 0;
-    if (cb.rho_new_part) {
-        double rn, rho;
-        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
-        beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
-    }
     __syncthreads();
     cpx<T> v[CR][PL::RMAX];
 #pragma unroll
@@ -840,24 +845,6 @@ k_fft_cols_fwd_mc(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ grid, con
         const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
 #pragma unroll
         for (int cc = 0; cc < CR; ++cc) v[cc][i] = tmp[ro + cc];
-    }
-    if (cb.rho_new_part) {
-        // F_rows p_new = F_rows r + beta F_rows p, kept in dirt
-#pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) {
-            const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
-#pragma unroll
-            for (int cc = 0; cc < CR; ++cc) v[cc][i] = v[cc][i] + beta * dirt[ro + cc];
-        }
-        __syncthreads();   // both parity groups have read dirt
-        if (r == 0) {
-#pragma unroll
-            for (int i = 0; i < PL::RMAX; ++i) {
-                const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
-#pragma unroll
-                for (int cc = 0; cc < CR; ++cc) dirt[ro + cc] = v[cc][i];
-            }
-        }
     }
     if (r) {
 #pragma unroll
@@ -989,12 +976,11 @@ k_fft_cols_adj(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ tmp, const 
 template <typename T, int LOGN, int C>
 __global__ void __launch_bounds__((2 * C * Plan1D<T, LOGN, 1>::TL))
 k_fft_cols_toep(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const cpx<T>* __restrict__ tw,
-                const cpx<T>* __restrict__ tw2, int sg, cpx<T>* __restrict__ dirt, CgBeta cb) {
+                const cpx<T>* __restrict__ tw2, int sg) {
     using PL = Plan1D<T, LOGN, 1>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[32];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int c = threadIdx.x % C, r = (threadIdx.x / C) & 1, tl = threadIdx.x / (2 * C);
     cpx<T>* lines = base + table_elems<T, LOGN>();
@@ -1004,29 +990,6 @@ k_fft_cols_toep(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const
     cpx<T> v[PL::RMAX];
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) v[i] = in[(size_t)PL::in_pos(tl, i) * K + col];
-    if (cb.rho_new_part) {
-        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt (short lines:
-        // F_rows p loaded before the partial sums are read, as in k_fft_cols_fwd)
-        constexpr bool PRE = PL::RMAX <= 8 && 2 * C * PL::TL <= 512;   // register budget
-        cpx<T> d[PRE ? PL::RMAX : 1];
-        if constexpr (PRE) {
-#pragma unroll
-            for (int i = 0; i < PL::RMAX; ++i) d[i] = dirt[(size_t)PL::in_pos(tl, i) * K + col];
-        }
-        double rn, rho;
-        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
-        const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
-#pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) {
-            if constexpr (PRE) v[i] = v[i] + beta * d[i];
-            else v[i] = v[i] + beta * dirt[(size_t)PL::in_pos(tl, i) * K + col];
-        }
-        __syncthreads();   // both parity groups have read dirt
-        if (r == 0) {
-#pragma unroll
-            for (int i = 0; i < PL::RMAX; ++i) dirt[(size_t)PL::in_pos(tl, i) * K + col] = v[i];
-        }
-    }
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
         if (r) v[i] = v[i] * tw2[PL::in_pos(tl, i)];
@@ -1069,12 +1032,11 @@ k_fft_cols_toep(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const
 template <typename T, int LOGN, int CR>
 __global__ void __launch_bounds__((2 * Plan1D<T, LOGN, 1>::TL)) __attribute__((amdgpu_waves_per_eu(mc_waves_per_eu<T, LOGN>())))
 k_fft_cols_toep_mc(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, const cpx<T>* __restrict__ tw,
-                   const cpx<T>* __restrict__ tw2, int sg, cpx<T>* __restrict__ dirt, CgBeta cb) {
+                   const cpx<T>* __restrict__ tw2, int sg) {
     using PL = Plan1D<T, LOGN, 1>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[32];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int r = threadIdx.x / PL::TL, tl = threadIdx.x % PL::TL;
     cpx<T>* lines = base + table_elems<T, LOGN>();
@@ -1088,27 +1050,6 @@ k_fft_cols_toep_mc(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, co
         const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
 #pragma unroll
         for (int cc = 0; cc < CR; ++cc) v[cc][i] = in[ro + cc];
-    }
-    if (cb.rho_new_part) {
-        // CG direction: F_rows p_new = F_rows r + beta F_rows p, kept in dirt
-        double rn, rho;
-        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
-        const T beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
-#pragma unroll
-        for (int i = 0; i < PL::RMAX; ++i) {
-            const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
-#pragma unroll
-            for (int cc = 0; cc < CR; ++cc) v[cc][i] = v[cc][i] + beta * dirt[ro + cc];
-        }
-        __syncthreads();   // both parity groups have read dirt
-        if (r == 0) {
-#pragma unroll
-            for (int i = 0; i < PL::RMAX; ++i) {
-                const size_t ro = (size_t)PL::in_pos(tl, i) * K + col0;
-#pragma unroll
-                for (int cc = 0; cc < CR; ++cc) dirt[ro + cc] = v[cc][i];
-            }
-        }
     }
     if (r) {
 #pragma unroll
@@ -1161,13 +1102,12 @@ template <typename T, int LOGN, int B>
 __global__ void __launch_bounds__((2 * B * Plan1D<T, LOGN, 0>::TL))
 k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* __restrict__ deap,
                const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ tw2, T c1,
-               cpx<T>* __restrict__ vin, T c2, double* __restrict__ dot_part, const cpx<T>* __restrict__ rin,
-               CgBeta cb) {
+               const cpx<T>* __restrict__ vin, T c2, double* __restrict__ dot_part, CgDots<T> dots) {
     using PL = Plan1D<T, LOGN, 0>;
     constexpr int N = PL::N, K = 2 * N;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* base = reinterpret_cast<cpx<T>*>(smem_raw);
-    __shared__ double red[32];
+    __shared__ double red[48];
     const cpx<T>* W = stage_twiddles<T, LOGN>(base, tw);
     const int r = threadIdx.x & 1, tl = (threadIdx.x >> 1) % PL::TL, lr = threadIdx.x / (2 * PL::TL);
     cpx<T>* lines = base + table_elems<T, LOGN>() + (2 * lr) * PL::LS;
@@ -1182,9 +1122,9 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
         const cpx<T> u = inr[2 * kp + r];
         v[i] = (kp & 1) ? neg(u) : u;
     }
-    // The epilogue's operands (v, and r of the CG direction update) and beta are read before
-    // the transform, so their loads and the partial sums overlap the input's (short lines;
-    // long lines read the operands in the epilogue).
+    // The epilogue's operands (v, and r of the CG dot products) are read before the
+    // transform, so their loads overlap the input's (short lines; long lines read them in the
+    // epilogue).
     constexpr int NQ = PL::RMAX / 2;
     constexpr bool PRE = PL::RMAX <= 8 && 2 * B * PL::TL <= 512;   // register budget
     cpx<T> pv[PRE ? NQ : 1], pr[PRE ? NQ : 1], tj[PRE ? NQ : 1];
@@ -1195,17 +1135,10 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
             const int j = r + 2 * tl + q * 2 * PL::TL;
             const size_t off = (size_t)row * N + j;
             if (vin) pv[q] = vin[off];
-            if (rin) pr[q] = rin[off];
+            if (dots.r) pr[q] = dots.r[off];
             tj[q] = tw2[j];
             dj[q] = deap[j];
         }
-    }
-    // CG direction update (with rin): v = r + beta v, written back to v
-    T beta = 0;
-    if (rin) {
-        double rn, rho;
-        sum_parts2_dyn(cb.rho_new_part, cb.rho_new_count, cb.rho_part, cb.rho_count, red, rn, rho);
-        beta = (T)(rho == 0.0 ? 0.0 : rn / rho);
     }
     line_fft<T, LOGN, 0, true>(v, line, tl, W);
     __syncthreads();
@@ -1213,7 +1146,7 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
     for (int i = 0; i < PL::RMAX; ++i) line[PL::out_at(tl, i)] = v[i];
     __syncthreads();
     const T srow = c1 * deap[row];
-    double acc = 0.0;
+    double acc = 0.0, arq = 0.0, aqq = 0.0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int j = r + 2 * tl + q * 2 * PL::TL, a = PL::at(r + 2 * tl) + PL::span(q * 2 * PL::TL);
@@ -1230,17 +1163,27 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
             cpx<T> vv;
             if constexpr (PRE) vv = pv[q];
             else vv = vin[off];
-            if (rin) {
-                if constexpr (PRE) vv = pr[q] + beta * vv;
-                else vv = rin[off] + beta * vv;
-                vin[off] = vv;
-            }
             o = o + c2 * vv;
             acc += (double)vv.x * (double)o.x + (double)vv.y * (double)o.y;
         }
+        if (dots.r) {
+            cpx<T> rr;
+            if constexpr (PRE) rr = pr[q];
+            else rr = dots.r[off];
+            arq += (double)rr.x * (double)o.x + (double)rr.y * (double)o.y;
+            aqq += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+        }
         x[off] = o;
     }
-    if (dot_part) {
+    if (dots.r) {
+        double t0, t1, t2;
+        block_sum3_dyn(acc, arq, aqq, red, t0, t1, t2);
+        if (threadIdx.x == 0) {
+            dot_part[blockIdx.x] = t0;
+            dots.rq_part[blockIdx.x] = t1;
+            dots.qq_part[blockIdx.x] = t2;
+        }
+    } else if (dot_part) {
         const double tot = block_sum_dyn(acc, red);
         if (threadIdx.x == 0) dot_part[blockIdx.x] = tot;
     }
@@ -1307,7 +1250,7 @@ void rows_init_impl(const Plan& P, cpx<T>* tmp, CgInit<T> ci, const T* deap, hip
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, tmp, deap, (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, ci);
 }
 template <typename T, int LOGN>
-void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, cpx<T>* dirt, CgBeta cb, hipStream_t s) {
+void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
     constexpr int C = cols_per_wg<T, LOGN>();
     constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
@@ -1321,13 +1264,13 @@ void cols_fwd_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, cpx<T>* dirt,
         auto f = k_fft_cols_fwd_mc<T, LOGN, CR>;
         set_lds_limit(f, lds1);
         hipLaunchKernelGGL(f, dim3(2 * N / CR), dim3(2 * Plan1D<T, LOGN, 1>::TL), lds1, s, tmp, grid,
-                           (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, 0, dirt, cb);
+                           (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, 0);
         return;
     }
     auto f = k_fft_cols_fwd<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, tmp, grid, (const cpx<T>*)P.tw,
-                       (const cpx<T>*)P.tw2, strip_groups(P, C), dirt, cb);
+                       (const cpx<T>*)P.tw2, strip_groups(P, C));
 }
 template <typename T, int LOGN>
 void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s) {
@@ -1350,7 +1293,7 @@ void cols_adj_impl(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s
                        (const cpx<T>*)P.tw2, strip_groups(P, C));
 }
 template <typename T, int LOGN>
-void cols_toep_impl(const Plan& P, const cpx<T>* in, cpx<T>* out, cpx<T>* dirt, CgBeta cb, hipStream_t s) {
+void cols_toep_impl(const Plan& P, const cpx<T>* in, cpx<T>* out, hipStream_t s) {
     constexpr int C = cols_per_wg<T, LOGN>();
     constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
@@ -1363,17 +1306,17 @@ void cols_toep_impl(const Plan& P, const cpx<T>* in, cpx<T>* out, cpx<T>* dirt, 
         auto f = k_fft_cols_toep_mc<T, LOGN, CR>;
         set_lds_limit(f, lds1);
         hipLaunchKernelGGL(f, dim3(2 * N / CR), dim3(2 * Plan1D<T, LOGN, 1>::TL), lds1, s, in, out,
-                           (const T*)P.chat, (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, 0, dirt, cb);
+                           (const T*)P.chat, (const cpx<T>*)P.tw, (const cpx<T>*)P.tw2, 0);
         return;
     }
     auto f = k_fft_cols_toep<T, LOGN, C>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(2 * N / C), dim3(NT), lds, s, in, out, (const T*)P.chat, (const cpx<T>*)P.tw,
-                       (const cpx<T>*)P.tw2, strip_groups(P, C), dirt, cb);
+                       (const cpx<T>*)P.tw2, strip_groups(P, C));
 }
 template <typename T, int LOGN>
-void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, cpx<T>* v,
-                   double c2, double* dot_part, const T* deap, const cpx<T>* rin, CgBeta cb, hipStream_t s) {
+void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* v,
+                   double c2, double* dot_part, const T* deap, CgDots<T> dots, hipStream_t s) {
     constexpr int B = rows_per_wg<T, LOGN>();
     constexpr int NT = 2 * B * Plan1D<T, LOGN, 0>::TL;
     constexpr int N = 1 << LOGN;
@@ -1381,7 +1324,7 @@ void rows_adj_impl(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, cpx<T
     auto f = k_fft_rows_adj<T, LOGN, B>;
     set_lds_limit(f, lds);
     hipLaunchKernelGGL(f, dim3(N / B), dim3(NT), lds, s, tmp, x, deap, (const cpx<T>*)P.tw,
-                       (const cpx<T>*)P.tw2, (T)c1, v, (T)c2, dot_part, rin, cb);
+                       (const cpx<T>*)P.tw2, (T)c1, v, (T)c2, dot_part, dots);
 }
 
 int ilog2(int n) {
@@ -1429,12 +1372,12 @@ int launch_fft_rows_init(const Plan& P, const cpx<T>* x1, const cpx<T>* x2, cons
 }
 template <typename T>
 void launch_fft_cols_fwd(const Plan& P, const cpx<T>* tmp, cpx<T>* grid, hipStream_t s) {
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_fwd_impl<T, L_>(P, tmp, grid, nullptr, CgBeta{}, s)));
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_fwd_impl<T, L_>(P, tmp, grid, s)));
 }
 template <typename T>
-int launch_fft_rows_xr(const Plan& P, cpx<T>* x, cpx<T>* r, const cpx<T>* p, const cpx<T>* q, const double* rho_part,
-                       int rho_count, const double* pq_part, int pq_count, double* rho_new_part, cpx<T>* tmp,
-                       hipStream_t s, const void* deap) {
+int launch_fft_rows_xr(const Plan& P, cpx<T>* x, cpx<T>* r, cpx<T>* p, const cpx<T>* q, const double* rho_part,
+                       int rho_count, const double* pq_part, const double* rq_part, const double* qq_part,
+                       int dot_count, double* rho_new_part, cpx<T>* tmp, hipStream_t s, const void* deap) {
     const T* dp = (const T*)(deap ? deap : P.deap);
     CgXr<T> cg;
     cg.x = x;
@@ -1444,33 +1387,24 @@ int launch_fft_rows_xr(const Plan& P, cpx<T>* x, cpx<T>* r, const cpx<T>* p, con
     cg.rho_part = rho_part;
     cg.rho_count = rho_count;
     cg.pq_part = pq_part;
-    cg.pq_count = pq_count;
+    cg.pq_count = dot_count;
+    cg.rq_part = rq_part;
+    cg.qq_part = qq_part;
     cg.rho_new_part = rho_new_part;
     int blocks = 0;
     PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_xr_impl<T, L_>(P, tmp, cg, dp, s), blocks = (1 << L_) / rows_per_wg<T, L_>()));
     return blocks;
 }
 template <typename T>
-void launch_fft_cols_fwd_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* dirt, const double* rho_new_part,
-                             int rho_new_count, const double* rho_part, int rho_count, cpx<T>* grid, hipStream_t s) {
-    CgBeta cb;
-    cb.rho_new_part = rho_new_part;
-    cb.rho_new_count = rho_new_count;
-    cb.rho_part = rho_part;
-    cb.rho_count = rho_count;
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_fwd_impl<T, L_>(P, tmp, grid, dirt, cb, s)));
-}
-template <typename T>
-void launch_fft_rows_adj_dir(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* r, cpx<T>* p,
-                             double c2, const double* rho_new_part, int rho_new_count, const double* rho_part,
-                             int rho_count, double* dot_part, hipStream_t s, const void* deap) {
+void launch_fft_rows_adj_cg(const Plan& P, const cpx<T>* tmp, cpx<T>* q, double c1, const cpx<T>* p, double c2,
+                            double* pq_part, const cpx<T>* r, double* rq_part, double* qq_part, hipStream_t s,
+                            const void* deap) {
     const T* dp = (const T*)(deap ? deap : P.deap);
-    CgBeta cb;
-    cb.rho_new_part = rho_new_part;
-    cb.rho_new_count = rho_new_count;
-    cb.rho_part = rho_part;
-    cb.rho_count = rho_count;
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, x, c1, p, c2, dot_part, dp, r, cb, s)));
+    CgDots<T> dots;
+    dots.r = r;
+    dots.rq_part = rq_part;
+    dots.qq_part = qq_part;
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, q, c1, p, c2, pq_part, dp, dots, s)));
 }
 template <typename T>
 void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStream_t s) {
@@ -1478,24 +1412,13 @@ void launch_fft_cols_adj(const Plan& P, const cpx<T>* grid, cpx<T>* tmp, hipStre
 }
 template <typename T>
 void launch_fft_cols_toep(const Plan& P, cpx<T>* tmp, hipStream_t s, const cpx<T>* in) {
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_toep_impl<T, L_>(P, in ? in : tmp, tmp, nullptr, CgBeta{}, s)));
-}
-template <typename T>
-void launch_fft_cols_toep_dir(const Plan& P, cpx<T>* tmp, cpx<T>* dirt, const double* rho_new_part, int rho_new_count,
-                              const double* rho_part, int rho_count, hipStream_t s) {
-    CgBeta cb;
-    cb.rho_new_part = rho_new_part;
-    cb.rho_new_count = rho_new_count;
-    cb.rho_part = rho_part;
-    cb.rho_count = rho_count;
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_toep_impl<T, L_>(P, tmp, tmp, dirt, cb, s)));
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (cols_toep_impl<T, L_>(P, in ? in : tmp, tmp, s)));
 }
 template <typename T>
 void launch_fft_rows_adj(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1, const cpx<T>* v,
                          double c2, double* dot_part, hipStream_t s, const void* deap) {
     const T* dp = (const T*)(deap ? deap : P.deap);
-    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, x, c1, const_cast<cpx<T>*>(v), c2, dot_part, dp,
-                                                          nullptr, CgBeta{}, s)));
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, x, c1, v, c2, dot_part, dp, CgDots<T>{}, s)));
 }
 template <typename T>
 int fft_rows_adj_blocks(const Plan& P) {
@@ -1516,28 +1439,20 @@ template void launch_fft_cols_fwd<float>(const Plan&, const cpx<float>*, cpx<flo
 template void launch_fft_cols_fwd<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
 template void launch_fft_cols_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, hipStream_t);
 template void launch_fft_cols_adj<double>(const Plan&, const cpx<double>*, cpx<double>*, hipStream_t);
-template int launch_fft_rows_xr<float>(const Plan&, cpx<float>*, cpx<float>*, const cpx<float>*, const cpx<float>*,
-                                       const double*, int, const double*, int, double*, cpx<float>*, hipStream_t,
-                                       const void*);
-template int launch_fft_rows_xr<double>(const Plan&, cpx<double>*, cpx<double>*, const cpx<double>*, const cpx<double>*,
-                                        const double*, int, const double*, int, double*, cpx<double>*, hipStream_t,
-                                        const void*);
-template void launch_fft_cols_fwd_dir<float>(const Plan&, const cpx<float>*, cpx<float>*, const double*, int,
-                                             const double*, int, cpx<float>*, hipStream_t);
-template void launch_fft_cols_fwd_dir<double>(const Plan&, const cpx<double>*, cpx<double>*, const double*, int,
-                                              const double*, int, cpx<double>*, hipStream_t);
-template void launch_fft_rows_adj_dir<float>(const Plan&, const cpx<float>*, cpx<float>*, double, const cpx<float>*,
-                                             cpx<float>*, double, const double*, int, const double*, int, double*,
-                                             hipStream_t, const void*);
-template void launch_fft_rows_adj_dir<double>(const Plan&, const cpx<double>*, cpx<double>*, double, const cpx<double>*,
-                                              cpx<double>*, double, const double*, int, const double*, int, double*,
-                                              hipStream_t, const void*);
+template int launch_fft_rows_xr<float>(const Plan&, cpx<float>*, cpx<float>*, cpx<float>*, const cpx<float>*,
+                                       const double*, int, const double*, const double*, const double*, int, double*,
+                                       cpx<float>*, hipStream_t, const void*);
+template int launch_fft_rows_xr<double>(const Plan&, cpx<double>*, cpx<double>*, cpx<double>*, const cpx<double>*,
+                                        const double*, int, const double*, const double*, const double*, int, double*,
+                                        cpx<double>*, hipStream_t, const void*);
+template void launch_fft_rows_adj_cg<float>(const Plan&, const cpx<float>*, cpx<float>*, double, const cpx<float>*,
+                                            double, double*, const cpx<float>*, double*, double*, hipStream_t,
+                                            const void*);
+template void launch_fft_rows_adj_cg<double>(const Plan&, const cpx<double>*, cpx<double>*, double, const cpx<double>*,
+                                             double, double*, const cpx<double>*, double*, double*, hipStream_t,
+                                             const void*);
 template void launch_fft_cols_toep<float>(const Plan&, cpx<float>*, hipStream_t, const cpx<float>*);
 template void launch_fft_cols_toep<double>(const Plan&, cpx<double>*, hipStream_t, const cpx<double>*);
-template void launch_fft_cols_toep_dir<float>(const Plan&, cpx<float>*, cpx<float>*, const double*, int, const double*,
-                                              int, hipStream_t);
-template void launch_fft_cols_toep_dir<double>(const Plan&, cpx<double>*, cpx<double>*, const double*, int,
-                                               const double*, int, hipStream_t);
 template void launch_fft_rows_adj<float>(const Plan&, const cpx<float>*, cpx<float>*, double,
                                          const cpx<float>*, double, double*, hipStream_t, const void*);
 template void launch_fft_rows_adj<double>(const Plan&, const cpx<double>*, cpx<double>*, double,

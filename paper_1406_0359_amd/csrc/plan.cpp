@@ -311,7 +311,6 @@ size_t layout(Plan& P, const purify_plan_desc* d, char* ws) {
     P.grid = carve(K * K * ce);
     P.grid2 = carve(K * K * ce);
     P.tmp = carve(K * P.n * ce);
-    P.dirt = carve(K * P.n * ce);
     P.unit = carve(P.n * es);
     P.chat = carve(K * K * es);
     P.part = (double*)carve((size_t)NUM_PARTIAL_BUFS * MAX_PARTIALS * sizeof(double));
