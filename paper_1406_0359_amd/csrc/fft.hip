@@ -26,6 +26,7 @@
 // twiddles come from an FP64-accurate table staged in LDS.
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "common.h"
 
@@ -1147,34 +1148,50 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
     __syncthreads();
     const T srow = c1 * deap[row];
     double acc = 0.0, arq = 0.0, aqq = 0.0;
+    // the epilogue, one straight-line copy per operand set (long lines: its operands are
+    // loaded first, all before the first store, so they are in flight together)
+    auto epilogue = [&](auto has_v, auto has_r) {
+        constexpr bool HV = decltype(has_v)::value, HR = decltype(has_r)::value;
+        cpx<T> ev[PRE ? 1 : NQ], er[PRE ? 1 : NQ], et[PRE ? 1 : NQ];
+        T ed[PRE ? 1 : NQ];
+        if constexpr (!PRE) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int j = r + 2 * tl + q * 2 * PL::TL, a = PL::at(r + 2 * tl) + PL::span(q * 2 * PL::TL);
-        cpx<T> o;
-        if constexpr (PRE) {
-            const cpx<T> t = lines[a] + mul_mi(mulc(lines[PL::LS + a], tj[q]));
-            o = (srow * dj[q]) * t;
-        } else {
-            const cpx<T> t = lines[a] + mul_mi(mulc(lines[PL::LS + a], tw2[j]));
-            o = (srow * deap[j]) * t;
+            for (int q = 0; q < NQ; ++q) {
+                const int j = r + 2 * tl + q * 2 * PL::TL;
+                const size_t off = (size_t)row * N + j;
+                if constexpr (HV) ev[q] = vin[off];
+                if constexpr (HR) er[q] = dots.r[off];
+                et[q] = tw2[j];
+                ed[q] = deap[j];
+            }
         }
-        const size_t off = (size_t)row * N + j;
-        if (vin) {
-            cpx<T> vv;
-            if constexpr (PRE) vv = pv[q];
-            else vv = vin[off];
-            o = o + c2 * vv;
-            acc += (double)vv.x * (double)o.x + (double)vv.y * (double)o.y;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int j = r + 2 * tl + q * 2 * PL::TL, a = PL::at(r + 2 * tl) + PL::span(q * 2 * PL::TL);
+            cpx<T> o;
+            if constexpr (PRE) {
+                const cpx<T> t = lines[a] + mul_mi(mulc(lines[PL::LS + a], tj[q]));
+                o = (srow * dj[q]) * t;
+            } else {
+                const cpx<T> t = lines[a] + mul_mi(mulc(lines[PL::LS + a], et[q]));
+                o = (srow * ed[q]) * t;
+            }
+            if constexpr (HV) {
+                const cpx<T> vv = PRE ? pv[q] : ev[PRE ? 0 : q];
+                o = o + c2 * vv;
+                acc += (double)vv.x * (double)o.x + (double)vv.y * (double)o.y;
+            }
+            if constexpr (HR) {
+                const cpx<T> rr = PRE ? pr[q] : er[PRE ? 0 : q];
+                arq += (double)rr.x * (double)o.x + (double)rr.y * (double)o.y;
+                aqq += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+            }
+            x[(size_t)row * N + j] = o;
         }
-        if (dots.r) {
-            cpx<T> rr;
-            if constexpr (PRE) rr = pr[q];
-            else rr = dots.r[off];
-            arq += (double)rr.x * (double)o.x + (double)rr.y * (double)o.y;
-            aqq += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
-        }
-        x[off] = o;
-    }
+    };
+    if (vin && dots.r) epilogue(std::true_type{}, std::true_type{});
+    else if (vin) epilogue(std::true_type{}, std::false_type{});
+    else epilogue(std::false_type{}, std::false_type{});
     if (dots.r) {
         double t0, t1, t2;
         block_sum3_dyn(acc, arq, aqq, red, t0, t1, t2);
