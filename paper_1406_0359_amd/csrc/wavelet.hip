@@ -27,6 +27,30 @@ struct WavArgs {
 // filters layout: [basis][0..15] = h, [basis][16..31] = g.  Kernels stage a basis' taps in
 // LDS (lanes index them by output parity, which a register array cannot serve).
 
+// Row and column of a flattened tile index: i / d and i mod d for 0 <= i < 2^20 and
+// 1 <= d < 2^12 (every tile and window index here) from a float reciprocal taken once.  The
+// float quotient is within 1/4 of i / d, so its truncation is off by at most one, which one
+// remainder test corrects; a few instructions instead of an integer division, in kernels
+// whose arithmetic, not memory, sets their time.
+struct SmallDiv {
+    int d;
+    float rd;
+    __device__ explicit SmallDiv(int d_) : d(d_), rd(1.0f / (float)d_) {}
+    __device__ __forceinline__ int quot(int i, int& rem) const {
+        int q = (int)((float)i * rd);
+        int r = i - q * d;
+        if (r >= d) {
+            ++q;
+            r -= d;
+        } else if (r < 0) {
+            --q;
+            r += d;
+        }
+        rem = r;
+        return q;
+    }
+};
+
 // Global-to-LDS staging of `count` elements (element i read by ld(i) and stored by st(i, v),
 // count <= MAXE NTH): a thread issues the loads of all its elements before storing any, so
 // they are in flight together rather than one memory latency after another.
@@ -92,7 +116,12 @@ k_wav_fwd_level(const cpx<T>* __restrict__ src, size_t src_bstride, int src_ld, 
     };
     if (z == A.nwav) {
         cpx<T>* d = alpha + (size_t)A.dirac_block * N;
-        auto at = [&](int i) { return (size_t)(r0 + i / (2 * ap)) * n + c0 + i % (2 * ap); };
+        const SmallDiv d2a(2 * ap);
+        auto at = [&](int i) {
+            int c;
+            const int r = d2a.quot(i, c);
+            return (size_t)(r0 + r) * n + c0 + c;
+        };
         stage_batched<cpx<T>, 4 * AP * AP / 256, 256>(
             4 * ap * ap, threadIdx.x, [&](int i) { return img(at(i)); },
             [&](int i, cpx<T> v) { d[at(i)] = scale * v; });
@@ -102,25 +131,29 @@ k_wav_fwd_level(const cpx<T>* __restrict__ src, size_t src_bstride, int src_ld, 
     const cpx<T>* s = src + (size_t)z * src_bstride;
     const int F = A.flen[z];
     const int R = 2 * ap + F - 2, RH = R >> 1;
+    const SmallDiv dR(R), da(ap), d2a(2 * ap);
     // the taps and the window (R <= AR) are loaded together, then stored to LDS
     const T tap = threadIdx.x < 2 * MAX_TAPS ? filt[z * 2 * MAX_TAPS + threadIdx.x] : (T)0;
     stage_batched<cpx<T>, (AR * AR + 255) / 256, 256>(
         R * R, threadIdx.x,
         [&](int i) {
-            const int a = i / R, b = i - a * R;
+            int b;
+            const int a = dR.quot(i, b);
             const size_t o = (size_t)((r0 + a) & (Ls - 1)) * src_ld + ((c0 + b) & (Ls - 1));
             if constexpr (XHAT) return img(o);
             else return s[o];
         },
         [&](int i, cpx<T> v) {
-            const int a = i / R, b = i - a * R;
+            int b;
+            const int a = dR.quot(i, b);
             in[a * IS + (b & 1) * RH + (b >> 1)] = v;
         });
     if (threadIdx.x < 2 * MAX_TAPS) tp[threadIdx.x] = tap;
     __syncthreads();
     // axis 1: window row a, position oi -> mid[a][oi] (low), mid[a][ap + oi] (high)
     for (int i = threadIdx.x; i < R * ap; i += 256) {
-        const int a = i / ap, oi = i - a * ap;
+        int oi;
+        const int a = da.quot(i, oi);
         const cpx<T>* row = in + a * IS + oi;
         T lx = 0, ly = 0, hx = 0, hy = 0;
 #pragma unroll
@@ -139,7 +172,8 @@ k_wav_fwd_level(const cpx<T>* __restrict__ src, size_t src_bstride, int src_ld, 
     __syncthreads();
     // axis 0: position oi, column o1 (low | high along axis 1) -> both axis-0 subbands
     for (int i = threadIdx.x; i < 2 * ap * ap; i += 256) {
-        const int oi = i / (2 * ap), o1 = i - oi * (2 * ap);
+        int o1;
+        const int oi = d2a.quot(i, o1);
         const cpx<T>* col = mid + 2 * oi * MS + o1;
         T lx = 0, ly = 0, hx = 0, hy = 0;
 #pragma unroll
@@ -179,16 +213,19 @@ k_wav_fwd_level0_all(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ alpha, c
     const int ti1 = blockIdx.x / tiles, ti2 = blockIdx.x % tiles;
     const int r0 = 2 * AP * ti1, c0 = 2 * AP * ti2;
     const int R = 2 * AP + Fmax - 2, RH = R >> 1;
+    const SmallDiv dR(R);
     // the taps of every basis (at most 256 values) and the window are loaded together
     const T tap = threadIdx.x < A.nwav * 2 * MAX_TAPS ? filt[threadIdx.x] : (T)0;
     stage_batched<cpx<T>, (AR * AR + 255) / 256, 256>(
         R * R, threadIdx.x,
         [&](int i) {
-            const int a = i / R, b = i - a * R;
+            int b;
+            const int a = dR.quot(i, b);
             return x[(size_t)((r0 + a) & (Ls - 1)) * n + ((c0 + b) & (Ls - 1))];
         },
         [&](int i, cpx<T> v) {
-            const int a = i / R, b = i - a * R;
+            int b;
+            const int a = dR.quot(i, b);
             in[a * IS + (b & 1) * RH + (b >> 1)] = v;
         });
     if (threadIdx.x < A.nwav * 2 * MAX_TAPS) tp[threadIdx.x / (2 * MAX_TAPS)][threadIdx.x % (2 * MAX_TAPS)] = tap;
@@ -267,13 +304,15 @@ __device__ __forceinline__ void synth_load(SynthWin<T, NTH, CMAX>& w, const cpx<
                                            const cpx<T>* __restrict__ lls, int lld, int n, int half, int po,
                                            int m0, int m1, int F, const T* __restrict__ ftaps, int tid) {
     const int C = po / 2 + F / 2 - 1;
+    const SmallDiv d2c(2 * C);
     const int s0 = m0 / 2 - F / 2 + 1, s1 = m1 / 2 - F / 2 + 1;   // first window index
     w.tap = tid < 2 * MAX_TAPS ? ftaps[tid] : (T)0;
 #pragma unroll
     for (int k = 0; k < SynthWin<T, NTH, CMAX>::E; ++k) {
         const int i = tid + k * NTH;
         if (i < 4 * C * C) {
-            const int u = i / (2 * C), v = i - u * (2 * C);
+            int v;
+            const int u = d2c.quot(i, v);
             const bool h0 = u >= C, h1 = v >= C;
             const int i0 = (s0 + (h0 ? u - C : u)) & (half - 1), i1 = (s1 + (h1 ? v - C : v)) & (half - 1);
             w.v[k] = (!h0 && !h1) ? lls[(size_t)i0 * lld + i1]
@@ -287,11 +326,13 @@ __device__ __forceinline__ void synth_store(const SynthWin<T, NTH, CMAX>& w, int
                                             int tid) {
     constexpr int WS = SynthWin<T, NTH, CMAX>::WS;
     const int C = po / 2 + F / 2 - 1;
+    const SmallDiv d2c(2 * C);
 #pragma unroll
     for (int k = 0; k < SynthWin<T, NTH, CMAX>::E; ++k) {
         const int i = tid + k * NTH;
         if (i < 4 * C * C) {
-            const int u = i / (2 * C), v = i - u * (2 * C);
+            int v;
+            const int u = d2c.quot(i, v);
             in[u * WS + v] = w.v[k];
         }
     }
@@ -304,8 +345,10 @@ __device__ __forceinline__ void synth_axis0(int po, int F, const T* tp, const cp
     constexpr int WS = SynthWin<T, NTH, CMAX>::WS;
     const int C = po / 2 + F / 2 - 1;
     const int hp = po / 2;
+    const SmallDiv d2c(2 * C);
     for (int i = tid; i < hp * 2 * C; i += NTH) {
-        const int jr = i / (2 * C), v = i - jr * (2 * C);
+        int v;
+        const int jr = d2c.quot(i, v);
         T ex = 0, ey = 0, ox = 0, oy = 0;
 #pragma unroll
         for (int t = 0; t < MAX_TAPS / 2; ++t) {
@@ -333,11 +376,13 @@ __device__ __forceinline__ void synth_axis1(int po, int F, const T* tp, const cp
     const int hp = po / 2;
     constexpr int PMAX = CMAX - MAX_TAPS / 2 + 1;          // largest po / 2
     constexpr int KMAX = (2 * PMAX * PMAX + NTH - 1) / NTH;
+    const SmallDiv dh(hp);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         const int i = tid + k * NTH;
         if (i >= po * hp) break;
-        const int r = i / hp, jc = i - r * hp;
+        int jc;
+        const int r = dh.quot(i, jc);
         T ex = 0, ey = 0, ox = 0, oy = 0;
 #pragma unroll
         for (int t = 0; t < MAX_TAPS / 2; ++t) {
@@ -362,6 +407,7 @@ __device__ __forceinline__ void synth_tile(const cpx<T>* __restrict__ alpha, siz
                                           Emit emit) {
     constexpr int WS = SynthWin<T, NTH, CMAX>::WS;
     const int C = po / 2 + F / 2 - 1;
+    const SmallDiv d2c(2 * C);
     const int s0 = m0 / 2 - F / 2 + 1, s1 = m1 / 2 - F / 2 + 1;   // first window index
     // the basis' taps (ftaps, into tp) and the window (C <= CMAX) are loaded together, then
     // stored to LDS
@@ -369,14 +415,16 @@ __device__ __forceinline__ void synth_tile(const cpx<T>* __restrict__ alpha, siz
     stage_batched<cpx<T>, (4 * CMAX * CMAX + NTH - 1) / NTH, NTH>(
         4 * C * C, tid,
         [&](int i) {
-            const int u = i / (2 * C), v = i - u * (2 * C);
+            int v;
+            const int u = d2c.quot(i, v);
             const bool h0 = u >= C, h1 = v >= C;
             const int i0 = (s0 + (h0 ? u - C : u)) & (half - 1), i1 = (s1 + (h1 ? v - C : v)) & (half - 1);
             return (!h0 && !h1) ? lls[(size_t)i0 * lld + i1]
                                 : alpha[blk + (size_t)(i0 + (h0 ? half : 0)) * n + i1 + (h1 ? half : 0)];
         },
         [&](int i, cpx<T> val) {
-            const int u = i / (2 * C), v = i - u * (2 * C);
+            int v;
+            const int u = d2c.quot(i, v);
             in[u * WS + v] = val;
         });
     if (tid < 2 * MAX_TAPS) tp[tid] = tap;
