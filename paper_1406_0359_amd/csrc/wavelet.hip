@@ -27,6 +27,9 @@ struct WavArgs {
 // filters layout: [basis][0..15] = h, [basis][16..31] = g.  Kernels stage a basis' taps in
 // LDS (lanes index them by output parity, which a register array cannot serve).
 
+__device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
+
 // Row and column of a flattened tile index: i / d and i mod d for 0 <= i < 2^20 and
 // 1 <= d < 2^12 (every tile and window index here) from a float reciprocal taken once.  The
 // float quotient is within 1/4 of i / d, so its truncation is off by at most one, which one
@@ -35,7 +38,7 @@ struct WavArgs {
 struct SmallDiv {
     int d;
     float rd;
-    __device__ explicit SmallDiv(int d_) : d(d_), rd(1.0f / (float)d_) {}
+    __device__ explicit SmallDiv(int d_) : d(d_), rd(__builtin_amdgcn_rcpf((float)d_)) {}   // 1-ulp reciprocal
     __device__ __forceinline__ int quot(int i, int& rem) const {
         int q = (int)((float)i * rd);
         int r = i - q * d;
@@ -357,10 +360,16 @@ __device__ __forceinline__ void synth_axis0(int po, int F, const T* tp, const cp
             const cpx<T> lo = in[u * WS + v], hv = in[(C + u) * WS + v];
             const T he = tp[2 * t], ge = tp[MAX_TAPS + 2 * t];
             const T ho = tp[2 * t + 1], go = tp[MAX_TAPS + 2 * t + 1];
-            ex += he * lo.x + ge * hv.x;
-            ey += he * lo.y + ge * hv.y;
-            ox += ho * lo.x + go * hv.x;
-            oy += ho * lo.y + go * hv.y;
+            // one fused multiply-add a product (the sum of the pair first costs a multiply,
+            // an FMA and an add)
+            ex = fma_(he, lo.x, ex);
+            ex = fma_(ge, hv.x, ex);
+            ey = fma_(he, lo.y, ey);
+            ey = fma_(ge, hv.y, ey);
+            ox = fma_(ho, lo.x, ox);
+            ox = fma_(go, hv.x, ox);
+            oy = fma_(ho, lo.y, oy);
+            oy = fma_(go, hv.y, oy);
         }
         mid[(2 * jr) * WS + v] = mk<T>(ex, ey);
         mid[(2 * jr + 1) * WS + v] = mk<T>(ox, oy);
@@ -391,10 +400,16 @@ __device__ __forceinline__ void synth_axis1(int po, int F, const T* tp, const cp
             const cpx<T> lo = mid[r * WS + v], hv = mid[r * WS + C + v];
             const T he = tp[2 * t], ge = tp[MAX_TAPS + 2 * t];
             const T ho = tp[2 * t + 1], go = tp[MAX_TAPS + 2 * t + 1];
-            ex += he * lo.x + ge * hv.x;
-            ey += he * lo.y + ge * hv.y;
-            ox += ho * lo.x + go * hv.x;
-            oy += ho * lo.y + go * hv.y;
+            // one fused multiply-add a product (the sum of the pair first costs a multiply,
+            // an FMA and an add)
+            ex = fma_(he, lo.x, ex);
+            ex = fma_(ge, hv.x, ex);
+            ey = fma_(he, lo.y, ey);
+            ey = fma_(ge, hv.y, ey);
+            ox = fma_(ho, lo.x, ox);
+            ox = fma_(go, hv.x, ox);
+            oy = fma_(ho, lo.y, oy);
+            oy = fma_(go, hv.y, oy);
         }
         emit(k, r, 2 * jc, mk<T>(ex, ey), mk<T>(ox, oy));
     }
