@@ -716,14 +716,18 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
     const size_t ro = (size_t)row * N;
     cpx<T>* outr = tmp + (size_t)row * K;
     // the row's loads are issued before the partial sums are read, so both are in flight
+    // (x only by parity group 0, which writes the row back)
     cpx<T> xv[PL::RMAX], rv[PL::RMAX], pv[PL::RMAX], qv[PL::RMAX];
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
         const int p = PL::in_pos(tl, i);
-        xv[i] = cg.x[ro + p];
         rv[i] = cg.r[ro + p];
         pv[i] = cg.p[ro + p];
         qv[i] = cg.q[ro + p];
+    }
+    if (r == 0) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) xv[i] = cg.x[ro + PL::in_pos(tl, i)];
     }
     // short lines: the transform's S and parity twiddles are read here too
     constexpr bool PRE = PL::RMAX <= 8 && 2 * B * PL::TL <= 512;   // register budget
@@ -746,7 +750,7 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
     double acc = 0;
 #pragma unroll
     for (int i = 0; i < PL::RMAX; ++i) {
-        xv[i] = xv[i] + alpha * pv[i];
+        if (r == 0) xv[i] = xv[i] + alpha * pv[i];
         rv[i] = rv[i] - alpha * qv[i];
         acc += (double)rv[i].x * rv[i].x + (double)rv[i].y * rv[i].y;
         pv[i] = rv[i] + beta * pv[i];
