@@ -268,13 +268,12 @@ purify_sdmm_params params_for(int i) {
 }
 
 // Direct solves on one plan (the plan's own streams, created on its first solve): plain,
-// eager, reweighted, and a stage timing.
-int direct_solves() {
-    std::mt19937_64 g(11);
-    const int n = 64;
-    const int64_t M = 3000;
+// eager, reweighted, then every stage timed; the plan is destroyed at the end (the caller
+// runs this for one plan after another, as a timing script over several workloads does).
+int direct_solves(int n, int64_t M, int precision, unsigned seed) {
+    std::mt19937_64 g(seed);
     std::vector<double> uv = uv_draw(g, M);
-    purify_plan_desc d = desc_for(n, M, uv.data(), PURIFY_FP64);
+    purify_plan_desc d = desc_for(n, M, uv.data(), precision);
     const size_t ws = purify_plan_workspace_bytes(&d);
     void* mem = aligned_alloc(256, (ws + 255) / 256 * 256);
     std::vector<unsigned char> y((size_t)M * 16, 0), x((size_t)n * n * 16, 0);
@@ -297,8 +296,15 @@ int direct_solves() {
     purify_sdmm_info info{};
     purify_reweight_info rinfo{};
     (void)purify_sdmm_reweighted(plan, y.data(), &p, &rw, w.data(), x.data(), &info, &rinfo, nullptr);
-    double ms = 0;
-    if (purify_time_stage(plan, PURIFY_STAGE_PHI, 3, nullptr, &ms) != PURIFY_OK) ++bad;
+    for (int st = 0; st <= PURIFY_STAGE_TV_STEP; ++st) {
+        double ms = 0;
+        if (purify_time_stage(plan, st, 3, nullptr, &ms) != PURIFY_OK) ++bad;
+    }
+    for (int i = 4; i < 7; ++i) {   // short solves after the timings, as before the next plan
+        purify_sdmm_params q = params_for(i);
+        purify_sdmm_info qi{};
+        if (purify_sdmm_solve(plan, y.data(), &q, x.data(), &qi, nullptr) != PURIFY_OK) ++bad;
+    }
     purify_plan_destroy(plan);
     free(mem);
     return bad;
@@ -308,7 +314,9 @@ int direct_solves() {
 
 int main(int argc, char** argv) {
     const int count = argc > 1 ? atoi(argv[1]) : 24, slots = argc > 2 ? atoi(argv[2]) : 8;
-    int bad = direct_solves();
+    int bad = direct_solves(64, 3000, PURIFY_FP64, 11);
+    bad += direct_solves(128, 9000, PURIFY_FP32, 12);
+    bad += direct_solves(64, 2500, PURIFY_FP64, 13);
     const size_t arena_bytes = (size_t)1 << 30;
     void* arena = aligned_alloc(256, arena_bytes);
     purify_server_desc sd{};

@@ -4,8 +4,9 @@ The library's host code (plan.cpp, api.cpp, solver_rt.cpp, server.cpp) is compil
 beside tests/host_harness/solver_lifetimes.cpp, whose stand-ins for the HIP runtime track
 every stream, event and graph, and beside kernel-launcher stubs generated here from the
 declarations in common.h (each marks its stream busy, and records the event a launcher is
-given, as the real one does).  Direct solves (graph and eager, reweighted, a stage timing) and
-a server stream of mixed requests on eight worker slots then run the real solve sequence;
+given, as the real one does).  Direct solves (graph and eager, reweighted, every stage timed, more solves, on three plans
+created and destroyed one after another in FP64 and FP32) and a server stream of mixed
+requests on eight worker slots then run the real solve sequence;
 the run fails on any unsafe use: an event destroyed while a stream waits on it, a stream or a
 launched graph destroyed with work pending, a call on a destroyed object, or two threads
 capturing or instantiating graphs at once.  The same run under ThreadSanitizer checks the
