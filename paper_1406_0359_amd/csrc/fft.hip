@@ -761,9 +761,14 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) {
             const int p = PL::in_pos(tl, i);
-            cg.x[ro + p] = xv[i];
-            cg.r[ro + p] = rv[i];
-            cg.p[ro + p] = pv[i];
+            // streaming stores: x, r and p are next read several launches later, so they
+            // should not push the row transforms this pass writes out of the caches
+            __builtin_nontemporal_store(xv[i].x, &cg.x[ro + p].x);
+            __builtin_nontemporal_store(xv[i].y, &cg.x[ro + p].y);
+            __builtin_nontemporal_store(rv[i].x, &cg.r[ro + p].x);
+            __builtin_nontemporal_store(rv[i].y, &cg.r[ro + p].y);
+            __builtin_nontemporal_store(pv[i].x, &cg.p[ro + p].x);
+            __builtin_nontemporal_store(pv[i].y, &cg.p[ro + p].y);
         }
     }
     const double tot = block_sum_dyn(r == 0 ? acc : 0.0, red);
