@@ -1195,7 +1195,8 @@ k_fft_rows_adj(const cpx<T>* __restrict__ tmp, cpx<T>* __restrict__ x, const T* 
                 arq += (double)rr.x * (double)o.x + (double)rr.y * (double)o.y;
                 aqq += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
             }
-            x[(size_t)row * N + j] = o;
+            __builtin_nontemporal_store(o.x, &x[(size_t)row * N + j].x);   // streaming, as in the
+            __builtin_nontemporal_store(o.y, &x[(size_t)row * N + j].y);   // CG row pass
         }
     };
     if (vin && dots.r) epilogue(std::true_type{}, std::true_type{});
