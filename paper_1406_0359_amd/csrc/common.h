@@ -207,6 +207,9 @@ template <typename T> void launch_fft_rows_adj(const Plan& P, const cpx<T>* tmp,
                                                const cpx<T>* v, double c2, double* dot_part,
                                                hipStream_t s, const void* deap = nullptr);
 template <typename T> int fft_rows_adj_blocks(const Plan& P);
+// width W of the column groups by which the stored operator's spectrum is laid out
+// (element (k1, k2) at ((k2 / W) K + k1) W + k2 mod W; W = K is the row-major grid)
+template <typename T> int fft_toep_group(const Plan& P);
 
 // G: y[perm ? perm[m] : m] = scale * sum psi psi grid
 template <typename T> void launch_degrid(const Plan& P, const cpx<T>* grid, cpx<T>* y, const int32_t* perm,

@@ -369,6 +369,16 @@ template <typename T, int LOGN>
 constexpr bool long_cols() { return LOGN >= 11 && (cols_per_wg<T, LOGN>() == 1 || twiddles_split<T, LOGN>()); }
 template <typename T, int LOGN>
 constexpr int long_cols_cr() { return sizeof(T) == 8 || Plan1D<T, LOGN, 1>::RMAX >= 16 ? 2 : 4; }
+// Column groups of the stored operator's spectrum: element (k1, k2) at
+// ((k2 / W) K + k1) W + k2 mod W.  Long FP32 columns (two a thread in registers; four, with the
+// spectrum's loads, spilled at the 128-register limit of the 1024-thread workgroup) store each
+// workgroup's K x 2 block contiguously, so it reads one run instead of 8 bytes from each of K
+// rows (4096^2 column stage 907 -> 672 us); elsewhere W = K, the row-major grid, which the
+// multi-column workgroups read in runs of C values (a blocked layout there measured slower).
+template <typename T, int LOGN>
+constexpr bool toep_mc() { return sizeof(T) == 4 && long_cols<T, LOGN>(); }
+template <typename T, int LOGN>
+constexpr int toep_group() { return toep_mc<T, LOGN>() ? 2 : 2 << LOGN; }
 // workgroups of a long-column kernel that can share a CU: two of 512 threads or fewer (16
 // waves at up to 128 VGPRs) if their twiddle table and two line buffers fit twice in LDS
 template <typename T, int LOGN>
@@ -1076,7 +1086,7 @@ k_fft_cols_toep_mc(const cpx<T>* in, cpx<T>* out, const T* __restrict__ chat, co
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) {
             const int kp = PL::out_pos(tl, i);
-            cpx<T> o = chat[(size_t)(2 * kp + r) * K + col0 + cc] * v[cc][i];
+            cpx<T> o = chat[((size_t)(col0 / CR) * K + 2 * kp + r) * CR + cc] * v[cc][i];
             v[cc][i] = r ? mul_i(o) : o;
         }
         __syncthreads();
@@ -1325,10 +1335,8 @@ void cols_toep_impl(const Plan& P, const cpx<T>* in, cpx<T>* out, hipStream_t s)
     constexpr int NT = 2 * C * Plan1D<T, LOGN, 1>::TL;
     constexpr int N = 1 << LOGN;
     const size_t lds = lds_bytes<T, LOGN, 1>(2 * C);
-    if constexpr (sizeof(T) == 4 && long_cols<T, LOGN>()) {
-        // long FP32 columns: two columns per thread in registers (four, with the spectrum's
-        // loads, spilled at the 128-register limit of the 1024-thread workgroup)
-        constexpr int CR = 2;
+    if constexpr (toep_mc<T, LOGN>()) {
+        constexpr int CR = toep_group<T, LOGN>();   // columns per thread, in registers
         const size_t lds1 = mc_lds_bytes<T, LOGN>();
         auto f = k_fft_cols_toep_mc<T, LOGN, CR>;
         set_lds_limit(f, lds1);
@@ -1448,6 +1456,12 @@ void launch_fft_rows_adj(const Plan& P, const cpx<T>* tmp, cpx<T>* x, double c1,
     PURIFY_LOGN_DISPATCH(ilog2(P.n), (rows_adj_impl<T, L_>(P, tmp, x, c1, v, c2, dot_part, dp, CgDots<T>{}, s)));
 }
 template <typename T>
+int fft_toep_group(const Plan& P) {
+    int w = 0;
+    PURIFY_LOGN_DISPATCH(ilog2(P.n), (w = toep_group<T, L_>()));
+    return w;
+}
+template <typename T>
 int fft_rows_adj_blocks(const Plan& P) {
     int r = 0;
     PURIFY_LOGN_DISPATCH(ilog2(P.n), (r = (1 << L_) / rows_per_wg<T, L_>()));
@@ -1484,6 +1498,8 @@ template void launch_fft_rows_adj<float>(const Plan&, const cpx<float>*, cpx<flo
                                          const cpx<float>*, double, double*, hipStream_t, const void*);
 template void launch_fft_rows_adj<double>(const Plan&, const cpx<double>*, cpx<double>*, double,
                                           const cpx<double>*, double, double*, hipStream_t, const void*);
+template int fft_toep_group<float>(const Plan&);
+template int fft_toep_group<double>(const Plan&);
 template int fft_rows_adj_blocks<float>(const Plan&);
 template int fft_rows_adj_blocks<double>(const Plan&);
 

@@ -41,10 +41,11 @@ __global__ void __launch_bounds__(256) k_zero_edge(cpx<T>* __restrict__ x, int n
 }
 
 // chat[k] (+)= Re(exp(-2 pi i k . s / K) H[k]) / K^2 for s = (sig1, sig2) n/2:
-// the phase is (-i)^e with e = (sig1 k1 + sig2 k2) mod 4
+// the phase is (-i)^e with e = (sig1 k1 + sig2 k2) mod 4.  chat is stored by groups of W
+// columns, the layout the column stage reads (element (k1, k2) at ((k2 / W) K + k1) W + k2 mod W).
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_chat_accum(const cpx<T>* __restrict__ H, int K, int sig1, int sig2, int first, double scale,
+k_chat_accum(const cpx<T>* __restrict__ H, int K, int sig1, int sig2, int first, double scale, int W,
              T* __restrict__ chat) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= (int64_t)K * K) return;
@@ -53,7 +54,8 @@ k_chat_accum(const cpx<T>* __restrict__ H, int K, int sig1, int sig2, int first,
     const cpx<T> h = H[i];
     const T re = e == 0 ? h.x : (e == 1 ? h.y : (e == 2 ? -h.x : -h.y));
     const T add = (T)scale * re;
-    chat[i] = first ? add : chat[i] + add;
+    const size_t o = ((size_t)(k2 / W) * K + k1) * W + k2 % W;
+    chat[o] = first ? add : chat[o] + add;
 }
 
 }  // namespace
@@ -72,7 +74,7 @@ template <typename T>
 void launch_chat_accum(const Plan& P, const cpx<T>* H, int sig1, int sig2, bool first, hipStream_t s) {
     const int64_t KK = (int64_t)P.K * P.K;
     hipLaunchKernelGGL(k_chat_accum<T>, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, s, H, P.K, sig1, sig2,
-                       (int)first, 1.0 / (double)KK, (T*)P.chat);
+                       (int)first, 1.0 / (double)KK, fft_toep_group<T>(P), (T*)P.chat);
 }
 
 #define PURIFY_INST_TOEP(T)                                                                     \
