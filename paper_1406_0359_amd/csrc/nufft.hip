@@ -482,11 +482,20 @@ k_grid(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ gin, const int32
     };
     if (slot < 0) {
         const T q = (T)ldexp(1.0, e);
+        // grids of 8192^2 and more (512 MB in FP32, twice the last-level cache) are written
+        // with streaming stores, so they do not push out what the next launches reuse
+        const bool stream = K >= 8192;
         for (int i = threadIdx.x; i < TT * TT; i += NT) {
             const int r = i / TT, c = i % TT;
             typename Acc::I re, im;
             cell((r + JM) * WA + c + JM, re, im);
-            grid[(size_t)(t1o + r) * K + t2o + c] = mk<T>(q * (T)re, q * (T)im);
+            cpx<T>* o = grid + (size_t)(t1o + r) * K + t2o + c;
+            if (stream) {
+                __builtin_nontemporal_store(q * (T)re, &o->x);
+                __builtin_nontemporal_store(q * (T)im, &o->y);
+            } else {
+                *o = mk<T>(q * (T)re, q * (T)im);
+            }
         }
         return;
     }
