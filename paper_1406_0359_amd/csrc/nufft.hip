@@ -521,16 +521,51 @@ k_grid_merge(const int32_t* __restrict__ merge, const typename FixedAcc<T>::I* _
     const int tile = merge[3 * blockIdx.x], parts = merge[3 * blockIdx.x + 1];
     const int slot0 = merge[3 * blockIdx.x + 2];
     const int t1o = (tile % nT) * TT, t2o = (tile / nT) * TT;
-    for (int i = threadIdx.x; i < TT * TT; i += 256) {
-        double sr = 0.0, si = 0.0;
-        for (int p = 0; p < parts; ++p) {
-            const typename FixedAcc<T>::I* pt = partial + (size_t)(slot0 + p) * 2 * TT * TT;
-            const int e = pexp[slot0 + p];
-            sr += ldexp((double)pt[2 * i], e);
-            si += ldexp((double)pt[2 * i + 1], e);
+    using I = typename FixedAcc<T>::I;
+    constexpr int EPT = (TT * TT + 255) / 256;   // cells a thread
+    constexpr int PB = 4;                          // parts whose loads are in flight together
+    double sr[EPT], si[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) sr[k] = si[k] = 0.0;
+    for (int p0 = 0; p0 < parts; p0 += PB) {
+        // a batch of parts is loaded before any is added; the sums still run in part order
+        I vr[PB][EPT], vi[PB][EPT];
+        int ex[PB];
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            if (p0 + b < parts) {
+                ex[b] = pexp[slot0 + p0 + b];
+                const I* pt = partial + (size_t)(slot0 + p0 + b) * 2 * TT * TT;
+#pragma unroll
+                for (int k = 0; k < EPT; ++k) {
+                    const int i = threadIdx.x + k * 256;
+                    if (i < TT * TT) {
+                        vr[b][k] = pt[2 * i];
+                        vi[b][k] = pt[2 * i + 1];
+                    }
+                }
+            }
         }
-        const int r = i / TT, c = i % TT;
-        grid[(size_t)(t1o + r) * K + t2o + c] = mk<T>((T)sr, (T)si);
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            if (p0 + b < parts) {
+#pragma unroll
+                for (int k = 0; k < EPT; ++k) {
+                    if (threadIdx.x + k * 256 < TT * TT) {
+                        sr[k] += ldexp((double)vr[b][k], ex[b]);
+                        si[k] += ldexp((double)vi[b][k], ex[b]);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int i = threadIdx.x + k * 256;
+        if (i < TT * TT) {
+            const int r = i / TT, c = i % TT;
+            grid[(size_t)(t1o + r) * K + t2o + c] = mk<T>((T)sr[k], (T)si[k]);
+        }
     }
 }
 
