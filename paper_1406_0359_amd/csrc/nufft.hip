@@ -149,17 +149,35 @@ k_degrid_tiles(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const in
     const int t1o = (tile % nT) * TT, t2o = (tile / nT) * TT;
     const int mask = K - 1;
     const int Jn = J > 0 ? J : Jr;
+    if constexpr (DMA) {
 #pragma unroll
-    for (int k = 0; k < WPT; ++k) {
-        const int i = threadIdx.x + k * NT;
-        if (i < WS * WS) {
-            const cpx<T>* src = grid + (size_t)((t1o + i / WS) & mask) * K + ((t2o + i % WS) & mask);
-            if constexpr (DMA)
+        for (int k = 0; k < WPT; ++k) {
+            const int i = threadIdx.x + k * NT;
+            if (i < WS * WS) {
+                const cpx<T>* src = grid + (size_t)((t1o + i / WS) & mask) * K + ((t2o + i % WS) & mask);
                 __builtin_amdgcn_global_load_lds(
                     (const void*)src, (__attribute__((address_space(3))) void*)(win + (threadIdx.x & ~63u) + k * NT),
                     16, 0, 0);
-            else
-                win[i] = *src;
+            }
+        }
+    } else {
+        // WB of a thread's window elements are loaded before any is stored to LDS, so their
+        // loads are in flight together
+        constexpr int WB = WPT < 10 ? WPT : 10;
+#pragma unroll
+        for (int k0 = 0; k0 < WPT; k0 += WB) {
+            cpx<T> t[WB];
+#pragma unroll
+            for (int kk = 0; kk < WB; ++kk) {
+                const int i = threadIdx.x + (k0 + kk) * NT;
+                if (k0 + kk < WPT && i < WS * WS)
+                    t[kk] = grid[(size_t)((t1o + i / WS) & mask) * K + ((t2o + i % WS) & mask)];
+            }
+#pragma unroll
+            for (int kk = 0; kk < WB; ++kk) {
+                const int i = threadIdx.x + (k0 + kk) * NT;
+                if (k0 + kk < WPT && i < WS * WS) win[i] = t[kk];
+            }
         }
     }
     __syncthreads();
