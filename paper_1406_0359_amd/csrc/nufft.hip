@@ -189,9 +189,7 @@ k_degrid_tiles(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const in
         visibility_weights<T, J>(wtab, kbc, idx, f, wa, wb, Jr);
         const cpx<T>* w0 = win + (((bk & 0xFFFF) - t1o) & mask) * WS + ((((bk >> 16) & 0xFFFF) - t2o) & mask);
         T ax = 0, ay = 0;
-#pragma unroll UNR
-        for (int a = 0; a < JJ; ++a) {
-            if (a >= Jn) break;
+        auto tap_row = [&](int a) {
             const cpx<T>* row = w0 + a * WS;
             T rx = 0, ry = 0;
 #pragma unroll UNR
@@ -203,6 +201,23 @@ k_degrid_tiles(const cpx<T>* __restrict__ grid, cpx<T>* __restrict__ y, const in
             }
             ax += wa[a] * rx;
             ay += wa[a] * ry;
+        };
+        // FP64 and J = 8: two rows at a time, so the window reads of all J rows are not all
+        // held in registers at once (158 -> 65 VGPRs at J = 8, four workgroups a CU instead
+        // of three: 4096^2 G 233 -> 220 us; FP64 256^2 4.0 -> 3.4 us); FP32 with J <= 6 keeps
+        // the fully unrolled form (1024^2 G 26.8 against 30.0 us)
+        if constexpr (sizeof(T) == 8 || J == 8) {
+#pragma unroll 2
+            for (int a = 0; a < JJ; ++a) {
+                if (a >= Jn) break;
+                tap_row(a);
+            }
+        } else {
+#pragma unroll UNR
+            for (int a = 0; a < JJ; ++a) {
+                if (a >= Jn) break;
+                tap_row(a);
+            }
         }
         y[perm ? perm[idx] : idx] = mk<T>(scale * ax, scale * ay);
     }
