@@ -727,20 +727,25 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
     cpx<T>* outr = tmp + (size_t)row * K;
     // the row's loads are issued before the partial sums are read, so both are in flight
     // (x only by parity group 0, which writes the row back)
+    // Long rows (one a workgroup): parity group 0 alone loads and updates the row and hands
+    // the new direction to group 1 through group 1's line buffer
+    constexpr bool PRE = PL::RMAX <= 8 && 2 * B * PL::TL <= 512;   // register budget
+    constexpr bool SHARE = !PRE && B == 1;
     cpx<T> xv[PL::RMAX], rv[PL::RMAX], pv[PL::RMAX], qv[PL::RMAX];
+    if (!SHARE || r == 0) {
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        const int p = PL::in_pos(tl, i);
-        rv[i] = cg.r[ro + p];
-        pv[i] = cg.p[ro + p];
-        qv[i] = cg.q[ro + p];
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int p = PL::in_pos(tl, i);
+            rv[i] = cg.r[ro + p];
+            pv[i] = cg.p[ro + p];
+            qv[i] = cg.q[ro + p];
+        }
     }
     if (r == 0) {
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) xv[i] = cg.x[ro + PL::in_pos(tl, i)];
     }
     // short lines: the transform's S and parity twiddles are read here too
-    constexpr bool PRE = PL::RMAX <= 8 && 2 * B * PL::TL <= 512;   // register budget
     T dq[PRE ? PL::RMAX : 1];
     cpx<T> t2[PRE ? PL::RMAX : 1];
     if constexpr (PRE) {
@@ -758,15 +763,17 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
     const double rn = rho - 2.0 * al * rq + al * al * qq;
     const T alpha = (T)al, beta = (T)(rho == 0.0 || !(rn > 0.0) ? 0.0 : rn / rho);
     double acc = 0;
+    if (!SHARE || r == 0) {
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        if (r == 0) xv[i] = xv[i] + alpha * pv[i];
-        rv[i] = rv[i] - alpha * qv[i];
-        acc += (double)rv[i].x * rv[i].x + (double)rv[i].y * rv[i].y;
-        pv[i] = rv[i] + beta * pv[i];
+        for (int i = 0; i < PL::RMAX; ++i) {
+            if (r == 0) xv[i] = xv[i] + alpha * pv[i];
+            rv[i] = rv[i] - alpha * qv[i];
+            acc += (double)rv[i].x * rv[i].x + (double)rv[i].y * rv[i].y;
+            pv[i] = rv[i] + beta * pv[i];
+        }
     }
     // both parity groups hold the whole row; group 0 writes it back once all have read it
-    __syncthreads();
+    if constexpr (!SHARE) __syncthreads();
     if (r == 0) {
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) {
@@ -783,18 +790,38 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
     }
     const double tot = block_sum_dyn(r == 0 ? acc : 0.0, red);
     if (threadIdx.x == 0) cg.rho_new_part[blockIdx.x] = tot;
+    if constexpr (SHARE) {
+        // group 0: S p into its registers and into group 1's line buffer; group 1 then
+        // applies its parity twiddles; a barrier before the first pass rewrites the buffer
+        cpx<T>* line1 = line + (1 - r) * PL::LS;
+        if (r == 0) {
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        const int p = PL::in_pos(tl, i);
-        cpx<T> a;
-        if constexpr (PRE) {
-            a = (srow * dq[i]) * pv[i];
-            if (r) a = a * t2[i];
-        } else {
-            a = (srow * deap[p]) * pv[i];
-            if (r) a = a * tw2[p];
+            for (int i = 0; i < PL::RMAX; ++i) {
+                const int p = PL::in_pos(tl, i);
+                pv[i] = (srow * deap[p]) * pv[i];
+                line1[PL::in_at(tl, i)] = pv[i];
+            }
         }
-        pv[i] = a;
+        __syncthreads();
+        if (r == 1) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) pv[i] = line[PL::in_at(tl, i)] * tw2[PL::in_pos(tl, i)];
+        }
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int p = PL::in_pos(tl, i);
+            cpx<T> a;
+            if constexpr (PRE) {
+                a = (srow * dq[i]) * pv[i];
+                if (r) a = a * t2[i];
+            } else {
+                a = (srow * deap[p]) * pv[i];
+                if (r) a = a * tw2[p];
+            }
+            pv[i] = a;
+        }
     }
     line_fft<T, LOGN, 0, false>(pv, line, tl, W);
     store_row_fwd<T, LOGN>(pv, line - r * PL::LS, outr, tl, r);
