@@ -613,11 +613,16 @@ k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* 
     const T srow = deap[row];
     const cpx<T>* xr = x + (size_t)row * N;
     cpx<T>* outr = tmp + (size_t)row * K;
-    cpx<T> v[PL::RMAX];
-#pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) v[i] = xr[PL::in_pos(tl, i)];
     // short lines: S and the parity twiddles are read before the barrier too
     constexpr bool PRE = PL::RMAX <= 8 && 2 * B * PL::TL <= 512;   // register budget
+    // long rows (one a workgroup): group 0 alone loads the row and hands S x to group 1
+    // through group 1's line buffer
+    constexpr bool SHARE = B == 1 && !PRE;
+    cpx<T> v[PL::RMAX];
+    if (!SHARE || r == 0) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) v[i] = xr[PL::in_pos(tl, i)];
+    }
     T dq[PRE ? PL::RMAX : 1];
     cpx<T> t2[PRE ? PL::RMAX : 1];
     if constexpr (PRE) {
@@ -628,19 +633,36 @@ k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* 
             t2[i] = r ? tw2[p] : mk<T>(1, 0);
         }
     }
-    __syncthreads();   // the twiddle table is staged
+    if constexpr (SHARE) {
+        cpx<T>* line1 = line + (1 - r) * PL::LS;
+        if (r == 0) {
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        const int p = PL::in_pos(tl, i);
-        cpx<T> a;
-        if constexpr (PRE) {
-            a = (srow * dq[i]) * v[i];
-            if (r) a = a * t2[i];
-        } else {
-            a = (srow * deap[p]) * v[i];
-            if (r) a = a * tw2[p];
+            for (int i = 0; i < PL::RMAX; ++i) {
+                v[i] = (srow * deap[PL::in_pos(tl, i)]) * v[i];
+                line1[PL::in_at(tl, i)] = v[i];
+            }
         }
-        v[i] = a;
+        __syncthreads();   // also: the twiddle table is staged
+        if (r == 1) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) v[i] = line[PL::in_at(tl, i)] * tw2[PL::in_pos(tl, i)];
+        }
+    }
+    __syncthreads();   // the twiddle table is staged (long rows: group 1 has read its buffer)
+    if constexpr (!SHARE) {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int p = PL::in_pos(tl, i);
+            cpx<T> a;
+            if constexpr (PRE) {
+                a = (srow * dq[i]) * v[i];
+                if (r) a = a * t2[i];
+            } else {
+                a = (srow * deap[p]) * v[i];
+                if (r) a = a * tw2[p];
+            }
+            v[i] = a;
+        }
     }
     line_fft<T, LOGN, 0, false>(v, line, tl, W);
     store_row_fwd<T, LOGN>(v, line - r * PL::LS, outr, tl, r);
@@ -675,17 +697,22 @@ k_fft_rows_init(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<
     const T srow = deap[row];
     const size_t ro = (size_t)row * N;
     cpx<T>* outr = tmp + (size_t)row * K;
+    // long rows (one a workgroup): group 0 alone loads the row and hands S r to group 1
+    // through group 1's line buffer; otherwise both parity groups load the whole row
+    constexpr bool SHARE = B == 1 && !(PL::RMAX <= 8 && 2 * B * PL::TL <= 512);
     cpx<T> v[PL::RMAX];
     double acc = 0;
+    if (!SHARE || r == 0) {
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        const int p = PL::in_pos(tl, i);
-        cpx<T> b = ci.x1[ro + p] + ci.x2[ro + p] + ci.x3[ro + p];
-        if (ci.q0) b = b - ci.q0[ro + p];
-        v[i] = b;
-        acc += (double)b.x * b.x + (double)b.y * b.y;
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int p = PL::in_pos(tl, i);
+            cpx<T> b = ci.x1[ro + p] + ci.x2[ro + p] + ci.x3[ro + p];
+            if (ci.q0) b = b - ci.q0[ro + p];
+            v[i] = b;
+            acc += (double)b.x * b.x + (double)b.y * b.y;
+        }
     }
-    // both parity groups hold the whole row: group 0 writes r and p and counts ||r||^2
+    // group 0 writes r and p and counts ||r||^2
     if (r == 0) {
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) {
@@ -696,12 +723,29 @@ k_fft_rows_init(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<
     }
     const double tot = block_sum_dyn(r == 0 ? acc : 0.0, red);   // also orders the twiddle staging
     if (threadIdx.x == 0) ci.rho_part[blockIdx.x] = tot;
+    if constexpr (SHARE) {
+        cpx<T>* line1 = line + (1 - r) * PL::LS;
+        if (r == 0) {
 #pragma unroll
-    for (int i = 0; i < PL::RMAX; ++i) {
-        const int p = PL::in_pos(tl, i);
-        cpx<T> a = (srow * deap[p]) * v[i];
-        if (r) a = a * tw2[p];
-        v[i] = a;
+            for (int i = 0; i < PL::RMAX; ++i) {
+                v[i] = (srow * deap[PL::in_pos(tl, i)]) * v[i];
+                line1[PL::in_at(tl, i)] = v[i];
+            }
+        }
+        __syncthreads();
+        if (r == 1) {
+#pragma unroll
+            for (int i = 0; i < PL::RMAX; ++i) v[i] = line[PL::in_at(tl, i)] * tw2[PL::in_pos(tl, i)];
+        }
+        __syncthreads();   // group 1 has read its buffer before the first pass rewrites it
+    } else {
+#pragma unroll
+        for (int i = 0; i < PL::RMAX; ++i) {
+            const int p = PL::in_pos(tl, i);
+            cpx<T> a = (srow * deap[p]) * v[i];
+            if (r) a = a * tw2[p];
+            v[i] = a;
+        }
     }
     line_fft<T, LOGN, 0, false>(v, line, tl, W);
     store_row_fwd<T, LOGN>(v, line - r * PL::LS, outr, tl, r);
