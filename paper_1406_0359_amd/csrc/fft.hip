@@ -615,9 +615,9 @@ k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* 
     cpx<T>* outr = tmp + (size_t)row * K;
     // short lines: S and the parity twiddles are read before the barrier too
     constexpr bool PRE = PL::RMAX <= 8 && 2 * B * PL::TL <= 512;   // register budget
-    // long rows (one a workgroup): group 0 alone loads the row and hands S x to group 1
-    // through group 1's line buffer
-    constexpr bool SHARE = B == 1 && !PRE;
+    // one row a workgroup: group 0 alone loads the row and hands S x to group 1 through
+    // group 1's line buffer
+    constexpr bool SHARE = B == 1;
     cpx<T> v[PL::RMAX];
     if (!SHARE || r == 0) {
 #pragma unroll
@@ -638,17 +638,17 @@ k_fft_rows_fwd(const cpx<T>* __restrict__ x, cpx<T>* __restrict__ tmp, const T* 
         if (r == 0) {
 #pragma unroll
             for (int i = 0; i < PL::RMAX; ++i) {
-                v[i] = (srow * deap[PL::in_pos(tl, i)]) * v[i];
+                v[i] = (srow * (PRE ? dq[i] : deap[PL::in_pos(tl, i)])) * v[i];
                 line1[PL::in_at(tl, i)] = v[i];
             }
         }
         __syncthreads();   // also: the twiddle table is staged
         if (r == 1) {
 #pragma unroll
-            for (int i = 0; i < PL::RMAX; ++i) v[i] = line[PL::in_at(tl, i)] * tw2[PL::in_pos(tl, i)];
+            for (int i = 0; i < PL::RMAX; ++i) v[i] = line[PL::in_at(tl, i)] * (PRE ? t2[i] : tw2[PL::in_pos(tl, i)]);
         }
     }
-    __syncthreads();   // the twiddle table is staged (long rows: group 1 has read its buffer)
+    __syncthreads();   // the twiddle table is staged (one row a workgroup: group 1 has read its buffer)
     if constexpr (!SHARE) {
 #pragma unroll
         for (int i = 0; i < PL::RMAX; ++i) {
@@ -697,9 +697,9 @@ k_fft_rows_init(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<
     const T srow = deap[row];
     const size_t ro = (size_t)row * N;
     cpx<T>* outr = tmp + (size_t)row * K;
-    // long rows (one a workgroup): group 0 alone loads the row and hands S r to group 1
-    // through group 1's line buffer; otherwise both parity groups load the whole row
-    constexpr bool SHARE = B == 1 && !(PL::RMAX <= 8 && 2 * B * PL::TL <= 512);
+    // one row a workgroup: group 0 alone loads the row and hands S r to group 1 through
+    // group 1's line buffer; otherwise both parity groups load the whole row
+    constexpr bool SHARE = B == 1;
     cpx<T> v[PL::RMAX];
     double acc = 0;
     if (!SHARE || r == 0) {
@@ -771,10 +771,10 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
     cpx<T>* outr = tmp + (size_t)row * K;
     // the row's loads are issued before the partial sums are read, so both are in flight
     // (x only by parity group 0, which writes the row back)
-    // Long rows (one a workgroup): parity group 0 alone loads and updates the row and hands
-    // the new direction to group 1 through group 1's line buffer
+    // One row a workgroup: parity group 0 alone loads and updates the row and hands the new
+    // direction to group 1 through group 1's line buffer
     constexpr bool PRE = PL::RMAX <= 8 && 2 * B * PL::TL <= 512;   // register budget
-    constexpr bool SHARE = !PRE && B == 1;
+    constexpr bool SHARE = B == 1;
     cpx<T> xv[PL::RMAX], rv[PL::RMAX], pv[PL::RMAX], qv[PL::RMAX];
     if (!SHARE || r == 0) {
 #pragma unroll
@@ -842,14 +842,14 @@ k_fft_rows_xr(cpx<T>* __restrict__ tmp, const T* __restrict__ deap, const cpx<T>
 #pragma unroll
             for (int i = 0; i < PL::RMAX; ++i) {
                 const int p = PL::in_pos(tl, i);
-                pv[i] = (srow * deap[p]) * pv[i];
+                pv[i] = (srow * (PRE ? dq[i] : deap[p])) * pv[i];
                 line1[PL::in_at(tl, i)] = pv[i];
             }
         }
         __syncthreads();
         if (r == 1) {
 #pragma unroll
-            for (int i = 0; i < PL::RMAX; ++i) pv[i] = line[PL::in_at(tl, i)] * tw2[PL::in_pos(tl, i)];
+            for (int i = 0; i < PL::RMAX; ++i) pv[i] = line[PL::in_at(tl, i)] * (PRE ? t2[i] : tw2[PL::in_pos(tl, i)]);
         }
         __syncthreads();
     } else {
